@@ -1,0 +1,209 @@
+/*
+ * rtucker - randomized Tucker compression on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of librtucker.so.  It computes the Tucker approximations of
+ * Minster, Saibaba and Kilmer, "Randomized Algorithms for Low-rank Tensor
+ * Decompositions in the Tucker Format":
+ *   rt_rhosvd            - R-HOSVD, Alg. 2 (§3.1)
+ *   rt_rsthosvd          - R-STHOSVD, Alg. 3 (§3.1)
+ *   rt_rsthosvd_adaptive - adaptive R-STHOSVD, Alg. 5 (§4)
+ * and exposes the steps of their hot path for testing: the on-the-fly Gaussian
+ * sketch Y = X_(n) Omega (Alg. 1 step 1), Q = orth(Y) (Alg. 1 step 2) and the
+ * projection B = X x_n Q^T (Alg. 1 step 3).
+ *
+ * Conventions (all calls):
+ *  - Tensors are dense, row-major (last index fastest), float32 or float64,
+ *    in device memory of the context's device.  Modes are 0-based.
+ *  - The mode-n unfolding X_(n) has the mode-n fibres as columns; column c is
+ *    the row-major linear index over the remaining modes in increasing order.
+ *  - Omega_n[c, k] ~ N(0, 1) comes from Philox4x32-10 with key (seed lo, seed hi)
+ *    and counter (c lo, c hi, k / 4, n), words mapped to (w + 1/2) 2^-32 and
+ *    through two Box-Muller pairs to columns 4 (k/4) .. 4 (k/4) + 3.  It is never
+ *    stored.  R-HOSVD mode n and the first R-STHOSVD step on mode n therefore
+ *    see the same Omega.
+ *  - Pointers are device pointers unless marked "host".  The caller keeps
+ *    ownership of every input; the library never writes an input tensor.
+ *  - Work is enqueued on the context's stream.  The decomposition calls return
+ *    after the stream has finished their work (their scalar results need it).
+ *  - Errors: argument errors return RT_EINVAL before anything is enqueued;
+ *    HIP failures return RT_EHIP; rt_last_error() gives a message (thread-local,
+ *    valid until the next call on the same thread).
+ */
+#ifndef RTUCKER_H
+#define RTUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = 1,      /* invalid argument (nothing enqueued) */
+    RT_ENOMEM = 2,      /* device allocation failed */
+    RT_ENONFINITE = 3,  /* the input holds NaN or Inf */
+    RT_ECAP = 4,        /* adaptive: rank cap reached before the tolerance */
+    RT_EHIP = 5         /* a HIP runtime call failed */
+} rt_status;
+
+typedef enum { RT_F32 = 0, RT_F64 = 1 } rt_dtype;
+
+/* Arithmetic of the hot path.
+ *  RT_PREC_F64: float64 input, every step in float64.
+ *  RT_PREC_F32: float32 input; sketch and projections in float32 with float32
+ *               accumulation; Gram matrices, Cholesky, eigenproblems in float64.
+ *  RT_PREC_BF16_SKETCH: as RT_PREC_F32 but the sketch multiplies bfloat16-rounded
+ *               X and Omega (float32 accumulation); orth, projection and
+ *               truncation stay float32/float64. */
+typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_precision;
+
+#define RT_MAXD 8
+#define RT_KEEP (-1) /* rank value: leave this mode uncompressed (factor = identity) */
+#define RT_LMAX 64   /* largest sketch width r + p (and adaptive rank) per mode */
+
+/* flags of rt_tucker */
+#define RT_FLAG_PADDED 1u    /* some sketch was numerically rank deficient; its basis
+                                was completed with zero-weight orthonormal columns */
+#define RT_FLAG_FALLBACK 2u  /* orth used the Householder fallback instead of CholeskyQR2 */
+
+typedef struct rt_ctx rt_ctx;
+
+/* Optional device allocator: must return `bytes` of device memory on the
+ * context's device (or NULL); `user` is passed through.  Without one the
+ * library uses hipMalloc / hipFree. */
+typedef void* (*rt_alloc_fn)(size_t bytes, void* user);
+typedef void (*rt_free_fn)(void* ptr, void* user);
+
+typedef struct {
+    int32_t ndim;             /* 2 .. RT_MAXD */
+    int64_t dims[RT_MAXD];    /* every dim >= 1 */
+    rt_dtype dtype;
+    const void* data;         /* device, dense row-major */
+} rt_tensor;
+
+typedef struct {
+    int32_t oversample;       /* p >= 0 */
+    uint64_t seed;            /* Omega seed */
+    const int32_t* order;     /* host, ndim mode indices (a permutation), or NULL:
+                                 largest modes first, ties by index (§3.3) */
+    rt_precision prec;        /* must match the input dtype: F64 <-> RT_F64 */
+} rt_opts;
+
+typedef struct {
+    int32_t ndim;
+    int64_t dims[RT_MAXD];      /* input dims */
+    int32_t ranks[RT_MAXD];     /* core dims */
+    rt_dtype dtype;
+    void* core;                 /* device, row-major ranks[0] x ... x ranks[ndim-1] */
+    void* factors[RT_MAXD];     /* device, row-major dims[j] x ranks[j], orthonormal
+                                   columns; NULL for an uncompressed mode */
+    double norm_x;              /* ||X||_F (fp64 accumulation) */
+    double core_norm;           /* ||G||_F */
+    double rel_err_est;         /* sqrt(max(0, ||X||^2 - ||G||^2)) / ||X|| */
+    uint32_t flags;             /* RT_FLAG_* */
+} rt_tucker;
+
+/* Library version string (static storage). */
+const char* rt_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* rt_last_error(void);
+
+/* Create a context on `device` that enqueues on `stream` (a hipStream_t, NULL =
+ * the default stream).  alloc/free may be NULL (hipMalloc/hipFree).  The
+ * context caches its device workspace between calls; it is not thread-safe. */
+rt_status rt_create(rt_ctx** ctx, int device, void* stream, rt_alloc_fn alloc, rt_free_fn free_fn, void* user);
+
+/* Change the stream of a context. */
+rt_status rt_set_stream(rt_ctx* ctx, void* stream);
+
+/* Free the workspace and the context. */
+rt_status rt_destroy(rt_ctx* ctx);
+
+/* R-HOSVD (Alg. 2, §3.1).  ranks (host, ndim entries): r_j >= 1 or RT_KEEP, with
+ * r_j + p <= min(I_j, prod_{i != j} I_i) and r_j + p <= RT_LMAX.  On success
+ * `out` holds a core and factors allocated with the context's allocator; release
+ * them with rt_tucker_release. */
+rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out);
+
+/* R-STHOSVD (Alg. 3, §3.1): modes in the order opts->order; the core shrinks
+ * after each mode.  Arguments as for rt_rhosvd. */
+rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out);
+
+/* Adaptive R-STHOSVD (Alg. 5, §4): the rank of each mode is grown `block`
+ * columns at a time until ||G_(n) - Q Q^T G_(n)||_F <= eps_n ||X||_F, with
+ * eps_n = eps / sqrt(d) (eps_per_mode == NULL) or eps_per_mode[n] (host array,
+ * sum of squares must equal eps^2 to 1e-12 relative; 0 leaves the mode
+ * uncompressed), then truncated to the smallest rank whose error estimate
+ * still meets eps_n ||X||_F.  max_rank (host, may be NULL) caps each mode
+ * (default min(I_n, RT_LMAX)); RT_ECAP is returned (with a valid result) when
+ * a cap stops a mode before its tolerance.  opts->oversample is ignored. */
+rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
+                               int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out);
+
+/* Release the core and factors of a result produced by this context. */
+rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t);
+
+/* ---- hot-path steps, exposed for testing --------------------------------------- */
+
+/* Y = X_(mode) Omega_mode[:, col0 : col0 + ell] (Alg. 1 step 1) for a row-major
+ * tensor X, written to Y (device, float64, dims[mode] x ell, row-major).
+ * prec selects the arithmetic (F64 needs an RT_F64 tensor).  If nrm2 is not NULL
+ * it receives ||X||_F^2 (device, one float64).  1 <= ell <= RT_LMAX. */
+rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
+                    rt_precision prec, double* Y, double* nrm2);
+
+/* Q = orth(Y) (Alg. 1 step 2): Y (device, float64, rows x ell, row-major) is
+ * overwritten by an orthonormal Q with range(Y) inside range(Q).  *flags (host)
+ * receives RT_FLAG_* bits.  ell <= rows, ell <= RT_LMAX. */
+rt_status rt_orth(rt_ctx* ctx, double* Y, int64_t rows, int32_t ell, uint32_t* flags);
+
+/* B = X x_mode Q^T (Alg. 1 step 3): Q (device, dims[mode] x ell, row-major,
+ * dtype qtype), B (device, X's dims with dims[mode] replaced by ell, X's dtype).
+ * qtype may be RT_F64 for an RT_F32 tensor (fp64 accumulation).  If gram is not
+ * NULL it receives B_(mode) B_(mode)^T (device, ell x ell float64). */
+rt_status rt_project(rt_ctx* ctx, const rt_tensor* X, int32_t mode, const void* Q, rt_dtype qtype, int32_t ell,
+                     void* B, double* gram);
+
+/* Omega_mode[c0 + i, col0 + j] for i < nrows, j < ncols into out (device,
+ * row-major, float32 or float64 transform). */
+rt_status rt_omega(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t nrows, int64_t col0,
+                   int32_t ncols, rt_dtype dtype, void* out);
+
+/* Raw Philox4x32-10 words of the Omega stream: out[4 i + t] = word t of the block
+ * at counter (c0 + i, q, mode) and key seed (device, uint32). */
+rt_status rt_philox_words(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t n, uint32_t q,
+                          uint32_t* out);
+
+/* ---- timing log --------------------------------------------------------------- */
+
+/* Kernel kinds of the timing log. */
+#define RT_KIND_SKETCH 0    /* Y = X_(n) Omega, bytes = X read, flops = 2 ell N */
+#define RT_KIND_PROJECT 1   /* B = X x_n Q^T, bytes = X read + B written, flops = 2 ell N */
+#define RT_KIND_ORTH 2      /* single-workgroup orth(Y) */
+#define RT_KIND_TRUNCATE 3  /* single-workgroup eigensolver + factor */
+
+/* Turn the per-launch timing log on (enable != 0) or off, clearing it.  While on,
+ * every sketch, projection, orth and truncation launch of this context is
+ * bracketed by HIP events on the context's stream. */
+rt_status rt_timing(rt_ctx* ctx, int32_t enable);
+
+/* Number of entries in the timing log. */
+rt_status rt_timing_count(rt_ctx* ctx, int64_t* n);
+
+/* Entry i of the timing log (host outputs): kind (RT_KIND_*), elapsed
+ * milliseconds between the bracketing events, algorithmic bytes and flops of the
+ * launch, rows (J) and columns (K) of the unfolding, and the sketch width. */
+rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, double* bytes, double* flops,
+                          int64_t* rows, int64_t* cols, int32_t* ell);
+
+/* Block until the context's stream is idle. */
+rt_status rt_sync(rt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTUCKER_H */

@@ -50,6 +50,7 @@ def adapt_range_finder(M, tau, b, seed, mode, delta=1e-10):
     B = np.zeros((0, K))
     i = 0
     stop = "tolerance"
+    hist = [E]
     while E > tau * tau:
         if Q.shape[1] >= cap:
             stop = "cap"
@@ -72,8 +73,9 @@ def adapt_range_finder(M, tau, b, seed, mode, delta=1e-10):
         Q = np.hstack([Q, Qi])
         B = np.vstack([B, Bi])
         E -= fro2(Bi)
+        hist.append(E)
         i += 1
-    return Q, B, E, {"blocks": i, "stop": stop}
+    return Q, B, E, {"blocks": i, "stop": stop, "E_hist": hist}
 
 
 def truncate_qb(Q, B, E, tau):

@@ -1,0 +1,111 @@
+// Launchers of the device kernels used by the host drivers (rtucker.cpp).
+// Every launcher enqueues on `stream` and returns the hipError_t of the launch.
+// Shapes: a row-major tensor is viewed, for mode n, as (L, J, R) with
+// L = prod of dims before n, J = dims[n], R = prod of dims after n; the
+// mode-n unfolding has J rows and K = L R columns, column c = l R + r.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rt {
+
+constexpr int LMAX = 64;     // largest sketch width / rank handled by the dense FP64 kernels
+
+enum class Dt : int { F32 = 0, F64 = 1 };
+
+struct Shape3 { int64_t L, J, R; };
+
+// ---- sketch:  Y = X_(n) Omega[:, col0 : col0 + ell]  (§2.4 Alg. 1 step 1) ------------
+// Writes split-K partial sums to `partial` ([nsplit][J][ell], accumulate type),
+// then `reduce_partials` folds them in a fixed order into Y (double, J x ell).
+// If nrm2_partial != nullptr, the kernel also accumulates sum x^2 (fp64) per
+// workgroup into nrm2_partial[workgroup] (every element is read exactly once).
+struct SketchPlan {
+    int nsplit;            // split-K factor (gridDim.x)
+    int nrowtile;          // gridDim.y
+    int64_t tiles_per_split;
+    size_t partial_elems;  // nsplit * J * ell
+    int nwg;               // nsplit * nrowtile
+    int kind;              // kernel variant
+};
+SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell);
+hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,
+                         int64_t col0, uint64_t seed, uint32_t mode, void* partial,
+                         double* nrm2_partial, hipStream_t stream);
+
+// out[e] = sum_{s < nparts} in[s * n + e] (in float or double, summed in fp64 in
+// the order s = 0, 1, ...).  out is double.
+hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
+                                  double* out, hipStream_t stream);
+// out[0] = sum of `n` doubles (single workgroup, fixed order of a tree)
+hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream);
+
+// ---- orthonormalisation:  Q = orth(Y)  (§2.4 Alg. 1 step 2) --------------------------
+// In place on Y (double, J x ell, row-major, ld = ell).  Shifted CholeskyQR3
+// with a rank-revealing eigen fallback; zero-weight orthonormal padding when Y is
+// numerically rank deficient.  Optionally writes a float copy Qf.  status[0] is
+// set to a bit mask: 1 = padded / rank deficient, 2 = fallback path used,
+// 4 = non-finite input.
+// `accept_ratio`: CholeskyQR2 is accepted when the smallest relative Cholesky pivot of
+// the first pass is >= accept_ratio and that of the second pass >= 1/2.
+// `scratch`: 2 J ell doubles.
+hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_ratio,
+                       uint32_t* status, double* scratch, hipStream_t stream);
+
+// ---- projection / core update:  B = G x_n Q^T  (Alg. 1 step 3; Alg. 3 core update) --
+// B[l, k, r] = sum_i Q[i, k] G[l, i, r], k < ell; Q is J x ell (row-major, ld = ldq).
+// tq: type of Q (F32 or F64); accumulation is in the wider of (X, Q) types.
+// If gram_partial != nullptr, each workgroup adds the fp64 Gram sum_c B[:, c] B[:, c]^T
+// of its columns to gram_partial[wg][ell][ell]; if nrm2_partial != nullptr, sum B^2
+// (fp64) per workgroup.  `nwg_out` receives the workgroup count.
+struct ProjectPlan { int nwg; int64_t ntiles; int kind; };
+ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell);
+// ldj: stride of the mode index in G (= s.J for a plain tensor; larger when only
+// the first s.J rows of a wider buffer are contracted).  B is written at
+// B[(l * ldk + koff + k) * R + r] (ldk = ell, koff = 0 for a plain tensor).
+hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj,
+                          const void* Q, int64_t ldq, int ell, void* B, int64_t ldk, int64_t koff,
+                          double* gram_partial, double* nrm2_partial, hipStream_t stream);
+// fp64 Gram partials of the first k mode rows of a (L, ldk, R) tensor; nwg from plan_gram3.
+int plan_gram3(int64_t L, int64_t R);
+hipError_t launch_gram3(const void* B, Dt dt, int64_t L, int64_t ldk, int64_t R, int k, double* partial, int nwg,
+                        hipStream_t stream);
+
+// ---- truncation (Alg. 1 steps 4-6) ----------------------------------------------------
+// W: ell x ell fp64 Gram of B (from the projection), Q: J x ell fp64.
+// Jacobi eigendecomposition of W, eigenvalues sorted in decreasing order.
+// Fixed rank: k = r.  Adaptive: k = smallest k with max(E,0) + sum_{t>=k} lambda_t
+// <= tau2 (E = *E_dev), capped at kmax.
+// Writes U (ell x k, double, and float copy Uf), A = Q U (J x k, in dtype `da`,
+// columns sign-fixed: largest-|.| entry positive), lam (ell, sorted eigenvalues),
+// kout[0] = k.
+hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
+                           const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da,
+                           double* lam, int* kout, hipStream_t stream);
+
+// ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
+// Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
+// then orthonormalised with a rank-revealing drop (singular values <= drop * ||Y_in||_F
+// are dropped).  The kept columns are appended to Qall at column k; knew[0] = number
+// appended; Qf (optional) gets the float copy of the appended columns.
+// `scratch`: 2 J b doubles.
+hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k,
+                             double drop, int* knew, double* scratch, hipStream_t stream);
+// one-time per-device set-up of the single-workgroup dense kernels (LDS > 64 KiB)
+hipError_t dense_init();
+
+// ---- misc ------------------------------------------------------------------------------
+// sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)
+int plan_norm(int64_t n);
+hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream);
+// dst (dtype) <- src (double), n elements
+hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream);
+// explicit Omega (testing): out[i][j] = Omega[c0 + i, col0 + j], fp32 or fp64 transform
+hipError_t launch_omega(uint64_t seed, uint32_t mode, int64_t c0, int64_t nrows, int64_t col0, int ncols,
+                        void* out, Dt dt, hipStream_t stream);
+// raw Philox words (testing): out[4 i + t] = word t of block (c0 + i, q, mode)
+hipError_t launch_philox_words(uint64_t seed, uint32_t mode, int64_t c0, int64_t n, uint32_t q,
+                               uint32_t* out, hipStream_t stream);
+// Tucker reconstruction helper is the projection kernel with the factor in place of Q^T.
+
+}  // namespace rt

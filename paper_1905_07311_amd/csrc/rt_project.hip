@@ -1,0 +1,335 @@
+// Mode-n projection B = G x_n Q^T (§2.4 Alg. 1 step 3, B = Q^T X on the unfolding;
+// the core update of Alg. 3 G_(n) <- U^T G_(n) is the same contraction), on the
+// strided (L, J, R) view: B[l, k, r] = sum_i Q[i, k] G[l, i, r].  The output keeps
+// the row-major layout with mode n resized to ell, so no transpose is needed
+// before the next mode.  Optionally fused: the fp64 Gram B_(n) B_(n)^T of the
+// workgroup's columns (input of the truncation SVD) and sum B^2 (fp64, the
+// adaptive error indicator update).
+//
+// Plus the small helpers: Frobenius norms with fp64 accumulation, dtype casts,
+// and the explicit Omega / raw Philox words used by the tests.
+#include "rt_kernels.hpp"
+#include "rt_philox.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int PJ_NC = 64;    // unfolding columns per tile
+constexpr int PJ_JT = 32;    // contraction rows per stage
+constexpr int PJ_NACC = LMAX / 4;
+
+template <typename TX, typename TQ, typename TA>
+__global__ __launch_bounds__(256) void project_generic_kernel(
+    const TX* __restrict__ G, int64_t L, int64_t J, int64_t ldj, int64_t R, const TQ* __restrict__ Q, int64_t ldq,
+    int ell, TX* __restrict__ B, int64_t ldk, int64_t koff, double* __restrict__ gram_partial,
+    double* __restrict__ nrm2_partial) {
+    __shared__ TA gs[PJ_JT][PJ_NC + 1];
+    __shared__ TA qs[PJ_JT][LMAX + 4];
+    __shared__ double bs[LMAX][PJ_NC + 1];
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int cl = tid % PJ_NC;
+    const int kg = tid / PJ_NC;
+    const int64_t K = L * R;
+    const int64_t ntiles = (K + PJ_NC - 1) / PJ_NC;
+    const bool want_gram = gram_partial != nullptr;
+    const int npairs = ell * (ell + 1) / 2;
+    double gacc[9];
+    int pa[9], pb[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        gacc[m] = 0.0;
+        const int t = tid + 256 * m;
+        int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((a + 1) * (a + 2) / 2 <= t) ++a;
+        while (a * (a + 1) / 2 > t) --a;
+        pa[m] = a;
+        pb[m] = t - a * (a + 1) / 2;
+    }
+    double nrm = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t cbase = tile * PJ_NC;
+        TA acc[PJ_NACC];
+#pragma unroll
+        for (int j = 0; j < PJ_NACC; ++j) acc[j] = TA(0);
+        for (int64_t i0 = 0; i0 < J; i0 += PJ_JT) {
+            __syncthreads();
+            for (int e = tid; e < PJ_JT * PJ_NC; e += 256) {
+                int ii, cc;
+                if (R == 1) { ii = e % PJ_JT; cc = e / PJ_JT; }
+                else        { cc = e % PJ_NC; ii = e / PJ_NC; }
+                const int64_t c = cbase + cc, i = i0 + ii;
+                TA v = TA(0);
+                if (c < K && i < J) {
+                    const int64_t l = c / R, r = c - l * R;
+                    v = (TA)G[(l * ldj + i) * R + r];
+                }
+                gs[ii][cc] = v;
+            }
+            for (int e = tid; e < PJ_JT * ell; e += 256) {
+                const int ii = e / ell, k = e % ell;
+                const int64_t i = i0 + ii;
+                qs[ii][k] = (i < J) ? (TA)Q[i * ldq + k] : TA(0);
+            }
+            __syncthreads();
+            const int rows = (int)((J - i0) < PJ_JT ? (J - i0) : PJ_JT);
+            for (int ii = 0; ii < rows; ++ii) {
+                const TA g = gs[ii][cl];
+#pragma unroll
+                for (int j = 0; j < PJ_NACC; ++j) {
+                    const int k = kg + 4 * j;
+                    if (k < ell) acc[j] += qs[ii][k] * g;
+                }
+            }
+        }
+        const int64_t c = cbase + cl;
+        const bool cvalid = c < K;
+        int64_t l = 0, r = 0;
+        if (cvalid) { l = c / R; r = c - l * R; }
+#pragma unroll
+        for (int j = 0; j < PJ_NACC; ++j) {
+            const int k = kg + 4 * j;
+            if (k < ell) {
+                const double v = cvalid ? (double)acc[j] : 0.0;
+                if (cvalid) B[(l * ldk + koff + k) * R + r] = (TX)acc[j];
+                nrm += v * v;
+                if (want_gram) bs[k][cl] = v;
+            }
+        }
+        if (want_gram) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                if (tid + 256 * m < npairs) {
+                    double s = 0.0;
+                    for (int q = 0; q < PJ_NC; ++q) s += bs[pa[m]][q] * bs[pb[m]][q];
+                    gacc[m] += s;
+                }
+            }
+        }
+    }
+    if (want_gram) {
+        double* gp = gram_partial + (int64_t)blockIdx.x * ell * ell;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            if (tid + 256 * m < npairs) {
+                gp[pa[m] * ell + pb[m]] = gacc[m];
+                gp[pb[m] * ell + pa[m]] = gacc[m];
+            }
+        }
+    }
+    if (nrm2_partial) {
+        __syncthreads();
+        red[tid] = nrm;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) nrm2_partial[blockIdx.x] = red[0];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void norm2_kernel(const T* __restrict__ X, int64_t n, double* __restrict__ partial) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double v = (double)X[e];
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cast_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = (T)src[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void omega_kernel(uint64_t seed, uint32_t mode, int64_t c0, int64_t nrows,
+                                                    int64_t col0, int ncols, T* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nrows * ncols) return;
+    const int64_t i = e / ncols;
+    const int j = (int)(e % ncols);
+    const int64_t k = col0 + j;
+    T z[4];
+    OmegaGen<T>::gen4(seed, mode, (uint64_t)(c0 + i), (uint32_t)(k / 4), z);
+    out[e] = z[k % 4];
+}
+
+__global__ __launch_bounds__(256) void philox_words_kernel(uint64_t seed, uint32_t mode, int64_t c0, int64_t n,
+                                                           uint32_t q, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    PhiloxOut w = omega_words(seed, mode, (uint64_t)(c0 + i), q);
+    out[4 * i + 0] = w.w0;
+    out[4 * i + 1] = w.w1;
+    out[4 * i + 2] = w.w2;
+    out[4 * i + 3] = w.w3;
+}
+
+}  // namespace
+
+ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell) {
+    (void)dx; (void)dq; (void)ell;
+    ProjectPlan p{};
+    const int64_t K = s.L * s.R;
+    p.ntiles = (K + PJ_NC - 1) / PJ_NC;
+    p.nwg = (int)(p.ntiles < 1024 ? p.ntiles : 1024);
+    if (p.nwg < 1) p.nwg = 1;
+    p.kind = 0;
+    return p;
+}
+
+hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q,
+                          int64_t ldq, int ell, void* B, int64_t ldk, int64_t koff, double* gram_partial,
+                          double* nrm2_partial, hipStream_t stream) {
+    dim3 grid(p.nwg);
+    if (dx == Dt::F64) {
+        if (dq != Dt::F64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((project_generic_kernel<double, double, double>), grid, dim3(256), 0, stream,
+                           (const double*)G, s.L, s.J, ldj, s.R, (const double*)Q, ldq, ell, (double*)B, ldk, koff,
+                           gram_partial, nrm2_partial);
+    } else if (dq == Dt::F64) {
+        hipLaunchKernelGGL((project_generic_kernel<float, double, double>), grid, dim3(256), 0, stream,
+                           (const float*)G, s.L, s.J, ldj, s.R, (const double*)Q, ldq, ell, (float*)B, ldk, koff,
+                           gram_partial, nrm2_partial);
+    } else {
+        hipLaunchKernelGGL((project_generic_kernel<float, float, float>), grid, dim3(256), 0, stream,
+                           (const float*)G, s.L, s.J, ldj, s.R, (const float*)Q, ldq, ell, (float*)B, ldk, koff,
+                           gram_partial, nrm2_partial);
+    }
+    return hipGetLastError();
+}
+
+// fp64 Gram of the first k mode rows of a (L, ldk, R) tensor: per-workgroup
+// partials W_wg[a][b] = sum over the workgroup's columns c of B[l, a, r] B[l, b, r].
+template <typename T>
+__global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int64_t L, int64_t ldk, int64_t R,
+                                                    int k, double* __restrict__ partial) {
+    __shared__ double bs[LMAX][PJ_NC + 1];
+    const int tid = threadIdx.x;
+    const int64_t K = L * R;
+    const int64_t ntiles = (K + PJ_NC - 1) / PJ_NC;
+    const int npairs = k * (k + 1) / 2;
+    double gacc[9];
+    int pa[9], pb[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        gacc[m] = 0.0;
+        const int t = tid + 256 * m;
+        int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((a + 1) * (a + 2) / 2 <= t) ++a;
+        while (a * (a + 1) / 2 > t) --a;
+        pa[m] = a;
+        pb[m] = t - a * (a + 1) / 2;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t cbase = tile * PJ_NC;
+        __syncthreads();
+        for (int e = tid; e < k * PJ_NC; e += 256) {
+            int a, cc;
+            if (R == 1) { a = e % k; cc = e / k; }
+            else        { cc = e % PJ_NC; a = e / PJ_NC; }
+            const int64_t c = cbase + cc;
+            double v = 0.0;
+            if (c < K) {
+                const int64_t l = c / R, r = c - l * R;
+                v = (double)B[(l * ldk + a) * R + r];
+            }
+            bs[a][cc] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            if (tid + 256 * m < npairs) {
+                double s = 0.0;
+                for (int q = 0; q < PJ_NC; ++q) s += bs[pa[m]][q] * bs[pb[m]][q];
+                gacc[m] += s;
+            }
+        }
+    }
+    double* gp = partial + (int64_t)blockIdx.x * k * k;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        if (tid + 256 * m < npairs) {
+            gp[pa[m] * k + pb[m]] = gacc[m];
+            gp[pb[m] * k + pa[m]] = gacc[m];
+        }
+    }
+}
+
+int plan_gram3(int64_t L, int64_t R) {
+    const int64_t nt = (L * R + PJ_NC - 1) / PJ_NC;
+    return (int)(nt < 512 ? (nt < 1 ? 1 : nt) : 512);
+}
+
+hipError_t launch_gram3(const void* B, Dt dt, int64_t L, int64_t ldk, int64_t R, int k, double* partial, int nwg,
+                        hipStream_t stream) {
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(gram3_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)B, L, ldk, R, k,
+                           partial);
+    else
+        hipLaunchKernelGGL(gram3_kernel<float>, dim3(nwg), dim3(256), 0, stream, (const float*)B, L, ldk, R, k,
+                           partial);
+    return hipGetLastError();
+}
+
+int plan_norm(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream) {
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(norm2_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)X, n, partial);
+    else
+        hipLaunchKernelGGL(norm2_kernel<float>, dim3(nwg), dim3(256), 0, stream, (const float*)X, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(cast_kernel<double>, dim3((unsigned)g), dim3(256), 0, stream, src, (double*)dst, n);
+    else
+        hipLaunchKernelGGL(cast_kernel<float>, dim3((unsigned)g), dim3(256), 0, stream, src, (float*)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega(uint64_t seed, uint32_t mode, int64_t c0, int64_t nrows, int64_t col0, int ncols, void* out,
+                        Dt dt, hipStream_t stream) {
+    const int64_t n = nrows * ncols;
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, stream, seed, mode, c0, nrows, col0, ncols,
+                           (double*)out);
+    else
+        hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, stream, seed, mode, c0, nrows, col0, ncols,
+                           (float*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_words(uint64_t seed, uint32_t mode, int64_t c0, int64_t n, uint32_t q, uint32_t* out,
+                               hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, seed, mode, c0,
+                       n, q, out);
+    return hipGetLastError();
+}
+
+}  // namespace rt

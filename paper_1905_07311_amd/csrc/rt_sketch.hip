@@ -1,0 +1,195 @@
+// Mode-n sketch Y = X_(n) Omega (§2.4 Alg. 1 step 1; Alg. 2 and Alg. 3 RandSVD
+// call), formed on the strided (L, J, R) view of a row-major tensor, so no
+// unfolding is ever materialised, with Omega generated on the fly.
+//
+// Generic LDS-staged kernel (any dtype, any stride class): a workgroup owns a
+// tile of 64 rows of Y and a contiguous run of 64-column tiles of the
+// unfolding.  Per tile it stages X[rows, cols] through LDS with loads that are
+// contiguous in memory for the tensor's stride class (along c when R > 1, along
+// the rows when R == 1) and generates the 64 x ell slab of Omega once into LDS;
+// each wave then accumulates a quarter of the ell columns for all 64 rows.
+#include "rt_kernels.hpp"
+#include "rt_philox.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int SK_MT = 64;     // rows per tile
+constexpr int SK_KC = 64;     // unfolding columns per tile
+constexpr int SK_NACC = LMAX / 4;
+
+template <typename TX, typename TA>
+__global__ __launch_bounds__(256) void sketch_generic_kernel(
+    const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
+    uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
+    double* __restrict__ nrm2_partial) {
+    __shared__ TA xs[SK_KC][SK_MT + 1];
+    __shared__ TA om[SK_KC][LMAX + 4];
+    __shared__ double red[256];
+
+    const int tid = threadIdx.x;
+    const int row = tid % SK_MT;
+    const int kg = tid / SK_MT;            // wave index: columns kg, kg + 4, ...
+    const int64_t K = L * R;
+    const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
+    const int64_t row0 = (int64_t)blockIdx.y * SK_MT;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_split;
+    const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+    const int64_t q_first = col0 / 4;
+    const int64_t q_last = (col0 + ell - 1) / 4;
+    const int nq = (int)(q_last - q_first + 1);
+
+    TA acc[SK_NACC];
+#pragma unroll
+    for (int j = 0; j < SK_NACC; ++j) acc[j] = TA(0);
+    double nrm = 0.0;
+
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        const int64_t cbase = t * SK_KC;
+        __syncthreads();
+        // stage X tile: 64 x 64 elements, 16 per thread
+        for (int e = tid; e < SK_MT * SK_KC; e += 256) {
+            int rl, cl;
+            if (R == 1) { rl = e % SK_MT; cl = e / SK_MT; }
+            else        { cl = e % SK_KC; rl = e / SK_KC; }
+            const int64_t c = cbase + cl;
+            const int64_t i = row0 + rl;
+            TA v = TA(0);
+            if (c < K && i < J) {
+                const int64_t l = c / R;
+                const int64_t r = c - l * R;
+                v = (TA)X[(l * J + i) * R + r];
+                if (nrm2_partial) nrm += (double)v * (double)v;
+            }
+            xs[cl][rl] = v;
+        }
+        // generate the Omega slab for these 64 unfolding columns
+        for (int e = tid; e < SK_KC * nq; e += 256) {
+            const int cl = e % SK_KC;
+            const int qi = e / SK_KC;
+            const int64_t q = q_first + qi;
+            TA z[4];
+            OmegaGen<TA>::gen4(seed, mode, (uint64_t)(cbase + cl), (uint32_t)q, z);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                const int64_t k = 4 * q + tt - col0;
+                if (k >= 0 && k < ell) om[cl][k] = z[tt];
+            }
+        }
+        __syncthreads();
+        const int cmax = (int)((K - cbase) < SK_KC ? (K - cbase) : SK_KC);
+        for (int cl = 0; cl < cmax; ++cl) {
+            const TA x = xs[cl][row];
+#pragma unroll
+            for (int j = 0; j < SK_NACC; ++j) {
+                const int k = kg + 4 * j;
+                if (k < ell) acc[j] += x * om[cl][k];
+            }
+        }
+    }
+    const int64_t i = row0 + row;
+    if (i < J) {
+        TA* dst = partial + ((int64_t)blockIdx.x * J + i) * ell;
+#pragma unroll
+        for (int j = 0; j < SK_NACC; ++j) {
+            const int k = kg + 4 * j;
+            if (k < ell) dst[k] = acc[j];
+        }
+    }
+    if (nrm2_partial) {
+        red[tid] = nrm;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) nrm2_partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel_f32(const float* __restrict__ in, int64_t nparts,
+                                                                  int64_t n, double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int64_t p = 0; p < nparts; ++p) s += (double)in[p * n + e];
+    out[e] = s;
+}
+__global__ __launch_bounds__(256) void reduce_partials_kernel_f64(const double* __restrict__ in, int64_t nparts,
+                                                                  int64_t n, double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int64_t p = 0; p < nparts; ++p) s += in[p * n + e];
+    out[e] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_scalar_kernel(const double* __restrict__ in, int64_t n,
+                                                         double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) s += in[e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace
+
+SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell) {
+    (void)dt; (void)prec;
+    SketchPlan p{};
+    const int64_t K = s.L * s.R;
+    const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
+    p.nrowtile = (int)((s.J + SK_MT - 1) / SK_MT);
+    int64_t want = 2048 / p.nrowtile;
+    if (want < 1) want = 1;
+    if (want > ntiles) want = ntiles;
+    p.tiles_per_split = (ntiles + want - 1) / want;
+    p.nsplit = (int)((ntiles + p.tiles_per_split - 1) / p.tiles_per_split);
+    if (p.nsplit < 1) p.nsplit = 1;
+    p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
+    p.nwg = p.nsplit * p.nrowtile;
+    p.kind = 0;
+    return p;
+}
+
+hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,
+                         int64_t col0, uint64_t seed, uint32_t mode, void* partial,
+                         double* nrm2_partial, hipStream_t stream) {
+    (void)prec;
+    dim3 grid(p.nsplit, p.nrowtile);
+    if (dt == Dt::F64) {
+        hipLaunchKernelGGL((sketch_generic_kernel<double, double>), grid, dim3(256), 0, stream,
+                           (const double*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
+                           (double*)partial, nrm2_partial);
+    } else {
+        hipLaunchKernelGGL((sketch_generic_kernel<float, float>), grid, dim3(256), 0, stream,
+                           (const float*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
+                           (float*)partial, nrm2_partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
+                                  double* out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (in_is_f64)
+        hipLaunchKernelGGL(reduce_partials_kernel_f64, grid, dim3(256), 0, stream, (const double*)in, nparts, n, out);
+    else
+        hipLaunchKernelGGL(reduce_partials_kernel_f32, grid, dim3(256), 0, stream, (const float*)in, nparts, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(sum_scalar_kernel, dim3(1), dim3(256), 0, stream, in, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,791 @@
+// C ABI of librtucker.so (include/rtucker.h): argument validation, the
+// per-context workspace, and the host drivers that sequence the device kernels
+// of R-HOSVD (Alg. 2), R-STHOSVD (Alg. 3) and adaptive R-STHOSVD (Alg. 5).
+#include "rtucker.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt_kernels.hpp"
+
+using rt::Dt;
+using rt::Shape3;
+
+namespace {
+
+thread_local std::string g_err;
+
+rt_status fail(rt_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define RT_HIP(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(RT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+#define RT_TRY(expr)                    \
+    do {                                \
+        rt_status s_ = (expr);          \
+        if (s_ != RT_OK) return s_;     \
+    } while (0)
+
+size_t dsize(rt_dtype t) { return t == RT_F64 ? 8 : 4; }
+Dt dt_of(rt_dtype t) { return t == RT_F64 ? Dt::F64 : Dt::F32; }
+
+}  // namespace
+
+struct rt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    rt_alloc_fn alloc = nullptr;
+    rt_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    // workspace: chunks kept across calls, bump-allocated within a call
+    struct Chunk { char* p; size_t size; size_t used; };
+    std::vector<Chunk> chunks;
+    double* host = nullptr;       // pinned scratch for small read-backs
+    std::vector<void*> outputs;   // outputs handed to the caller (for release)
+    // optional per-launch timing log (HIP events on the context's stream)
+    struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; };
+    bool timing = false;
+    std::vector<Timed> tlog;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    hipEvent_t next_event() {
+        if (evused < evpool.size()) return evpool[evused++];
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        evpool.push_back(e);
+        ++evused;
+        return e;
+    }
+    int64_t cur_J = 0;            // rows of the basis Q of the mode being truncated
+    double* last_nrm2 = nullptr;  // optional: receives ||core||^2 of the truncation's core update
+
+    void* raw_alloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        if (alloc) return alloc(bytes, user);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void raw_free(void* p) {
+        if (!p) return;
+        if (free_fn) free_fn(p, user);
+        else (void)hipFree(p);
+    }
+    void reset_ws() { for (auto& c : chunks) c.used = 0; }
+    void* ws(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto& c : chunks) {
+            if (c.size - c.used >= bytes) {
+                void* p = c.p + c.used;
+                c.used += bytes;
+                return p;
+            }
+        }
+        size_t sz = std::max(bytes, size_t(64) << 20);
+        char* p = (char*)raw_alloc(sz);
+        if (!p) return nullptr;
+        chunks.push_back({p, sz, bytes});
+        return p;
+    }
+};
+
+namespace {
+
+// Records HIP events around one kernel launch when the context's timing log is on.
+struct TimeScope {
+    rt_ctx* c;
+    rt_ctx::Timed t{};
+    bool on;
+    TimeScope(rt_ctx* ctx, int kind, double bytes, double flops, int64_t rows, int64_t cols, int ell)
+        : c(ctx), on(ctx->timing) {
+        if (!on) return;
+        t = rt_ctx::Timed{kind, c->next_event(), c->next_event(), bytes, flops, rows, cols, ell};
+        if (!t.a || !t.b) { on = false; return; }
+        (void)hipEventRecord(t.a, c->stream);
+    }
+    ~TimeScope() {
+        if (!on) return;
+        (void)hipEventRecord(t.b, c->stream);
+        c->tlog.push_back(t);
+    }
+};
+
+struct Call {
+    rt_ctx* c;
+    explicit Call(rt_ctx* ctx) : c(ctx) { c->reset_ws(); }
+    template <typename T> T* ws(size_t n) { return (T*)c->ws(n * sizeof(T)); }
+};
+
+Shape3 shape3(const std::vector<int64_t>& dims, int n) {
+    Shape3 s{1, dims[n], 1};
+    for (int i = 0; i < n; ++i) s.L *= dims[i];
+    for (int i = n + 1; i < (int)dims.size(); ++i) s.R *= dims[i];
+    return s;
+}
+
+rt_status check_tensor(const rt_tensor* X) {
+    if (!X) return fail(RT_EINVAL, "X is NULL");
+    if (X->ndim < 2 || X->ndim > RT_MAXD) return fail(RT_EINVAL, "ndim must be in [2, RT_MAXD]");
+    if (X->dtype != RT_F32 && X->dtype != RT_F64) return fail(RT_EINVAL, "dtype must be RT_F32 or RT_F64");
+    if (!X->data) return fail(RT_EINVAL, "X->data is NULL");
+    for (int i = 0; i < X->ndim; ++i)
+        if (X->dims[i] < 1) return fail(RT_EINVAL, "every dim must be >= 1");
+    return RT_OK;
+}
+
+rt_status check_prec(const rt_tensor* X, rt_precision prec) {
+    if (prec == RT_PREC_F64 && X->dtype != RT_F64) return fail(RT_EINVAL, "RT_PREC_F64 needs an RT_F64 tensor");
+    if (prec != RT_PREC_F64 && X->dtype != RT_F32) return fail(RT_EINVAL, "RT_PREC_F32/BF16 need an RT_F32 tensor");
+    if (prec != RT_PREC_F64 && prec != RT_PREC_F32 && prec != RT_PREC_BF16_SKETCH)
+        return fail(RT_EINVAL, "unknown precision");
+    return RT_OK;
+}
+
+rt_status make_order(const rt_tensor* X, const int32_t* order, std::vector<int>& out) {
+    const int d = X->ndim;
+    out.resize(d);
+    if (order) {
+        std::vector<int> seen(d, 0);
+        for (int i = 0; i < d; ++i) {
+            if (order[i] < 0 || order[i] >= d || seen[order[i]]) return fail(RT_EINVAL, "order is not a permutation");
+            seen[order[i]] = 1;
+            out[i] = order[i];
+        }
+    } else {
+        for (int i = 0; i < d; ++i) out[i] = i;
+        std::stable_sort(out.begin(), out.end(), [&](int a, int b) { return X->dims[a] > X->dims[b]; });
+    }
+    return RT_OK;
+}
+
+rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
+    if (!ranks) return fail(RT_EINVAL, "ranks is NULL");
+    if (p < 0) return fail(RT_EINVAL, "oversampling p must be >= 0");
+    int64_t total = 1;
+    for (int i = 0; i < X->ndim; ++i) total *= X->dims[i];
+    for (int j = 0; j < X->ndim; ++j) {
+        if (ranks[j] == RT_KEEP) continue;
+        if (ranks[j] < 1) return fail(RT_EINVAL, "ranks must be >= 1 or RT_KEEP");
+        const int64_t ell = (int64_t)ranks[j] + p;
+        if (ell > std::min<int64_t>(X->dims[j], total / X->dims[j]))
+            return fail(RT_EINVAL, "r_j + p exceeds min(I_j, prod_{i!=j} I_i) for mode " + std::to_string(j));
+        if (ell > RT_LMAX) return fail(RT_EINVAL, "r_j + p exceeds RT_LMAX for mode " + std::to_string(j));
+    }
+    return RT_OK;
+}
+
+// ---- building blocks ----------------------------------------------------------------
+
+// Y (J x ell, fp64) = G_(n) Omega[:, col0 : col0 + ell]; optional ||G||^2 into nrm2 (device).
+rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, int64_t col0, uint64_t seed,
+                    int mode, double* Y, double* nrm2) {
+    rt::SketchPlan plan = rt::plan_sketch(dt, prec, s, ell);
+    const bool f64acc = plan.kind == 0 && dt == Dt::F64;
+    void* partial = k.c->ws(plan.partial_elems * (f64acc ? 8 : 4));
+    double* np = nrm2 ? k.ws<double>(plan.nwg) : nullptr;
+    if (!partial || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
+    {
+        const double n = (double)s.L * s.J * s.R;
+        TimeScope ts(k.c, 0, n * (dt == Dt::F64 ? 8 : 4), 2.0 * ell * n, s.J, s.L * s.R, ell);
+        RT_HIP(rt::launch_sketch(plan, dt, prec, G, s, ell, col0, seed, (uint32_t)mode, partial, np, k.c->stream));
+    }
+    RT_HIP(rt::launch_reduce_partials(partial, f64acc, plan.nsplit, s.J * ell, Y, k.c->stream));
+    if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
+    return RT_OK;
+}
+
+rt_status do_norm2(Call& k, const void* X, Dt dt, int64_t n, double* out) {
+    int nwg = rt::plan_norm(n);
+    double* part = k.ws<double>(nwg);
+    if (!part) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(rt::launch_norm2(X, dt, n, part, nwg, k.c->stream));
+    RT_HIP(rt::launch_sum_scalar(part, nwg, out, k.c->stream));
+    return RT_OK;
+}
+
+// B = G x_n Q^T with the fp64 Gram of B reduced into W (ell x ell) when W != NULL.
+rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q, int64_t ldq,
+                     int ell, void* B, int64_t ldk, int64_t koff, double* W, double* nrm2) {
+    rt::ProjectPlan plan = rt::plan_project(dx, dq, s, ell);
+    double* gp = W ? k.ws<double>((size_t)plan.nwg * ell * ell) : nullptr;
+    double* np = nrm2 ? k.ws<double>(plan.nwg) : nullptr;
+    if ((W && !gp) || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
+    {
+        const double n = (double)s.L * s.J * s.R, es = dx == Dt::F64 ? 8 : 4;
+        TimeScope ts(k.c, 1, n * es + (double)s.L * ell * s.R * es, 2.0 * ell * n, s.J, s.L * s.R, ell);
+        RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, B, ldk, koff, gp, np, k.c->stream));
+    }
+    if (W) RT_HIP(rt::launch_reduce_partials(gp, true, plan.nwg, (int64_t)ell * ell, W, k.c->stream));
+    if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
+    return RT_OK;
+}
+
+double orth_accept_ratio() { return 1e-15; }
+
+// Truncation of a QB factorisation (Alg. 1 steps 4-6).  B is (L, ldb-strided mode
+// of kb rows, R) with its fp64 Gram W; Q (J x kb, fp64, leading dimension ldq).
+// Fixed rank: r_fixed >= 0.  Adaptive: r_fixed < 0 and the rank is the smallest
+// k with max(E, 0) + tail <= tau2 (E on the device).
+// Writes A_out (J x k, dtype dt), the new core (L, k, R) and returns k.
+// refine: eigenvectors of a Gram are accurate only to about u ||B||^2 / gap; for the
+// fp64 path the basis is refined by rotating B into the first eigenbasis
+// (C = U1^T B) and taking the eigenvectors of C C^T, whose entries carry relative
+// accuracy, before the final choice.
+rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, const double* W, const double* Q,
+                      int64_t ldq, int r_fixed, const double* Edev, double tau2, bool refine, void* A_out,
+                      void** core_out, int* k_host) {
+    hipStream_t st = k.c->stream;
+    const int kb = (int)sb.J;
+    double* lam = k.ws<double>(kb);
+    int* kdev = k.ws<int>(1);
+    double* U = k.ws<double>((size_t)kb * kb);
+    float* Uf = k.ws<float>((size_t)kb * kb);
+    if (!lam || !kdev || !U || !Uf) return fail(RT_ENOMEM, "workspace allocation failed");
+    const void* Bcur = B;
+    int64_t ldcur = ldb;
+    const double* Wcur = W;
+    const double* Qcur = Q;
+    int64_t ldqcur = ldq;
+    const int64_t Jq = k.c->cur_J;
+    if (refine) {
+        double* Q1 = k.ws<double>((size_t)Jq * kb);
+        void* C = k.c->ws((size_t)sb.L * kb * sb.R * (dt == Dt::F64 ? 8 : 4));
+        double* W2 = k.ws<double>((size_t)kb * kb);
+        if (!Q1 || !C || !W2) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, kb, nullptr, 0.0, U, Uf, Q1, Dt::F64, lam, kdev, st));
+        RT_TRY(do_project(k, dt, Dt::F64, Bcur, sb, ldcur, U, kb, kb, C, kb, 0, W2, nullptr));
+        Bcur = C;
+        ldcur = kb;
+        Wcur = W2;
+        Qcur = Q1;
+        ldqcur = kb;
+        U = k.ws<double>((size_t)kb * kb);
+        if (!U) return fail(RT_ENOMEM, "workspace allocation failed");
+    }
+    {
+        TimeScope ts(k.c, 3, 0.0, 0.0, Jq, kb, kb);
+        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, r_fixed, Edev, tau2, U, Uf, A_out, dt, lam, kdev, st));
+    }
+    int kk = r_fixed;
+    if (r_fixed < 0) {
+        RT_HIP(hipMemcpyAsync(k.c->host + 8, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        std::memcpy(&kk, k.c->host + 8, sizeof(int));
+    }
+    if (k_host) *k_host = kk;
+    if (core_out && kk > 0) {
+        const size_t es = dt == Dt::F64 ? 8 : 4;
+        if (!*core_out) *core_out = k.c->ws((size_t)sb.L * kk * sb.R * es);
+        if (!*core_out) return fail(RT_ENOMEM, "workspace allocation failed");
+        const bool f64q = dt == Dt::F64 || refine || r_fixed < 0;
+        RT_TRY(do_project(k, dt, f64q ? Dt::F64 : Dt::F32, Bcur, sb, ldcur, f64q ? (const void*)U : (const void*)Uf,
+                          kk, kk, *core_out, kk, 0, nullptr, k.c->last_nrm2));
+    }
+    return RT_OK;
+}
+
+// One fixed-rank RandSVD step (Alg. 1) on the mode-n unfolding of G:
+// A_out (J x r, dtype dt) and, if core_out != NULL, the truncated core (L, r, R).
+rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode, int ell, int r, uint64_t seed,
+                     void* A_out, void* core_out, double* nrm2_dev, uint32_t* status_dev) {
+    hipStream_t st = k.c->stream;
+    const int64_t J = s.J;
+    double* Y = k.ws<double>((size_t)J * ell);
+    double* scratch = k.ws<double>((size_t)2 * J * ell);
+    float* Qf = dt == Dt::F32 ? k.ws<float>((size_t)J * ell) : nullptr;
+    if (!Y || !scratch || (dt == Dt::F32 && !Qf)) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_TRY(do_sketch(k, dt, prec, G, s, ell, 0, seed, mode, Y, nrm2_dev));                      // Alg. 1 step 1
+    {
+        TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
+        RT_HIP(rt::launch_orth(Y, J, ell, Qf, orth_accept_ratio(), status_dev, scratch, st));    // step 2
+    }
+    void* B = k.c->ws((size_t)s.L * ell * s.R * (dt == Dt::F64 ? 8 : 4));
+    double* W = k.ws<double>((size_t)ell * ell);
+    if (!B || !W) return fail(RT_ENOMEM, "workspace allocation failed");
+    const void* Qp = dt == Dt::F64 ? (const void*)Y : (const void*)Qf;
+    RT_TRY(do_project(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell, 0, W, nullptr));               // step 3
+    k.c->cur_J = J;
+    k.c->last_nrm2 = nullptr;
+    void* core = core_out;
+    return do_truncate(k, dt, B, Shape3{s.L, ell, s.R}, ell, W, Y, ell, r, nullptr, 0.0, dt == Dt::F64, A_out,
+                       core_out ? &core : nullptr, nullptr);                                      // steps 4-6
+}
+
+void init_out(rt_tucker* out, const rt_tensor* X) {
+    std::memset(out, 0, sizeof(*out));
+    out->ndim = X->ndim;
+    out->dtype = X->dtype;
+    for (int i = 0; i < X->ndim; ++i) {
+        out->dims[i] = X->dims[i];
+        out->ranks[i] = (int32_t)X->dims[i];
+    }
+}
+
+void release_partial(rt_ctx* ctx, rt_tucker* out) {
+    if (!out) return;
+    ctx->raw_free(out->core);
+    out->core = nullptr;
+    for (int i = 0; i < RT_MAXD; ++i) {
+        ctx->raw_free(out->factors[i]);
+        out->factors[i] = nullptr;
+    }
+}
+
+// Scalars read back at the end of a decomposition (pinned host).
+struct Scalars { double nx2, ng2; uint32_t status[RT_MAXD]; };
+
+rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vector<int64_t>& cdims, Dt dt,
+                 double* nx2_dev, uint32_t* status_dev) {
+    int64_t n = 1;
+    for (auto v : cdims) n *= v;
+    const size_t bytes = (size_t)n * (dt == Dt::F64 ? 8 : 4);
+    out->core = k.c->raw_alloc(bytes);
+    if (!out->core) return fail(RT_ENOMEM, "core allocation failed");
+    if (n > 0) RT_HIP(hipMemcpyAsync(out->core, core_dev, bytes, hipMemcpyDeviceToDevice, k.c->stream));
+    double* ng2 = k.ws<double>(1);
+    if (!ng2) return fail(RT_ENOMEM, "workspace allocation failed");
+    if (n > 0) RT_TRY(do_norm2(k, out->core, dt, n, ng2));
+    else RT_HIP(hipMemsetAsync(ng2, 0, sizeof(double), k.c->stream));
+    Scalars* h = (Scalars*)k.c->host;
+    RT_HIP(hipMemcpyAsync(&h->nx2, nx2_dev, sizeof(double), hipMemcpyDeviceToHost, k.c->stream));
+    RT_HIP(hipMemcpyAsync(&h->ng2, ng2, sizeof(double), hipMemcpyDeviceToHost, k.c->stream));
+    RT_HIP(hipMemcpyAsync(h->status, status_dev, sizeof(uint32_t) * RT_MAXD, hipMemcpyDeviceToHost, k.c->stream));
+    RT_HIP(hipStreamSynchronize(k.c->stream));
+    out->norm_x = std::sqrt(std::max(h->nx2, 0.0));
+    out->core_norm = std::sqrt(std::max(h->ng2, 0.0));
+    out->rel_err_est = out->norm_x > 0 ? std::sqrt(std::max(0.0, h->nx2 - h->ng2)) / out->norm_x : 0.0;
+    uint32_t fl = 0;
+    bool nonfinite = false;
+    for (int i = 0; i < RT_MAXD; ++i) {
+        fl |= h->status[i] & 3u;
+        if (h->status[i] & 4u) nonfinite = true;
+    }
+    out->flags = fl;
+    if (nonfinite || !std::isfinite(h->nx2)) return fail(RT_ENONFINITE, "input holds NaN or Inf");
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_version(void) { return "rtucker 0.1 (gfx950)"; }
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+rt_status rt_create(rt_ctx** ctx, int device, void* stream, rt_alloc_fn alloc, rt_free_fn free_fn, void* user) {
+    if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(RT_EINVAL, "alloc and free must both be set or NULL");
+    RT_HIP(hipSetDevice(device));
+    RT_HIP(rt::dense_init());
+    rt_ctx* c = new rt_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    if (hipHostMalloc((void**)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(RT_ENOMEM, "pinned host allocation failed");
+    }
+    *ctx = c;
+    return RT_OK;
+}
+
+rt_status rt_set_stream(rt_ctx* ctx, void* stream) {
+    if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return RT_OK;
+}
+
+rt_status rt_destroy(rt_ctx* ctx) {
+    if (!ctx) return RT_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& c : ctx->chunks) ctx->raw_free(c.p);
+    ctx->chunks.clear();
+    for (auto e : ctx->evpool) (void)hipEventDestroy(e);
+    ctx->evpool.clear();
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx;
+    return RT_OK;
+}
+
+rt_status rt_timing(rt_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->timing = enable != 0;
+    ctx->tlog.clear();
+    ctx->evused = 0;
+    return RT_OK;
+}
+
+rt_status rt_timing_count(rt_ctx* ctx, int64_t* n) {
+    if (!ctx || !n) return fail(RT_EINVAL, "NULL argument");
+    *n = (int64_t)ctx->tlog.size();
+    return RT_OK;
+}
+
+rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, double* bytes, double* flops,
+                          int64_t* rows, int64_t* cols, int32_t* ell) {
+    if (!ctx || !kind || !ms || !bytes || !flops || !rows || !cols || !ell) return fail(RT_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int64_t)ctx->tlog.size()) return fail(RT_EINVAL, "entry index out of range");
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    const auto& t = ctx->tlog[(size_t)i];
+    float f = 0.0f;
+    RT_HIP(hipEventElapsedTime(&f, t.a, t.b));
+    *kind = t.kind;
+    *ms = f;
+    *bytes = t.bytes;
+    *flops = t.flops;
+    *rows = t.rows;
+    *cols = t.cols;
+    *ell = t.ell;
+    return RT_OK;
+}
+
+rt_status rt_sync(rt_ctx* ctx) {
+    if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t) {
+    if (!ctx || !t) return fail(RT_EINVAL, "NULL argument");
+    (void)hipStreamSynchronize(ctx->stream);
+    release_partial(ctx, t);
+    return RT_OK;
+}
+
+rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out) {
+    if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, opts->prec));
+    RT_TRY(check_ranks(X, ranks, opts->oversample));
+    std::vector<int> order;
+    RT_TRY(make_order(X, opts->order, order));
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    const Dt dt = dt_of(X->dtype);
+    const int prec = (int)opts->prec;
+    const size_t es = dsize(X->dtype);
+    init_out(out, X);
+    std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
+    double* nx2 = k.ws<double>(1);
+    uint32_t* status = k.ws<uint32_t>(RT_MAXD);
+    if (!nx2 || !status) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, ctx->stream));
+    const void* cur = X->data;
+    bool have_norm = false;
+    for (int n : order) {
+        if (ranks[n] == RT_KEEP) continue;
+        const int r = ranks[n];
+        const int ell = r + opts->oversample;
+        Shape3 s = shape3(dims, n);
+        out->factors[n] = ctx->raw_alloc((size_t)s.J * r * es);
+        void* core = k.c->ws((size_t)s.L * r * s.R * es);
+        if (!out->factors[n] || !core) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "allocation failed");
+        }
+        rt_status rs = fixed_mode(k, dt, prec, cur, s, n, ell, r, opts->seed, out->factors[n], core,
+                                  have_norm ? nullptr : nx2, status + n);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        have_norm = true;
+        out->ranks[n] = r;
+        dims[n] = r;
+        cur = core;
+    }
+    if (!have_norm) {
+        int64_t n = 1;
+        for (auto v : dims) n *= v;
+        rt_status rs = do_norm2(k, X->data, dt, n, nx2);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+    }
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
+    return rs;
+}
+
+rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out) {
+    if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, opts->prec));
+    RT_TRY(check_ranks(X, ranks, opts->oversample));
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    const Dt dt = dt_of(X->dtype);
+    const int prec = (int)opts->prec;
+    const size_t es = dsize(X->dtype);
+    const int d = X->ndim;
+    init_out(out, X);
+    std::vector<int64_t> xdims(X->dims, X->dims + d);
+    double* nx2 = k.ws<double>(1);
+    uint32_t* status = k.ws<uint32_t>(RT_MAXD);
+    if (!nx2 || !status) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, ctx->stream));
+    int first = -1;
+    void* core0 = nullptr;
+    for (int j = 0; j < d; ++j) {                          // Alg. 2: every mode from X itself
+        if (ranks[j] == RT_KEEP) continue;
+        const int r = ranks[j];
+        const int ell = r + opts->oversample;
+        Shape3 s = shape3(xdims, j);
+        out->factors[j] = ctx->raw_alloc((size_t)s.J * r * es);
+        void* core = nullptr;
+        if (first < 0) core = k.c->ws((size_t)s.L * r * s.R * es);
+        if (!out->factors[j] || (first < 0 && !core)) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "allocation failed");
+        }
+        rt_status rs = fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, out->factors[j], core,
+                                  first < 0 ? nx2 : nullptr, status + j);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        if (first < 0) { first = j; core0 = core; }
+        out->ranks[j] = r;
+    }
+    std::vector<int64_t> dims = xdims;
+    const void* cur = X->data;
+    if (first >= 0) {
+        // G = X x_1 A_1^T ... x_d A_d^T, starting from the truncated B of the first mode
+        dims[first] = ranks[first];
+        cur = core0;
+        for (int j = 0; j < d; ++j) {
+            if (j == first || ranks[j] == RT_KEEP) continue;
+            Shape3 s = shape3(dims, j);
+            const int r = ranks[j];
+            void* nc = k.c->ws((size_t)s.L * r * s.R * es);
+            if (!nc) { release_partial(ctx, out); return fail(RT_ENOMEM, "allocation failed"); }
+            rt_status rs = do_project(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r, 0, nullptr, nullptr);
+            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+            dims[j] = r;
+            cur = nc;
+        }
+    } else {
+        int64_t n = 1;
+        for (auto v : dims) n *= v;
+        rt_status rs = do_norm2(k, X->data, dt, n, nx2);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+    }
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
+    return rs;
+}
+
+rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode, int32_t block,
+                               const int32_t* max_rank, const rt_opts* opts, rt_tucker* out) {
+    if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, opts->prec));
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(RT_EINVAL, "eps must be finite and >= 0");
+    if (block < 1 || block > RT_LMAX) return fail(RT_EINVAL, "block must be in [1, RT_LMAX]");
+    const int d = X->ndim;
+    std::vector<double> epsn(d, eps / std::sqrt((double)d));
+    if (eps_per_mode) {
+        double s2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+            if (!(eps_per_mode[j] >= 0.0)) return fail(RT_EINVAL, "eps_per_mode entries must be >= 0");
+            epsn[j] = eps_per_mode[j];
+            s2 += epsn[j] * epsn[j];
+        }
+        if (std::fabs(s2 - eps * eps) > 1e-12 * std::max(eps * eps, 1e-300))
+            return fail(RT_EINVAL, "sum of eps_per_mode^2 must equal eps^2");
+    }
+    std::vector<int> order;
+    RT_TRY(make_order(X, opts->order, order));
+    if (max_rank)
+        for (int j = 0; j < d; ++j)
+            if (max_rank[j] < 1) return fail(RT_EINVAL, "max_rank entries must be >= 1");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    hipStream_t st = ctx->stream;
+    const Dt dt = dt_of(X->dtype);
+    const int prec = (int)opts->prec;
+    const size_t es = dsize(X->dtype);
+    const double drop = X->dtype == RT_F64 ? 1e-10 : 1e-5;
+    init_out(out, X);
+    std::vector<int64_t> dims(X->dims, X->dims + d);
+    double* nx2 = k.ws<double>(1);
+    double* tmp = k.ws<double>(4);
+    uint32_t* status = k.ws<uint32_t>(RT_MAXD);
+    int* kdev = k.ws<int>(4);
+    if (!nx2 || !tmp || !status || !kdev) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, st));
+    int64_t ntot = 1;
+    for (auto v : dims) ntot *= v;
+    RT_TRY(do_norm2(k, X->data, dt, ntot, nx2));
+    double* h = ctx->host;
+    RT_HIP(hipMemcpyAsync(h, nx2, sizeof(double), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    const double normx2 = h[0];
+    if (!std::isfinite(normx2)) return fail(RT_ENONFINITE, "input holds NaN or Inf");
+    const double normx = std::sqrt(normx2);
+    const void* cur = X->data;
+    double cur_norm2 = normx2;
+    bool capped = false;
+    for (int n : order) {
+        if (epsn[n] == 0.0) continue;
+        const double tau2 = (epsn[n] * normx) * (epsn[n] * normx);
+        Shape3 s = shape3(dims, n);
+        const int64_t J = s.J, K = s.L * s.R;
+        int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX);
+        if (max_rank) cap = std::min(cap, (int)max_rank[n]);
+        double* Qall = k.ws<double>((size_t)J * cap);
+        void* Bbuf = k.c->ws((size_t)s.L * cap * s.R * es);
+        double* Y = k.ws<double>((size_t)J * block);
+        double* scratch = k.ws<double>((size_t)2 * J * block);
+        double* W = k.ws<double>((size_t)cap * cap);
+        double* Edev = k.ws<double>(1);
+        if (!Qall || !Bbuf || !Y || !scratch || !W || !Edev) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "workspace allocation failed");
+        }
+        double E = cur_norm2;
+        int kcols = 0, blk = 0;
+        bool stop_cap = false;
+        while (E > tau2) {                                  // AdaptRangeFinder block loop
+            if (kcols >= cap) { stop_cap = true; break; }
+            const int bi = std::min(block, cap - kcols);
+            rt_status rs = do_sketch(k, dt, prec, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y, nullptr);
+            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+            RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, drop, kdev, scratch, st));
+            RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
+            RT_HIP(hipStreamSynchronize(st));
+            int kn = 0;
+            std::memcpy(&kn, h + 1, sizeof(int));
+            ++blk;
+            if (kn <= 0) break;                              // range exhausted
+            rs = do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
+            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+            RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
+            RT_HIP(hipStreamSynchronize(st));
+            E -= h[2];                                       // E <- E - ||B_i||^2
+            kcols += kn;
+        }
+        if (stop_cap && E > tau2) capped = true;
+        // SVD post-truncation: smallest k with max(E,0) + tail <= tau2
+        h[3] = E;
+        RT_HIP(hipMemcpyAsync(Edev, h + 3, sizeof(double), hipMemcpyHostToDevice, st));
+        int kfinal = 0;
+        void* A = k.c->ws((size_t)J * std::max(kcols, 1) * es);
+        void* core = nullptr;
+        if (!A) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
+        if (kcols > 0) {
+            int nwg = rt::plan_gram3(s.L, s.R);
+            double* gp = k.ws<double>((size_t)nwg * kcols * kcols);
+            if (!gp) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
+            RT_HIP(rt::launch_gram3(Bbuf, dt, s.L, cap, s.R, kcols, gp, nwg, st));
+            RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)kcols * kcols, W, st));
+            k.c->cur_J = J;
+            k.c->last_nrm2 = tmp;
+            rt_status rs = do_truncate(k, dt, Bbuf, Shape3{s.L, kcols, s.R}, cap, W, Qall, cap, -1, Edev, tau2,
+                                       dt == Dt::F64, A, &core, &kfinal);
+            k.c->last_nrm2 = nullptr;
+            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        }
+        out->factors[n] = ctx->raw_alloc((size_t)J * std::max(kfinal, 1) * es);
+        if (!core) core = k.c->ws((size_t)s.L * std::max(kfinal, 1) * s.R * es);
+        if (!out->factors[n] || !core) { release_partial(ctx, out); return fail(RT_ENOMEM, "allocation failed"); }
+        if (kfinal > 0) {
+            // A was written with leading dimension kfinal by the truncation kernel
+            RT_HIP(hipMemcpyAsync(out->factors[n], A, (size_t)J * kfinal * es, hipMemcpyDeviceToDevice, st));
+            RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
+            RT_HIP(hipStreamSynchronize(st));
+            cur_norm2 = h[2];
+        } else {
+            cur_norm2 = 0.0;
+        }
+        out->ranks[n] = kfinal;
+        dims[n] = kfinal;
+        cur = core;
+    }
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    if (rs != RT_OK && rs != RT_ENONFINITE) { release_partial(ctx, out); return rs; }
+    if (rs == RT_OK && capped) return fail(RT_ECAP, "a mode reached its rank cap before the tolerance");
+    return rs;
+}
+
+// ---- step entry points -------------------------------------------------------------------
+
+rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
+                    rt_precision prec, double* Y, double* nrm2) {
+    if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, prec));
+    if (mode < 0 || mode >= X->ndim) return fail(RT_EINVAL, "mode out of range");
+    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
+    if (col0 < 0) return fail(RT_EINVAL, "col0 must be >= 0");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
+    RT_TRY(do_sketch(k, dt_of(X->dtype), (int)prec, X->data, shape3(dims, mode), ell, col0, seed, mode, Y, nrm2));
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status rt_orth(rt_ctx* ctx, double* Y, int64_t rows, int32_t ell, uint32_t* flags) {
+    if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
+    if (ell < 1 || ell > RT_LMAX || rows < ell) return fail(RT_EINVAL, "need 1 <= ell <= min(rows, RT_LMAX)");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    double* scratch = k.ws<double>((size_t)2 * rows * ell);
+    uint32_t* st = k.ws<uint32_t>(1);
+    if (!scratch || !st) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(rt::launch_orth(Y, rows, ell, nullptr, orth_accept_ratio(), st, scratch, ctx->stream));
+    uint32_t* h = (uint32_t*)ctx->host;
+    RT_HIP(hipMemcpyAsync(h, st, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    if (flags) *flags = h[0] & 3u;
+    if (h[0] & 4u) return fail(RT_ENONFINITE, "Y holds NaN or Inf");
+    return RT_OK;
+}
+
+rt_status rt_project(rt_ctx* ctx, const rt_tensor* X, int32_t mode, const void* Q, rt_dtype qtype, int32_t ell,
+                     void* B, double* gram) {
+    if (!ctx || !Q || !B) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    if (mode < 0 || mode >= X->ndim) return fail(RT_EINVAL, "mode out of range");
+    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
+    if (X->dtype == RT_F64 && qtype != RT_F64) return fail(RT_EINVAL, "an RT_F64 tensor needs an RT_F64 Q");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
+    Shape3 s = shape3(dims, mode);
+    RT_TRY(do_project(k, dt_of(X->dtype), dt_of(qtype), X->data, s, s.J, Q, ell, ell, B, ell, 0, gram, nullptr));
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status rt_omega(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t nrows, int64_t col0, int32_t ncols,
+                   rt_dtype dtype, void* out) {
+    if (!ctx || !out) return fail(RT_EINVAL, "NULL argument");
+    if (c0 < 0 || nrows < 0 || col0 < 0 || ncols < 0 || mode < 0) return fail(RT_EINVAL, "negative argument");
+    RT_HIP(hipSetDevice(ctx->device));
+    RT_HIP(rt::launch_omega(seed, (uint32_t)mode, c0, nrows, col0, ncols, out, dt_of(dtype), ctx->stream));
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status rt_philox_words(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t n, uint32_t q, uint32_t* out) {
+    if (!ctx || !out) return fail(RT_EINVAL, "NULL argument");
+    if (c0 < 0 || n < 0 || mode < 0) return fail(RT_EINVAL, "negative argument");
+    RT_HIP(hipSetDevice(ctx->device));
+    RT_HIP(rt::launch_philox_words(seed, (uint32_t)mode, c0, n, q, out, ctx->stream));
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+}  // extern "C"

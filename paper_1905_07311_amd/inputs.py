@@ -47,7 +47,7 @@ def tucker_product(core, factors):
     X = np.asarray(core, dtype=np.float64)
     for n, U in enumerate(factors):
         X = np.moveaxis(np.tensordot(U, X, axes=(1, n)), 0, n)
-    return X
+    return np.ascontiguousarray(X)
 
 
 def lowrank_tensor(rng, dims, ranks, noise=0.0, core_scale=None):
@@ -60,7 +60,7 @@ def lowrank_tensor(rng, dims, ranks, noise=0.0, core_scale=None):
     X = tucker_product(core, factors)
     if noise:
         X = X + noise * rng.standard_normal(X.shape)
-    return X
+    return np.ascontiguousarray(X)
 
 
 def graded_scale(ranks, base):

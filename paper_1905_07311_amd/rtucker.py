@@ -1,0 +1,351 @@
+"""Thin ctypes binding of librtucker.so (include/rtucker.h).
+
+Argument marshalling only: torch supplies device memory (through an allocator
+callback, so PyTorch owns every buffer) and the current HIP stream; every step
+of the computation runs in the library's HIP kernels.  Importing this module
+does not load the library; the first call does, and raises if it is missing
+(there is no CPU fallback).
+"""
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librtucker.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_ENONFINITE, RT_ECAP, RT_EHIP = range(6)
+RT_F32, RT_F64 = 0, 1
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+RT_MAXD = 8
+RT_KEEP = -1
+RT_LMAX = 64
+RT_FLAG_PADDED = 1
+RT_FLAG_FALLBACK = 2
+
+EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
+            "rt_rsthosvd_adaptive", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
+            "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry"]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rtucker status {status}: {msg}")
+        self.status = status
+
+
+class rt_tensor(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD), ("dtype", ctypes.c_int),
+                ("data", ctypes.c_void_p)]
+
+
+class rt_opts(ctypes.Structure):
+    _fields_ = [("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64), ("order", ctypes.POINTER(ctypes.c_int32)),
+                ("prec", ctypes.c_int)]
+
+
+class rt_tucker(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD), ("ranks", ctypes.c_int32 * RT_MAXD),
+                ("dtype", ctypes.c_int), ("core", ctypes.c_void_p), ("factors", ctypes.c_void_p * RT_MAXD),
+                ("norm_x", ctypes.c_double), ("core_norm", ctypes.c_double), ("rel_err_est", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def load(path=None):
+    """Load librtucker.so (once).  Raises if the library is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1905_07311_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.rt_version.restype = ctypes.c_char_p
+    lib.rt_last_error.restype = ctypes.c_char_p
+    lib.rt_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P, ALLOC_FN, FREE_FN, P]
+    lib.rt_set_stream.argtypes = [P, P]
+    lib.rt_destroy.argtypes = [P]
+    for fn in ("rt_rhosvd", "rt_rsthosvd"):
+        getattr(lib, fn).argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(rt_opts), ctypes.POINTER(rt_tucker)]
+    lib.rt_rsthosvd_adaptive.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_opts),
+                                         ctypes.POINTER(rt_tucker)]
+    lib.rt_tucker_release.argtypes = [P, ctypes.POINTER(rt_tucker)]
+    lib.rt_sketch.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                              ctypes.c_uint64, ctypes.c_int, P, P]
+    lib.rt_orth.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]
+    lib.rt_project.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, P, ctypes.c_int, ctypes.c_int32, P, P]
+    lib.rt_omega.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_int32, ctypes.c_int, P]
+    lib.rt_philox_words.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_uint32, P]
+    lib.rt_sync.argtypes = [P]
+    lib.rt_timing.argtypes = [P, ctypes.c_int32]
+    lib.rt_timing_count.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.rt_timing_entry.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int32)]
+    for fn in EXPORTED:
+        if fn not in ("rt_version", "rt_last_error"):
+            getattr(lib, fn).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != RT_OK and status not in allow:
+        raise RtError(status, _lib.rt_last_error().decode())
+    return status
+
+
+@dataclass
+class Tucker:
+    core: object
+    factors: List[Optional[object]]
+    ranks: List[int]
+    norm_x: float
+    core_norm: float
+    rel_err_est: float
+    flags: int
+    status: int = RT_OK
+
+    def reconstruct(self):
+        """X_hat = G x_1 A_1 ... x_d A_d with torch (validation helper, not the hot path)."""
+        import torch
+        X = self.core
+        for n, A in enumerate(self.factors):
+            if A is not None:
+                X = torch.movedim(torch.tensordot(A, X, dims=([1], [n])), 0, n)
+        return X
+
+
+class Context:
+    """An rt_ctx bound to a torch device and its current stream."""
+
+    def __init__(self, device=None):
+        import torch
+        self.torch = torch
+        lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._bufs = {}
+
+        def _alloc(nbytes, user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self._bufs[p] = t
+            return p
+
+        def _free(ptr, user):
+            self._bufs.pop(ptr, None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.ctx = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib.rt_create(ctypes.byref(self.ctx), self.device.index, ctypes.c_void_p(stream), self._alloc_cb,
+                             self._free_cb, None))
+
+    def close(self):
+        if self.ctx:
+            _lib.rt_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+            self._bufs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------------
+    def _sync_stream(self):
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        _lib.rt_set_stream(self.ctx, ctypes.c_void_p(stream))
+
+    def _tensor(self, X):
+        torch = self.torch
+        if X.device != self.device:
+            raise ValueError("tensor is on another device")
+        if X.dtype not in (torch.float32, torch.float64):
+            raise ValueError("tensor must be float32 or float64")
+        if not X.is_contiguous():
+            raise ValueError("tensor must be contiguous (row-major)")
+        t = rt_tensor()
+        t.ndim = X.dim()
+        for i, s in enumerate(X.shape):
+            t.dims[i] = int(s)
+        t.dtype = RT_F64 if X.dtype == torch.float64 else RT_F32
+        t.data = X.data_ptr()
+        return t
+
+    def _take(self, ptr, shape, dtype):
+        torch = self.torch
+        if not ptr:
+            return None
+        buf = self._bufs.pop(ptr)
+        n = math.prod(shape)
+        return buf.view(dtype)[:n].view(*shape) if n > 0 else torch.empty(shape, dtype=dtype, device=self.device)
+
+    def _result(self, out, X, status):
+        torch = self.torch
+        d = X.dim()
+        ranks = [int(out.ranks[i]) for i in range(d)]
+        core = self._take(out.core, ranks, X.dtype)
+        factors = []
+        for j in range(d):
+            p = out.factors[j]
+            factors.append(self._take(p, (int(X.shape[j]), ranks[j]), X.dtype) if p else None)
+        return Tucker(core=core, factors=factors, ranks=ranks, norm_x=out.norm_x, core_norm=out.core_norm,
+                      rel_err_est=out.rel_err_est, flags=int(out.flags), status=status)
+
+    @staticmethod
+    def _prec(X, prec):
+        import torch
+        if prec is None:
+            return PREC["f64"] if X.dtype == torch.float64 else PREC["f32"]
+        return PREC[prec] if isinstance(prec, str) else int(prec)
+
+    def _opts(self, X, p, seed, order, prec):
+        o = rt_opts()
+        o.oversample = int(p)
+        o.seed = int(seed) & ((1 << 64) - 1)
+        if order is not None:
+            arr = (ctypes.c_int32 * X.dim())(*[int(v) for v in order])
+            o.order = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+            self._keep_order = arr
+        o.prec = self._prec(X, prec)
+        return o
+
+    # -- decompositions ----------------------------------------------------------
+    def rsthosvd(self, X, ranks, p, seed, order=None, prec=None):
+        return self._fixed("rt_rsthosvd", X, ranks, p, seed, order, prec)
+
+    def rhosvd(self, X, ranks, p, seed, prec=None):
+        return self._fixed("rt_rhosvd", X, ranks, p, seed, None, prec)
+
+    def _fixed(self, fn, X, ranks, p, seed, order, prec):
+        self._sync_stream()
+        t = self._tensor(X)
+        rk = (ctypes.c_int32 * X.dim())(*[RT_KEEP if (r is None or r < 0) else int(r) for r in ranks])
+        o = self._opts(X, p, seed, order, prec)
+        out = rt_tucker()
+        st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), rk, ctypes.byref(o), ctypes.byref(out)))
+        return self._result(out, X, st)
+
+    def rsthosvd_adaptive(self, X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):
+        self._sync_stream()
+        t = self._tensor(X)
+        o = self._opts(X, 0, seed, order, prec)
+        epm = (ctypes.c_double * X.dim())(*eps_per_mode) if eps_per_mode is not None else None
+        mr = (ctypes.c_int32 * X.dim())(*max_rank) if max_rank is not None else None
+        out = rt_tucker()
+        st = _check(_lib.rt_rsthosvd_adaptive(self.ctx, ctypes.byref(t), float(eps), epm, int(block), mr,
+                                              ctypes.byref(o), ctypes.byref(out)), allow=(RT_ECAP,))
+        return self._result(out, X, st)
+
+    # -- steps ----------------------------------------------------------------------
+    def sketch(self, X, mode, ell, seed, col0=0, prec=None, want_norm=False):
+        torch = self.torch
+        self._sync_stream()
+        t = self._tensor(X)
+        Y = torch.empty((int(X.shape[mode]), int(ell)), dtype=torch.float64, device=self.device)
+        nrm = torch.empty(1, dtype=torch.float64, device=self.device) if want_norm else None
+        _check(_lib.rt_sketch(self.ctx, ctypes.byref(t), int(mode), int(ell), int(col0), int(seed),
+                              self._prec(X, prec), Y.data_ptr(), nrm.data_ptr() if nrm is not None else None))
+        return (Y, nrm) if want_norm else Y
+
+    def orth(self, Y):
+        torch = self.torch
+        self._sync_stream()
+        if Y.dtype != torch.float64 or not Y.is_contiguous():
+            raise ValueError("Y must be contiguous float64")
+        Q = Y.clone()
+        flags = ctypes.c_uint32(0)
+        _check(_lib.rt_orth(self.ctx, Q.data_ptr(), int(Q.shape[0]), int(Q.shape[1]), ctypes.byref(flags)))
+        return Q, int(flags.value)
+
+    def project(self, X, mode, Q, want_gram=False):
+        torch = self.torch
+        self._sync_stream()
+        t = self._tensor(X)
+        ell = int(Q.shape[1])
+        shape = list(X.shape)
+        shape[mode] = ell
+        B = torch.empty(shape, dtype=X.dtype, device=self.device)
+        W = torch.empty((ell, ell), dtype=torch.float64, device=self.device) if want_gram else None
+        qt = RT_F64 if Q.dtype == torch.float64 else RT_F32
+        Qc = Q.contiguous()
+        _check(_lib.rt_project(self.ctx, ctypes.byref(t), int(mode), Qc.data_ptr(), qt, ell, B.data_ptr(),
+                               W.data_ptr() if W is not None else None))
+        return (B, W) if want_gram else B
+
+    def omega(self, seed, mode, c0, nrows, col0, ncols, dtype=None):
+        torch = self.torch
+        dtype = dtype or torch.float64
+        out = torch.empty((int(nrows), int(ncols)), dtype=dtype, device=self.device)
+        _check(_lib.rt_omega(self.ctx, int(seed), int(mode), int(c0), int(nrows), int(col0), int(ncols),
+                             RT_F64 if dtype == torch.float64 else RT_F32, out.data_ptr()))
+        return out
+
+    def philox_words(self, seed, mode, c0, n, q):
+        torch = self.torch
+        out = torch.empty((int(n), 4), dtype=torch.int32, device=self.device)
+        _check(_lib.rt_philox_words(self.ctx, int(seed), int(mode), int(c0), int(n), int(q), out.data_ptr()))
+        return out
+
+    def sync(self):
+        _check(_lib.rt_sync(self.ctx))
+
+    def timing(self, enable):
+        _check(_lib.rt_timing(self.ctx, 1 if enable else 0))
+
+    KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate"}
+
+    def timing_log(self):
+        """List of dicts, one per timed launch (kind, ms, bytes, flops, rows, cols, ell)."""
+        n = ctypes.c_int64(0)
+        _check(_lib.rt_timing_count(self.ctx, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            kind, ell = ctypes.c_int32(), ctypes.c_int32()
+            ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            rows, cols = ctypes.c_int64(), ctypes.c_int64()
+            _check(_lib.rt_timing_entry(self.ctx, i, ctypes.byref(kind), ctypes.byref(ms), ctypes.byref(by),
+                                        ctypes.byref(fl), ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(ell)))
+            out.append({"kind": self.KINDS.get(kind.value, str(kind.value)), "ms": ms.value, "bytes": by.value,
+                        "flops": fl.value, "rows": rows.value, "cols": cols.value, "ell": ell.value})
+        return out
+
+
+_default = {}
+
+
+def context(device=None):
+    """Per-device shared Context."""
+    import torch
+    idx = torch.cuda.current_device() if device is None else device
+    if idx not in _default:
+        _default[idx] = Context(idx)
+    return _default[idx]
+
+
+def rsthosvd(X, ranks, p, seed, order=None, prec=None):
+    return context(X.device.index).rsthosvd(X, ranks, p, seed, order, prec)
+
+
+def rhosvd(X, ranks, p, seed, prec=None):
+    return context(X.device.index).rhosvd(X, ranks, p, seed, prec)
+
+
+def rsthosvd_adaptive(X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):
+    return context(X.device.index).rsthosvd_adaptive(X, eps, block, seed, order, eps_per_mode, max_rank, prec)

@@ -1,0 +1,26 @@
+"""Shared helpers of the GPU tests (device context, comparisons)."""
+import numpy as np
+import pytest
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def projector_dist(A, B):
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    return np.linalg.norm(A @ A.T - B @ B.T, 2)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_np(t):
+    return t.detach().double().cpu().numpy()

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/rtucker.h, the binding's list matches, and
+argument errors are reported synchronously as RT_EINVAL."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_07311_amd import rtucker
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "rtucker.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = rtucker.load()
+    names = declared()
+    assert "rt_rsthosvd" in names and "rt_rhosvd" in names and "rt_rsthosvd_adaptive" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(rtucker.EXPORTED) == names
+
+
+def test_version_and_error_strings():
+    lib = rtucker.load()
+    assert lib.rt_version().startswith(b"rtucker")
+    assert isinstance(lib.rt_last_error(), bytes)
+
+
+def test_argument_errors_are_synchronous():
+    lib = rtucker.load()
+    out = rtucker.rt_tucker()
+    opts = rtucker.rt_opts()
+    x = rtucker.rt_tensor()
+    assert lib.rt_rsthosvd(None, ctypes.byref(x), None, ctypes.byref(opts), ctypes.byref(out)) == rtucker.RT_EINVAL
+    assert lib.rt_rhosvd(None, None, None, None, None) == rtucker.RT_EINVAL
+    assert b"NULL" in lib.rt_last_error()
+    ctx = ctypes.c_void_p()
+    # alloc without free is rejected before any device call
+    assert lib.rt_create(ctypes.byref(ctx), 0, None, rtucker.ALLOC_FN(lambda n, u: 0), rtucker.FREE_FN(0),
+                         None) == rtucker.RT_EINVAL
+    assert lib.rt_sync(None) == rtucker.RT_EINVAL
+
+
+def test_struct_layout_matches_header(tmp_path):
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "rtucker.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(rt_tensor), offsetof(rt_tensor, dtype), offsetof(rt_tensor, data));
+  printf("%zu %zu %zu\\n", sizeof(rt_opts), offsetof(rt_opts, order), offsetof(rt_opts, prec));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_tucker), offsetof(rt_tucker, core), offsetof(rt_tucker, factors),
+         offsetof(rt_tucker, norm_x), offsetof(rt_tucker, flags));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    T, O, K = rtucker.rt_tensor, rtucker.rt_opts, rtucker.rt_tucker
+    assert [int(v) for v in lines[0].split()] == [ctypes.sizeof(T), T.dtype.offset, T.data.offset]
+    assert [int(v) for v in lines[1].split()] == [ctypes.sizeof(O), O.order.offset, O.prec.offset]
+    assert [int(v) for v in lines[2].split()] == [ctypes.sizeof(K), K.core.offset, K.factors.offset,
+                                                 K.norm_x.offset, K.flags.offset]
