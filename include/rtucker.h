@@ -184,6 +184,7 @@ rt_status rt_philox_words(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, 
 #define RT_KIND_PROJECT 1   /* B = X x_n Q^T, bytes = X read + B written, flops = 2 ell N */
 #define RT_KIND_ORTH 2      /* single-workgroup orth(Y) */
 #define RT_KIND_TRUNCATE 3  /* single-workgroup eigensolver + factor */
+#define RT_KIND_GRAM 4      /* fp64 Gram of B for the truncation (unfused variant) */
 
 /* Turn the per-launch timing log on (enable != 0) or off, clearing it.  While on,
  * every sketch, projection, orth and truncation launch of this context is

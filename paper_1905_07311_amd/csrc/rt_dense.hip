@@ -26,127 +26,166 @@ constexpr int NT = 256;
 constexpr int LDW = LMAX + 1;
 typedef double Mat[LMAX][LDW];
 
+__device__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup (every thread gets the result).
 __device__ double blk_sum(double v, double* red) {
     const int tid = threadIdx.x;
+    v = wave_sum(v);
     __syncthreads();
-    red[tid] = v;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    double r = red[0];
+    double r = 0.0;
+    for (int w = 0; w < NT / 64; ++w) r += red[w];
     __syncthreads();
     return r;
 }
 
-// W = Y^T Y (n x n) for Y (J x n, row stride ldy) in global memory.
+// W = Y^T Y (n x n) for Y (J x n, row stride ldy) in global memory.  The upper
+// triangle of 4x4 tiles is spread over the threads, each thread accumulating
+// its tile over every G-th row straight from global memory (L2); the G partial
+// tiles are then summed through LDS.
 __device__ void blk_gram(const double* Y, int64_t J, int n, int64_t ldy, Mat& W, Mat& stage) {
     const int tid = threadIdx.x;
-    const int npairs = n * (n + 1) / 2;
-    double acc[9];
-    int pa[9], pb[9];
+    const int nt = (n + 3) / 4;
+    const int npt = nt * (nt + 1) / 2;
+    const int G = NT / npt > 0 ? NT / npt : 1;
+    double* part = &stage[0][0];                 // G x npt x 16 doubles (<= 4096)
+    if (tid < npt * G) {
+        const int pr = tid % npt, g = tid / npt;
+        int ti = 0, rem = pr;
+        while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
+        const int tj = ti + rem;
+        double acc[4][4];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        acc[m] = 0.0;
-        const int t = tid + NT * m;
-        int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((a + 1) * (a + 2) / 2 <= t) ++a;
-        while (a * (a + 1) / 2 > t) --a;
-        pa[m] = a;
-        pb[m] = t - a * (a + 1) / 2;
-    }
-    for (int64_t i0 = 0; i0 < J; i0 += LMAX) {
-        const int rows = (int)((J - i0) < LMAX ? (J - i0) : LMAX);
-        __syncthreads();
-        for (int e = tid; e < rows * n; e += NT) stage[e / n][e % n] = Y[(i0 + e / n) * ldy + e % n];
-        __syncthreads();
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int m = 0; m < 9; ++m) {
-            if (tid + NT * m < npairs) {
-                double s = 0.0;
-                for (int r = 0; r < rows; ++r) s += stage[r][pa[m]] * stage[r][pb[m]];
-                acc[m] += s;
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int64_t i = g; i < J; i += G) {
+            const double* row = Y + i * ldy;
+            double x[4], y[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                x[a] = (4 * ti + a < n) ? row[4 * ti + a] : 0.0;
+                y[a] = (4 * tj + a < n) ? row[4 * tj + a] : 0.0;
             }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
         }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) part[(g * npt + pr) * 16 + 4 * a + b] = acc[a][b];
     }
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        if (tid + NT * m < npairs) {
-            W[pa[m]][pb[m]] = acc[m];
-            W[pb[m]][pa[m]] = acc[m];
-        }
+    for (int e = tid; e < npt * 16; e += NT) {
+        const int pr = e / 16, ab = e % 16;
+        int ti = 0, rem = pr;
+        while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
+        const int tj = ti + rem;
+        double sum = 0.0;
+        for (int g = 0; g < G; ++g) sum += part[(g * npt + pr) * 16 + ab];
+        const int r = 4 * ti + ab / 4, c = 4 * tj + ab % 4;
+        if (r < n && c < n) { W[r][c] = sum; W[c][r] = sum; }
     }
     __syncthreads();
 }
 
-// In-place Cholesky W = L L^T (lower triangle).  Returns false on a non-positive
-// or non-finite pivot; *min_ratio = min_k pivot_k / W_kk(original), the squared
-// sine of the angle between column k and the span of the previous columns.
-__device__ bool blk_cholesky(Mat& W, int n, double* diag0, double* min_ratio, int* flag) {
+// In-place Cholesky W + shift I = L L^T (lower triangle), one barrier per
+// elimination step: every thread reads the pivot and updates its share of the
+// trailing triangle with W[i][j] -= W[i][k] W[j][k] / W[k][k]; the columns are
+// scaled by 1/sqrt(pivot) at the end.  Returns false on a non-positive or
+// non-finite pivot; *min_ratio = min_k pivot_k / W_kk(original), the squared sine
+// of the angle between column k and the span of the previous columns.
+__device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double* min_ratio, int* flag) {
     const int tid = threadIdx.x;
-    if (tid < n) diag0[tid] = W[tid][tid];
-    if (tid == 0) { flag[0] = 0; min_ratio[0] = 1.0; }
     __syncthreads();
+    if (tid < n) {
+        diag0[tid] = W[tid][tid];
+        W[tid][tid] += shift;
+    }
+    __syncthreads();
+    double mr = 1.0;
+    bool ok = true;
     for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            double d = W[k][k];
-            if (!(d > 0.0) || !isfinite(d) || !(diag0[k] > 0.0)) {
-                flag[0] = 1;
-                d = 1.0;
-            } else {
-                double ratio = d / diag0[k];
-                if (ratio < min_ratio[0]) min_ratio[0] = ratio;
-            }
-            W[k][k] = sqrt(d);
-        }
-        __syncthreads();
-        if (flag[0]) break;
-        const double dk = W[k][k];
-        for (int i = k + 1 + tid; i < n; i += NT) W[i][k] /= dk;
-        __syncthreads();
+        const double piv = W[k][k];
+        if (!(piv > 0.0) || !isfinite(piv) || !(diag0[k] + shift > 0.0)) { ok = false; break; }
+        mr = fmin(mr, piv / (diag0[k] + shift));
+        const double rp = 1.0 / piv;
         const int m = n - k - 1;
         for (int e = tid; e < m * m; e += NT) {
             const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) W[i][j] -= W[i][k] * W[j][k];
+            if (j <= i) W[i][j] -= W[i][k] * W[j][k] * rp;
         }
         __syncthreads();
     }
-    const bool ok = flag[0] == 0;
+    if (ok) {
+        // L[i][k] = W[i][k] / sqrt(W[k][k]) for i >= k
+        for (int e = tid; e < n * n; e += NT) {
+            const int i = e / n, k = e % n;
+            if (i > k) W[i][k] = W[i][k] / sqrt(W[k][k]);
+        }
+        __syncthreads();
+        if (tid < n) W[tid][tid] = sqrt(W[tid][tid]);
+    }
+    __syncthreads();
+    if (tid == 0) { flag[0] = ok ? 0 : 1; min_ratio[0] = mr; }
     __syncthreads();
     return ok;
 }
 
-// Rinv = L^{-T} (upper triangular) from the lower Cholesky factor in W.
+// Rinv = L^{-T} (upper triangular) from the lower Cholesky factor in W.  Thread j
+// solves L x = e_j by forward substitution with x held in registers (the loops are
+// unrolled over LMAX so every index is static) and writes Rinv[j][:] = x^T.
 __device__ void blk_tri_inv(const Mat& W, int n, Mat& Rinv) {
     const int tid = threadIdx.x;
-    // Solve L X = I column by column (X lower), then Rinv = X^T.
     if (tid < n) {
         const int j = tid;
-        for (int i = 0; i < n; ++i) {
+        double x[LMAX];
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i) {
             double s = (i == j) ? 1.0 : 0.0;
-            if (i < j) { Rinv[j][i] = 0.0; continue; }
-            for (int k = j; k < i; ++k) s -= W[i][k] * Rinv[j][k];
-            Rinv[j][i] = s / W[i][i];          // Rinv[j][i] = X[i][j]
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= W[i][k] * x[k];
+            x[i] = (i < j || i >= n) ? 0.0 : s / W[i][i];
         }
+#pragma unroll
+        for (int i = 0; i < LMAX; ++i)
+            if (i < n) Rinv[j][i] = x[i];
     }
     __syncthreads();
 }
 
-// Y <- Y * M (J x n times n x n), in place, staging 64-row chunks through LDS.
-__device__ void blk_apply_right(double* Y, int64_t J, int n, int64_t ldy, const Mat& M, Mat& stage) {
+// Yout = Y * M (J x n times n x nout, M in LDS); Yout may alias Y (each thread
+// reads its whole row into registers before writing it).  Rows are spread over
+// the threads; M is read with wave-uniform (broadcast) LDS accesses.
+__device__ void blk_apply_right(const double* Y, int64_t J, int n, int64_t ldy, const Mat& M, int nout,
+                                double* Yout, int64_t ldo) {
     const int tid = threadIdx.x;
-    for (int64_t i0 = 0; i0 < J; i0 += LMAX) {
-        const int rows = (int)((J - i0) < LMAX ? (J - i0) : LMAX);
-        __syncthreads();
-        for (int e = tid; e < rows * n; e += NT) stage[e / n][e % n] = Y[(i0 + e / n) * ldy + e % n];
-        __syncthreads();
-        for (int e = tid; e < rows * n; e += NT) {
-            const int r = e / n, j = e % n;
-            double s = 0.0;
-            for (int k = 0; k < n; ++k) s += stage[r][k] * M[k][j];
-            Y[(i0 + r) * ldy + j] = s;
+    for (int64_t i = tid; i < J; i += NT) {
+        double y[LMAX];
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) y[k] = (k < n) ? Y[i * ldy + k] : 0.0;
+        for (int j0 = 0; j0 < nout; j0 += 8) {
+            double z[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k) {
+                if (k < n) {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) z[jj] += y[k] * M[k][j0 + jj];
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                if (j0 + jj < nout) Yout[i * ldo + j0 + jj] = z[jj];
         }
     }
     __syncthreads();
@@ -233,53 +272,57 @@ __device__ void blk_householder_q(double* A, int64_t J, int n, int64_t lda, doub
     }
 }
 
-// Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS): on exit the
-// diagonal of A holds the eigenvalues and the columns of V the eigenvectors.
-__device__ void blk_jacobi_eig(Mat& A, int n, Mat& V, double* cs, int* pairs, double* red) {
+// Jacobi rotation (c, s) that zeroes A[p][q] of the symmetric 2x2 [app apq; apq aqq]
+// under A <- R^T A R with R = [c s; -s c]; t = tan of the smaller rotation angle.
+__device__ __forceinline__ void jrot(double app, double aqq, double apq, double& c, double& s) {
+    c = 1.0; s = 0.0;
+    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
+        const double d = aqq - app;
+        const double r = sqrt(d * d + 4.0 * apq * apq);
+        const double t = 2.0 * apq / (d >= 0.0 ? d + r : d - r);
+        c = rsqrt(t * t + 1.0);
+        s = t * c;
+    }
+}
+
+// Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS).  The round-robin
+// pairing of the m = n + (n odd) indices is tabulated once; every step then costs
+// two barriers: the half = m/2 pair owners compute their rotation from the pivots,
+// and all threads apply R^T A R to the disjoint 2x2 blocks in place and V <- V R.
+// Stops when the off-diagonal sum of squares is <= tol ||A||_F^2 (checked once per
+// sweep).  On exit A's diagonal holds the eigenvalues, V's columns the eigenvectors.
+__device__ void blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, unsigned short* sched, double* red) {
     const int tid = threadIdx.x;
-    const int m = (n % 2) ? n + 1 : n;    // even number of players (a dummy if n is odd)
+    const int m = (n % 2) ? n + 1 : n;
     const int half = m / 2;
     for (int e = tid; e < n * n; e += NT) V[e / n][e % n] = (e / n == e % n) ? 1.0 : 0.0;
-    __syncthreads();
+    for (int e = tid; e < (m - 1) * half; e += NT) {
+        const int step = e / half, t = e % half;
+        int a, b;
+        if (t == 0) { a = m - 1; b = step; }
+        else { a = (step + t) % (m - 1); b = (step - t + (m - 1)) % (m - 1); }
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        sched[e] = (unsigned short)(p | (q << 8));
+    }
     double tot = 0.0;
     for (int e = tid; e < n * n; e += NT) tot += A[e / n][e % n] * A[e / n][e % n];
     tot = blk_sum(tot, red);
-    if (tot == 0.0) return;
+    if (tot == 0.0 || n < 2) return;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        double off = 0.0;
-        for (int e = tid; e < n * n; e += NT)
-            if (e / n != e % n) off += A[e / n][e % n] * A[e / n][e % n];
-        off = blk_sum(off, red);
-        if (off <= 1e-30 * tot) break;
         for (int step = 0; step < m - 1; ++step) {
+            const unsigned short* sp = sched + step * half;
             if (tid < half) {
-                int a, b;
-                if (tid == 0) { a = m - 1; b = step; }
-                else { a = (step + tid) % (m - 1); b = (step - tid + (m - 1)) % (m - 1); }
-                int p = a < b ? a : b, q = a < b ? b : a;
-                double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double apq = A[p][q];
-                    const double app = A[p][p], aqq = A[q][q];
-                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                    }
-                }
-                pairs[2 * tid] = p; pairs[2 * tid + 1] = q;
-                cs[2 * tid] = c; cs[2 * tid + 1] = s;
+                const int p = sp[tid] & 255, q = sp[tid] >> 8;
+                double c = 1.0, sn = 0.0;
+                if (q < n) jrot(A[p][p], A[q][q], A[p][q], c, sn);
+                cs[2 * tid] = c;
+                cs[2 * tid + 1] = sn;
             }
             __syncthreads();
-            // A <- R^T A R on every 2x2 block (row pair bi, column pair bj), in place.
-            // When n is odd one pair holds the dummy index n: its real member is
-            // rotated by nobody (identity) but its entries still take the rotation
-            // of the other pair of the block.
             for (int e = tid; e < half * half; e += NT) {
-                const int bi = e / half, bj = e % half;
-                const int p = pairs[2 * bi], q = pairs[2 * bi + 1];
-                const int pp = pairs[2 * bj], qq = pairs[2 * bj + 1];
+                const int bi = e / half, bj = e - bi * half;
+                const int p = sp[bi] & 255, q = sp[bi] >> 8;
+                const int pp = sp[bj] & 255, qq = sp[bj] >> 8;
                 const double ci = cs[2 * bi], si = cs[2 * bi + 1];
                 const double cj = cs[2 * bj], sj = cs[2 * bj + 1];
                 const bool rq = q < n, cq = qq < n;
@@ -287,29 +330,30 @@ __device__ void blk_jacobi_eig(Mat& A, int n, Mat& V, double* cs, int* pairs, do
                 const double b = cq ? A[p][qq] : 0.0;
                 const double c = rq ? A[q][pp] : 0.0;
                 const double d = (rq && cq) ? A[q][qq] : 0.0;
-                // left: rows (p, q) <- R_i^T: [ci -si; si ci]  (identity for a dummy pair)
                 const double a1 = ci * a - si * c, b1 = ci * b - si * d;
                 const double c1 = si * a + ci * c, d1 = si * b + ci * d;
-                // right: cols (pp, qq) <- * R_j: [cj sj; -sj cj]
                 A[p][pp] = a1 * cj - b1 * sj;
                 if (cq) A[p][qq] = a1 * sj + b1 * cj;
                 if (rq) A[q][pp] = c1 * cj - d1 * sj;
                 if (rq && cq) A[q][qq] = c1 * sj + d1 * cj;
             }
-            // V <- V R
             for (int e = tid; e < n * half; e += NT) {
-                const int r = e / half, bj = e % half;
-                const int p = pairs[2 * bj], q = pairs[2 * bj + 1];
+                const int r = e / half, bj = e - r * half;
+                const int p = sp[bj] & 255, q = sp[bj] >> 8;
                 if (q >= n) continue;
-                const double c = cs[2 * bj], s = cs[2 * bj + 1];
+                const double c = cs[2 * bj], sn = cs[2 * bj + 1];
                 const double vp = V[r][p], vq = V[r][q];
-                V[r][p] = c * vp - s * vq;
-                V[r][q] = s * vp + c * vq;
+                V[r][p] = c * vp - sn * vq;
+                V[r][q] = sn * vp + c * vq;
             }
             __syncthreads();
         }
+        double off = 0.0;
+        for (int e = tid; e < n * n; e += NT)
+            if (e / n != e % n) off += A[e / n][e % n] * A[e / n][e % n];
+        off = blk_sum(off, red);
+        if (off <= tol * tot) break;
     }
-    __syncthreads();
 }
 
 // Rank positions: perm[t] = index of the t-th largest diagonal entry (ties by index).
@@ -339,12 +383,18 @@ struct DenseShared {
     double v0[LMAX];
     double rdiag[LMAX];
     double cs[LMAX + 2];
+    unsigned short sched[LMAX * LMAX / 2];
     double lam[LMAX];
     double minr[1];
     int pairs[LMAX + 2];
     int perm[LMAX];
     int flag[4];
 };
+
+__device__ void cholqr_apply(double* Y, int64_t J, int ell, DenseShared& S) {
+    blk_tri_inv(S.W, ell, S.M2);
+    blk_apply_right(Y, J, ell, ell, S.M2, ell, Y, ell);
+}
 
 __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_t J, int ell, float* __restrict__ Qf,
                                                   double* __restrict__ V, double accept_ratio,
@@ -353,39 +403,46 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
     const int tid = threadIdx.x;
     uint32_t st = 0;
     if (tid == 0) S.flag[1] = 0;
-    // keep a copy of Y in V's second half? The CholeskyQR passes work in place; the
-    // fallback restarts from the copy held in V[J*ell ...].
+    // keep a copy of Y for the Householder fallback
     double* Ycopy = V + J * (int64_t)ell;
-    double nonfinite = 0.0;
+    double nonfinite = 0.0, fro = 0.0;
     for (int64_t e = tid; e < J * ell; e += NT) {
         const double y = Y[e];
         Ycopy[e] = y;
         if (!isfinite(y)) nonfinite += 1.0;
+        else fro += y * y;
     }
     nonfinite = blk_sum(nonfinite, S.red);
-    bool ok = nonfinite == 0.0;
-    if (!ok) st |= 4u;
-    double ratio1 = 0.0, ratio2 = 0.0;
+    fro = blk_sum(fro, S.red);
+    bool ok = nonfinite == 0.0 && fro > 0.0;
+    if (nonfinite != 0.0) st |= 4u;
     if (ok) {
+        // CholeskyQR2: accepted when the first factorisation keeps every pivot
+        // ratio >= accept_ratio (kappa(Y) ~ 1/sqrt(ratio)) and the second one is
+        // nearly orthogonal already (ratio >= 1/2).
         blk_gram(Y, J, ell, ell, S.W, S.stage);
-        ok = blk_cholesky(S.W, ell, S.diag0, S.minr, S.flag);
-        ratio1 = S.minr[0];
-        __syncthreads();
-        if (ok && ratio1 >= accept_ratio) {
-            blk_tri_inv(S.W, ell, S.M2);
-            blk_apply_right(Y, J, ell, ell, S.M2, S.stage);
+        ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= accept_ratio;
+        if (!ok) {
+            // shifted CholeskyQR3 (Fukaya et al. 2020): factor Y^T Y + s I with
+            // s = 11 (J ell + ell (ell + 1)) u ||Y||_F^2, which bounds kappa of
+            // Y R^-1 by O(u^-1/2), then CholeskyQR2 on the result.
             blk_gram(Y, J, ell, ell, S.W, S.stage);
-            ok = blk_cholesky(S.W, ell, S.diag0, S.minr, S.flag);
-            ratio2 = S.minr[0];
-            __syncthreads();
-            if (ok && ratio2 >= 0.5) {
-                blk_tri_inv(S.W, ell, S.M2);
-                blk_apply_right(Y, J, ell, ell, S.M2, S.stage);
-            } else {
-                ok = false;
+            const double shift = 11.0 * ((double)J * ell + (double)ell * (ell + 1)) * 0x1p-53 * fro;
+            ok = blk_cholesky(S.W, ell, shift, S.diag0, S.minr, S.flag);
+            if (ok) {
+                cholqr_apply(Y, J, ell, S);
+                blk_gram(Y, J, ell, ell, S.W, S.stage);
+                ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= accept_ratio;
+                // a direction of Y far below sqrt(shift) leaves a pivot ratio near u:
+                // Y was numerically rank deficient and Q holds padding directions
+                if (ok && S.minr[0] < 1e-6) st |= 1u;
             }
-        } else {
-            ok = false;
+        }
+        if (ok) {
+            cholqr_apply(Y, J, ell, S);
+            blk_gram(Y, J, ell, ell, S.W, S.stage);
+            ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= 0.5;
+            if (ok) cholqr_apply(Y, J, ell, S);
         }
     }
     if (!ok) {
@@ -406,7 +463,6 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
     if (Qf)
         for (int64_t e = tid; e < J * ell; e += NT) Qf[e] = (float)Y[e];
     if (tid == 0 && status) status[0] = st;
-    (void)ratio2;
 }
 
 // Truncation: eigen-decomposition of the Gram W (ell x ell) of B, rank choice,
@@ -417,12 +473,13 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
                                                       const double* __restrict__ E_dev, double tau2,
                                                       double* __restrict__ U, float* __restrict__ Uf,
                                                       void* __restrict__ Aout, int a_is_f64,
-                                                      double* __restrict__ lam_out, int* __restrict__ kout) {
+                                                      double* __restrict__ lam_out, int* __restrict__ kout,
+                                                      double jtol) {
     __shared__ DenseShared S;
     const int tid = threadIdx.x;
     for (int e = tid; e < ell * ell; e += NT) S.W[e / ell][e % ell] = W[e];
     __syncthreads();
-    blk_jacobi_eig(S.W, ell, S.M2, S.cs, S.pairs, S.red);
+    blk_jacobi_eig(S.W, ell, S.M2, jtol, S.cs, S.sched, S.red);
     blk_sort_desc(S.W, ell, S.perm, S.lam);
     if (tid == 0) {
         int k;
@@ -446,54 +503,100 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
     const int k = S.flag[2];
     if (lam_out && tid < ell) lam_out[tid] = S.lam[tid];
     if (kout && tid == 0) kout[0] = k;
-    // U columns = eigenvectors in sorted order: stage as S.W (ell x k)
+    // U columns = eigenvectors in sorted order (ell x k, in S.W)
     for (int e = tid; e < ell * k; e += NT) {
         const int i = e / k, j = e % k;
         S.W[i][j] = S.M2[i][S.perm[j]];
     }
+    for (int e = tid; e < ell * LMAX; e += NT) {      // zero the unused columns (read by the row product)
+        const int i = e / LMAX, j = e % LMAX;
+        if (j >= k) S.W[i][j] = 0.0;
+    }
     __syncthreads();
-    // sign fix: column j of A = Q U[:, j]; find the entry of largest magnitude
-    for (int j = 0; j < k; ++j) {
-        double best = -1.0;
-        int64_t bi = 0;
-        double bval = 0.0;
+    // A = Q U, eight columns at a time; each column is then flipped so that its
+    // entry of largest magnitude (lowest row on ties) is positive, and U with it.
+    double* A64 = (double*)Aout;
+    float* A32 = (float*)Aout;
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        double best[8], bval[8];
+        int64_t bidx[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) { best[jj] = -1.0; bval[jj] = 0.0; bidx[jj] = INT64_MAX; }
         for (int64_t i = tid; i < J; i += NT) {
-            double a = 0.0;
-            for (int t = 0; t < ell; ++t) a += Q[i * ldq + t] * S.W[t][j];
-            if (fabs(a) > best) { best = fabs(a); bi = i; bval = a; }
-        }
-        // block argmax (ties -> lowest index)
-        S.red[tid] = best;
-        S.stage[tid / LMAX][tid % LMAX] = bval;
-        __syncthreads();
-        if (tid == 0) {
-            double b = -1.0, v = 0.0;
-            for (int t = 0; t < NT; ++t) {
-                if (S.red[t] > b) { b = S.red[t]; v = S.stage[t / LMAX][t % LMAX]; }
+            double q[LMAX];
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
+            double z[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t) {
+                if (t < ell) {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) z[jj] += q[t] * S.W[t][j0 + jj];
+                }
             }
-            S.cs[0] = (v < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                if (j0 + jj < k) {
+                    const double a = fabs(z[jj]);
+                    if (a > best[jj]) { best[jj] = a; bval[jj] = z[jj]; bidx[jj] = i; }
+                    if (Aout) {
+                        if (a_is_f64) A64[i * k + j0 + jj] = z[jj];
+                        else A32[i * k + j0 + jj] = (float)z[jj];
+                    }
+                }
+            }
+        }
+        // workgroup argmax per column: wave shuffles, then the four waves in LDS
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            double b = best[jj], v = bval[jj];
+            int64_t ix = bidx[jj];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(b, off, 64);
+                const double ov = __shfl_xor(v, off, 64);
+                const int64_t oi = __shfl_xor(ix, off, 64);
+                if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
+            }
+            if (lane == 0) {
+                S.stage[0][wave * 8 + jj] = b;
+                S.stage[1][wave * 8 + jj] = v;
+                S.stage[2][wave * 8 + jj] = (double)ix;
+            }
         }
         __syncthreads();
-        const double sgn = S.cs[0];
+        if (tid < 8) {
+            double b = -1.0, v = 0.0, ix = 1e300;
+            for (int w = 0; w < NT / 64; ++w) {
+                const double ob = S.stage[0][w * 8 + tid], ov = S.stage[1][w * 8 + tid], oi = S.stage[2][w * 8 + tid];
+                if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
+            }
+            S.cs[tid] = (v < 0.0) ? -1.0 : 1.0;
+        }
         __syncthreads();
-        if (tid < ell) S.W[tid][j] *= sgn;
+        // flip the columns with a negative leading entry
+        if (Aout) {
+            for (int64_t e = tid; e < J * 8; e += NT) {
+                const int64_t i = e / 8;
+                const int jj = (int)(e % 8);
+                if (j0 + jj < k && S.cs[jj] < 0.0) {
+                    if (a_is_f64) A64[i * k + j0 + jj] = -A64[i * k + j0 + jj];
+                    else A32[i * k + j0 + jj] = -A32[i * k + j0 + jj];
+                }
+            }
+        }
+        if (tid < ell)
+            for (int jj = 0; jj < 8; ++jj)
+                if (j0 + jj < k) S.W[tid][j0 + jj] *= S.cs[jj];
         __syncthreads();
-        (void)bi;
     }
     for (int e = tid; e < ell * k; e += NT) {
         const int i = e / k, j = e % k;
         U[i * k + j] = S.W[i][j];
         if (Uf) Uf[i * k + j] = (float)S.W[i][j];
-    }
-    if (Aout) {
-        for (int64_t e = tid; e < J * k; e += NT) {
-            const int64_t i = e / k;
-            const int j = (int)(e % k);
-            double a = 0.0;
-            for (int t = 0; t < ell; ++t) a += Q[i * ldq + t] * S.W[t][j];
-            if (a_is_f64) ((double*)Aout)[e] = a;
-            else ((float*)Aout)[e] = (float)a;
-        }
     }
 }
 
@@ -617,10 +720,10 @@ hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_r
 
 hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da, double* lam,
-                           int* kout, hipStream_t stream) {
+                           int* kout, double jtol, hipStream_t stream) {
     hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(NT), 0, stream, W, ell, Q, ldq, J, r_fixed, E_dev,
                        tau2,
-                       U, Uf, A, da == Dt::F64 ? 1 : 0, lam, kout);
+                       U, Uf, A, da == Dt::F64 ? 1 : 0, lam, kout, jtol);
     return hipGetLastError();
 }
 

@@ -26,9 +26,10 @@ struct SketchPlan {
     int64_t tiles_per_split;
     size_t partial_elems;  // nsplit * J * ell
     int nwg;               // nsplit * nrowtile
-    int kind;              // kernel variant
+    int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32
+    int rb;                // MFMA variant: 64-row blocks per wave (1 or 2)
 };
-SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell);
+SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X);
 hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,
                          int64_t col0, uint64_t seed, uint32_t mode, void* partial,
                          double* nrm2_partial, hipStream_t stream);
@@ -59,7 +60,7 @@ hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_r
 // of its columns to gram_partial[wg][ell][ell]; if nrm2_partial != nullptr, sum B^2
 // (fp64) per workgroup.  `nwg_out` receives the workgroup count.
 struct ProjectPlan { int nwg; int64_t ntiles; int kind; };
-ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell);
+ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 // ldj: stride of the mode index in G (= s.J for a plain tensor; larger when only
 // the first s.J rows of a wider buffer are contracted).  B is written at
 // B[(l * ldk + koff + k) * R + r] (ldk = ell, koff = 0 for a plain tensor).
@@ -79,9 +80,10 @@ hipError_t launch_gram3(const void* B, Dt dt, int64_t L, int64_t ldk, int64_t R,
 // Writes U (ell x k, double, and float copy Uf), A = Q U (J x k, in dtype `da`,
 // columns sign-fixed: largest-|.| entry positive), lam (ell, sorted eigenvalues),
 // kout[0] = k.
+// jtol: Jacobi stops when the off-diagonal sum of squares is <= jtol ||W||_F^2.
 hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da,
-                           double* lam, int* kout, hipStream_t stream);
+                           double* lam, int* kout, double jtol, hipStream_t stream);
 
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
@@ -93,6 +95,16 @@ hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq,
                              double drop, int* knew, double* scratch, hipStream_t stream);
 // one-time per-device set-up of the single-workgroup dense kernels (LDS > 64 KiB)
 hipError_t dense_init();
+
+// ---- MFMA variants (float32 data, v_mfma_f32_4x4x1_16b) -------------------------------
+bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X);
+hipError_t launch_sketch_mfma(int nsplit, int nrowtile, int64_t tiles_per_split, int rb, const float* X, Shape3 s,
+                              int ell, int64_t col0, uint64_t seed, uint32_t mode, float* partial, double* nrm2,
+                              hipStream_t stream);
+bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff);
+int plan_project_mfma(Shape3 s, int ell);
+hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
+                               float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
 
 // ---- misc ------------------------------------------------------------------------------
 // sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)

@@ -1,0 +1,425 @@
+// MFMA kernels of the FP32 hot path on gfx950: the mode-n sketch
+// Y = X_(n) Omega (§2.4 Alg. 1 step 1) and the projection B = X x_n Q^T
+// (Alg. 1 step 3; also the core update G <- U^T G of Alg. 3).
+//
+// Both use v_mfma_f32_4x4x1_16b_f32: sixteen independent 4x4 outer products per
+// instruction, so the narrow side of these skinny contractions (ell = r + p
+// columns of Omega, or rows of Q^T) is padded to a multiple of 4 only
+// (ell = 35 -> 36), not 16 or 32.  Operand layout (checked on the device):
+// lane l = 4 blk + t holds A[blk][t] and B[blk][t]; accumulator register v of
+// lane l holds D[blk][v][t].
+//
+// Sketch: a workgroup owns 256 or 512 rows of Y and a contiguous run of
+// 32-column tiles of the unfolding.  Each tile of X is loaded with coalesced
+// 16-byte loads (contiguous along the unfolding columns when R % 32 == 0, along
+// the rows when R == 1) one tile ahead into registers, stored to LDS, and read
+// back as four consecutive columns per lane; Omega for the tile is generated
+// once per workgroup (Philox + Box-Muller) into LDS, one tile ahead.  The
+// sixteen MFMA blocks are sixteen groups of four rows; a wave keeps 64 or 128
+// rows x ell columns of Y in accumulators.  Split-K partials are summed later in
+// a fixed order.
+//
+// Projection: a wave owns 256 consecutive unfolding columns (four per lane, so
+// every row of the strip is one 1 KiB load) and streams all J rows of them from
+// HBM, twelve rows in flight; Q^T is held in LDS.  The MFMA blocks are sixteen
+// groups of four columns, the four lanes' adjacent columns are four separate
+// accumulator sets.  The result is stored in the (L, ell, R) layout directly.
+#include "rt_kernels.hpp"
+#include "rt_philox.hpp"
+
+namespace rt {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int MK_KC = 32;          // unfolding columns per sketch tile
+constexpr int MK_XLD = MK_KC + 4;  // LDS row stride of the X tile (floats)
+constexpr int MK_NQ = 16;          // max column quads (ell <= 64)
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// LOAD_ROWS: R % MK_KC == 0, a tile lies inside one l-slab, each row contiguous.
+// LOAD_COLS: R == 1, element (i, c) at c J + i; J % 4 == 0.
+enum { LOAD_ROWS = 0, LOAD_COLS = 1 };
+
+template <int RB, int LOADER>
+__global__ __launch_bounds__(256) void sketch_mfma_kernel(const float* __restrict__ X, int64_t L, int64_t J, int64_t R,
+                                                          int ell, int64_t col0, uint64_t seed, uint32_t mode,
+                                                          int64_t tiles_per_split, float* __restrict__ partial,
+                                                          double* __restrict__ nrm2_partial) {
+    constexpr int MT = 256 * RB;                 // rows of Y per workgroup
+    constexpr int NLOAD = MT * MK_KC / 4 / 256;  // float4 loads per thread per tile
+    __shared__ __align__(16) float xs[MT * MK_XLD];
+    __shared__ __align__(16) float os[MK_KC * 4 * MK_NQ];   // Omega tile: [c][t][j]
+    __shared__ double red[4];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int blk = lane >> 2, t = lane & 3;
+    const int64_t K = L * R;
+    const int64_t ntiles = (K + MK_KC - 1) / MK_KC;
+    const int64_t row0 = (int64_t)blockIdx.y * MT;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_split;
+    const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+    const int nq = (ell + 3) / 4;
+    const int64_t qbase = col0 / 4;                    // Omega blocks needed: q in [qbase, qlast]
+    const int nqblk = (int)((col0 + ell - 1) / 4 - qbase + 1);
+    const int shift = (int)(col0 - 4 * qbase);         // column k of the sketch = Omega column col0 + k
+
+    f4 acc[RB][MK_NQ];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < MK_NQ; ++j) acc[rb][j] = f4{0.f, 0.f, 0.f, 0.f};
+    double nrm = 0.0;
+
+    f4 pre[NLOAD];
+    float opre[8];  // Omega values generated ahead by this thread (<= 2 blocks of 4)
+
+    auto load_tile = [&](int64_t tile) {
+        const int64_t c0 = tile * MK_KC;
+        if (LOADER == LOAD_ROWS) {
+            const int64_t l = c0 / R;
+            const int64_t r0 = c0 - l * R;
+            const float* base = X + l * J * R + r0;
+#pragma unroll
+            for (int it = 0; it < NLOAD; ++it) {
+                const int rr = (tid >> 3) + 32 * it;
+                const int cc = 4 * (tid & 7);
+                const int64_t i = row0 + rr;
+                f4 v = f4{0.f, 0.f, 0.f, 0.f};
+                if (i < J && c0 + cc < K) v = *reinterpret_cast<const f4*>(base + i * R + cc);
+                pre[it] = v;
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < NLOAD; ++it) {
+                const int e = tid + 256 * it;           // float4 index inside the tile
+                const int cc = e / (MT / 4);
+                const int rr = 4 * (e % (MT / 4));
+                const int64_t c = c0 + cc, i = row0 + rr;
+                f4 v = f4{0.f, 0.f, 0.f, 0.f};
+                if (i < J && c < K) v = *reinterpret_cast<const f4*>(X + c * J + i);
+                pre[it] = v;
+            }
+        }
+    };
+    auto store_tile = [&]() {
+        if (LOADER == LOAD_ROWS) {
+#pragma unroll
+            for (int it = 0; it < NLOAD; ++it) {
+                const int rr = (tid >> 3) + 32 * it;
+                const int cc = 4 * (tid & 7);
+                *reinterpret_cast<f4*>(&xs[rr * MK_XLD + cc]) = pre[it];
+                if (nrm2_partial) {
+                    nrm += (double)pre[it].x * pre[it].x + (double)pre[it].y * pre[it].y +
+                           (double)pre[it].z * pre[it].z + (double)pre[it].w * pre[it].w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < NLOAD; ++it) {
+                const int e = tid + 256 * it;
+                const int cc = e / (MT / 4);
+                const int rr = 4 * (e % (MT / 4));
+                xs[(rr + 0) * MK_XLD + cc] = pre[it].x;
+                xs[(rr + 1) * MK_XLD + cc] = pre[it].y;
+                xs[(rr + 2) * MK_XLD + cc] = pre[it].z;
+                xs[(rr + 3) * MK_XLD + cc] = pre[it].w;
+                if (nrm2_partial) {
+                    nrm += (double)pre[it].x * pre[it].x + (double)pre[it].y * pre[it].y +
+                           (double)pre[it].z * pre[it].z + (double)pre[it].w * pre[it].w;
+                }
+            }
+        }
+    };
+    // Omega of a tile: MK_KC rows x nqblk Philox blocks, at most 2 blocks per thread
+    auto gen_omega = [&](int64_t tile) {
+        const int64_t c0 = tile * MK_KC;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;
+            if (e < MK_KC * nqblk) {
+                const int cc = e % MK_KC, qi = e / MK_KC;
+                float z[4];
+                omega4_f32(seed, mode, (uint64_t)(c0 + cc), (uint32_t)(qbase + qi), z);
+                opre[4 * h + 0] = z[0]; opre[4 * h + 1] = z[1]; opre[4 * h + 2] = z[2]; opre[4 * h + 3] = z[3];
+            }
+        }
+    };
+    auto store_omega = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;
+            if (e < MK_KC * nqblk) {
+                const int cc = e % MK_KC, qi = e / MK_KC;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * qi + u - shift;      // sketch column
+                    if (k >= 0 && k < ell) os[(cc * 4 + (k & 3)) * MK_NQ + (k >> 2)] = opre[4 * h + u];
+                }
+            }
+        }
+    };
+
+    // zero the padding columns of the Omega tile once (columns ell .. 4 nq - 1)
+    for (int e = tid; e < MK_KC * 4 * MK_NQ; e += 256) os[e] = 0.f;
+    if (t_begin < t_end) {
+        load_tile(t_begin);
+        gen_omega(t_begin);
+    }
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        __syncthreads();
+        store_tile();
+        store_omega();
+        __syncthreads();
+        if (tile + 1 < t_end) {
+            load_tile(tile + 1);
+            gen_omega(tile + 1);
+        }
+        // MFMAs over the 32 columns, four at a time
+#pragma unroll 2
+        for (int c4 = 0; c4 < MK_KC; c4 += 4) {
+            f4 a[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                a[rb] = *reinterpret_cast<const f4*>(&xs[(wave * 64 * RB + rb * 64 + 4 * blk + t) * MK_XLD + c4]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float* orow = &os[((c4 + u) * 4 + t) * MK_NQ];
+                float bv[MK_NQ];
+#pragma unroll
+                for (int j4 = 0; j4 < MK_NQ; j4 += 4) {
+                    const f4 v = *reinterpret_cast<const f4*>(orow + j4);
+                    bv[j4] = v.x; bv[j4 + 1] = v.y; bv[j4 + 2] = v.z; bv[j4 + 3] = v.w;
+                }
+#pragma unroll
+                for (int j = 0; j < MK_NQ; ++j) {
+                    if (j < nq) {
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) acc[rb][j] = mfma4(a[rb][u], bv[j], acc[rb][j]);
+                    }
+                }
+            }
+        }
+    }
+    // partial Y rows: lane (blk, t) holds rows 4 blk + v (v = register) of column 4 j + t
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = row0 + wave * 64 * RB + rb * 64 + 4 * blk + v;
+            if (i < J) {
+                float* dst = partial + ((int64_t)blockIdx.x * J + i) * ell;
+#pragma unroll
+                for (int j = 0; j < MK_NQ; ++j) {
+                    const int k = 4 * j + t;
+                    if (j < nq && k < ell) dst[k] = acc[rb][j][v];
+                }
+            }
+        }
+    }
+    if (nrm2_partial) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        if (lane == 0) red[wave] = nrm;
+        __syncthreads();
+        if (tid == 0) nrm2_partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// ---- projection -------------------------------------------------------------------------
+
+constexpr int PM_DEPTH = 8;   // rows of the strip in flight per lane
+constexpr int PM_QCH = 128;   // rows of Q staged in LDS at a time
+
+// B[l, k, r] = sum_i Q[i, k] G[l, i, r].  Each wave owns a strip of 64 * SETS
+// consecutive unfolding columns, SETS adjacent columns per lane (one vector load
+// per row), and streams all J rows of the strip.  Requires R % SETS == 0.
+// NQ: column quads of the output (ell <= 4 NQ).
+template <int NQ, int SETS>
+__global__ __launch_bounds__(256) void project_mfma_kernel(const float* __restrict__ G, int64_t L, int64_t J,
+                                                           int64_t ldj, int64_t R, const float* __restrict__ Q,
+                                                           int64_t ldq, int ell, float* __restrict__ B, int64_t ldk,
+                                                           int64_t koff, double* __restrict__ nrm2_partial) {
+    typedef float vec __attribute__((ext_vector_type(SETS)));
+    constexpr int QW = (NQ + 3) / 4 * 4;                    // padded quads per Q row in LDS
+    __shared__ __align__(16) float qs[PM_QCH * 4 * QW];     // [i][t][j] = Q[i][4 j + t]
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int t = lane & 3;
+    const int64_t K = L * R;
+    constexpr int SW = 64 * SETS;                           // strip width (columns)
+    const int64_t nstrips = (K + SW - 1) / SW;
+    double nrm = 0.0;
+    for (int64_t s0 = (int64_t)blockIdx.x * 4; s0 < nstrips; s0 += (int64_t)gridDim.x * 4) {
+        const int64_t strip = s0 + wave;
+        const int64_t c = strip * SW + SETS * lane;          // this lane's columns c .. c + SETS - 1
+        const bool valid = strip < nstrips && c < K;
+        int64_t l = 0, r = 0;
+        if (valid) { l = c / R; r = c - l * R; }
+        const float* gp = G + (l * ldj) * R + r;
+        f4 acc[SETS][NQ];
+#pragma unroll
+        for (int s = 0; s < SETS; ++s)
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) acc[s][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int64_t i0 = 0; i0 < J; i0 += PM_QCH) {
+            const int rows = (int)((J - i0) < PM_QCH ? (J - i0) : PM_QCH);
+            __syncthreads();
+            for (int e = tid; e < PM_QCH * 4 * QW; e += 256) {
+                const int ii = e / (4 * QW), tt = (e / QW) & 3, j = e % QW;
+                const int k = 4 * j + tt;
+                qs[e] = (ii < rows && k < ell) ? Q[(i0 + ii) * ldq + k] : 0.f;
+            }
+            __syncthreads();
+            vec ring[PM_DEPTH];
+#pragma unroll
+            for (int d = 0; d < PM_DEPTH; ++d) {
+                vec v = vec(0.f);
+                if (valid && d < rows) v = *reinterpret_cast<const vec*>(gp + (i0 + d) * R);
+                ring[d] = v;
+            }
+            for (int ii = 0; ii < rows; ii += PM_DEPTH) {
+#pragma unroll
+                for (int d = 0; d < PM_DEPTH; ++d) {
+                    const int row = ii + d;
+                    if (row < rows) {
+                        const vec x = ring[d];
+                        const int nxt = row + PM_DEPTH;
+                        vec v = vec(0.f);
+                        if (valid && nxt < rows) v = *reinterpret_cast<const vec*>(gp + (i0 + nxt) * R);
+                        ring[d] = v;
+                        const float* qrow = &qs[(row * 4 + t) * QW];
+                        float av[QW];
+#pragma unroll
+                        for (int j4 = 0; j4 < QW; j4 += 4) {
+                            const f4 q = *reinterpret_cast<const f4*>(qrow + j4);
+                            av[j4] = q.x; av[j4 + 1] = q.y; av[j4 + 2] = q.z; av[j4 + 3] = q.w;
+                        }
+#pragma unroll
+                        for (int j = 0; j < NQ; ++j)
+#pragma unroll
+                            for (int s = 0; s < SETS; ++s) acc[s][j] = mfma4(av[j], x[s], acc[s][j]);
+                    }
+                }
+            }
+        }
+        // set s of lane l holds B[4 j + v][c + s] in register v of acc[s][j]
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int k = 4 * j + v;
+                    if (k < ell) {
+                        vec o;
+#pragma unroll
+                        for (int s = 0; s < SETS; ++s) o[s] = acc[s][j][v];
+                        *reinterpret_cast<vec*>(B + (l * ldk + koff + k) * R + r) = o;
+                        if (nrm2_partial)
+#pragma unroll
+                            for (int s = 0; s < SETS; ++s) nrm += (double)o[s] * o[s];
+                    }
+                }
+            }
+        }
+    }
+    if (nrm2_partial) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        __syncthreads();
+        if (lane == 0) red[wave] = nrm;
+        __syncthreads();
+        if (tid == 0) nrm2_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+template <int NQ, int SETS>
+hipError_t launch_pm(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell, float* B,
+                     int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream) {
+    hipLaunchKernelGGL((project_mfma_kernel<NQ, SETS>), dim3(nwg), dim3(256), 0, stream, G, s.L, s.J, ldj, s.R, Q,
+                       ldq, ell, B, ldk, koff, nrm2);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X) {
+    if (ell > 4 * MK_NQ) return false;
+    if (((uintptr_t)X & 15) != 0) return false;
+    if ((col0 + ell - 1) / 4 - col0 / 4 + 1 > 16) return false;   // Omega blocks per tile row: 2 per thread
+    if (s.R % MK_KC == 0) return true;
+    if (s.R == 1 && s.J % 4 == 0) return true;
+    return false;
+}
+
+hipError_t launch_sketch_mfma(int nsplit, int nrowtile, int64_t tiles_per_split, int rb, const float* X, Shape3 s,
+                              int ell, int64_t col0, uint64_t seed, uint32_t mode, float* partial, double* nrm2,
+                              hipStream_t stream) {
+    dim3 grid(nsplit, nrowtile);
+    const bool rows = s.R % MK_KC == 0;
+    if (rb == 2) {
+        if (rows)
+            hipLaunchKernelGGL((sketch_mfma_kernel<2, LOAD_ROWS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tiles_per_split, partial, nrm2);
+        else
+            hipLaunchKernelGGL((sketch_mfma_kernel<2, LOAD_COLS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tiles_per_split, partial, nrm2);
+    } else {
+        if (rows)
+            hipLaunchKernelGGL((sketch_mfma_kernel<1, LOAD_ROWS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tiles_per_split, partial, nrm2);
+        else
+            hipLaunchKernelGGL((sketch_mfma_kernel<1, LOAD_COLS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tiles_per_split, partial, nrm2);
+    }
+    return hipGetLastError();
+}
+
+int project_sets(Shape3 s, int ell) {
+    const int nq = (ell + 3) / 4;
+    if (nq <= 10 && s.R % 4 == 0) return 4;
+    if (s.R % 2 == 0) return 2;
+    return 1;
+}
+
+bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff) {
+    if (ell > 4 * MK_NQ || s.R < 2 || s.R % 2 != 0) return false;
+    const int sets = project_sets(s, ell);
+    const uintptr_t al = 4u * (uintptr_t)sets - 1u;
+    return (((uintptr_t)G & al) == 0) && (((uintptr_t)B & al) == 0) && ((koff * s.R) % sets == 0);
+}
+
+int plan_project_mfma(Shape3 s, int ell) {
+    const int sets = project_sets(s, ell);
+    const int64_t nstrips = (s.L * s.R + 64 * sets - 1) / (64 * sets);
+    int64_t g = (nstrips + 3) / 4;
+    if (g > 2048) g = 2048;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
+                               float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream) {
+    const int nq = (ell + 3) / 4;
+    const int sets = project_sets(s, ell);
+#define RT_PM(NQV, S) return launch_pm<NQV, S>(nwg, G, s, ldj, Q, ldq, ell, B, ldk, koff, nrm2, stream)
+    if (sets == 4) {
+        if (nq <= 2) RT_PM(2, 4);
+        if (nq <= 4) RT_PM(4, 4);
+        if (nq <= 7) RT_PM(7, 4);
+        if (nq <= 9) RT_PM(9, 4);
+        RT_PM(10, 4);
+    }
+    if (nq <= 4) RT_PM(4, 2);
+    if (nq <= 9) RT_PM(9, 2);
+    if (nq <= 12) RT_PM(12, 2);
+    RT_PM(16, 2);
+#undef RT_PM
+}
+
+}  // namespace rt

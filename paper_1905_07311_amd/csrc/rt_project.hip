@@ -179,9 +179,14 @@ __global__ __launch_bounds__(256) void philox_words_kernel(uint64_t seed, uint32
 
 }  // namespace
 
-ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell) {
-    (void)dx; (void)dq; (void)ell;
+ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const void* B, int64_t koff) {
     ProjectPlan p{};
+    if (dx == Dt::F32 && dq == Dt::F32 && project_mfma_ok(s, ell, G, B, koff)) {
+        p.kind = 1;
+        p.nwg = plan_project_mfma(s, ell);
+        p.ntiles = 0;
+        return p;
+    }
     const int64_t K = s.L * s.R;
     p.ntiles = (K + PJ_NC - 1) / PJ_NC;
     p.nwg = (int)(p.ntiles < 1024 ? p.ntiles : 1024);
@@ -193,6 +198,11 @@ ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell) {
 hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q,
                           int64_t ldq, int ell, void* B, int64_t ldk, int64_t koff, double* gram_partial,
                           double* nrm2_partial, hipStream_t stream) {
+    if (p.kind == 1) {
+        if (gram_partial) return hipErrorInvalidValue;   // the MFMA variant has no fused Gram
+        return launch_project_mfma(p.nwg, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk, koff,
+                                   nrm2_partial, stream);
+    }
     dim3 grid(p.nwg);
     if (dx == Dt::F64) {
         if (dq != Dt::F64) return hipErrorInvalidValue;

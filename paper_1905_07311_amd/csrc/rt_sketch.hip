@@ -141,10 +141,24 @@ __global__ __launch_bounds__(256) void sum_scalar_kernel(const double* __restric
 
 }  // namespace
 
-SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell) {
-    (void)dt; (void)prec;
+SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X) {
     SketchPlan p{};
     const int64_t K = s.L * s.R;
+    if (dt == Dt::F32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X)) {
+        p.kind = 1;
+        p.rb = s.J > 256 ? 2 : 1;
+        const int64_t mt = 256 * p.rb;
+        const int64_t ntl = (K + 31) / 32;
+        p.nrowtile = (int)((s.J + mt - 1) / mt);
+        int64_t want = (p.rb == 2 ? 256 : 512) / p.nrowtile;
+        if (want < 1) want = 1;
+        if (want > ntl) want = ntl;
+        p.tiles_per_split = (ntl + want - 1) / want;
+        p.nsplit = (int)((ntl + p.tiles_per_split - 1) / p.tiles_per_split);
+        p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
+        p.nwg = p.nsplit * p.nrowtile;
+        return p;
+    }
     const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
     p.nrowtile = (int)((s.J + SK_MT - 1) / SK_MT);
     int64_t want = 2048 / p.nrowtile;
@@ -156,6 +170,7 @@ SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell) {
     p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
     p.nwg = p.nsplit * p.nrowtile;
     p.kind = 0;
+    p.rb = 0;
     return p;
 }
 
@@ -163,6 +178,9 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                          int64_t col0, uint64_t seed, uint32_t mode, void* partial,
                          double* nrm2_partial, hipStream_t stream) {
     (void)prec;
+    if (p.kind == 1)
+        return launch_sketch_mfma(p.nsplit, p.nrowtile, p.tiles_per_split, p.rb, (const float*)X, s, ell, col0, seed,
+                                  mode, (float*)partial, nrm2_partial, stream);
     dim3 grid(p.nsplit, p.nrowtile);
     if (dt == Dt::F64) {
         hipLaunchKernelGGL((sketch_generic_kernel<double, double>), grid, dim3(256), 0, stream,

@@ -192,8 +192,8 @@ rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
 // Y (J x ell, fp64) = G_(n) Omega[:, col0 : col0 + ell]; optional ||G||^2 into nrm2 (device).
 rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, int64_t col0, uint64_t seed,
                     int mode, double* Y, double* nrm2) {
-    rt::SketchPlan plan = rt::plan_sketch(dt, prec, s, ell);
-    const bool f64acc = plan.kind == 0 && dt == Dt::F64;
+    rt::SketchPlan plan = rt::plan_sketch(dt, prec, s, ell, col0, G);
+    const bool f64acc = dt == Dt::F64;
     void* partial = k.c->ws(plan.partial_elems * (f64acc ? 8 : 4));
     double* np = nrm2 ? k.ws<double>(plan.nwg) : nullptr;
     if (!partial || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
@@ -219,16 +219,30 @@ rt_status do_norm2(Call& k, const void* X, Dt dt, int64_t n, double* out) {
 // B = G x_n Q^T with the fp64 Gram of B reduced into W (ell x ell) when W != NULL.
 rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q, int64_t ldq,
                      int ell, void* B, int64_t ldk, int64_t koff, double* W, double* nrm2) {
-    rt::ProjectPlan plan = rt::plan_project(dx, dq, s, ell);
-    double* gp = W ? k.ws<double>((size_t)plan.nwg * ell * ell) : nullptr;
+    rt::ProjectPlan plan = rt::plan_project(dx, dq, s, ell, G, B, koff);
+    const bool fused_gram = W && plan.kind == 0;
+    double* gp = fused_gram ? k.ws<double>((size_t)plan.nwg * ell * ell) : nullptr;
     double* np = nrm2 ? k.ws<double>(plan.nwg) : nullptr;
-    if ((W && !gp) || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
+    if ((fused_gram && !gp) || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
     {
         const double n = (double)s.L * s.J * s.R, es = dx == Dt::F64 ? 8 : 4;
         TimeScope ts(k.c, 1, n * es + (double)s.L * ell * s.R * es, 2.0 * ell * n, s.J, s.L * s.R, ell);
         RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, B, ldk, koff, gp, np, k.c->stream));
     }
-    if (W) RT_HIP(rt::launch_reduce_partials(gp, true, plan.nwg, (int64_t)ell * ell, W, k.c->stream));
+    if (fused_gram) RT_HIP(rt::launch_reduce_partials(gp, true, plan.nwg, (int64_t)ell * ell, W, k.c->stream));
+    if (W && !fused_gram) {
+        // fp64 Gram of the freshly written B rows koff .. koff + ell
+        const int nwg = rt::plan_gram3(s.L, s.R);
+        double* g3 = k.ws<double>((size_t)nwg * ell * ell);
+        if (!g3) return fail(RT_ENOMEM, "workspace allocation failed");
+        const size_t es = dx == Dt::F64 ? 8 : 4;
+        const char* Bk = (const char*)B + (size_t)koff * s.R * es;
+        {
+            TimeScope ts(k.c, 4, (double)s.L * ell * s.R * es, 2.0 * ell * ell * (double)s.L * s.R, ell, s.L * s.R, ell);
+            RT_HIP(rt::launch_gram3(Bk, dx, s.L, ldk, s.R, ell, g3, nwg, k.c->stream));
+        }
+        RT_HIP(rt::launch_reduce_partials(g3, true, nwg, (int64_t)ell * ell, W, k.c->stream));
+    }
     if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
     return RT_OK;
 }
@@ -265,7 +279,8 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
         void* C = k.c->ws((size_t)sb.L * kb * sb.R * (dt == Dt::F64 ? 8 : 4));
         double* W2 = k.ws<double>((size_t)kb * kb);
         if (!Q1 || !C || !W2) return fail(RT_ENOMEM, "workspace allocation failed");
-        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, kb, nullptr, 0.0, U, Uf, Q1, Dt::F64, lam, kdev, st));
+        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, kb, nullptr, 0.0, U, Uf, Q1, Dt::F64, lam, kdev,
+                                   1e-20, st));
         RT_TRY(do_project(k, dt, Dt::F64, Bcur, sb, ldcur, U, kb, kb, C, kb, 0, W2, nullptr));
         Bcur = C;
         ldcur = kb;
@@ -277,7 +292,8 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
     }
     {
         TimeScope ts(k.c, 3, 0.0, 0.0, Jq, kb, kb);
-        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, r_fixed, Edev, tau2, U, Uf, A_out, dt, lam, kdev, st));
+        RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, r_fixed, Edev, tau2, U, Uf, A_out, dt, lam, kdev,
+                                   dt == Dt::F64 ? 1e-30 : 1e-24, st));
     }
     int kk = r_fixed;
     if (r_fixed < 0) {

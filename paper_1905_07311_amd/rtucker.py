@@ -309,7 +309,7 @@ class Context:
     def timing(self, enable):
         _check(_lib.rt_timing(self.ctx, 1 if enable else 0))
 
-    KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate"}
+    KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate", 4: "gram"}
 
     def timing_log(self):
         """List of dicts, one per timed launch (kind, ms, bytes, flops, rows, cols, ell)."""

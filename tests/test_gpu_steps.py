@@ -139,3 +139,38 @@ def test_projection_and_gram(ctx, shape, dtype):
             B64 = ctx.project(X, n, torch.from_numpy(Qh).cuda())
             ref64 = oracle.ttm(Xh.astype(np.float64), Qh.T, n)
             assert rel(to_np(B64), ref64) < 1e-7
+
+
+# shapes that take the MFMA (float32) kernels: R % 32 == 0 or R == 1 with J % 4 == 0
+# for the sketch; R even for the projection (four columns per lane when R % 4 == 0)
+MFMA_SHAPES = [(40, 96, 64), (300, 32, 64), (600, 32, 32), (8, 1024, 32), (16, 24, 6)]
+
+
+@pytest.mark.parametrize("shape", MFMA_SHAPES)
+def test_sketch_mfma_shapes(ctx, shape):
+    rng = np.random.default_rng(sum(shape) + 1)
+    Xh = rng.standard_normal(shape).astype(np.float32)
+    X = torch.from_numpy(Xh).cuda()
+    for n in range(len(shape)):
+        M = oracle.unfold(Xh.astype(np.float64), n)
+        for ell, col0 in ((min(35, shape[n]), 0), (min(13, shape[n]), 5), (min(64, shape[n]), 0), (1, 3)):
+            Y, nrm = ctx.sketch(X, n, ell, seed=7, col0=col0, want_norm=True)
+            ref = M @ oracle.omega(7, n, M.shape[1], range(col0, col0 + ell))
+            assert rel(to_np(Y), ref) < 2e-6, (shape, n, ell, col0)
+            assert abs(float(nrm.item()) - oracle.fro2(Xh)) <= 1e-10 * oracle.fro2(Xh)
+
+
+@pytest.mark.parametrize("shape", MFMA_SHAPES)
+def test_projection_mfma_shapes(ctx, shape):
+    rng = np.random.default_rng(sum(shape) + 2)
+    Xh = rng.standard_normal(shape).astype(np.float32)
+    X = torch.from_numpy(Xh).cuda()
+    for n in range(len(shape)):
+        for ell in (min(35, shape[n]), min(64, shape[n]), min(6, shape[n])):
+            Qh, _ = np.linalg.qr(rng.standard_normal((shape[n], ell)))
+            Qf = Qh.astype(np.float32)
+            B, W = ctx.project(X, n, torch.from_numpy(Qf).cuda(), want_gram=True)
+            ref = oracle.ttm(Xh.astype(np.float64), Qf.astype(np.float64).T, n)
+            assert rel(to_np(B), ref) < 2e-6, (shape, n, ell)
+            Bn = oracle.unfold(to_np(B), n)
+            assert rel(to_np(W), Bn @ Bn.T) < 1e-12
