@@ -18,11 +18,18 @@
 
 #include "rt_kernels.hpp"
 
+// Phase timestamps for offline tuning builds; empty in the library.
+#ifndef RT_DENSE_TRACE
+#define RT_DENSE_TRACE(slot)
+#define RT_DENSE_TRACE_VAL(slot, v)
+#endif
+
 namespace rt {
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;              // threads of every dense kernel (8 waves)
+constexpr int NRG = NT / LMAX;       // row groups of the Householder column sweeps
 constexpr int LDW = LMAX + 1;
 typedef double Mat[LMAX][LDW];
 
@@ -45,18 +52,19 @@ __device__ double blk_sum(double v, double* red) {
     return r;
 }
 
-// W = Y^T Y (n x n) for Y (J x n, row stride ldy) in global memory.  The upper
-// triangle of 4x4 tiles is spread over the threads, each thread accumulating
-// its tile over every G-th row straight from global memory (L2); the G partial
-// tiles are then summed through LDS.
-__device__ void blk_gram(const double* Y, int64_t J, int n, int64_t ldy, Mat& W, Mat& stage) {
+// W = Y^T Y (n x n) for Y (J x n, row stride ldy) in global memory.  Each thread
+// owns one 4x4 tile of the upper triangle and every G-th row (G a power of two,
+// the G threads of a tile adjacent in one wave); rows are loaded two at a time
+// so that 16 loads are in flight per thread, and the G partial tiles are summed
+// with shuffles.
+__device__ __attribute__((noinline)) void blk_gram(const double* Y, int64_t J, int n, int64_t ldy, Mat& W) {
     const int tid = threadIdx.x;
     const int nt = (n + 3) / 4;
     const int npt = nt * (nt + 1) / 2;
-    const int G = NT / npt > 0 ? NT / npt : 1;
-    double* part = &stage[0][0];                 // G x npt x 16 doubles (<= 4096)
-    if (tid < npt * G) {
-        const int pr = tid % npt, g = tid / npt;
+    int G = 64;
+    while (G > 1 && G * npt > NT) G >>= 1;
+    const int pr = tid / G, g = tid % G;
+    if (pr < npt) {
         int ti = 0, rem = pr;
         while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
         const int tj = ti + rem;
@@ -65,7 +73,26 @@ __device__ void blk_gram(const double* Y, int64_t J, int n, int64_t ldy, Mat& W,
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-        for (int64_t i = g; i < J; i += G) {
+        int64_t i = g;
+        for (; i + G < J; i += 2 * G) {
+            double x[2][4], y[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double* row = Y + (i + u * G) * ldy;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    x[u][a] = (4 * ti + a < n) ? row[4 * ti + a] : 0.0;
+                    y[u][a] = (4 * tj + a < n) ? row[4 * tj + a] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += x[u][a] * y[u][b];
+        }
+        for (; i < J; i += G) {
             const double* row = Y + i * ldy;
             double x[4], y[4];
 #pragma unroll
@@ -81,30 +108,35 @@ __device__ void blk_gram(const double* Y, int64_t J, int n, int64_t ldy, Mat& W,
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) part[(g * npt + pr) * 16 + 4 * a + b] = acc[a][b];
-    }
-    __syncthreads();
-    for (int e = tid; e < npt * 16; e += NT) {
-        const int pr = e / 16, ab = e % 16;
-        int ti = 0, rem = pr;
-        while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
-        const int tj = ti + rem;
-        double sum = 0.0;
-        for (int g = 0; g < G; ++g) sum += part[(g * npt + pr) * 16 + ab];
-        const int r = 4 * ti + ab / 4, c = 4 * tj + ab % 4;
-        if (r < n && c < n) { W[r][c] = sum; W[c][r] = sum; }
+            for (int b = 0; b < 4; ++b) {
+                double v = acc[a][b];
+                for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                acc[a][b] = v;
+            }
+        if (g == 0) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int r = 4 * ti + a, c = 4 * tj + b;
+                    if (r < n && c < n) { W[r][c] = acc[a][b]; W[c][r] = acc[a][b]; }
+                }
+        }
     }
     __syncthreads();
 }
 
 // In-place Cholesky W + shift I = L L^T (lower triangle), one barrier per
 // elimination step: every thread reads the pivot and updates its share of the
-// trailing triangle with W[i][j] -= W[i][k] W[j][k] / W[k][k]; the columns are
-// scaled by 1/sqrt(pivot) at the end.  Returns false on a non-positive or
-// non-finite pivot; *min_ratio = min_k pivot_k / W_kk(original), the squared sine
-// of the angle between column k and the span of the previous columns.
-__device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double* min_ratio, int* flag) {
+// trailing triangle with W[i][j] -= W[i][k] W[j][k] / W[k][k] (a 32 x 16 grid of
+// threads covers the trailing block); the columns are scaled by
+// 1/sqrt(pivot) at the end and invd[k] = 1 / L[k][k] is left for the solves.
+// Returns false on a non-positive or non-finite pivot; *min_ratio = min_k
+// pivot_k / W_kk(original), the squared sine of the angle between column k and
+// the span of the previous columns.
+__device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double* min_ratio, int* flag, double* invd) {
     const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;      // 32 x 16 grid of threads
     __syncthreads();
     if (tid < n) {
         diag0[tid] = W[tid][tid];
@@ -118,21 +150,19 @@ __device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double*
         if (!(piv > 0.0) || !isfinite(piv) || !(diag0[k] + shift > 0.0)) { ok = false; break; }
         mr = fmin(mr, piv / (diag0[k] + shift));
         const double rp = 1.0 / piv;
-        const int m = n - k - 1;
-        for (int e = tid; e < m * m; e += NT) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) W[i][j] -= W[i][k] * W[j][k] * rp;
+        for (int i = k + 1 + ty; i < n; i += NT / 16) {
+            const double wik = W[i][k] * rp;
+            for (int j = k + 1 + tx; j <= i; j += 16) W[i][j] -= wik * W[j][k];
         }
         __syncthreads();
     }
     if (ok) {
-        // L[i][k] = W[i][k] / sqrt(W[k][k]) for i >= k
-        for (int e = tid; e < n * n; e += NT) {
-            const int i = e / n, k = e % n;
-            if (i > k) W[i][k] = W[i][k] / sqrt(W[k][k]);
-        }
+        if (tid < n) invd[tid] = 1.0 / sqrt(W[tid][tid]);
         __syncthreads();
-        if (tid < n) W[tid][tid] = sqrt(W[tid][tid]);
+        for (int i = ty; i < n; i += NT / 16)
+            for (int k = tx; k < i; k += 16) W[i][k] *= invd[k];
+        __syncthreads();
+        if (tid < n) W[tid][tid] = 1.0 / invd[tid];
     }
     __syncthreads();
     if (tid == 0) { flag[0] = ok ? 0 : 1; min_ratio[0] = mr; }
@@ -140,53 +170,32 @@ __device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double*
     return ok;
 }
 
-// Rinv = L^{-T} (upper triangular) from the lower Cholesky factor in W.  Thread j
-// solves L x = e_j by forward substitution with x held in registers (the loops are
-// unrolled over LMAX so every index is static) and writes Rinv[j][:] = x^T.
-__device__ void blk_tri_inv(const Mat& W, int n, Mat& Rinv) {
-    const int tid = threadIdx.x;
-    if (tid < n) {
-        const int j = tid;
-        double x[LMAX];
-#pragma unroll
-        for (int i = 0; i < LMAX; ++i) {
-            double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) s -= W[i][k] * x[k];
-            x[i] = (i < j || i >= n) ? 0.0 : s / W[i][i];
-        }
-#pragma unroll
-        for (int i = 0; i < LMAX; ++i)
-            if (i < n) Rinv[j][i] = x[i];
-    }
-    __syncthreads();
-}
-
-// Yout = Y * M (J x n times n x nout, M in LDS); Yout may alias Y (each thread
-// reads its whole row into registers before writing it).  Rows are spread over
-// the threads; M is read with wave-uniform (broadcast) LDS accesses.
-__device__ void blk_apply_right(const double* Y, int64_t J, int n, int64_t ldy, const Mat& M, int nout,
-                                double* Yout, int64_t ldo) {
+// Y <- Y R^{-1} with R = L^T (L lower, in W; invd = 1 / diag(L)), row by row
+// (right-looking): z_j = y_j / L[j][j], then y_k -= z_j L[k][j] for k > j, with the
+// row held in registers and L read with wave-uniform (broadcast) LDS accesses.
+template <int NR>
+__device__ void blk_trsm_rows(double* Y, int64_t J, int n, int64_t ldy, const Mat& W, const double* invd) {
     const int tid = threadIdx.x;
     for (int64_t i = tid; i < J; i += NT) {
-        double y[LMAX];
+        double y[NR];
 #pragma unroll
-        for (int k = 0; k < LMAX; ++k) y[k] = (k < n) ? Y[i * ldy + k] : 0.0;
-        for (int j0 = 0; j0 < nout; j0 += 8) {
-            double z[8];
+        for (int j = 0; j < NR; ++j) y[j] = (j < n) ? Y[i * ldy + j] : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
+        for (int j = 0; j < NR; ++j) {
+            if (j < n) {
+                const double zj = y[j] * invd[j];
+                y[j] = zj;
 #pragma unroll
-            for (int k = 0; k < LMAX; ++k) {
-                if (k < n) {
-#pragma unroll
-                    for (int jj = 0; jj < 8; ++jj) z[jj] += y[k] * M[k][j0 + jj];
+                for (int k = j + 1; k < NR; ++k) {
+                    y[k] -= zj * W[k][j];
+                    if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the hoisted loads
                 }
             }
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-                if (j0 + jj < nout) Yout[i * ldo + j0 + jj] = z[jj];
+            __builtin_amdgcn_sched_barrier(0);   // keep the column loads of step j local
         }
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (j < n) Y[i * ldy + j] = y[j];
     }
     __syncthreads();
 }
@@ -226,18 +235,18 @@ __device__ void blk_householder_q(double* A, int64_t J, int n, int64_t lda, doub
             double w = 0.0;
             const int j = jj;
             if (j > k && j < n)
-                for (int64_t i = k + rg; i < J; i += NT / LMAX) w += V[i * n + k] * A[i * lda + j];
+                for (int64_t i = k + rg; i < J; i += NRG) w += V[i * n + k] * A[i * lda + j];
             wbuf[rg * LDW + jj] = w;
             __syncthreads();
             if (rg == 0) {
                 double t = 0.0;
-                for (int g = 0; g < NT / LMAX; ++g) t += wbuf[g * LDW + jj];
-                wbuf[4 * LDW + jj] = t * tk;
+                for (int g = 0; g < NRG; ++g) t += wbuf[g * LDW + jj];
+                wbuf[NRG * LDW + jj] = t * tk;
             }
             __syncthreads();
             if (j > k && j < n) {
-                const double f = wbuf[4 * LDW + j];
-                for (int64_t i = k + rg; i < J; i += NT / LMAX) A[i * lda + j] -= f * V[i * n + k];
+                const double f = wbuf[NRG * LDW + j];
+                for (int64_t i = k + rg; i < J; i += NRG) A[i * lda + j] -= f * V[i * n + k];
             }
             __syncthreads();
         }
@@ -255,46 +264,81 @@ __device__ void blk_householder_q(double* A, int64_t J, int n, int64_t lda, doub
         double w = 0.0;
         const int j = jj;
         if (j >= k && j < n)
-            for (int64_t i = k + rg; i < J; i += NT / LMAX) w += V[i * n + k] * A[i * lda + j];
+            for (int64_t i = k + rg; i < J; i += NRG) w += V[i * n + k] * A[i * lda + j];
         wbuf[rg * LDW + jj] = w;
         __syncthreads();
         if (rg == 0) {
             double t = 0.0;
-            for (int g = 0; g < NT / LMAX; ++g) t += wbuf[g * LDW + jj];
-            wbuf[4 * LDW + jj] = t * tk;
+            for (int g = 0; g < NRG; ++g) t += wbuf[g * LDW + jj];
+            wbuf[NRG * LDW + jj] = t * tk;
         }
         __syncthreads();
         if (j >= k && j < n) {
-            const double f = wbuf[4 * LDW + j];
-            for (int64_t i = k + rg; i < J; i += NT / LMAX) A[i * lda + j] -= f * V[i * n + k];
+            const double f = wbuf[NRG * LDW + j];
+            for (int64_t i = k + rg; i < J; i += NRG) A[i * lda + j] -= f * V[i * n + k];
         }
         __syncthreads();
     }
 }
 
-// Jacobi rotation (c, s) that zeroes A[p][q] of the symmetric 2x2 [app apq; apq aqq]
-// under A <- R^T A R with R = [c s; -s c]; t = tan of the smaller rotation angle.
+// Jacobi rotation (c, s) that (nearly) zeroes A[p][q] of the symmetric 2x2
+// [app apq; apq aqq] under A <- R^T A R with R = [c s; -s c].  The tangent t of
+// the smaller angle is formed in single precision (an inexact angle only slows
+// convergence down to the single-precision level per rotation); c = 1/sqrt(1+t^2)
+// and s = t c are formed in double precision, so R is orthogonal to working
+// precision and the similarity is exact up to rounding.
 __device__ __forceinline__ void jrot(double app, double aqq, double apq, double& c, double& s) {
     c = 1.0; s = 0.0;
     if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
         const double d = aqq - app;
-        const double r = sqrt(d * d + 4.0 * apq * apq);
-        const double t = 2.0 * apq / (d >= 0.0 ? d + r : d - r);
+        const double sc = fmax(fabs(d), fabs(apq));
+        const float df = (float)(d / sc), af = (float)(apq / sc);
+        const float r = sqrtf(df * df + 4.0f * af * af);
+        const float tf = 2.0f * af / (df >= 0.0f ? df + r : df - r);
+        const double t = (double)tf;
         c = rsqrt(t * t + 1.0);
         s = t * c;
     }
 }
 
 // Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS).  The round-robin
-// pairing of the m = n + (n odd) indices is tabulated once; every step then costs
-// two barriers: the half = m/2 pair owners compute their rotation from the pivots,
-// and all threads apply R^T A R to the disjoint 2x2 blocks in place and V <- V R.
-// Stops when the off-diagonal sum of squares is <= tol ||A||_F^2 (checked once per
-// sweep).  On exit A's diagonal holds the eigenvalues, V's columns the eigenvectors.
-__device__ void blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, unsigned short* sched, double* red) {
+// pairing of the m = n + (n odd) indices is tabulated once.  A step costs two
+// barriers: in phase A the half = m/2 pair owners (wave 0) compute their
+// rotation while waves 1.. apply the previous step's rotations to V; in phase B
+// a 16 x 32 grid of threads applies R^T A R to the disjoint 2x2 blocks in place
+// (all loads of a thread issued before its stores).  Stops when the off-diagonal
+// sum of squares is <= tol ||A||_F^2 (checked once per sweep).  On exit A's
+// diagonal holds the eigenvalues and V's columns the eigenvectors.
+__device__ __forceinline__ void jacobi_v_update(Mat& V, int n, int half, const unsigned short* sp, const double* cs) {
+    const int tid = threadIdx.x - 64;             // waves 1..7: 448 threads
+    if (tid < 0) return;
+    const int tx = tid & 31, vy = tid >> 5;       // 14 x 32 grid
+    if (tx >= half) return;
+    const int pp = sp[tx] & 255, qq = sp[tx] >> 8;
+    if (qq >= n) return;
+    const double c = cs[2 * tx], sn = cs[2 * tx + 1];
+    double vp[5], vq[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        const int r = vy + 14 * a;
+        if (r < n) { vp[a] = V[r][pp]; vq[a] = V[r][qq]; }
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        const int r = vy + 14 * a;
+        if (r < n) {
+            V[r][pp] = c * vp[a] - sn * vq[a];
+            V[r][qq] = sn * vp[a] + c * vq[a];
+        }
+    }
+}
+
+__device__ int blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, unsigned short* sched, double* red) {
     const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;       // 16 x 32 grid
     const int m = (n % 2) ? n + 1 : n;
     const int half = m / 2;
+    const int CSW = LMAX + 2;                      // two slots of published rotations
     for (int e = tid; e < n * n; e += NT) V[e / n][e % n] = (e / n == e % n) ? 1.0 : 0.0;
     for (int e = tid; e < (m - 1) * half; e += NT) {
         const int step = e / half, t = e % half;
@@ -307,53 +351,72 @@ __device__ void blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, un
     double tot = 0.0;
     for (int e = tid; e < n * n; e += NT) tot += A[e / n][e % n] * A[e / n][e % n];
     tot = blk_sum(tot, red);
-    if (tot == 0.0 || n < 2) return;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        for (int step = 0; step < m - 1; ++step) {
+    if (tot == 0.0 || n < 2) return 0;
+    int sweep = 0, gstep = 0, prev = -1;
+    for (; sweep < 40; ++sweep) {
+        for (int step = 0; step < m - 1; ++step, ++gstep) {
             const unsigned short* sp = sched + step * half;
+            double* csn = cs + (gstep & 1) * CSW;
+            // phase A: rotations of this step (wave 0) | V update of the previous step
             if (tid < half) {
                 const int p = sp[tid] & 255, q = sp[tid] >> 8;
                 double c = 1.0, sn = 0.0;
                 if (q < n) jrot(A[p][p], A[q][q], A[p][q], c, sn);
-                cs[2 * tid] = c;
-                cs[2 * tid + 1] = sn;
+                csn[2 * tid] = c;
+                csn[2 * tid + 1] = sn;
             }
+            if (prev >= 0) jacobi_v_update(V, n, half, sched + prev * half, cs + ((gstep - 1) & 1) * CSW);
             __syncthreads();
-            for (int e = tid; e < half * half; e += NT) {
-                const int bi = e / half, bj = e - bi * half;
-                const int p = sp[bi] & 255, q = sp[bi] >> 8;
+            // phase B: A <- R^T A R on the 2x2 blocks (rows bi, columns bj = tx)
+            if (tx < half) {
+                const int bj = tx;
                 const int pp = sp[bj] & 255, qq = sp[bj] >> 8;
-                const double ci = cs[2 * bi], si = cs[2 * bi + 1];
-                const double cj = cs[2 * bj], sj = cs[2 * bj + 1];
-                const bool rq = q < n, cq = qq < n;
-                const double a = A[p][pp];
-                const double b = cq ? A[p][qq] : 0.0;
-                const double c = rq ? A[q][pp] : 0.0;
-                const double d = (rq && cq) ? A[q][qq] : 0.0;
-                const double a1 = ci * a - si * c, b1 = ci * b - si * d;
-                const double c1 = si * a + ci * c, d1 = si * b + ci * d;
-                A[p][pp] = a1 * cj - b1 * sj;
-                if (cq) A[p][qq] = a1 * sj + b1 * cj;
-                if (rq) A[q][pp] = c1 * cj - d1 * sj;
-                if (rq && cq) A[q][qq] = c1 * sj + d1 * cj;
+                const double cj = csn[2 * bj], sj = csn[2 * bj + 1];
+                const bool cq = qq < n;
+                double av[2], bv[2], cv[2], dv[2], ci[2], si[2];
+                int pr[2], qr[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int bi = ty + 16 * u;
+                    if (bi < half) {
+                        pr[u] = sp[bi] & 255;
+                        qr[u] = sp[bi] >> 8;
+                        ci[u] = csn[2 * bi];
+                        si[u] = csn[2 * bi + 1];
+                        const bool rq = qr[u] < n;
+                        av[u] = A[pr[u]][pp];
+                        bv[u] = cq ? A[pr[u]][qq] : 0.0;
+                        cv[u] = rq ? A[qr[u]][pp] : 0.0;
+                        dv[u] = (rq && cq) ? A[qr[u]][qq] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int bi = ty + 16 * u;
+                    if (bi < half) {
+                        const bool rq = qr[u] < n;
+                        const double a1 = ci[u] * av[u] - si[u] * cv[u], b1 = ci[u] * bv[u] - si[u] * dv[u];
+                        const double c1 = si[u] * av[u] + ci[u] * cv[u], d1 = si[u] * bv[u] + ci[u] * dv[u];
+                        A[pr[u]][pp] = a1 * cj - b1 * sj;
+                        if (cq) A[pr[u]][qq] = a1 * sj + b1 * cj;
+                        if (rq) A[qr[u]][pp] = c1 * cj - d1 * sj;
+                        if (rq && cq) A[qr[u]][qq] = c1 * sj + d1 * cj;
+                    }
+                }
             }
-            for (int e = tid; e < n * half; e += NT) {
-                const int r = e / half, bj = e - r * half;
-                const int p = sp[bj] & 255, q = sp[bj] >> 8;
-                if (q >= n) continue;
-                const double c = cs[2 * bj], sn = cs[2 * bj + 1];
-                const double vp = V[r][p], vq = V[r][q];
-                V[r][p] = c * vp - sn * vq;
-                V[r][q] = sn * vp + c * vq;
-            }
+            prev = step;
             __syncthreads();
         }
         double off = 0.0;
-        for (int e = tid; e < n * n; e += NT)
-            if (e / n != e % n) off += A[e / n][e % n] * A[e / n][e % n];
+        for (int i = ty; i < n; i += 16)
+            for (int j = tx; j < n; j += 32)
+                if (i != j) off += A[i][j] * A[i][j];
         off = blk_sum(off, red);
-        if (off <= tol * tot) break;
+        if (off <= tol * tot) { ++sweep; break; }
     }
+    if (prev >= 0) jacobi_v_update(V, n, half, sched + prev * half, cs + ((gstep - 1) & 1) * CSW);
+    __syncthreads();
+    return sweep;
 }
 
 // Rank positions: perm[t] = index of the t-th largest diagonal entry (ties by index).
@@ -377,12 +440,14 @@ struct DenseShared {
     Mat M2;
     Mat stage;
     double red[NT];
-    double wbuf[5 * LDW];
+    double wbuf[(NRG + 1) * LDW];
     double diag0[LMAX];
+    double invd[LMAX];
     double tau[LMAX];
     double v0[LMAX];
     double rdiag[LMAX];
-    double cs[LMAX + 2];
+    double cs[2 * (LMAX + 2)];
+    double sgn[8];
     unsigned short sched[LMAX * LMAX / 2];
     double lam[LMAX];
     double minr[1];
@@ -391,11 +456,12 @@ struct DenseShared {
     int flag[4];
 };
 
+template <int NR>
 __device__ void cholqr_apply(double* Y, int64_t J, int ell, DenseShared& S) {
-    blk_tri_inv(S.W, ell, S.M2);
-    blk_apply_right(Y, J, ell, ell, S.M2, ell, Y, ell);
+    blk_trsm_rows<NR>(Y, J, ell, ell, S.W, S.invd);
 }
 
+template <int NR>
 __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_t J, int ell, float* __restrict__ Qf,
                                                   double* __restrict__ V, double accept_ratio,
                                                   uint32_t* __restrict__ status) {
@@ -406,43 +472,58 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
     // keep a copy of Y for the Householder fallback
     double* Ycopy = V + J * (int64_t)ell;
     double nonfinite = 0.0, fro = 0.0;
-    for (int64_t e = tid; e < J * ell; e += NT) {
-        const double y = Y[e];
-        Ycopy[e] = y;
-        if (!isfinite(y)) nonfinite += 1.0;
-        else fro += y * y;
+    const int64_t tot = J * (int64_t)ell;
+    for (int64_t e0 = tid; e0 < tot; e0 += 8 * NT) {
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[u] = (e0 + u * NT < tot) ? Y[e0 + u * NT] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (e0 + u * NT < tot) {
+                Ycopy[e0 + u * NT] = y[u];
+                if (!isfinite(y[u])) nonfinite += 1.0;
+                else fro += y[u] * y[u];
+            }
+        }
     }
     nonfinite = blk_sum(nonfinite, S.red);
     fro = blk_sum(fro, S.red);
+    RT_DENSE_TRACE(1);
     bool ok = nonfinite == 0.0 && fro > 0.0;
     if (nonfinite != 0.0) st |= 4u;
     if (ok) {
         // CholeskyQR2: accepted when the first factorisation keeps every pivot
         // ratio >= accept_ratio (kappa(Y) ~ 1/sqrt(ratio)) and the second one is
         // nearly orthogonal already (ratio >= 1/2).
-        blk_gram(Y, J, ell, ell, S.W, S.stage);
-        ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= accept_ratio;
+        blk_gram(Y, J, ell, ell, S.W);
+        RT_DENSE_TRACE(2);
+        ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
+        RT_DENSE_TRACE(3);
         if (!ok) {
             // shifted CholeskyQR3 (Fukaya et al. 2020): factor Y^T Y + s I with
             // s = 11 (J ell + ell (ell + 1)) u ||Y||_F^2, which bounds kappa of
             // Y R^-1 by O(u^-1/2), then CholeskyQR2 on the result.
-            blk_gram(Y, J, ell, ell, S.W, S.stage);
+            blk_gram(Y, J, ell, ell, S.W);
             const double shift = 11.0 * ((double)J * ell + (double)ell * (ell + 1)) * 0x1p-53 * fro;
-            ok = blk_cholesky(S.W, ell, shift, S.diag0, S.minr, S.flag);
+            ok = blk_cholesky(S.W, ell, shift, S.diag0, S.minr, S.flag, S.invd);
             if (ok) {
-                cholqr_apply(Y, J, ell, S);
-                blk_gram(Y, J, ell, ell, S.W, S.stage);
-                ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= accept_ratio;
+                cholqr_apply<NR>(Y, J, ell, S);
+                blk_gram(Y, J, ell, ell, S.W);
+                ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
                 // a direction of Y far below sqrt(shift) leaves a pivot ratio near u:
                 // Y was numerically rank deficient and Q holds padding directions
                 if (ok && S.minr[0] < 1e-6) st |= 1u;
             }
         }
         if (ok) {
-            cholqr_apply(Y, J, ell, S);
-            blk_gram(Y, J, ell, ell, S.W, S.stage);
-            ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag) && S.minr[0] >= 0.5;
-            if (ok) cholqr_apply(Y, J, ell, S);
+            cholqr_apply<NR>(Y, J, ell, S);
+            RT_DENSE_TRACE(4);
+            blk_gram(Y, J, ell, ell, S.W);
+            RT_DENSE_TRACE(5);
+            ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= 0.5;
+            RT_DENSE_TRACE(6);
+            if (ok) cholqr_apply<NR>(Y, J, ell, S);
+            RT_DENSE_TRACE(7);
         }
     }
     if (!ok) {
@@ -467,6 +548,7 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
 
 // Truncation: eigen-decomposition of the Gram W (ell x ell) of B, rank choice,
 // U = leading eigenvectors, A = Q U with sign fix (largest |.| entry positive).
+template <int NR>
 __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__ W, int ell,
                                                       const double* __restrict__ Q, int64_t ldq, int64_t J,
                                                       int r_fixed,
@@ -479,23 +561,26 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
     const int tid = threadIdx.x;
     for (int e = tid; e < ell * ell; e += NT) S.W[e / ell][e % ell] = W[e];
     __syncthreads();
-    blk_jacobi_eig(S.W, ell, S.M2, jtol, S.cs, S.sched, S.red);
+    RT_DENSE_TRACE(1);
+    const int sweeps = blk_jacobi_eig(S.W, ell, S.M2, jtol, S.cs, S.sched, S.red);
+    (void)sweeps;
+    RT_DENSE_TRACE_VAL(9, sweeps);
+    RT_DENSE_TRACE(2);
     blk_sort_desc(S.W, ell, S.perm, S.lam);
     if (tid == 0) {
         int k;
         if (r_fixed >= 0) {
             k = r_fixed < ell ? r_fixed : ell;
         } else {
+            // smallest k with max(E, 0) + sum_{t >= k} max(lam_t, 0) <= tau2
             const double E = E_dev ? fmax(E_dev[0], 0.0) : 0.0;
-            // tail[k] = sum_{t >= k} max(lam_t, 0)
             double tail = 0.0;
+            for (int t = ell - 1; t >= 0; --t) tail += fmax(S.lam[t], 0.0);
             k = ell;
-            // smallest k with E + tail[k] <= tau2: scan from the end
-            double tails[LMAX + 1];
-            tails[ell] = 0.0;
-            for (int t = ell - 1; t >= 0; --t) { tail += fmax(S.lam[t], 0.0); tails[t] = tail; }
-            for (int kk = 0; kk <= ell; ++kk)
-                if (E + tails[kk] <= tau2) { k = kk; break; }
+            for (int kk = 0; kk <= ell; ++kk) {
+                if (E + tail <= tau2) { k = kk; break; }
+                if (kk < ell) tail -= fmax(S.lam[kk], 0.0);
+            }
         }
         S.flag[2] = k;
     }
@@ -503,6 +588,7 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
     const int k = S.flag[2];
     if (lam_out && tid < ell) lam_out[tid] = S.lam[tid];
     if (kout && tid == 0) kout[0] = k;
+    RT_DENSE_TRACE(3);
     // U columns = eigenvectors in sorted order (ell x k, in S.W)
     for (int e = tid; e < ell * k; e += NT) {
         const int i = e / k, j = e % k;
@@ -515,41 +601,45 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
     __syncthreads();
     // A = Q U, eight columns at a time; each column is then flipped so that its
     // entry of largest magnitude (lowest row on ties) is positive, and U with it.
+    // The rows of Q owned by a thread stay in registers when J <= NT; a column
+    // chunk is formed once to find the signs and again to store it.
     double* A64 = (double*)Aout;
     float* A32 = (float*)Aout;
     const int lane = tid & 63, wave = tid >> 6;
+    const bool qreg = J <= NT;
+    double q[NR];
+    if (qreg) {
+#pragma unroll
+        for (int t = 0; t < NR; ++t) q[t] = (tid < J && t < ell) ? Q[(int64_t)tid * ldq + t] : 0.0;
+    }
     for (int j0 = 0; j0 < k; j0 += 8) {
         double best[8], bval[8];
         int64_t bidx[8];
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) { best[jj] = -1.0; bval[jj] = 0.0; bidx[jj] = INT64_MAX; }
         for (int64_t i = tid; i < J; i += NT) {
-            double q[LMAX];
+            if (!qreg) {
 #pragma unroll
-            for (int t = 0; t < LMAX; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
+                for (int t = 0; t < NR; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
+            }
             double z[8];
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
 #pragma unroll
-            for (int t = 0; t < LMAX; ++t) {
+            for (int t = 0; t < NR; ++t) {
                 if (t < ell) {
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) z[jj] += q[t] * S.W[t][j0 + jj];
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
-                if (j0 + jj < k) {
-                    const double a = fabs(z[jj]);
-                    if (a > best[jj]) { best[jj] = a; bval[jj] = z[jj]; bidx[jj] = i; }
-                    if (Aout) {
-                        if (a_is_f64) A64[i * k + j0 + jj] = z[jj];
-                        else A32[i * k + j0 + jj] = (float)z[jj];
-                    }
-                }
+                const double a = fabs(z[jj]);
+                if (j0 + jj < k && a > best[jj]) { best[jj] = a; bval[jj] = z[jj]; bidx[jj] = i; }
             }
         }
-        // workgroup argmax per column: wave shuffles, then the four waves in LDS
+        // workgroup argmax per column: wave shuffles, then the waves through LDS
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
             double b = best[jj], v = bval[jj];
@@ -574,23 +664,42 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
                 const double ob = S.stage[0][w * 8 + tid], ov = S.stage[1][w * 8 + tid], oi = S.stage[2][w * 8 + tid];
                 if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
             }
-            S.cs[tid] = (v < 0.0) ? -1.0 : 1.0;
+            S.sgn[tid] = (v < 0.0) ? -1.0 : 1.0;
         }
         __syncthreads();
-        // flip the columns with a negative leading entry
+        double sg[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) sg[jj] = S.sgn[jj];
         if (Aout) {
-            for (int64_t e = tid; e < J * 8; e += NT) {
-                const int64_t i = e / 8;
-                const int jj = (int)(e % 8);
-                if (j0 + jj < k && S.cs[jj] < 0.0) {
-                    if (a_is_f64) A64[i * k + j0 + jj] = -A64[i * k + j0 + jj];
-                    else A32[i * k + j0 + jj] = -A32[i * k + j0 + jj];
+            for (int64_t i = tid; i < J; i += NT) {
+                if (!qreg) {
+#pragma unroll
+                    for (int t = 0; t < NR; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
+                }
+                double z[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
+#pragma unroll
+                for (int t = 0; t < NR; ++t) {
+                    if (t < ell) {
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) z[jj] += q[t] * S.W[t][j0 + jj];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    if (j0 + jj < k) {
+                        if (a_is_f64) A64[i * k + j0 + jj] = z[jj] * sg[jj];
+                        else A32[i * k + j0 + jj] = (float)(z[jj] * sg[jj]);
+                    }
                 }
             }
         }
+        __syncthreads();
         if (tid < ell)
             for (int jj = 0; jj < 8; ++jj)
-                if (j0 + jj < k) S.W[tid][j0 + jj] *= S.cs[jj];
+                if (j0 + jj < k) S.W[tid][j0 + jj] *= sg[jj];
         __syncthreads();
     }
     for (int e = tid; e < ell * k; e += NT) {
@@ -713,17 +822,35 @@ __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, 
 
 hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_ratio, uint32_t* status,
                        double* scratch, hipStream_t stream) {
-    hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, ell, Qf, scratch, accept_ratio,
-                       status);
+#define RT_ORTH(NRV) \
+    hipLaunchKernelGGL(orth_kernel<NRV>, dim3(1), dim3(NT), 0, stream, Y, J, ell, Qf, scratch, accept_ratio, status)
+    if (ell <= 8) RT_ORTH(8);
+    else if (ell <= 16) RT_ORTH(16);
+    else if (ell <= 24) RT_ORTH(24);
+    else if (ell <= 32) RT_ORTH(32);
+    else if (ell <= 40) RT_ORTH(40);
+    else if (ell <= 48) RT_ORTH(48);
+    else if (ell <= 56) RT_ORTH(56);
+    else RT_ORTH(64);
+#undef RT_ORTH
     return hipGetLastError();
 }
 
 hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da, double* lam,
                            int* kout, double jtol, hipStream_t stream) {
-    hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(NT), 0, stream, W, ell, Q, ldq, J, r_fixed, E_dev,
-                       tau2,
-                       U, Uf, A, da == Dt::F64 ? 1 : 0, lam, kout, jtol);
+#define RT_TRUNC(NRV)                                                                                        \
+    hipLaunchKernelGGL(truncate_kernel<NRV>, dim3(1), dim3(NT), 0, stream, W, ell, Q, ldq, J, r_fixed, E_dev, tau2, \
+                       U, Uf, A, da == Dt::F64 ? 1 : 0, lam, kout, jtol)
+    if (ell <= 8) RT_TRUNC(8);
+    else if (ell <= 16) RT_TRUNC(16);
+    else if (ell <= 24) RT_TRUNC(24);
+    else if (ell <= 32) RT_TRUNC(32);
+    else if (ell <= 40) RT_TRUNC(40);
+    else if (ell <= 48) RT_TRUNC(48);
+    else if (ell <= 56) RT_TRUNC(56);
+    else RT_TRUNC(64);
+#undef RT_TRUNC
     return hipGetLastError();
 }
 

@@ -36,8 +36,10 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
 
 // out[e] = sum_{s < nparts} in[s * n + e] (in float or double, summed in fp64 in
 // the order s = 0, 1, ...).  out is double.
+// tmp: ceil(nparts / 32) * n doubles of scratch (needed when nparts > 32)
 hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
-                                  double* out, hipStream_t stream);
+                                  double* out, hipStream_t stream, double* tmp);
+inline size_t reduce_partials_tmp(int64_t nparts, int64_t n) { return nparts > 32 ? (size_t)((nparts + 31) / 32) * n : 0; }
 // out[0] = sum of `n` doubles (single workgroup, fixed order of a tree)
 hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream);
 
@@ -59,7 +61,7 @@ hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_r
 // If gram_partial != nullptr, each workgroup adds the fp64 Gram sum_c B[:, c] B[:, c]^T
 // of its columns to gram_partial[wg][ell][ell]; if nrm2_partial != nullptr, sum B^2
 // (fp64) per workgroup.  `nwg_out` receives the workgroup count.
-struct ProjectPlan { int nwg; int64_t ntiles; int kind; };
+struct ProjectPlan { int nwg; int64_t ntiles; int kind; };  // kind 0 generic, 1 MFMA strips, 2 MFMA rows (R == 1)
 ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 // ldj: stride of the mode index in G (= s.J for a plain tensor; larger when only
 // the first s.J rows of a wider buffer are contracted).  B is written at
@@ -105,6 +107,10 @@ bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t ko
 int plan_project_mfma(Shape3 s, int ell);
 hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
                                float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
+// last mode (R == 1): B (L x ldk, columns koff..) = G (L x J, row stride ldj) Q
+int plan_project_r1_mfma(Shape3 s);
+hipError_t launch_project_r1_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
+                                  float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
 
 // ---- misc ------------------------------------------------------------------------------
 // sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)

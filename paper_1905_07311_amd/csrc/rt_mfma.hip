@@ -347,6 +347,100 @@ hipError_t launch_pm(int nwg, const float* G, Shape3 s, int64_t ldj, const float
     return hipGetLastError();
 }
 
+// Projection of the last mode (R == 1): B[l, k] = sum_i G[l, i] Q[i, k], a plain
+// row-major (L x J) times (J x ell) product.  Each wave owns 64 rows l (sixteen
+// MFMA blocks of four rows); every lane streams its own row of G, four
+// consecutive i at a time (one 16-byte load when J % 4 == 0), and Q^T sits in
+// LDS in chunks of QCH rows.
+template <int NQ>
+__global__ __launch_bounds__(256) void project_r1_mfma_kernel(const float* __restrict__ G, int64_t L, int64_t J,
+                                                              int64_t ldj, const float* __restrict__ Q, int64_t ldq,
+                                                              int ell, float* __restrict__ B, int64_t ldk, int64_t koff,
+                                                              double* __restrict__ nrm2_partial) {
+    constexpr int QW = (NQ + 3) / 4 * 4;
+    __shared__ __align__(16) float qs[PM_QCH * 4 * QW];
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int blk = lane >> 2, t = lane & 3;
+    const int64_t l = (int64_t)blockIdx.x * 256 + wave * 64 + lane;     // the row this lane streams
+    const bool lvalid = l < L;
+    const float* grow = G + (lvalid ? l : 0) * ldj;
+    const bool vec4 = (J % 4 == 0) && (ldj % 4 == 0) && ((((uintptr_t)G) & 15) == 0);
+    f4 acc[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t i0 = 0; i0 < J; i0 += PM_QCH) {
+        const int rows = (int)((J - i0) < PM_QCH ? (J - i0) : PM_QCH);
+        __syncthreads();
+        for (int e = tid; e < PM_QCH * 4 * QW; e += 256) {
+            const int ii = e / (4 * QW), tt = (e / QW) & 3, j = e % QW;
+            const int k = 4 * j + tt;
+            qs[e] = (ii < rows && k < ell) ? Q[(i0 + ii) * ldq + k] : 0.f;
+        }
+        __syncthreads();
+        for (int ii = 0; ii < rows; ii += 4) {
+            // this lane's four G values G[l, i0+ii .. +3]; the MFMA block of lane
+            // (blk, t) uses A = G[4 blk + v, i] via the lane that owns row 4 blk + v
+            f4 x = f4{0.f, 0.f, 0.f, 0.f};
+            if (lvalid) {
+                if (vec4 && ii + 3 < rows) x = *reinterpret_cast<const f4*>(grow + i0 + ii);
+                else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x[u] = (ii + u < rows) ? grow[i0 + ii + u] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (ii + u < rows) {
+                    const float* qrow = &qs[((ii + u) * 4 + t) * QW];
+                    float bv[QW];
+#pragma unroll
+                    for (int j4 = 0; j4 < QW; j4 += 4) {
+                        const f4 q = *reinterpret_cast<const f4*>(qrow + j4);
+                        bv[j4] = q.x; bv[j4 + 1] = q.y; bv[j4 + 2] = q.z; bv[j4 + 3] = q.w;
+                    }
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) acc[j] = mfma4(x[u], bv[j], acc[j]);
+                }
+            }
+        }
+    }
+    // lane (blk, t) holds B[4 blk + v][4 j + t] in register v of acc[j]
+    double nrm = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t lr = (int64_t)blockIdx.x * 256 + wave * 64 + 4 * blk + v;
+        if (lr < L) {
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                const int k = 4 * j + t;
+                if (k < ell) {
+                    const float o = acc[j][v];
+                    B[lr * ldk + koff + k] = o;
+                    nrm += (double)o * o;
+                }
+            }
+        }
+    }
+    if (nrm2_partial) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+        __syncthreads();
+        if (lane == 0) red[wave] = nrm;
+        __syncthreads();
+        if (tid == 0) nrm2_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+template <int NQ>
+hipError_t launch_pr1(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell, float* B,
+                      int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream) {
+    hipLaunchKernelGGL((project_r1_mfma_kernel<NQ>), dim3(nwg), dim3(256), 0, stream, G, s.L, s.J, ldj, Q, ldq, ell, B,
+                       ldk, koff, nrm2);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X) {
@@ -420,6 +514,24 @@ hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, c
     if (nq <= 12) RT_PM(12, 2);
     RT_PM(16, 2);
 #undef RT_PM
+}
+
+int plan_project_r1_mfma(Shape3 s) {
+    int64_t g = (s.L + 255) / 256;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_project_r1_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
+                                  float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream) {
+    const int nq = (ell + 3) / 4;
+#define RT_PR1(NQV) return launch_pr1<NQV>(nwg, G, s, ldj, Q, ldq, ell, B, ldk, koff, nrm2, stream)
+    if (nq <= 2) RT_PR1(2);
+    if (nq <= 4) RT_PR1(4);
+    if (nq <= 7) RT_PR1(7);
+    if (nq <= 9) RT_PR1(9);
+    if (nq <= 12) RT_PR1(12);
+    RT_PR1(16);
+#undef RT_PR1
 }
 
 }  // namespace rt

@@ -187,6 +187,12 @@ ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const v
         p.ntiles = 0;
         return p;
     }
+    if (dx == Dt::F32 && dq == Dt::F32 && s.R == 1 && ell <= LMAX) {
+        p.kind = 2;
+        p.nwg = plan_project_r1_mfma(s);
+        p.ntiles = 0;
+        return p;
+    }
     const int64_t K = s.L * s.R;
     p.ntiles = (K + PJ_NC - 1) / PJ_NC;
     p.nwg = (int)(p.ntiles < 1024 ? p.ntiles : 1024);
@@ -198,8 +204,11 @@ ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const v
 hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q,
                           int64_t ldq, int ell, void* B, int64_t ldk, int64_t koff, double* gram_partial,
                           double* nrm2_partial, hipStream_t stream) {
-    if (p.kind == 1) {
-        if (gram_partial) return hipErrorInvalidValue;   // the MFMA variant has no fused Gram
+    if (p.kind == 1 || p.kind == 2) {
+        if (gram_partial) return hipErrorInvalidValue;   // the MFMA variants have no fused Gram
+        if (p.kind == 2)
+            return launch_project_r1_mfma(p.nwg, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk,
+                                          koff, nrm2_partial, stream);
         return launch_project_mfma(p.nwg, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk, koff,
                                    nrm2_partial, stream);
     }

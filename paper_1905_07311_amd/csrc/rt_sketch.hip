@@ -108,21 +108,31 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_partials_kernel_f32(const float* __restrict__ in, int64_t nparts,
-                                                                  int64_t n, double* __restrict__ out) {
+// out[chunk][e] = sum of in[p][e] over p in [chunk * PC, min(nparts, (chunk+1) * PC)),
+// summed in fp64 in a fixed order (eight independent running sums combined
+// pairwise), so the result does not depend on the launch shape.
+constexpr int RP_PC = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const T* __restrict__ in, int64_t nparts, int64_t n,
+                                                              double* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.y * RP_PC;
+    const int64_t p1 = p0 + RP_PC < nparts ? p0 + RP_PC : nparts;
     if (e >= n) return;
-    double s = 0.0;
-    for (int64_t p = 0; p < nparts; ++p) s += (double)in[p * n + e];
-    out[e] = s;
-}
-__global__ __launch_bounds__(256) void reduce_partials_kernel_f64(const double* __restrict__ in, int64_t nparts,
-                                                                  int64_t n, double* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    double s = 0.0;
-    for (int64_t p = 0; p < nparts; ++p) s += in[p * n + e];
-    out[e] = s;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int64_t p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = in[(p + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += (double)v[u];
+    }
+    for (; p < p1; ++p) a[0] += (double)in[p * n + e];
+    out[(int64_t)blockIdx.y * n + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 __global__ __launch_bounds__(256) void sum_scalar_kernel(const double* __restrict__ in, int64_t n,
@@ -195,13 +205,30 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
 }
 
 hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
-                                  double* out, hipStream_t stream) {
+                                  double* out, hipStream_t stream, double* tmp) {
     if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + 255) / 256));
+    const unsigned ex = (unsigned)((n + 255) / 256);
+    const int64_t nchunk = (nparts + RP_PC - 1) / RP_PC;
+    if (nchunk <= 1) {
+        // one pass over all parts (fixed order)
+        if (in_is_f64)
+            hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)in,
+                               nparts, n, out);
+        else
+            hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, 1), dim3(256), 0, stream, (const float*)in,
+                               nparts, n, out);
+        return hipGetLastError();
+    }
+    if (tmp == nullptr) return hipErrorInvalidValue;
+    // two passes: chunks of RP_PC parts, then the chunk sums
     if (in_is_f64)
-        hipLaunchKernelGGL(reduce_partials_kernel_f64, grid, dim3(256), 0, stream, (const double*)in, nparts, n, out);
+        hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
+                           (const double*)in, nparts, n, tmp);
     else
-        hipLaunchKernelGGL(reduce_partials_kernel_f32, grid, dim3(256), 0, stream, (const float*)in, nparts, n, out);
+        hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
+                           (const float*)in, nparts, n, tmp);
+    hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)tmp, nchunk,
+                       n, out);
     return hipGetLastError();
 }
 

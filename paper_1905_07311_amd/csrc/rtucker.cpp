@@ -202,7 +202,9 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
         TimeScope ts(k.c, 0, n * (dt == Dt::F64 ? 8 : 4), 2.0 * ell * n, s.J, s.L * s.R, ell);
         RT_HIP(rt::launch_sketch(plan, dt, prec, G, s, ell, col0, seed, (uint32_t)mode, partial, np, k.c->stream));
     }
-    RT_HIP(rt::launch_reduce_partials(partial, f64acc, plan.nsplit, s.J * ell, Y, k.c->stream));
+    double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
+    if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(rt::launch_reduce_partials(partial, f64acc, plan.nsplit, s.J * ell, Y, k.c->stream, rtmp));
     if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
     return RT_OK;
 }
@@ -229,7 +231,11 @@ rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj
         TimeScope ts(k.c, 1, n * es + (double)s.L * ell * s.R * es, 2.0 * ell * n, s.J, s.L * s.R, ell);
         RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, B, ldk, koff, gp, np, k.c->stream));
     }
-    if (fused_gram) RT_HIP(rt::launch_reduce_partials(gp, true, plan.nwg, (int64_t)ell * ell, W, k.c->stream));
+    if (fused_gram) {
+        double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nwg, (int64_t)ell * ell) + 1);
+        if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_reduce_partials(gp, true, plan.nwg, (int64_t)ell * ell, W, k.c->stream, rtmp));
+    }
     if (W && !fused_gram) {
         // fp64 Gram of the freshly written B rows koff .. koff + ell
         const int nwg = rt::plan_gram3(s.L, s.R);
@@ -241,7 +247,9 @@ rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj
             TimeScope ts(k.c, 4, (double)s.L * ell * s.R * es, 2.0 * ell * ell * (double)s.L * s.R, ell, s.L * s.R, ell);
             RT_HIP(rt::launch_gram3(Bk, dx, s.L, ldk, s.R, ell, g3, nwg, k.c->stream));
         }
-        RT_HIP(rt::launch_reduce_partials(g3, true, nwg, (int64_t)ell * ell, W, k.c->stream));
+        double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)ell * ell) + 1);
+        if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_reduce_partials(g3, true, nwg, (int64_t)ell * ell, W, k.c->stream, rtmp));
     }
     if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
     return RT_OK;
@@ -704,7 +712,9 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
             double* gp = k.ws<double>((size_t)nwg * kcols * kcols);
             if (!gp) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
             RT_HIP(rt::launch_gram3(Bbuf, dt, s.L, cap, s.R, kcols, gp, nwg, st));
-            RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)kcols * kcols, W, st));
+            double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)kcols * kcols) + 1);
+            if (!rtmp) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
+            RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)kcols * kcols, W, st, rtmp));
             k.c->cur_J = J;
             k.c->last_nrm2 = tmp;
             rt_status rs = do_truncate(k, dt, Bbuf, Shape3{s.L, kcols, s.R}, cap, W, Qall, cap, -1, Edev, tau2,
