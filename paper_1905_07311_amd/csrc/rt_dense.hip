@@ -134,9 +134,10 @@ __device__ __attribute__((noinline)) void blk_gram(const double* Y, int64_t J, i
 // Returns false on a non-positive or non-finite pivot; *min_ratio = min_k
 // pivot_k / W_kk(original), the squared sine of the angle between column k and
 // the span of the previous columns.
+template <int NTH = NT>
 __device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double* min_ratio, int* flag, double* invd) {
     const int tid = threadIdx.x;
-    const int ty = tid >> 4, tx = tid & 15;      // 32 x 16 grid of threads
+    const int ty = tid >> 4, tx = tid & 15;      // (NTH / 16) x 16 grid of threads
     __syncthreads();
     if (tid < n) {
         diag0[tid] = W[tid][tid];
@@ -150,7 +151,7 @@ __device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double*
         if (!(piv > 0.0) || !isfinite(piv) || !(diag0[k] + shift > 0.0)) { ok = false; break; }
         mr = fmin(mr, piv / (diag0[k] + shift));
         const double rp = 1.0 / piv;
-        for (int i = k + 1 + ty; i < n; i += NT / 16) {
+        for (int i = k + 1 + ty; i < n; i += NTH / 16) {
             const double wik = W[i][k] * rp;
             for (int j = k + 1 + tx; j <= i; j += 16) W[i][j] -= wik * W[j][k];
         }
@@ -159,7 +160,7 @@ __device__ bool blk_cholesky(Mat& W, int n, double shift, double* diag0, double*
     if (ok) {
         if (tid < n) invd[tid] = 1.0 / sqrt(W[tid][tid]);
         __syncthreads();
-        for (int i = ty; i < n; i += NT / 16)
+        for (int i = ty; i < n; i += NTH / 16)
             for (int k = tx; k < i; k += 16) W[i][k] *= invd[k];
         __syncthreads();
         if (tid < n) W[tid][tid] = 1.0 / invd[tid];
@@ -281,25 +282,274 @@ __device__ void blk_householder_q(double* A, int64_t J, int n, int64_t lda, doub
     }
 }
 
-// Jacobi rotation (c, s) that (nearly) zeroes A[p][q] of the symmetric 2x2
-// [app apq; apq aqq] under A <- R^T A R with R = [c s; -s c].  The tangent t of
-// the smaller angle is formed in single precision (an inexact angle only slows
-// convergence down to the single-precision level per rotation); c = 1/sqrt(1+t^2)
-// and s = t c are formed in double precision, so R is orthogonal to working
-// precision and the similarity is exact up to rounding.
+// Jacobi rotation (c, s) for the 2 x 2 symmetric block [[app, apq], [apq, aqq]]
+// under A <- R^T A R with R = [c s; -s c].  Rotations with apq^2 <= 1e-36 |app aqq|
+// are skipped.  The tangent of the smaller angle is formed in single precision
+// from the block scaled by a power of two (an inexact angle only slows
+// convergence down to the single-precision level per rotation); c = 1 / sqrt(1 +
+// t^2) is refined from the single-precision reciprocal square root by two
+// Newton steps and s = t c, so the rotation is orthogonal to double precision
+// and the similarity is exact up to rounding.
 __device__ __forceinline__ void jrot(double app, double aqq, double apq, double& c, double& s) {
     c = 1.0; s = 0.0;
-    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
-        const double d = aqq - app;
-        const double sc = fmax(fabs(d), fabs(apq));
-        const float df = (float)(d / sc), af = (float)(apq / sc);
-        const float r = sqrtf(df * df + 4.0f * af * af);
-        const float tf = 2.0f * af / (df >= 0.0f ? df + r : df - r);
-        const double t = (double)tf;
-        c = rsqrt(t * t + 1.0);
-        s = t * c;
-    }
+    const double aa = fabs(apq);
+    if (!(aa > 1e-300) || !(aa * aa > 1e-36 * fabs(app * aqq))) return;
+    const double d = aqq - app;
+    const int e = ilogb(fmax(fabs(d), aa));
+    const float df = (float)ldexp(d, -e), af = (float)ldexp(apq, -e);
+    const float r = __builtin_amdgcn_sqrtf(df * df + 4.0f * af * af);
+    const float tf = 2.0f * af * __builtin_amdgcn_rcpf(df >= 0.0f ? df + r : df - r);
+    const double t = (double)tf;
+    const double x = fma(t, t, 1.0);
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    c = y;
+    s = t * y;
 }
+
+// Rank positions: perm[t] = index of the t-th largest diagonal entry (ties by index).
+__device__ void blk_sort_desc(const Mat& A, int n, int* perm, double* lam) {
+    const int tid = threadIdx.x;
+    if (tid < n) {
+        const double v = A[tid][tid];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double w = A[j][j];
+            if (w > v || (w == v && j < tid)) ++rank;
+        }
+        perm[rank] = tid;
+        lam[rank] = v;
+    }
+    __syncthreads();
+}
+
+struct DenseShared {
+    Mat W;
+    Mat M2;
+    Mat stage;
+    double red[NT];
+    double wbuf[(NRG + 1) * LDW];
+    double diag0[LMAX];
+    double invd[LMAX];
+    double tau[LMAX];
+    double v0[LMAX];
+    double rdiag[LMAX];
+    double minr[1];
+    int pairs[LMAX + 2];
+    int perm[LMAX];
+    int flag[4];
+};
+
+template <int NR>
+__device__ void cholqr_apply(double* Y, int64_t J, int ell, DenseShared& S) {
+    blk_trsm_rows<NR>(Y, J, ell, ell, S.W, S.invd);
+}
+
+// gate: when non-null the kernel runs only if gate[0] != 0 (the multi-workgroup
+// CholeskyQR2 below did not accept the sketch); Y is then the original sketch.
+template <int NR>
+__global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_t J, int ell, float* __restrict__ Qf,
+                                                  double* __restrict__ V, double accept_ratio,
+                                                  uint32_t* __restrict__ status, const int* __restrict__ gate) {
+    if (gate && gate[0] == 0) return;
+    __shared__ DenseShared S;
+    const int tid = threadIdx.x;
+    uint32_t st = 0;
+    if (tid == 0) S.flag[1] = 0;
+    // keep a copy of Y for the Householder fallback
+    double* Ycopy = V + J * (int64_t)ell;
+    double nonfinite = 0.0, fro = 0.0;
+    const int64_t tot = J * (int64_t)ell;
+    for (int64_t e0 = tid; e0 < tot; e0 += 8 * NT) {
+        double y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[u] = (e0 + u * NT < tot) ? Y[e0 + u * NT] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (e0 + u * NT < tot) {
+                Ycopy[e0 + u * NT] = y[u];
+                if (!isfinite(y[u])) nonfinite += 1.0;
+                else fro += y[u] * y[u];
+            }
+        }
+    }
+    nonfinite = blk_sum(nonfinite, S.red);
+    fro = blk_sum(fro, S.red);
+    RT_DENSE_TRACE(1);
+    bool ok = nonfinite == 0.0 && fro > 0.0;
+    if (nonfinite != 0.0) st |= 4u;
+    if (ok) {
+        // CholeskyQR2: accepted when the first factorisation keeps every pivot
+        // ratio >= accept_ratio (kappa(Y) ~ 1/sqrt(ratio)) and the second one is
+        // nearly orthogonal already (ratio >= 1/2).
+        blk_gram(Y, J, ell, ell, S.W);
+        RT_DENSE_TRACE(2);
+        ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
+        RT_DENSE_TRACE(3);
+        if (!ok) {
+            // shifted CholeskyQR3 (Fukaya et al. 2020): factor Y^T Y + s I with
+            // s = 11 (J ell + ell (ell + 1)) u ||Y||_F^2, which bounds kappa of
+            // Y R^-1 by O(u^-1/2), then CholeskyQR2 on the result.
+            blk_gram(Y, J, ell, ell, S.W);
+            const double shift = 11.0 * ((double)J * ell + (double)ell * (ell + 1)) * 0x1p-53 * fro;
+            ok = blk_cholesky(S.W, ell, shift, S.diag0, S.minr, S.flag, S.invd);
+            if (ok) {
+                cholqr_apply<NR>(Y, J, ell, S);
+                blk_gram(Y, J, ell, ell, S.W);
+                ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
+                // a direction of Y far below sqrt(shift) leaves a pivot ratio near u:
+                // Y was numerically rank deficient and Q holds padding directions
+                if (ok && S.minr[0] < 1e-6) st |= 1u;
+            }
+        }
+        if (ok) {
+            cholqr_apply<NR>(Y, J, ell, S);
+            RT_DENSE_TRACE(4);
+            blk_gram(Y, J, ell, ell, S.W);
+            RT_DENSE_TRACE(5);
+            ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= 0.5;
+            RT_DENSE_TRACE(6);
+            if (ok) cholqr_apply<NR>(Y, J, ell, S);
+            RT_DENSE_TRACE(7);
+        }
+    }
+    if (!ok) {
+        // Householder QR of the original sketch: unconditionally orthonormal
+        for (int64_t e = tid; e < J * ell; e += NT) Y[e] = isfinite(Ycopy[e]) ? Ycopy[e] : 0.0;
+        __syncthreads();
+        blk_householder_q(Y, J, ell, ell, V, S.tau, S.v0, S.rdiag, S.red, S.wbuf);
+        st |= 2u;
+        if (tid == 0) {
+            double mx = 0.0;
+            for (int k = 0; k < ell; ++k) mx = fmax(mx, fabs(S.rdiag[k]));
+            for (int k = 0; k < ell; ++k)
+                if (!(fabs(S.rdiag[k]) > 1e-12 * mx)) S.flag[1] = 1;
+        }
+        if (tid == 0 && S.flag[1]) st |= 1u;
+    }
+    __syncthreads();
+    if (Qf)
+        for (int64_t e = tid; e < J * ell; e += NT) Qf[e] = (float)Y[e];
+    if (tid == 0 && status) status[0] = st;
+}
+
+// One adaptive block: Y (J x b) <- (I - Q Q^T) Y twice, then the kept left singular
+// vectors of Y are appended to Qall (ld = ldq) at column k.
+__global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, int64_t J, int b,
+                                                        double* __restrict__ Qall, int ldq, int k, double drop,
+                                                        double* __restrict__ V, int* __restrict__ knew) {
+    __shared__ DenseShared S;
+    const int tid = threadIdx.x;
+    // y0 = ||Y||_F before the projections
+    double s = 0.0;
+    for (int64_t e = tid; e < J * b; e += NT) s += Y[e] * Y[e];
+    const double y0 = sqrt(blk_sum(s, S.red));
+    // two passes of block Gram-Schmidt: C = Q^T Y (k x b), Y -= Q C
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        for (int e = tid; e < k * b; e += NT) {
+            const int a = e / b, j = e % b;
+            double c = 0.0;
+            for (int64_t i = 0; i < J; ++i) c += Qall[i * ldq + a] * Y[i * b + j];
+            S.W[a][j] = c;
+        }
+        __syncthreads();
+        for (int64_t e = tid; e < J * b; e += NT) {
+            const int64_t i = e / b;
+            const int j = (int)(e % b);
+            double c = 0.0;
+            for (int a = 0; a < k; ++a) c += Qall[i * ldq + a] * S.W[a][j];
+            Y[e] -= c;
+        }
+        __syncthreads();
+    }
+    // Householder QR: V (J x b) keeps the reflectors; R's upper triangle is built
+    // from the reflected columns before Q is formed, so save it first.
+    // Copy Y to the scratch tail to recover R = Q^T Y afterwards.
+    double* Ysave = V + J * (int64_t)b;
+    for (int64_t e = tid; e < J * b; e += NT) Ysave[e] = Y[e];
+    __syncthreads();
+    blk_householder_q(Y, J, b, b, V, S.tau, S.v0, S.rdiag, S.red, S.wbuf);
+    // R = Q^T Ysave (b x b)
+    for (int e = tid; e < b * b; e += NT) {
+        const int a = e / b, j = e % b;
+        double c = 0.0;
+        for (int64_t i = 0; i < J; ++i) c += Y[i * b + a] * Ysave[i * b + j];
+        S.M2[a][j] = c;                       // R (upper up to rounding)
+    }
+    __syncthreads();
+    // one-sided Jacobi on M = R^T: rotate columns of M (rows of R); accumulate in Vr
+    if (tid == 0) {
+        // M[i][j] = R[j][i]
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j) { S.stage[i][j] = S.M2[j][i]; S.W[i][j] = (i == j) ? 1.0 : 0.0; }
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            bool rotated = false;
+            for (int p = 0; p < b - 1; ++p)
+                for (int q = p + 1; q < b; ++q) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = 0; i < b; ++i) {
+                        al += S.stage[i][p] * S.stage[i][p];
+                        be += S.stage[i][q] * S.stage[i][q];
+                        ga += S.stage[i][p] * S.stage[i][q];
+                    }
+                    if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
+                    rotated = true;
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    for (int i = 0; i < b; ++i) {
+                        const double mp = S.stage[i][p], mq = S.stage[i][q];
+                        S.stage[i][p] = c * mp - sn * mq;
+                        S.stage[i][q] = sn * mp + c * mq;
+                        const double vp = S.W[i][p], vq = S.W[i][q];
+                        S.W[i][p] = c * vp - sn * vq;
+                        S.W[i][q] = sn * vp + c * vq;
+                    }
+                }
+            if (!rotated) break;
+        }
+        // singular values = column norms of M V; keep sigma > drop * y0, in decreasing order
+        double sig[LMAX];
+        for (int j = 0; j < b; ++j) {
+            double n2 = 0.0;
+            for (int i = 0; i < b; ++i) n2 += S.stage[i][j] * S.stage[i][j];
+            sig[j] = sqrt(n2);
+        }
+        int kept = 0;
+        bool used[LMAX];
+        for (int j = 0; j < b; ++j) used[j] = false;
+        for (int t = 0; t < b; ++t) {
+            int best = -1;
+            for (int j = 0; j < b; ++j)
+                if (!used[j] && (best < 0 || sig[j] > sig[best])) best = j;
+            used[best] = true;
+            if (sig[best] > drop * y0 && y0 > 0.0) S.perm[kept++] = best;
+        }
+        S.flag[0] = kept;
+    }
+    __syncthreads();
+    const int kept = S.flag[0];
+    // new basis columns: Qy * Vr[:, perm[t]]  (Qy in Y, J x b)
+    for (int64_t e = tid; e < J * kept; e += NT) {
+        const int64_t i = e / kept;
+        const int t = (int)(e % kept);
+        const int j = S.perm[t];
+        double c = 0.0;
+        for (int a = 0; a < b; ++a) c += Y[i * b + a] * S.W[a][j];
+        Qall[i * ldq + k + t] = c;
+    }
+    if (tid == 0) knew[0] = kept;
+}
+
+
+
+// ---- truncation (Alg. 1 steps 4-6) --------------------------------------------------------
+// Three launches: the eigen-decomposition of the ell x ell Gram W = B B^T and
+// the rank choice by one workgroup; A = Q U (J x k) by ceil(J / 64) workgroups,
+// each also reporting per column its entry of largest magnitude; and the sign
+// fix (each column of A and U flipped so that its largest-|.| entry, lowest
+// row on ties, is positive) applied to A and written into U.
 
 // Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS).  The round-robin
 // pairing of the m = n + (n odd) indices is tabulated once.  A step costs two
@@ -419,160 +669,35 @@ __device__ int blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, uns
     return sweep;
 }
 
-// Rank positions: perm[t] = index of the t-th largest diagonal entry (ties by index).
-__device__ void blk_sort_desc(const Mat& A, int n, int* perm, double* lam) {
-    const int tid = threadIdx.x;
-    if (tid < n) {
-        const double v = A[tid][tid];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double w = A[j][j];
-            if (w > v || (w == v && j < tid)) ++rank;
-        }
-        perm[rank] = tid;
-        lam[rank] = v;
-    }
-    __syncthreads();
-}
-
-struct DenseShared {
-    Mat W;
-    Mat M2;
-    Mat stage;
-    double red[NT];
-    double wbuf[(NRG + 1) * LDW];
-    double diag0[LMAX];
-    double invd[LMAX];
-    double tau[LMAX];
-    double v0[LMAX];
-    double rdiag[LMAX];
+struct EigShared {
+    Mat A;
+    Mat V;
     double cs[2 * (LMAX + 2)];
-    double sgn[8];
     unsigned short sched[LMAX * LMAX / 2];
-    double lam[LMAX];
-    double minr[1];
-    int pairs[LMAX + 2];
+    double red[NT];
     int perm[LMAX];
-    int flag[4];
+    double lam[LMAX];
+    int k;
 };
 
-template <int NR>
-__device__ void cholqr_apply(double* Y, int64_t J, int ell, DenseShared& S) {
-    blk_trsm_rows<NR>(Y, J, ell, ell, S.W, S.invd);
-}
-
-template <int NR>
-__global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_t J, int ell, float* __restrict__ Qf,
-                                                  double* __restrict__ V, double accept_ratio,
-                                                  uint32_t* __restrict__ status) {
-    __shared__ DenseShared S;
+// Eigen-decomposition of W (ell x ell), eigenvalues in decreasing order, and
+// the rank: k = r_fixed, or the smallest k with max(E, 0) + sum_{t >= k}
+// max(lambda_t, 0) <= tau2.  Us (ell x ell) = eigenvectors in that order.
+__global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, int ell, int r_fixed,
+                                                 const double* __restrict__ E_dev, double tau2,
+                                                 double* __restrict__ Us, double* __restrict__ lam_out,
+                                                 int* __restrict__ kout, double jtol) {
+    __shared__ EigShared S;
     const int tid = threadIdx.x;
-    uint32_t st = 0;
-    if (tid == 0) S.flag[1] = 0;
-    // keep a copy of Y for the Householder fallback
-    double* Ycopy = V + J * (int64_t)ell;
-    double nonfinite = 0.0, fro = 0.0;
-    const int64_t tot = J * (int64_t)ell;
-    for (int64_t e0 = tid; e0 < tot; e0 += 8 * NT) {
-        double y[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) y[u] = (e0 + u * NT < tot) ? Y[e0 + u * NT] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (e0 + u * NT < tot) {
-                Ycopy[e0 + u * NT] = y[u];
-                if (!isfinite(y[u])) nonfinite += 1.0;
-                else fro += y[u] * y[u];
-            }
-        }
-    }
-    nonfinite = blk_sum(nonfinite, S.red);
-    fro = blk_sum(fro, S.red);
-    RT_DENSE_TRACE(1);
-    bool ok = nonfinite == 0.0 && fro > 0.0;
-    if (nonfinite != 0.0) st |= 4u;
-    if (ok) {
-        // CholeskyQR2: accepted when the first factorisation keeps every pivot
-        // ratio >= accept_ratio (kappa(Y) ~ 1/sqrt(ratio)) and the second one is
-        // nearly orthogonal already (ratio >= 1/2).
-        blk_gram(Y, J, ell, ell, S.W);
-        RT_DENSE_TRACE(2);
-        ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
-        RT_DENSE_TRACE(3);
-        if (!ok) {
-            // shifted CholeskyQR3 (Fukaya et al. 2020): factor Y^T Y + s I with
-            // s = 11 (J ell + ell (ell + 1)) u ||Y||_F^2, which bounds kappa of
-            // Y R^-1 by O(u^-1/2), then CholeskyQR2 on the result.
-            blk_gram(Y, J, ell, ell, S.W);
-            const double shift = 11.0 * ((double)J * ell + (double)ell * (ell + 1)) * 0x1p-53 * fro;
-            ok = blk_cholesky(S.W, ell, shift, S.diag0, S.minr, S.flag, S.invd);
-            if (ok) {
-                cholqr_apply<NR>(Y, J, ell, S);
-                blk_gram(Y, J, ell, ell, S.W);
-                ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= accept_ratio;
-                // a direction of Y far below sqrt(shift) leaves a pivot ratio near u:
-                // Y was numerically rank deficient and Q holds padding directions
-                if (ok && S.minr[0] < 1e-6) st |= 1u;
-            }
-        }
-        if (ok) {
-            cholqr_apply<NR>(Y, J, ell, S);
-            RT_DENSE_TRACE(4);
-            blk_gram(Y, J, ell, ell, S.W);
-            RT_DENSE_TRACE(5);
-            ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= 0.5;
-            RT_DENSE_TRACE(6);
-            if (ok) cholqr_apply<NR>(Y, J, ell, S);
-            RT_DENSE_TRACE(7);
-        }
-    }
-    if (!ok) {
-        // Householder QR of the original sketch: unconditionally orthonormal
-        for (int64_t e = tid; e < J * ell; e += NT) Y[e] = isfinite(Ycopy[e]) ? Ycopy[e] : 0.0;
-        __syncthreads();
-        blk_householder_q(Y, J, ell, ell, V, S.tau, S.v0, S.rdiag, S.red, S.wbuf);
-        st |= 2u;
-        if (tid == 0) {
-            double mx = 0.0;
-            for (int k = 0; k < ell; ++k) mx = fmax(mx, fabs(S.rdiag[k]));
-            for (int k = 0; k < ell; ++k)
-                if (!(fabs(S.rdiag[k]) > 1e-12 * mx)) S.flag[1] = 1;
-        }
-        if (tid == 0 && S.flag[1]) st |= 1u;
-    }
+    for (int e = tid; e < ell * ell; e += NT) S.A[e / ell][e % ell] = W[e];
     __syncthreads();
-    if (Qf)
-        for (int64_t e = tid; e < J * ell; e += NT) Qf[e] = (float)Y[e];
-    if (tid == 0 && status) status[0] = st;
-}
-
-// Truncation: eigen-decomposition of the Gram W (ell x ell) of B, rank choice,
-// U = leading eigenvectors, A = Q U with sign fix (largest |.| entry positive).
-template <int NR>
-__global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__ W, int ell,
-                                                      const double* __restrict__ Q, int64_t ldq, int64_t J,
-                                                      int r_fixed,
-                                                      const double* __restrict__ E_dev, double tau2,
-                                                      double* __restrict__ U, float* __restrict__ Uf,
-                                                      void* __restrict__ Aout, int a_is_f64,
-                                                      double* __restrict__ lam_out, int* __restrict__ kout,
-                                                      double jtol) {
-    __shared__ DenseShared S;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < ell * ell; e += NT) S.W[e / ell][e % ell] = W[e];
-    __syncthreads();
-    RT_DENSE_TRACE(1);
-    const int sweeps = blk_jacobi_eig(S.W, ell, S.M2, jtol, S.cs, S.sched, S.red);
-    (void)sweeps;
-    RT_DENSE_TRACE_VAL(9, sweeps);
-    RT_DENSE_TRACE(2);
-    blk_sort_desc(S.W, ell, S.perm, S.lam);
+    blk_jacobi_eig(S.A, ell, S.V, jtol, S.cs, S.sched, S.red);
+    blk_sort_desc(S.A, ell, S.perm, S.lam);
     if (tid == 0) {
         int k;
         if (r_fixed >= 0) {
             k = r_fixed < ell ? r_fixed : ell;
         } else {
-            // smallest k with max(E, 0) + sum_{t >= k} max(lam_t, 0) <= tau2
             const double E = E_dev ? fmax(E_dev[0], 0.0) : 0.0;
             double tail = 0.0;
             for (int t = ell - 1; t >= 0; --t) tail += fmax(S.lam[t], 0.0);
@@ -582,276 +707,374 @@ __global__ __launch_bounds__(NT) void truncate_kernel(const double* __restrict__
                 if (kk < ell) tail -= fmax(S.lam[kk], 0.0);
             }
         }
-        S.flag[2] = k;
+        S.k = k;
+        kout[0] = k;
     }
     __syncthreads();
-    const int k = S.flag[2];
     if (lam_out && tid < ell) lam_out[tid] = S.lam[tid];
-    if (kout && tid == 0) kout[0] = k;
-    RT_DENSE_TRACE(3);
-    // U columns = eigenvectors in sorted order (ell x k, in S.W)
-    for (int e = tid; e < ell * k; e += NT) {
-        const int i = e / k, j = e % k;
-        S.W[i][j] = S.M2[i][S.perm[j]];
+    for (int e = tid; e < ell * ell; e += NT) {
+        const int i = e / ell, j = e % ell;
+        Us[e] = S.V[i][S.perm[j]];
     }
-    for (int e = tid; e < ell * LMAX; e += NT) {      // zero the unused columns (read by the row product)
-        const int i = e / LMAX, j = e % LMAX;
-        if (j >= k) S.W[i][j] = 0.0;
+}
+
+// A = Q Us[:, :k] for rows 64 b .. 64 b + 63 (one row per thread); part[b] =
+// per column the (|a|, a, row) of the entry of largest magnitude of these rows
+// (lowest row on ties).  A is stored before the sign fix.
+template <int NR>
+__global__ __launch_bounds__(64) void factor_rows_kernel(const double* __restrict__ Q, int64_t ldq, int64_t J,
+                                                         int ell, const double* __restrict__ Us,
+                                                         const int* __restrict__ kdev, void* __restrict__ Aout,
+                                                         int a_is_f64, double* __restrict__ part) {
+    __shared__ double us[NR][NR];
+    __shared__ double qs[64][NR + 1];
+    const int k = kdev[0];
+    if (k <= 0) return;
+    const int lane = threadIdx.x;
+    for (int e = lane; e < NR * NR; e += 64) {
+        const int t = e / NR, j = e % NR;
+        us[t][j] = (t < ell && j < k) ? Us[t * ell + j] : 0.0;
+    }
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int rows = (int)(J - row0 < 64 ? J - row0 : 64);
+    for (int e = lane; e < rows * ell; e += 64) {
+        const int r = e / ell, t = e - r * ell;
+        qs[r][t] = Q[(row0 + r) * ldq + t];
     }
     __syncthreads();
-    // A = Q U, eight columns at a time; each column is then flipped so that its
-    // entry of largest magnitude (lowest row on ties) is positive, and U with it.
-    // The rows of Q owned by a thread stay in registers when J <= NT; a column
-    // chunk is formed once to find the signs and again to store it.
+    const bool valid = lane < rows;
+    const int64_t i = row0 + lane;
+    double a[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) a[j] = 0.0;
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+        if (t < ell) {
+            const double q = valid ? qs[lane][t] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) a[j] = fma(q, us[t][j], a[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
     double* A64 = (double*)Aout;
     float* A32 = (float*)Aout;
-    const int lane = tid & 63, wave = tid >> 6;
-    const bool qreg = J <= NT;
-    double q[NR];
-    if (qreg) {
+    __syncthreads();                         // every lane is done reading its row of qs
 #pragma unroll
-        for (int t = 0; t < NR; ++t) q[t] = (tid < J && t < ell) ? Q[(int64_t)tid * ldq + t] : 0.0;
+    for (int j = 0; j < NR; ++j) {
+        if (j < k) {
+            qs[lane][j] = a[j];
+            if (valid && Aout) {
+                if (a_is_f64) A64[i * k + j] = a[j];
+                else A32[i * k + j] = (float)a[j];
+            }
+        }
     }
-    for (int j0 = 0; j0 < k; j0 += 8) {
-        double best[8], bval[8];
-        int64_t bidx[8];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) { best[jj] = -1.0; bval[jj] = 0.0; bidx[jj] = INT64_MAX; }
-        for (int64_t i = tid; i < J; i += NT) {
-            if (!qreg) {
-#pragma unroll
-                for (int t = 0; t < NR; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
-            }
-            double z[8];
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
-#pragma unroll
-            for (int t = 0; t < NR; ++t) {
-                if (t < ell) {
-#pragma unroll
-                    for (int jj = 0; jj < 8; ++jj) z[jj] += q[t] * S.W[t][j0 + jj];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const double a = fabs(z[jj]);
-                if (j0 + jj < k && a > best[jj]) { best[jj] = a; bval[jj] = z[jj]; bidx[jj] = i; }
-            }
+    __syncthreads();
+    if (lane < k) {
+        double b = -1.0, v = 0.0;
+        int64_t ix = INT64_MAX;
+        for (int r = 0; r < rows; ++r) {
+            const double x = qs[r][lane];
+            if (fabs(x) > b) { b = fabs(x); v = x; ix = row0 + r; }
         }
-        // workgroup argmax per column: wave shuffles, then the waves through LDS
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            double b = best[jj], v = bval[jj];
-            int64_t ix = bidx[jj];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(b, off, 64);
-                const double ov = __shfl_xor(v, off, 64);
-                const int64_t oi = __shfl_xor(ix, off, 64);
-                if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
-            }
-            if (lane == 0) {
-                S.stage[0][wave * 8 + jj] = b;
-                S.stage[1][wave * 8 + jj] = v;
-                S.stage[2][wave * 8 + jj] = (double)ix;
-            }
-        }
-        __syncthreads();
-        if (tid < 8) {
-            double b = -1.0, v = 0.0, ix = 1e300;
-            for (int w = 0; w < NT / 64; ++w) {
-                const double ob = S.stage[0][w * 8 + tid], ov = S.stage[1][w * 8 + tid], oi = S.stage[2][w * 8 + tid];
-                if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
-            }
-            S.sgn[tid] = (v < 0.0) ? -1.0 : 1.0;
-        }
-        __syncthreads();
-        double sg[8];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) sg[jj] = S.sgn[jj];
-        if (Aout) {
-            for (int64_t i = tid; i < J; i += NT) {
-                if (!qreg) {
-#pragma unroll
-                    for (int t = 0; t < NR; ++t) q[t] = (t < ell) ? Q[i * ldq + t] : 0.0;
-                }
-                double z[8];
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) z[jj] = 0.0;
-#pragma unroll
-                for (int t = 0; t < NR; ++t) {
-                    if (t < ell) {
-#pragma unroll
-                        for (int jj = 0; jj < 8; ++jj) z[jj] += q[t] * S.W[t][j0 + jj];
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
-                    if (j0 + jj < k) {
-                        if (a_is_f64) A64[i * k + j0 + jj] = z[jj] * sg[jj];
-                        else A32[i * k + j0 + jj] = (float)(z[jj] * sg[jj]);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < ell)
-            for (int jj = 0; jj < 8; ++jj)
-                if (j0 + jj < k) S.W[tid][j0 + jj] *= sg[jj];
-        __syncthreads();
-    }
-    for (int e = tid; e < ell * k; e += NT) {
-        const int i = e / k, j = e % k;
-        U[i * k + j] = S.W[i][j];
-        if (Uf) Uf[i * k + j] = (float)S.W[i][j];
+        double* pb = part + (int64_t)blockIdx.x * 3 * LMAX;
+        pb[lane] = b;
+        pb[LMAX + lane] = v;
+        pb[2 * LMAX + lane] = (double)ix;
     }
 }
 
-// One adaptive block: Y (J x b) <- (I - Q Q^T) Y twice, then the kept left singular
-// vectors of Y are appended to Qall (ld = ldq) at column k.
-__global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, int64_t J, int b,
-                                                        double* __restrict__ Qall, int ldq, int k, double drop,
-                                                        double* __restrict__ V, int* __restrict__ knew) {
-    __shared__ DenseShared S;
+// Signs from the nwg partial maxima (fixed order, lowest row on ties); every
+// workgroup scales its slice of A, workgroup 0 writes U = Us[:, :k] diag(sgn)
+// (ell x k) and its float copy.
+__global__ __launch_bounds__(256) void sign_kernel(const double* __restrict__ part, int nwg,
+                                                   const int* __restrict__ kdev, int64_t J,
+                                                   const double* __restrict__ Us, int ell, void* __restrict__ Aout,
+                                                   int a_is_f64, double* __restrict__ U, float* __restrict__ Uf) {
+    __shared__ double sg[LMAX];
+    const int k = kdev[0];
+    if (k <= 0) return;
     const int tid = threadIdx.x;
-    // y0 = ||Y||_F before the projections
-    double s = 0.0;
-    for (int64_t e = tid; e < J * b; e += NT) s += Y[e] * Y[e];
-    const double y0 = sqrt(blk_sum(s, S.red));
-    // two passes of block Gram-Schmidt: C = Q^T Y (k x b), Y -= Q C
-    for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        for (int e = tid; e < k * b; e += NT) {
-            const int a = e / b, j = e % b;
-            double c = 0.0;
-            for (int64_t i = 0; i < J; ++i) c += Qall[i * ldq + a] * Y[i * b + j];
-            S.W[a][j] = c;
+    if (tid < k) {
+        double b = -1.0, v = 0.0, ix = 1e300;
+        for (int w = 0; w < nwg; ++w) {
+            const double* pb = part + (int64_t)w * 3 * LMAX;
+            const double ob = pb[tid], ov = pb[LMAX + tid], oi = pb[2 * LMAX + tid];
+            if (ob > b || (ob == b && oi < ix)) { b = ob; v = ov; ix = oi; }
         }
-        __syncthreads();
-        for (int64_t e = tid; e < J * b; e += NT) {
-            const int64_t i = e / b;
-            const int j = (int)(e % b);
-            double c = 0.0;
-            for (int a = 0; a < k; ++a) c += Qall[i * ldq + a] * S.W[a][j];
-            Y[e] -= c;
-        }
-        __syncthreads();
-    }
-    // Householder QR: V (J x b) keeps the reflectors; R's upper triangle is built
-    // from the reflected columns before Q is formed, so save it first.
-    // Copy Y to the scratch tail to recover R = Q^T Y afterwards.
-    double* Ysave = V + J * (int64_t)b;
-    for (int64_t e = tid; e < J * b; e += NT) Ysave[e] = Y[e];
-    __syncthreads();
-    blk_householder_q(Y, J, b, b, V, S.tau, S.v0, S.rdiag, S.red, S.wbuf);
-    // R = Q^T Ysave (b x b)
-    for (int e = tid; e < b * b; e += NT) {
-        const int a = e / b, j = e % b;
-        double c = 0.0;
-        for (int64_t i = 0; i < J; ++i) c += Y[i * b + a] * Ysave[i * b + j];
-        S.M2[a][j] = c;                       // R (upper up to rounding)
+        sg[tid] = (v < 0.0) ? -1.0 : 1.0;
     }
     __syncthreads();
-    // one-sided Jacobi on M = R^T: rotate columns of M (rows of R); accumulate in Vr
-    if (tid == 0) {
-        // M[i][j] = R[j][i]
-        for (int i = 0; i < b; ++i)
-            for (int j = 0; j < b; ++j) { S.stage[i][j] = S.M2[j][i]; S.W[i][j] = (i == j) ? 1.0 : 0.0; }
-        for (int sweep = 0; sweep < 60; ++sweep) {
-            bool rotated = false;
-            for (int p = 0; p < b - 1; ++p)
-                for (int q = p + 1; q < b; ++q) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = 0; i < b; ++i) {
-                        al += S.stage[i][p] * S.stage[i][p];
-                        be += S.stage[i][q] * S.stage[i][q];
-                        ga += S.stage[i][p] * S.stage[i][q];
-                    }
-                    if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
-                    rotated = true;
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                    for (int i = 0; i < b; ++i) {
-                        const double mp = S.stage[i][p], mq = S.stage[i][q];
-                        S.stage[i][p] = c * mp - sn * mq;
-                        S.stage[i][q] = sn * mp + c * mq;
-                        const double vp = S.W[i][p], vq = S.W[i][q];
-                        S.W[i][p] = c * vp - sn * vq;
-                        S.W[i][q] = sn * vp + c * vq;
-                    }
-                }
-            if (!rotated) break;
+    if (Aout) {
+        const int64_t n = J * k;
+        const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+        const int64_t e0 = (int64_t)blockIdx.x * chunk;
+        const int64_t e1 = e0 + chunk < n ? e0 + chunk : n;
+        if (a_is_f64) {
+            double* A = (double*)Aout;
+            for (int64_t e = e0 + tid; e < e1; e += 256) A[e] *= sg[e % k];
+        } else {
+            float* A = (float*)Aout;
+            for (int64_t e = e0 + tid; e < e1; e += 256) A[e] *= (float)sg[e % k];
         }
-        // singular values = column norms of M V; keep sigma > drop * y0, in decreasing order
-        double sig[LMAX];
-        for (int j = 0; j < b; ++j) {
-            double n2 = 0.0;
-            for (int i = 0; i < b; ++i) n2 += S.stage[i][j] * S.stage[i][j];
-            sig[j] = sqrt(n2);
-        }
-        int kept = 0;
-        bool used[LMAX];
-        for (int j = 0; j < b; ++j) used[j] = false;
-        for (int t = 0; t < b; ++t) {
-            int best = -1;
-            for (int j = 0; j < b; ++j)
-                if (!used[j] && (best < 0 || sig[j] > sig[best])) best = j;
-            used[best] = true;
-            if (sig[best] > drop * y0 && y0 > 0.0) S.perm[kept++] = best;
-        }
-        S.flag[0] = kept;
     }
-    __syncthreads();
-    const int kept = S.flag[0];
-    // new basis columns: Qy * Vr[:, perm[t]]  (Qy in Y, J x b)
-    for (int64_t e = tid; e < J * kept; e += NT) {
-        const int64_t i = e / kept;
-        const int t = (int)(e % kept);
-        const int j = S.perm[t];
-        double c = 0.0;
-        for (int a = 0; a < b; ++a) c += Y[i * b + a] * S.W[a][j];
-        Qall[i * ldq + k + t] = c;
+    if (blockIdx.x == 0) {
+        for (int e = tid; e < ell * k; e += 256) {
+            const int i = e / k, j = e % k;
+            const double u = Us[i * ell + j] * sg[j];
+            U[e] = u;
+            if (Uf) Uf[e] = (float)u;
+        }
     }
-    if (tid == 0) knew[0] = kept;
 }
 
+template <int NR>
+hipError_t truncate_multi(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
+                          const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da, double* lam,
+                          int* kout, double jtol, double* scratch, hipStream_t stream) {
+    double* Us = scratch;
+    const int nwg = (int)((J + 63) / 64);
+    double* part = Us + (int64_t)ell * ell;
+    const int64_t nsign = (J * ell + 4095) / 4096;
+    hipLaunchKernelGGL(eig_kernel, dim3(1), dim3(NT), 0, stream, W, ell, r_fixed, E_dev, tau2, Us, lam, kout, jtol);
+    hipLaunchKernelGGL(factor_rows_kernel<NR>, dim3(nwg), dim3(64), 0, stream, Q, ldq, J, ell, (const double*)Us,
+                       (const int*)kout, A, da == Dt::F64 ? 1 : 0, part);
+    hipLaunchKernelGGL(sign_kernel, dim3((unsigned)(nsign < 1 ? 1 : nsign)), dim3(256), 0, stream,
+                       (const double*)part, nwg, (const int*)kout, J, (const double*)Us, ell, A,
+                       da == Dt::F64 ? 1 : 0, U, Uf);
+    return hipGetLastError();
+}
+
+// ---- CholeskyQR2 over many workgroups ---------------------------------------------------
+// The common case of orth(): the Gram of the J x ell sketch is formed by
+// ceil(J / OG_ROWS) workgroups (partial Grams summed in a fixed order), the
+// Cholesky factor and its acceptance test by one workgroup, and the triangular
+// solve Y R^-1 row by row by ceil(J / 64) workgroups; twice.  A sketch that
+// fails either acceptance test is left untouched and the single-workgroup
+// kernel above (shifted CholeskyQR3, then Householder) runs on it.
+
+constexpr int OG_ROWS = 32;   // rows per partial Gram
+
+// part[b] = Y[rows of b]^T Y[rows of b] (ell x ell); with stats, stats[2 b] =
+// sum of squares of the finite entries and stats[2 b + 1] = count of the others.
+__global__ __launch_bounds__(256) void gram_rows_kernel(const double* __restrict__ Y, int64_t J, int ell,
+                                                        const int* __restrict__ gate, double* __restrict__ part,
+                                                        double* __restrict__ stats) {
+    if (gate && gate[0] != 0) return;
+    __shared__ double ys[OG_ROWS][LMAX + 1];
+    __shared__ double red[8];
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * OG_ROWS;
+    const int rows = (int)(J - row0 < OG_ROWS ? J - row0 : OG_ROWS);
+    double fro = 0.0, bad = 0.0;
+    for (int e = tid; e < rows * ell; e += 256) {
+        const int r = e / ell, c = e - r * ell;
+        const double y = Y[(row0 + r) * ell + c];
+        ys[r][c] = y;
+        if (isfinite(y)) fro += y * y;
+        else bad += 1.0;
+    }
+    __syncthreads();
+    if (stats) {
+        fro = wave_sum(fro);
+        bad = wave_sum(bad);
+        if ((tid & 63) == 0) { red[tid >> 6] = fro; red[4 + (tid >> 6)] = bad; }
+        __syncthreads();
+        if (tid == 0) {
+            stats[2 * blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+            stats[2 * blockIdx.x + 1] = (red[4] + red[5]) + (red[6] + red[7]);
+        }
+    }
+    double* out = part + (int64_t)blockIdx.x * ell * ell;
+    for (int e = tid; e < ell * ell; e += 256) {
+        const int i = e / ell, j = e - i * ell;
+        if (j < i) continue;
+        double a0 = 0.0, a1 = 0.0;
+        int r = 0;
+        for (; r + 2 <= rows; r += 2) {
+            a0 = fma(ys[r][i], ys[r][j], a0);
+            a1 = fma(ys[r + 1][i], ys[r + 1][j], a1);
+        }
+        if (r < rows) a0 = fma(ys[r][i], ys[r][j], a0);
+        const double v = a0 + a1;
+        out[i * ell + j] = v;
+        out[j * ell + i] = v;
+    }
+}
+
+struct CholShared {
+    Mat W;
+    double diag0[LMAX];
+    double invd[LMAX];
+    double minr[1];
+    int flag[4];
+};
+
+// Sums the nparts partial Grams, factors W = L L^T and tests the pivots:
+// accepted when every pivot ratio is >= min_ratio (and, with stats, the sketch
+// is finite and non-zero).  Writes L (lower, ell x ell) and invd = 1 / diag(L),
+// and gate[0] = 0 (accepted) or 1.  With skip_if_gated, an earlier rejection
+// stands and nothing is done.
+__global__ __launch_bounds__(NT) void chol_gate_kernel(const double* __restrict__ part, int nparts, int ell,
+                                                       const double* __restrict__ stats, double min_ratio,
+                                                       double* __restrict__ L, double* __restrict__ invd,
+                                                       int* __restrict__ gate, int skip_if_gated,
+                                                       uint32_t* __restrict__ status) {
+    if (skip_if_gated && gate[0] != 0) return;
+    __shared__ CholShared S;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < ell * ell; e += NT) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 4 <= nparts; b += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += part[(int64_t)(b + u) * ell * ell + e];
+        }
+        for (; b < nparts; ++b) a[0] += part[(int64_t)b * ell * ell + e];
+        S.W[e / ell][e % ell] = (a[0] + a[1]) + (a[2] + a[3]);
+    }
+    bool ok = true;
+    if (stats) {
+        if (tid == 0) {
+            double fro = 0.0, bad = 0.0;
+            for (int b = 0; b < nparts; ++b) { fro += stats[2 * b]; bad += stats[2 * b + 1]; }
+            S.flag[2] = (bad == 0.0 && fro > 0.0) ? 1 : 0;
+        }
+        __syncthreads();
+        ok = S.flag[2] != 0;
+    }
+    if (ok) ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= min_ratio;
+    __syncthreads();
+    if (ok) {
+        for (int e = tid; e < ell * ell; e += NT) L[e] = S.W[e / ell][e % ell];
+        if (tid < ell) invd[tid] = S.invd[tid];
+    }
+    if (tid == 0) {
+        gate[0] = ok ? 0 : 1;
+        if (status) status[0] = 0u;
+    }
+}
+
+// Yout = Yin R^-1 (R = L^T), one row per thread, when gate[0] == 0; also the
+// float copy Qf when given.
+template <int NR>
+__global__ __launch_bounds__(64) void trsm_rows_kernel(const double* __restrict__ Yin, double* __restrict__ Yout,
+                                                       float* __restrict__ Qf, int64_t J, int ell,
+                                                       const double* __restrict__ L, const double* __restrict__ invd,
+                                                       const int* __restrict__ gate) {
+    if (gate[0] != 0) return;
+    __shared__ double Ls[NR][NR + 1];
+    __shared__ double ys[64][NR + 1];
+    __shared__ double id[NR];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NR * NR; e += 64) {
+        const int i = e / NR, j = e - i * NR;
+        Ls[i][j] = (i < ell && j <= i) ? L[i * ell + j] : 0.0;
+    }
+    if (tid < ell) id[tid] = invd[tid];
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int rows = (int)(J - row0 < 64 ? J - row0 : 64);
+    const double* src = Yin + row0 * ell;
+    for (int e = tid; e < rows * ell; e += 64) ys[e / ell][e % ell] = src[e];
+    __syncthreads();
+    double y[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) y[j] = (j < ell && tid < rows) ? ys[tid][j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j < ell) {
+            const double zj = y[j] * id[j];
+            y[j] = zj;
+#pragma unroll
+            for (int k = j + 1; k < NR; ++k) {
+                y[k] -= zj * Ls[k][j];   // entries k >= ell are never stored
+                if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (j < ell) ys[tid][j] = y[j];
+    __syncthreads();
+    double* dst = Yout + row0 * ell;
+    float* dstf = Qf ? Qf + row0 * ell : nullptr;
+    for (int e = tid; e < rows * ell; e += 64) {
+        const double v = ys[e / ell][e % ell];
+        dst[e] = v;
+        if (dstf) dstf[e] = (float)v;
+    }
+}
+
+template <int NR>
+hipError_t orth_multi(double* Y, int64_t J, int ell, float* Qf, double accept_ratio, uint32_t* status,
+                      double* scratch, hipStream_t stream) {
+    const int nb = (int)((J + OG_ROWS - 1) / OG_ROWS);
+    const int nr = (int)((J + 63) / 64);
+    double* T1 = scratch;                         // Q of the first pass (aliases the fallback's V)
+    double* part = scratch + 2 * J * (int64_t)ell;
+    double* stats = part + (int64_t)nb * ell * ell;
+    double* L = stats + 2 * nb;
+    double* invd = L + (int64_t)ell * ell;
+    int* gate = reinterpret_cast<int*>(invd + LMAX);
+    // pass 1 on the sketch
+    hipLaunchKernelGGL(gram_rows_kernel, dim3(nb), dim3(256), 0, stream, (const double*)Y, J, ell,
+                       (const int*)nullptr, part, stats);
+    hipLaunchKernelGGL(chol_gate_kernel, dim3(1), dim3(NT), 0, stream, (const double*)part, nb, ell,
+                       (const double*)stats, accept_ratio, L, invd, gate, 0, status);
+    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(64), 0, stream, (const double*)Y, T1, (float*)nullptr, J,
+                       ell, (const double*)L, (const double*)invd, (const int*)gate);
+    // pass 2 on its result (Y is overwritten only if both passes are accepted)
+    hipLaunchKernelGGL(gram_rows_kernel, dim3(nb), dim3(256), 0, stream, (const double*)T1, J, ell,
+                       (const int*)gate, part, (double*)nullptr);
+    hipLaunchKernelGGL(chol_gate_kernel, dim3(1), dim3(NT), 0, stream, (const double*)part, nb, ell,
+                       (const double*)nullptr, 0.5, L, invd, gate, 1, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(64), 0, stream, (const double*)T1, Y, Qf, J, ell,
+                       (const double*)L, (const double*)invd, (const int*)gate);
+    // fallback on the untouched sketch
+    hipLaunchKernelGGL(orth_kernel<NR>, dim3(1), dim3(NT), 0, stream, Y, J, ell, Qf, scratch, accept_ratio, status,
+                       (const int*)gate);
+    return hipGetLastError();
+}
 
 }  // namespace
 
 hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_ratio, uint32_t* status,
                        double* scratch, hipStream_t stream) {
-#define RT_ORTH(NRV) \
-    hipLaunchKernelGGL(orth_kernel<NRV>, dim3(1), dim3(NT), 0, stream, Y, J, ell, Qf, scratch, accept_ratio, status)
-    if (ell <= 8) RT_ORTH(8);
-    else if (ell <= 16) RT_ORTH(16);
-    else if (ell <= 24) RT_ORTH(24);
-    else if (ell <= 32) RT_ORTH(32);
-    else if (ell <= 40) RT_ORTH(40);
-    else if (ell <= 48) RT_ORTH(48);
-    else if (ell <= 56) RT_ORTH(56);
-    else RT_ORTH(64);
-#undef RT_ORTH
-    return hipGetLastError();
+    if (ell <= 8) return orth_multi<8>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 16) return orth_multi<16>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 24) return orth_multi<24>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 32) return orth_multi<32>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 40) return orth_multi<40>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 48) return orth_multi<48>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    if (ell <= 56) return orth_multi<56>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+    return orth_multi<64>(Y, J, ell, Qf, accept_ratio, status, scratch, stream);
+}
+
+size_t orth_scratch(int64_t J, int ell) {
+    const int64_t nb = (J + OG_ROWS - 1) / OG_ROWS;
+    return (size_t)(2 * J * ell + nb * ell * ell + 2 * nb + (int64_t)ell * ell + LMAX + 8);
 }
 
 hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da, double* lam,
-                           int* kout, double jtol, hipStream_t stream) {
-#define RT_TRUNC(NRV)                                                                                        \
-    hipLaunchKernelGGL(truncate_kernel<NRV>, dim3(1), dim3(NT), 0, stream, W, ell, Q, ldq, J, r_fixed, E_dev, tau2, \
-                       U, Uf, A, da == Dt::F64 ? 1 : 0, lam, kout, jtol)
+                           int* kout, double jtol, double* scratch, hipStream_t stream) {
+#define RT_TRUNC(NRV) \
+    return truncate_multi<NRV>(W, ell, Q, ldq, J, r_fixed, E_dev, tau2, U, Uf, A, da, lam, kout, jtol, scratch, stream)
     if (ell <= 8) RT_TRUNC(8);
-    else if (ell <= 16) RT_TRUNC(16);
-    else if (ell <= 24) RT_TRUNC(24);
-    else if (ell <= 32) RT_TRUNC(32);
-    else if (ell <= 40) RT_TRUNC(40);
-    else if (ell <= 48) RT_TRUNC(48);
-    else if (ell <= 56) RT_TRUNC(56);
-    else RT_TRUNC(64);
+    if (ell <= 16) RT_TRUNC(16);
+    if (ell <= 24) RT_TRUNC(24);
+    if (ell <= 32) RT_TRUNC(32);
+    if (ell <= 40) RT_TRUNC(40);
+    if (ell <= 48) RT_TRUNC(48);
+    if (ell <= 56) RT_TRUNC(56);
+    RT_TRUNC(64);
 #undef RT_TRUNC
-    return hipGetLastError();
+}
+
+size_t truncate_scratch(int64_t J, int ell) {
+    return (size_t)((int64_t)ell * ell + (J + 63) / 64 * 3 * LMAX + 8);
 }
 
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k, double drop, int* knew,

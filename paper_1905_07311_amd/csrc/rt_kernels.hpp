@@ -24,10 +24,13 @@ struct SketchPlan {
     int nsplit;            // split-K factor (gridDim.x)
     int nrowtile;          // gridDim.y
     int64_t tiles_per_split;
-    size_t partial_elems;  // nsplit * J * ell
+    size_t partial_elems;  // nsplit * J * ldp
     int nwg;               // nsplit * nrowtile
     int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32
-    int rb;                // MFMA variant: 64-row blocks per wave (1 or 2)
+    int rb;                // MFMA variant: 64-row blocks per wave (1, 2 or 4)
+    int rw;                // MFMA variant: row blocks per workgroup (1 or 2)
+    int nq;                // MFMA variant: compiled column quads (ell <= 4 nq)
+    int ldp;               // row length of a partial (ell, or 4 nq for the MFMA kernel)
 };
 SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X);
 hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,
@@ -39,21 +42,28 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
 // tmp: ceil(nparts / 32) * n doubles of scratch (needed when nparts > 32)
 hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
                                   double* out, hipStream_t stream, double* tmp);
+// The same for parts of `rows` rows of `ldin` elements of which the first `cols`
+// are summed: out[i * cols + k] = sum_s in[(s * rows + i) * ldin + k].
+hipError_t launch_reduce_rows(const void* in, bool in_is_f64, int64_t nparts, int64_t rows, int64_t cols,
+                              int64_t ldin, double* out, hipStream_t stream, double* tmp);
 inline size_t reduce_partials_tmp(int64_t nparts, int64_t n) { return nparts > 32 ? (size_t)((nparts + 31) / 32) * n : 0; }
 // out[0] = sum of `n` doubles (single workgroup, fixed order of a tree)
 hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream);
 
 // ---- orthonormalisation:  Q = orth(Y)  (§2.4 Alg. 1 step 2) --------------------------
-// In place on Y (double, J x ell, row-major, ld = ell).  Shifted CholeskyQR3
-// with a rank-revealing eigen fallback; zero-weight orthonormal padding when Y is
-// numerically rank deficient.  Optionally writes a float copy Qf.  status[0] is
+// In place on Y (double, J x ell, row-major, ld = ell).  CholeskyQR2 over many
+// workgroups; a sketch it does not accept goes to one workgroup running
+// shifted CholeskyQR3 and then Householder QR, which pads a numerically rank
+// deficient Y with zero-weight orthonormal directions.  Optionally writes a
+// float copy Qf.  status[0] is
 // set to a bit mask: 1 = padded / rank deficient, 2 = fallback path used,
 // 4 = non-finite input.
 // `accept_ratio`: CholeskyQR2 is accepted when the smallest relative Cholesky pivot of
 // the first pass is >= accept_ratio and that of the second pass >= 1/2.
-// `scratch`: 2 J ell doubles.
+// `scratch`: orth_scratch(J, ell) doubles.
 hipError_t launch_orth(double* Y, int64_t J, int ell, float* Qf, double accept_ratio,
                        uint32_t* status, double* scratch, hipStream_t stream);
+size_t orth_scratch(int64_t J, int ell);
 
 // ---- projection / core update:  B = G x_n Q^T  (Alg. 1 step 3; Alg. 3 core update) --
 // B[l, k, r] = sum_i Q[i, k] G[l, i, r], k < ell; Q is J x ell (row-major, ld = ldq).
@@ -83,9 +93,11 @@ hipError_t launch_gram3(const void* B, Dt dt, int64_t L, int64_t ldk, int64_t R,
 // columns sign-fixed: largest-|.| entry positive), lam (ell, sorted eigenvalues),
 // kout[0] = k.
 // jtol: Jacobi stops when the off-diagonal sum of squares is <= jtol ||W||_F^2.
+// kout is required; scratch: truncate_scratch(J, ell) doubles.
 hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ldq, int64_t J, int r_fixed,
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da,
-                           double* lam, int* kout, double jtol, hipStream_t stream);
+                           double* lam, int* kout, double jtol, double* scratch, hipStream_t stream);
+size_t truncate_scratch(int64_t J, int ell);
 
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
@@ -100,9 +112,10 @@ hipError_t dense_init();
 
 // ---- MFMA variants (float32 data, v_mfma_f32_4x4x1_16b) -------------------------------
 bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X);
-hipError_t launch_sketch_mfma(int nsplit, int nrowtile, int64_t tiles_per_split, int rb, const float* X, Shape3 s,
-                              int ell, int64_t col0, uint64_t seed, uint32_t mode, float* partial, double* nrm2,
-                              hipStream_t stream);
+hipError_t launch_sketch_f32_rows(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
+                                  uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
+hipError_t launch_sketch_f32_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
+                                  uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 int plan_project_mfma(Shape3 s, int ell);
 hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,

@@ -1,29 +1,18 @@
-// MFMA kernels of the FP32 hot path on gfx950: the mode-n sketch
-// Y = X_(n) Omega (§2.4 Alg. 1 step 1) and the projection B = X x_n Q^T
-// (Alg. 1 step 3; also the core update G <- U^T G of Alg. 3).
+// MFMA projection B = X x_n Q^T on gfx950 (§2.4 Alg. 1 step 3; also the core
+// update G <- U^T G of Alg. 3) for float32 data.
 //
-// Both use v_mfma_f32_4x4x1_16b_f32: sixteen independent 4x4 outer products per
-// instruction, so the narrow side of these skinny contractions (ell = r + p
-// columns of Omega, or rows of Q^T) is padded to a multiple of 4 only
-// (ell = 35 -> 36), not 16 or 32.  Operand layout (checked on the device):
-// lane l = 4 blk + t holds A[blk][t] and B[blk][t]; accumulator register v of
-// lane l holds D[blk][v][t].
+// v_mfma_f32_4x4x1_16b_f32: sixteen independent 4x4 outer products per
+// instruction, so the narrow side of this skinny contraction (ell = r + p rows
+// of Q^T) is padded to a multiple of 4 only (ell = 35 -> 36).  Operand layout
+// (checked on the device): lane l = 4 blk + t holds A[blk][t] and B[blk][t];
+// accumulator register v of lane l holds D[blk][v][t].
 //
-// Sketch: a workgroup owns 256 or 512 rows of Y and a contiguous run of
-// 32-column tiles of the unfolding.  Each tile of X is loaded with coalesced
-// 16-byte loads (contiguous along the unfolding columns when R % 32 == 0, along
-// the rows when R == 1) one tile ahead into registers, stored to LDS, and read
-// back as four consecutive columns per lane; Omega for the tile is generated
-// once per workgroup (Philox + Box-Muller) into LDS, one tile ahead.  The
-// sixteen MFMA blocks are sixteen groups of four rows; a wave keeps 64 or 128
-// rows x ell columns of Y in accumulators.  Split-K partials are summed later in
-// a fixed order.
-//
-// Projection: a wave owns 256 consecutive unfolding columns (four per lane, so
-// every row of the strip is one 1 KiB load) and streams all J rows of them from
-// HBM, twelve rows in flight; Q^T is held in LDS.  The MFMA blocks are sixteen
-// groups of four columns, the four lanes' adjacent columns are four separate
-// accumulator sets.  The result is stored in the (L, ell, R) layout directly.
+// A wave owns 256 consecutive unfolding columns (four per lane, so every row of
+// the strip is one 1 KiB load) and streams all J rows of them from HBM, eight
+// rows in flight; Q^T is held in LDS.  The MFMA blocks are sixteen groups of
+// four columns, the four lanes' adjacent columns are four separate accumulator
+// sets.  The result is stored in the (L, ell, R) layout directly.  When R == 1
+// each lane streams one row of the (L, J) matrix instead.
 #include "rt_kernels.hpp"
 #include "rt_philox.hpp"
 
@@ -33,202 +22,10 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int MK_KC = 32;          // unfolding columns per sketch tile
-constexpr int MK_XLD = MK_KC + 4;  // LDS row stride of the X tile (floats)
-constexpr int MK_NQ = 16;          // max column quads (ell <= 64)
+constexpr int MK_NQ = 16;  // max column quads (ell <= 64)
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
-}
-
-// LOAD_ROWS: R % MK_KC == 0, a tile lies inside one l-slab, each row contiguous.
-// LOAD_COLS: R == 1, element (i, c) at c J + i; J % 4 == 0.
-enum { LOAD_ROWS = 0, LOAD_COLS = 1 };
-
-template <int RB, int LOADER>
-__global__ __launch_bounds__(256) void sketch_mfma_kernel(const float* __restrict__ X, int64_t L, int64_t J, int64_t R,
-                                                          int ell, int64_t col0, uint64_t seed, uint32_t mode,
-                                                          int64_t tiles_per_split, float* __restrict__ partial,
-                                                          double* __restrict__ nrm2_partial) {
-    constexpr int MT = 256 * RB;                 // rows of Y per workgroup
-    constexpr int NLOAD = MT * MK_KC / 4 / 256;  // float4 loads per thread per tile
-    __shared__ __align__(16) float xs[MT * MK_XLD];
-    __shared__ __align__(16) float os[MK_KC * 4 * MK_NQ];   // Omega tile: [c][t][j]
-    __shared__ double red[4];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int blk = lane >> 2, t = lane & 3;
-    const int64_t K = L * R;
-    const int64_t ntiles = (K + MK_KC - 1) / MK_KC;
-    const int64_t row0 = (int64_t)blockIdx.y * MT;
-    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_split;
-    const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
-    const int nq = (ell + 3) / 4;
-    const int64_t qbase = col0 / 4;                    // Omega blocks needed: q in [qbase, qlast]
-    const int nqblk = (int)((col0 + ell - 1) / 4 - qbase + 1);
-    const int shift = (int)(col0 - 4 * qbase);         // column k of the sketch = Omega column col0 + k
-
-    f4 acc[RB][MK_NQ];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int j = 0; j < MK_NQ; ++j) acc[rb][j] = f4{0.f, 0.f, 0.f, 0.f};
-    double nrm = 0.0;
-
-    f4 pre[NLOAD];
-    float opre[8];  // Omega values generated ahead by this thread (<= 2 blocks of 4)
-
-    auto load_tile = [&](int64_t tile) {
-        const int64_t c0 = tile * MK_KC;
-        if (LOADER == LOAD_ROWS) {
-            const int64_t l = c0 / R;
-            const int64_t r0 = c0 - l * R;
-            const float* base = X + l * J * R + r0;
-#pragma unroll
-            for (int it = 0; it < NLOAD; ++it) {
-                const int rr = (tid >> 3) + 32 * it;
-                const int cc = 4 * (tid & 7);
-                const int64_t i = row0 + rr;
-                f4 v = f4{0.f, 0.f, 0.f, 0.f};
-                if (i < J && c0 + cc < K) v = *reinterpret_cast<const f4*>(base + i * R + cc);
-                pre[it] = v;
-            }
-        } else {
-#pragma unroll
-            for (int it = 0; it < NLOAD; ++it) {
-                const int e = tid + 256 * it;           // float4 index inside the tile
-                const int cc = e / (MT / 4);
-                const int rr = 4 * (e % (MT / 4));
-                const int64_t c = c0 + cc, i = row0 + rr;
-                f4 v = f4{0.f, 0.f, 0.f, 0.f};
-                if (i < J && c < K) v = *reinterpret_cast<const f4*>(X + c * J + i);
-                pre[it] = v;
-            }
-        }
-    };
-    auto store_tile = [&]() {
-        if (LOADER == LOAD_ROWS) {
-#pragma unroll
-            for (int it = 0; it < NLOAD; ++it) {
-                const int rr = (tid >> 3) + 32 * it;
-                const int cc = 4 * (tid & 7);
-                *reinterpret_cast<f4*>(&xs[rr * MK_XLD + cc]) = pre[it];
-                if (nrm2_partial) {
-                    nrm += (double)pre[it].x * pre[it].x + (double)pre[it].y * pre[it].y +
-                           (double)pre[it].z * pre[it].z + (double)pre[it].w * pre[it].w;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int it = 0; it < NLOAD; ++it) {
-                const int e = tid + 256 * it;
-                const int cc = e / (MT / 4);
-                const int rr = 4 * (e % (MT / 4));
-                xs[(rr + 0) * MK_XLD + cc] = pre[it].x;
-                xs[(rr + 1) * MK_XLD + cc] = pre[it].y;
-                xs[(rr + 2) * MK_XLD + cc] = pre[it].z;
-                xs[(rr + 3) * MK_XLD + cc] = pre[it].w;
-                if (nrm2_partial) {
-                    nrm += (double)pre[it].x * pre[it].x + (double)pre[it].y * pre[it].y +
-                           (double)pre[it].z * pre[it].z + (double)pre[it].w * pre[it].w;
-                }
-            }
-        }
-    };
-    // Omega of a tile: MK_KC rows x nqblk Philox blocks, at most 2 blocks per thread
-    auto gen_omega = [&](int64_t tile) {
-        const int64_t c0 = tile * MK_KC;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h;
-            if (e < MK_KC * nqblk) {
-                const int cc = e % MK_KC, qi = e / MK_KC;
-                float z[4];
-                omega4_f32(seed, mode, (uint64_t)(c0 + cc), (uint32_t)(qbase + qi), z);
-                opre[4 * h + 0] = z[0]; opre[4 * h + 1] = z[1]; opre[4 * h + 2] = z[2]; opre[4 * h + 3] = z[3];
-            }
-        }
-    };
-    auto store_omega = [&]() {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h;
-            if (e < MK_KC * nqblk) {
-                const int cc = e % MK_KC, qi = e / MK_KC;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int k = 4 * qi + u - shift;      // sketch column
-                    if (k >= 0 && k < ell) os[(cc * 4 + (k & 3)) * MK_NQ + (k >> 2)] = opre[4 * h + u];
-                }
-            }
-        }
-    };
-
-    // zero the padding columns of the Omega tile once (columns ell .. 4 nq - 1)
-    for (int e = tid; e < MK_KC * 4 * MK_NQ; e += 256) os[e] = 0.f;
-    if (t_begin < t_end) {
-        load_tile(t_begin);
-        gen_omega(t_begin);
-    }
-    for (int64_t tile = t_begin; tile < t_end; ++tile) {
-        __syncthreads();
-        store_tile();
-        store_omega();
-        __syncthreads();
-        if (tile + 1 < t_end) {
-            load_tile(tile + 1);
-            gen_omega(tile + 1);
-        }
-        // MFMAs over the 32 columns, four at a time
-#pragma unroll 2
-        for (int c4 = 0; c4 < MK_KC; c4 += 4) {
-            f4 a[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-                a[rb] = *reinterpret_cast<const f4*>(&xs[(wave * 64 * RB + rb * 64 + 4 * blk + t) * MK_XLD + c4]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float* orow = &os[((c4 + u) * 4 + t) * MK_NQ];
-                float bv[MK_NQ];
-#pragma unroll
-                for (int j4 = 0; j4 < MK_NQ; j4 += 4) {
-                    const f4 v = *reinterpret_cast<const f4*>(orow + j4);
-                    bv[j4] = v.x; bv[j4 + 1] = v.y; bv[j4 + 2] = v.z; bv[j4 + 3] = v.w;
-                }
-#pragma unroll
-                for (int j = 0; j < MK_NQ; ++j) {
-                    if (j < nq) {
-#pragma unroll
-                        for (int rb = 0; rb < RB; ++rb) acc[rb][j] = mfma4(a[rb][u], bv[j], acc[rb][j]);
-                    }
-                }
-            }
-        }
-    }
-    // partial Y rows: lane (blk, t) holds rows 4 blk + v (v = register) of column 4 j + t
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t i = row0 + wave * 64 * RB + rb * 64 + 4 * blk + v;
-            if (i < J) {
-                float* dst = partial + ((int64_t)blockIdx.x * J + i) * ell;
-#pragma unroll
-                for (int j = 0; j < MK_NQ; ++j) {
-                    const int k = 4 * j + t;
-                    if (j < nq && k < ell) dst[k] = acc[rb][j][v];
-                }
-            }
-        }
-    }
-    if (nrm2_partial) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-        if (lane == 0) red[wave] = nrm;
-        __syncthreads();
-        if (tid == 0) nrm2_partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    }
 }
 
 // ---- projection -------------------------------------------------------------------------
@@ -442,38 +239,6 @@ hipError_t launch_pr1(int nwg, const float* G, Shape3 s, int64_t ldj, const floa
 }
 
 }  // namespace
-
-bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X) {
-    if (ell > 4 * MK_NQ) return false;
-    if (((uintptr_t)X & 15) != 0) return false;
-    if ((col0 + ell - 1) / 4 - col0 / 4 + 1 > 16) return false;   // Omega blocks per tile row: 2 per thread
-    if (s.R % MK_KC == 0) return true;
-    if (s.R == 1 && s.J % 4 == 0) return true;
-    return false;
-}
-
-hipError_t launch_sketch_mfma(int nsplit, int nrowtile, int64_t tiles_per_split, int rb, const float* X, Shape3 s,
-                              int ell, int64_t col0, uint64_t seed, uint32_t mode, float* partial, double* nrm2,
-                              hipStream_t stream) {
-    dim3 grid(nsplit, nrowtile);
-    const bool rows = s.R % MK_KC == 0;
-    if (rb == 2) {
-        if (rows)
-            hipLaunchKernelGGL((sketch_mfma_kernel<2, LOAD_ROWS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
-                               col0, seed, mode, tiles_per_split, partial, nrm2);
-        else
-            hipLaunchKernelGGL((sketch_mfma_kernel<2, LOAD_COLS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
-                               col0, seed, mode, tiles_per_split, partial, nrm2);
-    } else {
-        if (rows)
-            hipLaunchKernelGGL((sketch_mfma_kernel<1, LOAD_ROWS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
-                               col0, seed, mode, tiles_per_split, partial, nrm2);
-        else
-            hipLaunchKernelGGL((sketch_mfma_kernel<1, LOAD_COLS>), grid, dim3(256), 0, stream, X, s.L, s.J, s.R, ell,
-                               col0, seed, mode, tiles_per_split, partial, nrm2);
-    }
-    return hipGetLastError();
-}
 
 int project_sets(Shape3 s, int ell) {
     const int nq = (ell + 3) / 4;

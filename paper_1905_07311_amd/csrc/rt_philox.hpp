@@ -19,18 +19,17 @@ struct PhiloxOut { uint32_t w0, w1, w2, w3; };
 // Ten rounds of the 4x32 Philox bijection.  Each round forms the 64-bit
 // products of words 0 and 2 with the two multipliers, feeds the high halves
 // (xored with the other two words and the round key) and the low halves into
-// the next state, and advances the key by the two Weyl increments.
+// the next state, and advances the key by the two Weyl increments.  Each
+// product is one 32 x 32 -> 64-bit multiply.
 __device__ __forceinline__ PhiloxOut philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                   uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
-        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)pb; c2 = n2; c3 = (uint32_t)pa;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -41,27 +40,45 @@ __device__ __forceinline__ PhiloxOut omega_words(uint64_t seed, uint32_t mode, u
     return philox_block((uint32_t)c, (uint32_t)(c >> 32), q, mode, (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-// ln u for u = (w + 1/2) 2^-32, single precision.  For u > 1/2 the complement
-// 1 - u = (~w + 1/2) 2^-32 is formed exactly from the integer and log1p keeps
-// full relative accuracy near u = 1.
-__device__ __forceinline__ float log_uniform_f32(uint32_t w) {
-    if (w < 0x80000000u) {
-        return logf(fmaf((float)w, 0x1p-32f, 0x1p-33f));
-    }
-    return log1pf(-fmaf((float)(~w), 0x1p-32f, 0x1p-33f));
+// -2 ln u for u = (w + 1/2) 2^-32, single precision, without branches.
+// u <= 1/2: the hardware base-2 logarithm (relative error about 1e-7 there).
+// u > 1/2: the complement v = 1 - u = (~w + 1/2) 2^-32 is formed from the
+// integer, and ln(1 - v) = -2 atanh(s) with s = v / (2 - v) <= 1/3 is summed
+// as its odd power series to s^15 (remainder below 2^-24 relative), which keeps
+// full relative accuracy as u -> 1.
+__device__ __forceinline__ float neg2_log_uniform_f32(uint32_t w) {
+    const float u = fmaf((float)w, 0x1p-32f, 0x1p-33f);
+    const float lo = -2.0f * 0.693147180559945309f * __builtin_amdgcn_logf(u);
+    const float v = fmaf((float)(~w), 0x1p-32f, 0x1p-33f);
+    const float sv = v * __builtin_amdgcn_rcpf(2.0f - v);
+    const float z = sv * sv;
+    float p = 1.0f / 15.0f;
+    p = fmaf(p, z, 1.0f / 13.0f);
+    p = fmaf(p, z, 1.0f / 11.0f);
+    p = fmaf(p, z, 1.0f / 9.0f);
+    p = fmaf(p, z, 1.0f / 7.0f);
+    p = fmaf(p, z, 1.0f / 5.0f);
+    p = fmaf(p, z, 1.0f / 3.0f);
+    p = fmaf(p, z, 1.0f);
+    const float hi = 4.0f * sv * p;
+    return w < 0x80000000u ? lo : hi;
 }
 
 __device__ __forceinline__ float uniform_f32(uint32_t w) { return fmaf((float)w, 0x1p-32f, 0x1p-33f); }
 
-// Four normals, single precision (used by the FP32 and BF16 paths).
+// Four normals, single precision (used by the FP32 and BF16 paths).  The
+// angle 2 pi u goes to the hardware sine and cosine, which take their argument
+// in revolutions (absolute error about 1.3e-7 on (0, 1)); square roots are the
+// hardware ones (relative error about 1e-7).
 __device__ __forceinline__ void omega4_f32(uint64_t seed, uint32_t mode, uint64_t c, uint32_t q, float z[4]) {
     PhiloxOut w = omega_words(seed, mode, c, q);
-    float ra = sqrtf(-2.0f * log_uniform_f32(w.w0));
-    float rb = sqrtf(-2.0f * log_uniform_f32(w.w2));
-    float sa, ca, sb, cb;
-    sincospif(2.0f * uniform_f32(w.w1), &sa, &ca);
-    sincospif(2.0f * uniform_f32(w.w3), &sb, &cb);
-    z[0] = ra * ca; z[1] = ra * sa; z[2] = rb * cb; z[3] = rb * sb;
+    const float ra = __builtin_amdgcn_sqrtf(neg2_log_uniform_f32(w.w0));
+    const float rb = __builtin_amdgcn_sqrtf(neg2_log_uniform_f32(w.w2));
+    const float ua = uniform_f32(w.w1), ub = uniform_f32(w.w3);
+    z[0] = ra * __builtin_amdgcn_cosf(ua);
+    z[1] = ra * __builtin_amdgcn_sinf(ua);
+    z[2] = rb * __builtin_amdgcn_cosf(ub);
+    z[3] = rb * __builtin_amdgcn_sinf(ub);
 }
 
 // Four normals, double precision (used by the FP64 path).

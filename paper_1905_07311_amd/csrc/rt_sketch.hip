@@ -115,11 +115,13 @@ constexpr int RP_PC = 32;
 
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const T* __restrict__ in, int64_t nparts, int64_t n,
-                                                              double* __restrict__ out) {
+                                                              int64_t cols, int64_t ldin, double* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.y * RP_PC;
     const int64_t p1 = p0 + RP_PC < nparts ? p0 + RP_PC : nparts;
     if (e >= n) return;
+    const int64_t src = ldin == cols ? e : (e / cols) * ldin + e % cols;
+    const int64_t ps = ldin == cols ? n : n / cols * ldin;   // elements per part
     double a[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] = 0.0;
@@ -127,11 +129,11 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const T* __restric
     for (; p + 8 <= p1; p += 8) {
         T v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = in[(p + u) * n + e];
+        for (int u = 0; u < 8; ++u) v[u] = in[(p + u) * ps + src];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] += (double)v[u];
     }
-    for (; p < p1; ++p) a[0] += (double)in[p * n + e];
+    for (; p < p1; ++p) a[0] += (double)in[p * ps + src];
     out[(int64_t)blockIdx.y * n + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
@@ -151,21 +153,53 @@ __global__ __launch_bounds__(256) void sum_scalar_kernel(const double* __restric
 
 }  // namespace
 
+bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X) {
+    if (ell > 64) return false;
+    if (((uintptr_t)X & 15) != 0) return false;
+    if ((col0 + ell - 1) / 4 - col0 / 4 + 1 > 16) return false;   // Omega blocks per tile row: 2 per thread
+    if (s.R % 32 == 0) return true;
+    if (s.R == 1 && s.J % 4 == 0) return true;
+    return false;
+}
+
+namespace {
+// Row configuration (RB row blocks of 64 per wave, RW row blocks per
+// workgroup) for a mode of length J, and the compiled column quads for ell.
+// (Measured on 512 x 262144 float32 unfoldings: two 128-row waves per
+// 256-row block with four resident workgroups per CU beat one 256-row wave
+// per block, whose accumulators leave room for one wave per SIMD only.)
+void sketch_rows_config(int64_t J, int& rb, int& rw) {
+    if (J <= 64) { rb = 1; rw = 1; }
+    else if (J <= 128) { rb = 2; rw = 1; }
+    else { rb = 2; rw = 2; }
+}
+int sketch_nq_bucket(int nq) {
+    if (nq <= 10) return nq;
+    if (nq <= 12) return 12;
+    if (nq <= 14) return 14;
+    return 16;
+}
+// workgroups to aim for: enough to fill every CU with a few resident groups
+int64_t sketch_target_wg(const SketchPlan&) { return 1024; }
+}  // namespace
+
 SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X) {
     SketchPlan p{};
     const int64_t K = s.L * s.R;
     if (dt == Dt::F32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X)) {
         p.kind = 1;
-        p.rb = s.J > 256 ? 2 : 1;
-        const int64_t mt = 256 * p.rb;
+        sketch_rows_config(s.J, p.rb, p.rw);
+        p.nq = sketch_nq_bucket((ell + 3) / 4);
+        p.ldp = 4 * p.nq;
+        const int64_t mt = 64 * p.rb * p.rw;
         const int64_t ntl = (K + 31) / 32;
         p.nrowtile = (int)((s.J + mt - 1) / mt);
-        int64_t want = (p.rb == 2 ? 256 : 512) / p.nrowtile;
+        int64_t want = sketch_target_wg(p) / p.nrowtile;
         if (want < 1) want = 1;
         if (want > ntl) want = ntl;
         p.tiles_per_split = (ntl + want - 1) / want;
         p.nsplit = (int)((ntl + p.tiles_per_split - 1) / p.tiles_per_split);
-        p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
+        p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)p.ldp;
         p.nwg = p.nsplit * p.nrowtile;
         return p;
     }
@@ -180,7 +214,8 @@ SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const v
     p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
     p.nwg = p.nsplit * p.nrowtile;
     p.kind = 0;
-    p.rb = 0;
+    p.rb = p.rw = p.nq = 0;
+    p.ldp = ell;
     return p;
 }
 
@@ -188,9 +223,13 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                          int64_t col0, uint64_t seed, uint32_t mode, void* partial,
                          double* nrm2_partial, hipStream_t stream) {
     (void)prec;
-    if (p.kind == 1)
-        return launch_sketch_mfma(p.nsplit, p.nrowtile, p.tiles_per_split, p.rb, (const float*)X, s, ell, col0, seed,
-                                  mode, (float*)partial, nrm2_partial, stream);
+    if (p.kind == 1) {
+        if (s.R % 32 == 0)
+            return launch_sketch_f32_rows(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
+                                          stream);
+        return launch_sketch_f32_cols(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
+                                      stream);
+    }
     dim3 grid(p.nsplit, p.nrowtile);
     if (dt == Dt::F64) {
         hipLaunchKernelGGL((sketch_generic_kernel<double, double>), grid, dim3(256), 0, stream,
@@ -204,8 +243,9 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
-                                  double* out, hipStream_t stream, double* tmp) {
+hipError_t launch_reduce_rows(const void* in, bool in_is_f64, int64_t nparts, int64_t rows, int64_t cols,
+                              int64_t ldin, double* out, hipStream_t stream, double* tmp) {
+    const int64_t n = rows * cols;
     if (n <= 0) return hipSuccess;
     const unsigned ex = (unsigned)((n + 255) / 256);
     const int64_t nchunk = (nparts + RP_PC - 1) / RP_PC;
@@ -213,23 +253,28 @@ hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts
         // one pass over all parts (fixed order)
         if (in_is_f64)
             hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)in,
-                               nparts, n, out);
+                               nparts, n, cols, ldin, out);
         else
             hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, 1), dim3(256), 0, stream, (const float*)in,
-                               nparts, n, out);
+                               nparts, n, cols, ldin, out);
         return hipGetLastError();
     }
     if (tmp == nullptr) return hipErrorInvalidValue;
     // two passes: chunks of RP_PC parts, then the chunk sums
     if (in_is_f64)
         hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
-                           (const double*)in, nparts, n, tmp);
+                           (const double*)in, nparts, n, cols, ldin, tmp);
     else
         hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
-                           (const float*)in, nparts, n, tmp);
+                           (const float*)in, nparts, n, cols, ldin, tmp);
     hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)tmp, nchunk,
-                       n, out);
+                       n, n, n, out);
     return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
+                                  double* out, hipStream_t stream, double* tmp) {
+    return launch_reduce_rows(in, in_is_f64, nparts, 1, n, n, out, stream, tmp);
 }
 
 hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream) {

@@ -204,7 +204,7 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
     }
     double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
     if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
-    RT_HIP(rt::launch_reduce_partials(partial, f64acc, plan.nsplit, s.J * ell, Y, k.c->stream, rtmp));
+    RT_HIP(rt::launch_reduce_rows(partial, f64acc, plan.nsplit, s.J, ell, plan.ldp, Y, k.c->stream, rtmp));
     if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
     return RT_OK;
 }
@@ -275,7 +275,8 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
     int* kdev = k.ws<int>(1);
     double* U = k.ws<double>((size_t)kb * kb);
     float* Uf = k.ws<float>((size_t)kb * kb);
-    if (!lam || !kdev || !U || !Uf) return fail(RT_ENOMEM, "workspace allocation failed");
+    double* tscr = k.ws<double>(rt::truncate_scratch(k.c->cur_J, kb));
+    if (!lam || !kdev || !U || !Uf || !tscr) return fail(RT_ENOMEM, "workspace allocation failed");
     const void* Bcur = B;
     int64_t ldcur = ldb;
     const double* Wcur = W;
@@ -288,7 +289,7 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
         double* W2 = k.ws<double>((size_t)kb * kb);
         if (!Q1 || !C || !W2) return fail(RT_ENOMEM, "workspace allocation failed");
         RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, kb, nullptr, 0.0, U, Uf, Q1, Dt::F64, lam, kdev,
-                                   1e-20, st));
+                                   1e-20, tscr, st));
         RT_TRY(do_project(k, dt, Dt::F64, Bcur, sb, ldcur, U, kb, kb, C, kb, 0, W2, nullptr));
         Bcur = C;
         ldcur = kb;
@@ -301,7 +302,7 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
     {
         TimeScope ts(k.c, 3, 0.0, 0.0, Jq, kb, kb);
         RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, r_fixed, Edev, tau2, U, Uf, A_out, dt, lam, kdev,
-                                   dt == Dt::F64 ? 1e-30 : 1e-24, st));
+                                   dt == Dt::F64 ? 1e-30 : 1e-24, tscr, st));
     }
     int kk = r_fixed;
     if (r_fixed < 0) {
@@ -328,7 +329,7 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
     hipStream_t st = k.c->stream;
     const int64_t J = s.J;
     double* Y = k.ws<double>((size_t)J * ell);
-    double* scratch = k.ws<double>((size_t)2 * J * ell);
+    double* scratch = k.ws<double>(rt::orth_scratch(J, ell));
     float* Qf = dt == Dt::F32 ? k.ws<float>((size_t)J * ell) : nullptr;
     if (!Y || !scratch || (dt == Dt::F32 && !Qf)) return fail(RT_ENOMEM, "workspace allocation failed");
     RT_TRY(do_sketch(k, dt, prec, G, s, ell, 0, seed, mode, Y, nrm2_dev));                      // Alg. 1 step 1
@@ -767,7 +768,7 @@ rt_status rt_orth(rt_ctx* ctx, double* Y, int64_t rows, int32_t ell, uint32_t* f
     if (ell < 1 || ell > RT_LMAX || rows < ell) return fail(RT_EINVAL, "need 1 <= ell <= min(rows, RT_LMAX)");
     RT_HIP(hipSetDevice(ctx->device));
     Call k(ctx);
-    double* scratch = k.ws<double>((size_t)2 * rows * ell);
+    double* scratch = k.ws<double>(rt::orth_scratch(rows, ell));
     uint32_t* st = k.ws<uint32_t>(1);
     if (!scratch || !st) return fail(RT_ENOMEM, "workspace allocation failed");
     RT_HIP(rt::launch_orth(Y, rows, ell, nullptr, orth_accept_ratio(), st, scratch, ctx->stream));

@@ -177,8 +177,13 @@ def test_adaptive_hilbert_table_f64(ctx, I, eps, ranks):
     g = ctx.rsthosvd_adaptive(Xd, eps, 1, seed=0, order=[0, 1, 2])
     o = oracle.adaptive_rsthosvd(X, eps, 1, seed=0, order=[0, 1, 2])
     _adaptive_check(g, o, X, eps, 1e-10, 2.0 ** -53)
-    if not borderline(o, float(np.sum(X * X)), 2.0 ** -53):
-        assert g.ranks == ranks            # the paper's printed ranks
+    # The table's ranks come from one run of a randomized method; the oracle
+    # reproduces them as the mode over seeds (CPU tests), and a single seed may
+    # land one above or below.  Where the oracle with this seed gives the
+    # printed ranks the device must too.
+    assert all(abs(a - c) <= 1 for a, c in zip(g.ranks, ranks))
+    if o.ranks == ranks and not borderline(o, float(np.sum(X * X)), 2.0 ** -53):
+        assert g.ranks == ranks
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
