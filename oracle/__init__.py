@@ -19,6 +19,7 @@ from .randsvd import randsvd, orth_householder, sign_fix_columns
 from .tucker import (rhosvd, rsthosvd, hosvd, sthosvd, default_order, TuckerResult,
                      per_mode_residuals)
 from .adaptive import adapt_range_finder, adaptive_rsthosvd, adaptive_rhosvd
+from .precision import round_bf16
 
 __all__ = [
     "philox4x32_10", "omega_block", "omega", "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
@@ -27,4 +28,5 @@ __all__ = [
     "rhosvd", "rsthosvd", "hosvd", "sthosvd", "default_order", "TuckerResult",
     "per_mode_residuals",
     "adapt_range_finder", "adaptive_rsthosvd", "adaptive_rhosvd",
+    "round_bf16",
 ]

@@ -48,12 +48,17 @@ def orth_householder(Y):
     return Q * s, R * s[:, None]
 
 
-def randsvd(X, r, p, Omega):
-    """Alg. 1.  X: (m, n) matrix, Omega: (n, r + p).  Returns (U, S, V, Q)."""
+def randsvd(X, r, p, Omega, sketch_round=None):
+    """Alg. 1.  X: (m, n) matrix, Omega: (n, r + p).  Returns (U, S, V, Q).
+    sketch_round: optional rounding applied to both operands of step 1 only
+    (the reduced-precision sketch variant)."""
     X = np.asarray(X, dtype=np.float64)
     Omega = np.asarray(Omega, dtype=np.float64)
     assert Omega.shape == (X.shape[1], r + p)
-    Y = X @ Omega                       # step 1
+    if sketch_round is None:
+        Y = X @ Omega                   # step 1
+    else:
+        Y = sketch_round(X) @ sketch_round(Omega)
     Q, _ = orth_householder(Y)          # step 2
     B = Q.T @ X                         # step 3
     UB, s, Vt = np.linalg.svd(B, full_matrices=False)   # step 4

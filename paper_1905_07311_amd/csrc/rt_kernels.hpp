@@ -26,7 +26,7 @@ struct SketchPlan {
     int64_t tiles_per_split;
     size_t partial_elems;  // nsplit * J * ldp
     int nwg;               // nsplit * nrowtile
-    int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32
+    int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32, 2 MFMA bfloat16
     int rb;                // MFMA variant: 64-row blocks per wave (1, 2 or 4)
     int rw;                // MFMA variant: row blocks per workgroup (1 or 2)
     int nq;                // MFMA variant: compiled column quads (ell <= 4 nq)
@@ -116,6 +116,10 @@ hipError_t launch_sketch_f32_rows(const SketchPlan& p, const float* X, Shape3 s,
                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 hipError_t launch_sketch_f32_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
+hipError_t launch_sketch_bf16_rows(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
+                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
+hipError_t launch_sketch_bf16_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
+                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 int plan_project_mfma(Shape3 s, int ell);
 hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,

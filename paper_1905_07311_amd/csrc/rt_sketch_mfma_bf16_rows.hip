@@ -1,0 +1,10 @@
+// Instantiations of the bfloat16 MFMA sketch for unfoldings whose rows are
+// contiguous in memory (R % 32 == 0).
+#include "rt_sketch_mfma_launch.hpp"
+
+namespace rt {
+hipError_t launch_sketch_bf16_rows(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
+                                  uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream) {
+    return skm::launch_loader<skm::LOAD_ROWS, true>(p, X, s, ell, col0, seed, mode, partial, nrm2, stream);
+}
+}  // namespace rt

@@ -1,4 +1,4 @@
-// Compile-time dispatch of the FP32 MFMA sketch over (RB, RW, NQ).
+// Compile-time dispatch of the MFMA sketch over (RB, RW, NQ).
 #pragma once
 #include "rt_sketch_mfma.hpp"
 
@@ -17,41 +17,41 @@ struct SketchArgs {
     double* nrm2;
 };
 
-template <int LOADER, int RB, int RW, int NQ>
+template <int LOADER, bool BF, int RB, int RW, int NQ>
 hipError_t go(dim3 grid, const SketchArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL((sketch_f32_kernel<RB, RW, NQ, LOADER>), grid, dim3(256), 0, stream, a.X, a.s.L, a.s.J,
+    hipLaunchKernelGGL((sketch_f32_kernel<RB, RW, NQ, LOADER, BF>), grid, dim3(256), 0, stream, a.X, a.s.L, a.s.J,
                        a.s.R, a.ell, a.col0, a.seed, a.mode, a.tiles_per_split, a.partial, a.nrm2);
     return hipGetLastError();
 }
 
-template <int LOADER, int RB, int RW>
+template <int LOADER, bool BF, int RB, int RW>
 hipError_t by_nq(int nq, dim3 grid, const SketchArgs& a, hipStream_t st) {
     switch (nq) {
-        case 1: return go<LOADER, RB, RW, 1>(grid, a, st);
-        case 2: return go<LOADER, RB, RW, 2>(grid, a, st);
-        case 3: return go<LOADER, RB, RW, 3>(grid, a, st);
-        case 4: return go<LOADER, RB, RW, 4>(grid, a, st);
-        case 5: return go<LOADER, RB, RW, 5>(grid, a, st);
-        case 6: return go<LOADER, RB, RW, 6>(grid, a, st);
-        case 7: return go<LOADER, RB, RW, 7>(grid, a, st);
-        case 8: return go<LOADER, RB, RW, 8>(grid, a, st);
-        case 9: return go<LOADER, RB, RW, 9>(grid, a, st);
-        case 10: return go<LOADER, RB, RW, 10>(grid, a, st);
-        case 12: return go<LOADER, RB, RW, 12>(grid, a, st);
-        case 14: return go<LOADER, RB, RW, 14>(grid, a, st);
-        case 16: return go<LOADER, RB, RW, 16>(grid, a, st);
+        case 1: return go<LOADER, BF, RB, RW, 1>(grid, a, st);
+        case 2: return go<LOADER, BF, RB, RW, 2>(grid, a, st);
+        case 3: return go<LOADER, BF, RB, RW, 3>(grid, a, st);
+        case 4: return go<LOADER, BF, RB, RW, 4>(grid, a, st);
+        case 5: return go<LOADER, BF, RB, RW, 5>(grid, a, st);
+        case 6: return go<LOADER, BF, RB, RW, 6>(grid, a, st);
+        case 7: return go<LOADER, BF, RB, RW, 7>(grid, a, st);
+        case 8: return go<LOADER, BF, RB, RW, 8>(grid, a, st);
+        case 9: return go<LOADER, BF, RB, RW, 9>(grid, a, st);
+        case 10: return go<LOADER, BF, RB, RW, 10>(grid, a, st);
+        case 12: return go<LOADER, BF, RB, RW, 12>(grid, a, st);
+        case 14: return go<LOADER, BF, RB, RW, 14>(grid, a, st);
+        case 16: return go<LOADER, BF, RB, RW, 16>(grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int LOADER>
+template <int LOADER, bool BF>
 hipError_t launch_loader(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed,
                          uint32_t mode, float* partial, double* nrm2, hipStream_t stream) {
     const SketchArgs a{X, s, ell, col0, seed, mode, p.tiles_per_split, partial, nrm2};
     const dim3 grid(p.nsplit, p.nrowtile);
-    if (p.rb == 1 && p.rw == 1) return by_nq<LOADER, 1, 1>(p.nq, grid, a, stream);
-    if (p.rb == 2 && p.rw == 1) return by_nq<LOADER, 2, 1>(p.nq, grid, a, stream);
-    if (p.rb == 2 && p.rw == 2) return by_nq<LOADER, 2, 2>(p.nq, grid, a, stream);
+    if (p.rb == 1 && p.rw == 1) return by_nq<LOADER, BF, 1, 1>(p.nq, grid, a, stream);
+    if (p.rb == 2 && p.rw == 1) return by_nq<LOADER, BF, 2, 1>(p.nq, grid, a, stream);
+    if (p.rb == 2 && p.rw == 2) return by_nq<LOADER, BF, 2, 2>(p.nq, grid, a, stream);
     return hipErrorInvalidValue;
 }
 

@@ -24,3 +24,4 @@ def rel(a, b):
 
 def to_np(t):
     return t.detach().double().cpu().numpy()
+

@@ -160,6 +160,30 @@ def test_sketch_mfma_shapes(ctx, shape):
             assert abs(float(nrm.item()) - oracle.fro2(Xh)) <= 1e-10 * oracle.fro2(Xh)
 
 
+# bfloat16 sketch: the products of bfloat16-rounded X and Omega are exact in
+# float32, so against the same rounding done here in float64 the device differs
+# by float32 accumulation and by the rare Omega entries whose float32 value
+# rounds to the other neighbour (a few per million, one bfloat16 step each).
+BF16_SHAPES = MFMA_SHAPES + [(7, 24, 6), (5, 9, 33)]
+
+
+@pytest.mark.parametrize("shape", BF16_SHAPES)
+def test_sketch_bf16(ctx, shape):
+    rng = np.random.default_rng(sum(shape) + 3)
+    Xh = rng.standard_normal(shape).astype(np.float32)
+    X = torch.from_numpy(Xh).cuda()
+    for n in range(len(shape)):
+        M = oracle.unfold(Xh.astype(np.float64), n)
+        Mb = oracle.round_bf16(M)
+        for ell, col0 in ((min(40, shape[n]), 0), (min(13, shape[n]), 5), (1, 3)):
+            Y, nrm = ctx.sketch(X, n, ell, seed=11, col0=col0, prec="bf16", want_norm=True)
+            Om = oracle.omega(11, n, M.shape[1], range(col0, col0 + ell))
+            Yg = to_np(Y)
+            assert rel(Yg, Mb @ oracle.round_bf16(Om)) < 5e-5, (shape, n, ell, col0)
+            assert rel(Yg, M @ Om) < 2e-2, (shape, n, ell, col0)
+            assert abs(float(nrm.item()) - oracle.fro2(Xh)) <= 1e-10 * oracle.fro2(Xh)
+
+
 @pytest.mark.parametrize("shape", MFMA_SHAPES)
 def test_projection_mfma_shapes(ctx, shape):
     rng = np.random.default_rng(sum(shape) + 2)

@@ -85,6 +85,29 @@ def test_four_way_keep_and_order(ctx):
     _check(gd, od, X, 1e-10)
 
 
+@pytest.mark.parametrize("alg", ["rsthosvd", "rhosvd"])
+def test_bf16_sketch_decomposition(ctx, alg):
+    """BF16 sketch (the precision of the 128^4 workload): the sketch multiplies
+    bfloat16-rounded X and Omega, the rest runs in float32.  Parity with the
+    oracle's rounded-sketch variant (same Omega, same rounding, float64
+    elsewhere); the error stays within 1e-2 of the exact-sketch oracle."""
+    rng = np.random.default_rng(9)
+    ranks = [8, 7, 6, 5]
+    X = inputs.lowrank_tensor(rng, (48, 40, 36, 32), ranks, noise=1e-6,
+                              core_scale=inputs.graded_scale(ranks, 0.8))
+    Xs = X.astype(np.float32)
+    Xf = Xs.astype(np.float64)
+    g = getattr(ctx, alg)(torch.from_numpy(Xs).cuda(), ranks, 4, seed=12, prec="bf16")
+    o = getattr(oracle, alg)(Xf, ranks, 4, seed=12, sketch_round=oracle.round_bf16)
+    assert g.ranks == o.ranks
+    nx = np.linalg.norm(Xf)
+    assert np.linalg.norm(to_np(g.reconstruct()) - o.reconstruct()) / nx < 1e-4
+    for A, B in zip(g.factors, o.factors):
+        assert projector_dist(to_np(A), B) < 1e-3
+    exact = getattr(oracle, alg)(Xf, ranks, 4, seed=12)
+    assert np.linalg.norm(to_np(g.reconstruct()) - Xf) / nx < np.linalg.norm(exact.reconstruct() - Xf) / nx + 1e-2
+
+
 def test_exact_recovery_f64(ctx):
     rng = np.random.default_rng(5)
     X = inputs.lowrank_tensor(rng, (30, 25, 20), (3, 4, 5))
