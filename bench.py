@@ -15,7 +15,15 @@ Prints one JSON line:
                workload, Omega generation included), in the same unit.
   plus tensors/s and p50/p99 per-step latency.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4] [--no-cpu]
+Workload c5 (serving) instead times the continuous-batching server on 1024
+adaptive requests (sides uniform in [32, 256], exact Tucker ranks uniform in
+[4, 32] plus 1e-6 noise, eps = 1e-3, b = 8): value = completed tensors/s with
+all requests queued at once, beside the plain per-tensor float32 path (one
+request after another on one stream, host copies included) and the p50/p99
+latency of an open-loop run with Poisson arrivals at 400/s.  Every result of
+both paths is checked against a direct fp64 residual <= 1e-3.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu]
 """
 import argparse
 import json
@@ -76,6 +84,9 @@ WORKLOADS = {
                p=10, seed=2, prec="bf16", algo="rsthosvd"),
     "c4": dict(desc="adaptive R-STHOSVD, dense 48^5 float32 odeco tensor with mode spectra 0.7^k, eps=1e-3, b=8",
                dims=(48,) * 5, eps=1e-3, block=8, seed=3, prec="f32", algo="adaptive"),
+    "c5": dict(desc="serving: 1024 adaptive R-STHOSVD requests, dense 3-way float32, sides U[32,256], exact Tucker "
+                    "ranks U[4,32] + 1e-6 N(0,1), eps=1e-3, b=8, BF16 sketch, Poisson arrivals at 400/s",
+               nreq=1024, rate=400.0, eps=1e-3, block=8, prec="bf16", slots=8, pool=256, algo="serving"),
 }
 
 
@@ -127,6 +138,122 @@ def cpu_baseline(name, X_host):
                       f"explicit Omega generation included)", "seconds_per_call": dt}
 
 
+def run_serving(args):
+    """Workload c5: the continuous-batching server against the plain per-tensor path."""
+    import numpy as np
+    import torch
+    from paper_1905_07311_amd import inputs, rtucker
+    w = WORKLOADS["c5"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    arrivals, sides, ranks = inputs.serving_schedule(nreq=w["nreq"], rate=w["rate"])
+    # a pool of distinct tensors drawn from the same shape/rank distribution,
+    # request i uses pool entry i mod pool with its own Omega seed
+    pool = []
+    for i in range(min(w["pool"], w["nreq"])):
+        Xd = inputs.lowrank_device(inputs.config_seed(5) * 1000 + i, tuple(sides[i]), tuple(ranks[i]), dev,
+                                   torch.float32, noise=1e-6)
+        pool.append(Xd.cpu().pin_memory())
+    torch.cuda.synchronize()
+    reqs = [(pool[i % len(pool)], 9000 + i) for i in range(w["nreq"])]
+    nent = float(np.mean([X.numel() for X, _ in reqs]))
+
+    def residual(X, core, factors):
+        Xg = X.to(dev, dtype=torch.float64)
+        H = torch.from_numpy(np.asarray(core, dtype=np.float64)).to(dev)
+        for n, A in enumerate(factors):
+            H = torch.movedim(torch.tensordot(torch.from_numpy(np.asarray(A, dtype=np.float64)).to(dev), H,
+                                              dims=([1], [n])), 0, n)
+        return float(torch.linalg.norm((H - Xg).reshape(-1)) / torch.linalg.norm(Xg.reshape(-1)))
+
+    # plain per-tensor float32 path: one request after another on one stream, host copies included
+    ctx = rtucker.Context(0)
+    for X, s in reqs[:4]:
+        ctx.rsthosvd_adaptive(X.to(dev, non_blocking=True), w["eps"], w["block"], s)
+    torch.cuda.synchronize()
+    plain_err = 0.0
+    t0 = time.perf_counter()
+    plain_out = []
+    for X, s in reqs:
+        g = ctx.rsthosvd_adaptive(X.to(dev, non_blocking=True), w["eps"], w["block"], s, prec="f32")
+        plain_out.append((g.core.cpu().numpy(), [A.cpu().numpy() for A in g.factors]))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for (X, _), (core, fac) in zip(reqs, plain_out):
+        plain_err = max(plain_err, residual(X, core, fac))
+    del plain_out
+    ctx.close()
+
+    # server, closed loop: every request queued at once
+    srv = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec=w["prec"])
+    for X, s in reqs[:2 * w["slots"]]:
+        srv.wait(srv.submit(X, s))
+    t0 = time.perf_counter()
+    tickets = [srv.submit(X, s) for X, s in reqs]
+    served = [srv.wait(t) for t in tickets]
+    t_srv = time.perf_counter() - t0
+    srv_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, served))
+    statuses = {}
+    for r in served:
+        statuses[str(r.status)] = statuses.get(str(r.status), 0) + 1
+    del served
+    # server, open loop: Poisson arrivals at the workload rate
+    t0 = time.perf_counter()
+    tickets = []
+    for (X, s), ta in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(srv.submit(X, s))
+    open_res = [srv.wait(t) for t in tickets]
+    t_open = time.perf_counter() - t0
+    srv.close()
+    # the same server with float32 sketches
+    srv32 = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec="f32")
+    for X, s in reqs[:2 * w["slots"]]:
+        srv32.wait(srv32.submit(X, s))
+    t0 = time.perf_counter()
+    tickets = [srv32.submit(X, s) for X, s in reqs]
+    served32 = [srv32.wait(t) for t in tickets]
+    t_srv32 = time.perf_counter() - t0
+    srv32.close()
+    srv32_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, served32))
+    del served32
+    lat = np.array([r.latency_s for r in open_res])
+    open_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, open_res))
+    value = w["nreq"] / t_srv
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "tensors/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(t_srv * 1e3, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "requests": w["nreq"], "slots": w["slots"],
+                   "distinct_tensors": len(pool), "mean_entries": round(nent), "parallelism": "single-gpu"},
+        "plain_f32_tensors_per_s": round(w["nreq"] / t_plain, 2),
+        "served_f32_sketch_tensors_per_s": round(w["nreq"] / t_srv32, 2),
+        "request_status_counts": statuses,
+        "speedup_vs_plain": round(t_plain / t_srv, 3),
+        "open_loop": {"rate_per_s": w["rate"], "achieved_per_s": round(w["nreq"] / t_open, 2),
+                      "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                      "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+        "max_rel_err": {"served_closed": srv_err, "served_open": open_err, "served_f32_sketch": srv32_err,
+                        "plain": plain_err},
+        "roofline": None,
+    }
+    if not args.no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_info
+        t0 = time.perf_counter()
+        nsamp = 8
+        for X, s in reqs[:nsamp]:
+            oracle.adaptive_rsthosvd(X.numpy().astype(np.float64), w["eps"], w["block"], s)
+        dt = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        out["cpu_baseline"] = {"value": round(nsamp / dt, 3), "unit": "tensors/s", "cores": int(threads),
+                               "kind": "oracle", "sample": f"the first {nsamp} requests, one after another "
+                                                           f"(float64 NumPy/LAPACK), {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +266,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only: the multi-GPU layout is design-only "
                                    "(see the sharding note in DESIGN.md); use --gpus 1"}))
         sys.exit(2)
+    if args.workload == "c5":
+        run_serving(args)
+        return
     import numpy as np
     import torch
     from paper_1905_07311_amd import rtucker

@@ -56,7 +56,10 @@ typedef enum { RT_F32 = 0, RT_F64 = 1 } rt_dtype;
  *               accumulation; Gram matrices, Cholesky, eigenproblems in float64.
  *  RT_PREC_BF16_SKETCH: as RT_PREC_F32 but the sketch multiplies bfloat16-rounded
  *               X and Omega (float32 accumulation); orth, projection and
- *               truncation stay float32/float64. */
+ *               truncation stay float32/float64.  In the adaptive call a
+ *               block keeps only directions above 1e-2 of its norm (the
+ *               bfloat16 noise lies below), and once a bfloat16 block adds no
+ *               direction the mode continues with float32 sketches. */
 typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_precision;
 
 #define RT_MAXD 8
@@ -202,6 +205,58 @@ rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, dou
 
 /* Block until the context's stream is idle. */
 rt_status rt_sync(rt_ctx* ctx);
+
+/* ---- serving: continuous batching of many requests --------------------------- */
+/* A server runs adaptive R-STHOSVD (Alg. 5, §4) on a stream of float32 tensors of
+ * uneven shapes.  Requests wait in arrival order and are admitted to one of
+ * `max_inflight` slots as soon as a slot is free and the estimated device
+ * memory of the admitted requests stays within `hbm_budget`; every slot has its
+ * own stream, workspace and cached device memory, so the work of admitted
+ * requests overlaps on the device while later requests keep arriving.  A
+ * request's result does not depend on what else is in flight (the kernels'
+ * reductions have a fixed order). */
+typedef struct rt_server rt_server;
+
+typedef struct {
+    int32_t max_inflight;     /* slots: 1 .. 64 */
+    size_t hbm_budget;        /* bytes; 0 = 3/4 of the device memory free at creation */
+    rt_precision prec;        /* RT_PREC_F32 or RT_PREC_BF16_SKETCH */
+    double eps;               /* relative tolerance of every request (eps_n = eps / sqrt(d)) */
+    int32_t block;            /* adaptive block size, 1 .. RT_LMAX */
+} rt_server_opts;
+
+typedef struct {
+    rt_status status;         /* of the request's computation */
+    int32_t ndim;
+    int64_t dims[RT_MAXD];
+    int32_t ranks[RT_MAXD];
+    const float* core;        /* host, row-major core, owned by the server until rt_server_release */
+    const float* factors[RT_MAXD];  /* host, row-major dims[j] x ranks[j] */
+    double norm_x, core_norm, rel_err_est;
+    uint32_t flags;
+    double queue_s;           /* submission -> admission, seconds */
+    double latency_s;         /* submission -> result on the host, seconds */
+} rt_result;
+
+/* Start a server on `device` (its threads and streams live until destroy). */
+rt_status rt_server_create(rt_server** srv, int device, const rt_server_opts* opts);
+
+/* Queue a request.  X->data is HOST memory (float32, dense row-major) that must
+ * stay valid and unchanged until the request completes; page-locked memory lets
+ * the copy to the device overlap other work.  *ticket identifies the request. */
+rt_status rt_server_submit(rt_server* srv, const rt_tensor* X, uint64_t seed, uint64_t* ticket);
+
+/* *done = 1 and *out filled when the request has completed, else *done = 0. */
+rt_status rt_server_poll(rt_server* srv, uint64_t ticket, int32_t* done, rt_result* out);
+
+/* Block until the request has completed, then fill *out. */
+rt_status rt_server_wait(rt_server* srv, uint64_t ticket, rt_result* out);
+
+/* Free the host result of a completed request (its pointers become invalid). */
+rt_status rt_server_release(rt_server* srv, uint64_t ticket);
+
+/* Finish the queued requests, stop the threads, free all memory. */
+rt_status rt_server_destroy(rt_server* srv);
 
 #ifdef __cplusplus
 }

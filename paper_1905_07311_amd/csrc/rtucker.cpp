@@ -44,6 +44,11 @@ Dt dt_of(rt_dtype t) { return t == RT_F64 ? Dt::F64 : Dt::F32; }
 
 }  // namespace
 
+namespace rt {
+// error message of the calling thread, for the other translation units of the library
+rt_status set_error(rt_status s, const char* msg) { return fail(s, msg); }
+}  // namespace rt
+
 struct rt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -641,6 +646,11 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     const int prec = (int)opts->prec;
     const size_t es = dsize(X->dtype);
     const double drop = X->dtype == RT_F64 ? 1e-10 : 1e-5;
+    // With the bfloat16 sketch a block's directions below ~1e-3 of its norm are
+    // sketch noise: such blocks use a drop threshold above that level, and once a
+    // bfloat16 block resolves no new direction the mode continues with float32
+    // sketches, so the tolerance is still met.
+    const double drop_bf16 = 1e-2;
     init_out(out, X);
     std::vector<int64_t> dims(X->dims, X->dims + d);
     double* nx2 = k.ws<double>(1);
@@ -681,24 +691,41 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         double E = cur_norm2;
         int kcols = 0, blk = 0;
         bool stop_cap = false;
-        while (E > tau2) {                                  // AdaptRangeFinder block loop
-            if (kcols >= cap) { stop_cap = true; break; }
-            const int bi = std::min(block, cap - kcols);
-            rt_status rs = do_sketch(k, dt, prec, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y, nullptr);
-            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
-            RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, drop, kdev, scratch, st));
-            RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
-            RT_HIP(hipStreamSynchronize(st));
-            int kn = 0;
-            std::memcpy(&kn, h + 1, sizeof(int));
-            ++blk;
-            if (kn <= 0) break;                              // range exhausted
-            rs = do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
-            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
-            RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
-            RT_HIP(hipStreamSynchronize(st));
-            E -= h[2];                                       // E <- E - ||B_i||^2
-            kcols += kn;
+        int prec_cur = prec;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            E = cur_norm2;
+            kcols = 0;
+            blk = 0;
+            stop_cap = false;
+            prec_cur = attempt == 0 ? prec : (int)RT_PREC_F32;
+            while (E > tau2) {                                  // AdaptRangeFinder block loop
+                if (kcols >= cap) { stop_cap = true; break; }
+                const int bi = std::min(block, cap - kcols);
+                rt_status rs = do_sketch(k, dt, prec_cur, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y, nullptr);
+                if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+                RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop,
+                                             kdev, scratch, st));
+                RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
+                RT_HIP(hipStreamSynchronize(st));
+                int kn = 0;
+                std::memcpy(&kn, h + 1, sizeof(int));
+                ++blk;
+                if (kn <= 0 && prec_cur == RT_PREC_BF16_SKETCH) {   // bfloat16 resolves nothing more
+                    prec_cur = RT_PREC_F32;
+                    continue;
+                }
+                if (kn <= 0) break;                              // range exhausted
+                rs = do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
+                if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+                RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
+                RT_HIP(hipStreamSynchronize(st));
+                E -= h[2];                                       // E <- E - ||B_i||^2
+                kcols += kn;
+            }
+            // A mode whose columns all went into a basis carrying the bfloat16
+            // sketch's ~1e-3 subspace error (rank cap = K) may stop above the
+            // tolerance: it is redone with float32 sketches.
+            if (!(stop_cap && E > tau2 && prec == RT_PREC_BF16_SKETCH)) break;
         }
         if (stop_cap && E > tau2) capped = true;
         // SVD post-truncation: smallest k with max(E,0) + tail <= tau2

@@ -26,7 +26,9 @@ RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
             "rt_rsthosvd_adaptive", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
-            "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry"]
+            "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry",
+            "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
+            "rt_server_destroy"]
 
 
 class RtError(RuntimeError):
@@ -50,6 +52,19 @@ class rt_tucker(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("core", ctypes.c_void_p), ("factors", ctypes.c_void_p * RT_MAXD),
                 ("norm_x", ctypes.c_double), ("core_norm", ctypes.c_double), ("rel_err_est", ctypes.c_double),
                 ("flags", ctypes.c_uint32)]
+
+
+class rt_server_opts(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("prec", ctypes.c_int),
+                ("eps", ctypes.c_double), ("block", ctypes.c_int32)]
+
+
+class rt_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD),
+                ("ranks", ctypes.c_int32 * RT_MAXD), ("core", ctypes.POINTER(ctypes.c_float)),
+                ("factors", ctypes.POINTER(ctypes.c_float) * RT_MAXD), ("norm_x", ctypes.c_double),
+                ("core_norm", ctypes.c_double), ("rel_err_est", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -95,6 +110,12 @@ def load(path=None):
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.rt_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(rt_server_opts)]
+    lib.rt_server_submit.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_result)]
+    lib.rt_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(rt_result)]
+    lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.rt_server_destroy.argtypes = [P]
     for fn in EXPORTED:
         if fn not in ("rt_version", "rt_last_error"):
             getattr(lib, fn).restype = ctypes.c_int
@@ -349,3 +370,102 @@ def rhosvd(X, ranks, p, seed, prec=None):
 
 def rsthosvd_adaptive(X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):
     return context(X.device.index).rsthosvd_adaptive(X, eps, block, seed, order, eps_per_mode, max_rank, prec)
+
+
+@dataclass
+class ServedResult:
+    """Host copy of one served request: float32 numpy core and factors."""
+    status: int
+    ranks: List[int]
+    core: "object"
+    factors: List["object"]
+    norm_x: float
+    core_norm: float
+    rel_err_est: float
+    flags: int
+    queue_s: float
+    latency_s: float
+
+    def reconstruct(self):
+        import numpy as np
+        X = np.asarray(self.core, dtype=np.float64)
+        for n, A in enumerate(self.factors):
+            if A is not None:
+                X = np.moveaxis(np.tensordot(np.asarray(A, dtype=np.float64), X, axes=([1], [n])), 0, n)
+        return X
+
+
+class Server:
+    """Continuous-batching server of adaptive R-STHOSVD requests (float32 host
+    tensors in, host results out).  submit() takes a CPU float32 tensor (ideally
+    page-locked) that must stay alive until the request completes."""
+
+    def __init__(self, device=0, max_inflight=8, eps=1e-3, block=8, prec="f32", hbm_budget=0):
+        load()
+        o = rt_server_opts()
+        o.max_inflight = int(max_inflight)
+        o.hbm_budget = int(hbm_budget)
+        o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        o.eps = float(eps)
+        o.block = int(block)
+        self.srv = ctypes.c_void_p()
+        _check(_lib.rt_server_create(ctypes.byref(self.srv), int(device), ctypes.byref(o)))
+        self._keep = {}
+
+    def submit(self, X, seed):
+        import torch
+        if X.device.type != "cpu" or X.dtype != torch.float32 or not X.is_contiguous():
+            raise ValueError("X must be a contiguous float32 CPU tensor")
+        t = rt_tensor()
+        t.ndim = X.dim()
+        for i, s in enumerate(X.shape):
+            t.dims[i] = int(s)
+        t.dtype = RT_F32
+        t.data = X.data_ptr()
+        ticket = ctypes.c_uint64(0)
+        _check(_lib.rt_server_submit(self.srv, ctypes.byref(t), int(seed) & ((1 << 64) - 1), ctypes.byref(ticket)))
+        self._keep[ticket.value] = X
+        return ticket.value
+
+    def _take(self, ticket, r):
+        import numpy as np
+        ranks = [int(r.ranks[i]) for i in range(r.ndim)]
+        dims = [int(r.dims[i]) for i in range(r.ndim)]
+        core = factors = None
+        if r.status in (RT_OK, RT_ECAP):
+            core = np.ctypeslib.as_array(r.core, shape=(int(np.prod(ranks)),)).copy().reshape(ranks)
+            factors = []
+            for i in range(r.ndim):
+                if r.factors[i]:
+                    factors.append(np.ctypeslib.as_array(r.factors[i], shape=(dims[i] * ranks[i],)).copy()
+                                   .reshape(dims[i], ranks[i]))
+                else:
+                    factors.append(None)
+        out = ServedResult(int(r.status), ranks, core, factors, r.norm_x, r.core_norm, r.rel_err_est, int(r.flags),
+                           r.queue_s, r.latency_s)
+        _check(_lib.rt_server_release(self.srv, ctypes.c_uint64(ticket)))
+        self._keep.pop(ticket, None)
+        return out
+
+    def poll(self, ticket):
+        done = ctypes.c_int32(0)
+        r = rt_result()
+        _check(_lib.rt_server_poll(self.srv, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(r)))
+        return self._take(ticket, r) if done.value else None
+
+    def wait(self, ticket):
+        r = rt_result()
+        _check(_lib.rt_server_wait(self.srv, ctypes.c_uint64(ticket), ctypes.byref(r)), allow=(RT_ECAP,))
+        return self._take(ticket, r)
+
+    def close(self):
+        if getattr(self, "srv", None) and _lib is not None:
+            _lib.rt_server_destroy(self.srv)
+            self.srv = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -46,6 +46,17 @@ def test_argument_errors_are_synchronous():
     assert lib.rt_create(ctypes.byref(ctx), 0, None, rtucker.ALLOC_FN(lambda n, u: 0), rtucker.FREE_FN(0),
                          None) == rtucker.RT_EINVAL
     assert lib.rt_sync(None) == rtucker.RT_EINVAL
+    # serving: argument errors before any thread or device call
+    srv = ctypes.c_void_p()
+    o = rtucker.rt_server_opts()
+    o.max_inflight, o.prec, o.eps, o.block = 0, rtucker.PREC["f32"], 1e-3, 8
+    assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
+    o.max_inflight, o.prec = 4, rtucker.PREC["f64"]
+    assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
+    o.prec, o.block = rtucker.PREC["f32"], 0
+    assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
+    assert lib.rt_server_submit(None, None, 0, None) == rtucker.RT_EINVAL
+    assert lib.rt_server_destroy(None) == rtucker.RT_OK
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -64,6 +75,10 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(rt_opts), offsetof(rt_opts, order), offsetof(rt_opts, prec));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_tucker), offsetof(rt_tucker, core), offsetof(rt_tucker, factors),
          offsetof(rt_tucker, norm_x), offsetof(rt_tucker, flags));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_server_opts), offsetof(rt_server_opts, hbm_budget),
+         offsetof(rt_server_opts, prec), offsetof(rt_server_opts, eps), offsetof(rt_server_opts, block));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_result), offsetof(rt_result, ranks), offsetof(rt_result, core),
+         offsetof(rt_result, factors), offsetof(rt_result, flags), offsetof(rt_result, latency_s));
   return 0;
 }
 """)
@@ -75,3 +90,8 @@ int main(void) {
     assert [int(v) for v in lines[1].split()] == [ctypes.sizeof(O), O.order.offset, O.prec.offset]
     assert [int(v) for v in lines[2].split()] == [ctypes.sizeof(K), K.core.offset, K.factors.offset,
                                                  K.norm_x.offset, K.flags.offset]
+    S, R = rtucker.rt_server_opts, rtucker.rt_result
+    assert [int(v) for v in lines[3].split()] == [ctypes.sizeof(S), S.hbm_budget.offset, S.prec.offset,
+                                                 S.eps.offset, S.block.offset]
+    assert [int(v) for v in lines[4].split()] == [ctypes.sizeof(R), R.ranks.offset, R.core.offset,
+                                                 R.factors.offset, R.flags.offset, R.latency_s.offset]

@@ -1,0 +1,101 @@
+"""GPU tests of the serving path: continuous batching of adaptive R-STHOSVD
+requests (Alg. 5, §4) of uneven shapes and ranks.
+
+* every result meets the tolerance, ||X - X_hat|| <= eps ||X|| (direct fp64
+  residual on the host), in float32 and with the bfloat16 sketch;
+* a request's result is the same alone and in the mix (the kernels' reductions
+  have a fixed order, so the comparison is exact);
+* the ranks agree with the single-call adaptive entry point on the same data.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1905_07311_amd import inputs, rtucker
+from gpu_common import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n, seed=77):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        dims = tuple(int(v) for v in rng.integers(24, 72, size=3))
+        ranks = tuple(int(min(v, d)) for v, d in zip(rng.integers(3, 12, size=3), dims))
+        X = inputs.serving_request_host(1000 + i, dims, ranks)
+        reqs.append((torch.from_numpy(X).pin_memory(), 500 + i))
+    return reqs
+
+
+def _rel_err(res, X):
+    Xf = X.numpy().astype(np.float64)
+    return np.linalg.norm(res.reconstruct() - Xf) / np.linalg.norm(Xf)
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    need_gpu()
+    return _requests(12)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_served_results_meet_tolerance(reqs, prec):
+    eps = 1e-3
+    srv = rtucker.Server(max_inflight=4, eps=eps, block=8, prec=prec)
+    try:
+        tickets = [srv.submit(X, s) for X, s in reqs]
+        for (X, _), t in zip(reqs, tickets):
+            r = srv.wait(t)
+            assert r.status == rtucker.RT_OK
+            assert _rel_err(r, X) <= eps
+            assert r.latency_s >= r.queue_s >= 0.0
+    finally:
+        srv.close()
+
+
+def test_alone_equals_mix(reqs):
+    alone = rtucker.Server(max_inflight=1, eps=1e-3, block=8)
+    mix = rtucker.Server(max_inflight=6, eps=1e-3, block=8)
+    try:
+        solo = [alone.wait(alone.submit(X, s)) for X, s in reqs]           # one at a time
+        tickets = [mix.submit(X, s) for X, s in reqs]                       # all in flight together
+        both = [mix.wait(t) for t in tickets]
+        for a, b in zip(solo, both):
+            assert a.ranks == b.ranks
+            assert np.array_equal(a.core, b.core)
+            for fa, fb in zip(a.factors, b.factors):
+                assert np.array_equal(fa, fb)
+    finally:
+        alone.close()
+        mix.close()
+
+
+def test_served_matches_single_call(reqs):
+    ctx = rtucker.Context(0)
+    srv = rtucker.Server(max_inflight=3, eps=1e-3, block=8)
+    try:
+        tickets = [srv.submit(X, s) for X, s in reqs[:6]]
+        for (X, s), t in zip(reqs[:6], tickets):
+            r = srv.wait(t)
+            g = ctx.rsthosvd_adaptive(X.cuda(), 1e-3, 8, seed=s)
+            assert r.ranks == g.ranks
+            assert np.allclose(r.reconstruct(), g.reconstruct().double().cpu().numpy(), rtol=0, atol=1e-6 * r.norm_x)
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_budget_admission_and_release():
+    need_gpu()
+    X = torch.from_numpy(inputs.serving_request_host(7, (40, 30, 20), (5, 4, 3))).pin_memory()
+    # a budget below one request's footprint still admits it when nothing else is in flight
+    srv = rtucker.Server(max_inflight=2, eps=1e-3, block=4, hbm_budget=1)
+    try:
+        ts = [srv.submit(X, k) for k in range(3)]
+        rs = [srv.wait(t) for t in ts]
+        assert all(r.status == rtucker.RT_OK for r in rs)
+        with pytest.raises(rtucker.RtError):
+            srv.poll(ts[0])                 # released by wait()
+    finally:
+        srv.close()
