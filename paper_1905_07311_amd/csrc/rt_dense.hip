@@ -39,8 +39,28 @@ __device__ double wave_sum(double v) {
     return v;
 }
 
+
+// dst[e] = src(e) for e < n by `nthr` threads with PER loads in flight per
+// thread (all issued before the first store), for the small staging copies.
+template <int PER, typename F, typename G>
+__device__ __forceinline__ void batched_copy(int n, int tid, int nthr, F load, G store) {
+    for (int e0 = 0; e0 < n; e0 += PER * nthr) {
+        double v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + u * nthr + tid;
+            v[u] = e < n ? load(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + u * nthr + tid;
+            if (e < n) store(e, v[u]);
+        }
+    }
+}
+
 // Sum over the workgroup (every thread gets the result).
-__device__ double blk_sum(double v, double* red) {
+__device__ __forceinline__ double blk_sum(double v, double* red) {
     const int tid = threadIdx.x;
     v = wave_sum(v);
     __syncthreads();
@@ -551,129 +571,115 @@ __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, 
 // fix (each column of A and U flipped so that its largest-|.| entry, lowest
 // row on ties, is positive) applied to A and written into U.
 
-// Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS).  The round-robin
-// pairing of the m = n + (n odd) indices is tabulated once.  A step costs two
-// barriers: in phase A the half = m/2 pair owners (wave 0) compute their
-// rotation while waves 1.. apply the previous step's rotations to V; in phase B
-// a 16 x 32 grid of threads applies R^T A R to the disjoint 2x2 blocks in place
-// (all loads of a thread issued before its stores).  Stops when the off-diagonal
-// sum of squares is <= tol ||A||_F^2 (checked once per sweep).  On exit A's
-// diagonal holds the eigenvalues and V's columns the eigenvectors.
-__device__ __forceinline__ void jacobi_v_update(Mat& V, int n, int half, const unsigned short* sp, const double* cs) {
-    const int tid = threadIdx.x - 64;             // waves 1..7: 448 threads
-    if (tid < 0) return;
-    const int tx = tid & 31, vy = tid >> 5;       // 14 x 32 grid
-    if (tx >= half) return;
-    const int pp = sp[tx] & 255, qq = sp[tx] >> 8;
-    if (qq >= n) return;
-    const double c = cs[2 * tx], sn = cs[2 * tx + 1];
-    double vp[5], vq[5];
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-        const int r = vy + 14 * a;
-        if (r < n) { vp[a] = V[r][pp]; vq[a] = V[r][qq]; }
+// ---- Jacobi with one barrier per step ------------------------------------------------
+// Parallel cyclic Jacobi on the symmetric n x n matrix in Ab[0] (round-robin
+// pairing of m = n + (n odd) indices; when n is odd, index n is a phantom whose
+// row and column are kept zero, so its rotations are the identity).  The matrix
+// is double buffered: in a step every thread owns 2 x 2 blocks (rows of pair bi,
+// columns of pair bj), loads the diagonal blocks of both pairs, its block and
+// its block of V in one batch, computes both rotations (the same values, so the
+// same bits, in every thread), writes R^T A R of its block to the other buffer
+// and V R in place; one barrier ends the step.  Stops when the off-diagonal sum
+// of squares is <= tol ||A||_F^2 (checked once per sweep).  Returns the buffer
+// that holds the result; V's columns are the eigenvectors.
+__device__ __forceinline__ void jpair(int step, int t, int m, int& p, int& q) {
+    int a, b;
+    if (t == 0) { a = m - 1; b = step; }
+    else {
+        a = step + t; if (a >= m - 1) a -= m - 1;
+        b = step - t + (m - 1); if (b >= m - 1) b -= m - 1;
     }
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-        const int r = vy + 14 * a;
-        if (r < n) {
-            V[r][pp] = c * vp[a] - sn * vq[a];
-            V[r][qq] = sn * vp[a] + c * vq[a];
-        }
-    }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
 }
 
-__device__ int blk_jacobi_eig(Mat& A, int n, Mat& V, double tol, double* cs, unsigned short* sched, double* red) {
+// jrot without early exits (identity where jrot would skip)
+__device__ __forceinline__ void jrot_nb(double app, double aqq, double apq, double& c, double& s) {
+    const double aa = fabs(apq);
+    const bool skip = !(aa > 1e-300) || !(aa * aa > 1e-36 * fabs(app * aqq));
+    const double d = aqq - app;
+    const int e = ilogb(fmax(fmax(fabs(d), aa), 1e-300));
+    const float df = (float)ldexp(d, -e), af = (float)ldexp(apq, -e);
+    const float r = __builtin_amdgcn_sqrtf(df * df + 4.0f * af * af);
+    const float den = df >= 0.0f ? df + r : df - r;
+    const float tf = 2.0f * af * __builtin_amdgcn_rcpf(den == 0.0f ? 1.0f : den);
+    const double t = (double)tf;
+    const double x = fma(t, t, 1.0);
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    c = skip ? 1.0 : y;
+    s = skip ? 0.0 : t * y;
+}
+
+__device__ __forceinline__ int jacobi_1b(Mat* Ab, int n, Mat& V, double tol, double* red) {
     const int tid = threadIdx.x;
-    const int ty = tid >> 5, tx = tid & 31;       // 16 x 32 grid
     const int m = (n % 2) ? n + 1 : n;
     const int half = m / 2;
-    const int CSW = LMAX + 2;                      // two slots of published rotations
-    for (int e = tid; e < n * n; e += NT) V[e / n][e % n] = (e / n == e % n) ? 1.0 : 0.0;
-    for (int e = tid; e < (m - 1) * half; e += NT) {
-        const int step = e / half, t = e % half;
-        int a, b;
-        if (t == 0) { a = m - 1; b = step; }
-        else { a = (step + t) % (m - 1); b = (step - t + (m - 1)) % (m - 1); }
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        sched[e] = (unsigned short)(p | (q << 8));
+    const int nblk = half * half;
+    for (int e = tid; e < m * m; e += NT) {
+        const int i = e / m, j = e % m;
+        V[i][j] = (i == j && i < n) ? 1.0 : 0.0;
+        if (i >= n || j >= n) { Ab[0][i][j] = 0.0; Ab[1][i][j] = 0.0; }
     }
     double tot = 0.0;
-    for (int e = tid; e < n * n; e += NT) tot += A[e / n][e % n] * A[e / n][e % n];
+    for (int e = tid; e < n * n; e += NT) tot += Ab[0][e / n][e % n] * Ab[0][e / n][e % n];
     tot = blk_sum(tot, red);
     if (tot == 0.0 || n < 2) return 0;
-    int sweep = 0, gstep = 0, prev = -1;
-    for (; sweep < 40; ++sweep) {
-        for (int step = 0; step < m - 1; ++step, ++gstep) {
-            const unsigned short* sp = sched + step * half;
-            double* csn = cs + (gstep & 1) * CSW;
-            // phase A: rotations of this step (wave 0) | V update of the previous step
-            if (tid < half) {
-                const int p = sp[tid] & 255, q = sp[tid] >> 8;
-                double c = 1.0, sn = 0.0;
-                if (q < n) jrot(A[p][p], A[q][q], A[p][q], c, sn);
-                csn[2 * tid] = c;
-                csn[2 * tid + 1] = sn;
-            }
-            if (prev >= 0) jacobi_v_update(V, n, half, sched + prev * half, cs + ((gstep - 1) & 1) * CSW);
-            __syncthreads();
-            // phase B: A <- R^T A R on the 2x2 blocks (rows bi, columns bj = tx)
-            if (tx < half) {
-                const int bj = tx;
-                const int pp = sp[bj] & 255, qq = sp[bj] >> 8;
-                const double cj = csn[2 * bj], sj = csn[2 * bj + 1];
-                const bool cq = qq < n;
-                double av[2], bv[2], cv[2], dv[2], ci[2], si[2];
-                int pr[2], qr[2];
+    // a thread owns blocks tid and tid + NT (nblk <= 1024)
+    const bool own0 = tid < nblk, own1 = tid + NT < nblk;
+    const int bi0 = own0 ? tid / half : 0, bj0 = own0 ? tid % half : 0;
+    const int bi1 = own1 ? (tid + NT) / half : 0, bj1 = own1 ? (tid + NT) % half : 0;
+    int cur = 0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        for (int step = 0; step < m - 1; ++step) {
+            const Mat& A = Ab[cur];
+            Mat& B = Ab[cur ^ 1];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int bi = ty + 16 * u;
-                    if (bi < half) {
-                        pr[u] = sp[bi] & 255;
-                        qr[u] = sp[bi] >> 8;
-                        ci[u] = csn[2 * bi];
-                        si[u] = csn[2 * bi + 1];
-                        const bool rq = qr[u] < n;
-                        av[u] = A[pr[u]][pp];
-                        bv[u] = cq ? A[pr[u]][qq] : 0.0;
-                        cv[u] = rq ? A[qr[u]][pp] : 0.0;
-                        dv[u] = (rq && cq) ? A[qr[u]][qq] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int bi = ty + 16 * u;
-                    if (bi < half) {
-                        const bool rq = qr[u] < n;
-                        const double a1 = ci[u] * av[u] - si[u] * cv[u], b1 = ci[u] * bv[u] - si[u] * dv[u];
-                        const double c1 = si[u] * av[u] + ci[u] * cv[u], d1 = si[u] * bv[u] + ci[u] * dv[u];
-                        A[pr[u]][pp] = a1 * cj - b1 * sj;
-                        if (cq) A[pr[u]][qq] = a1 * sj + b1 * cj;
-                        if (rq) A[qr[u]][pp] = c1 * cj - d1 * sj;
-                        if (rq && cq) A[qr[u]][qq] = c1 * sj + d1 * cj;
-                    }
+            for (int u = 0; u < 2; ++u) {
+                if (u == 0 ? own0 : own1) {
+                    const int bi = u == 0 ? bi0 : bi1, bj = u == 0 ? bj0 : bj1;
+                    int pi, qi, pj, qj;
+                    jpair(step, bi, m, pi, qi);
+                    jpair(step, bj, m, pj, qj);
+                    const double aipp = A[pi][pi], aiqq = A[qi][qi], aipq = A[pi][qi];
+                    const double ajpp = A[pj][pj], ajqq = A[qj][qj], ajpq = A[pj][qj];
+                    const double a = A[pi][pj], b = A[pi][qj], c = A[qi][pj], d = A[qi][qj];
+                    const double vpp = V[pi][pj], vpq = V[pi][qj], vqp = V[qi][pj], vqq = V[qi][qj];
+                    double ci, si, cj, sj;
+                    jrot_nb(aipp, aiqq, aipq, ci, si);
+                    jrot_nb(ajpp, ajqq, ajpq, cj, sj);
+                    const double a1 = ci * a - si * c, b1 = ci * b - si * d;
+                    const double c1 = si * a + ci * c, d1 = si * b + ci * d;
+                    B[pi][pj] = a1 * cj - b1 * sj;
+                    B[pi][qj] = a1 * sj + b1 * cj;
+                    B[qi][pj] = c1 * cj - d1 * sj;
+                    B[qi][qj] = c1 * sj + d1 * cj;
+                    V[pi][pj] = cj * vpp - sj * vpq;
+                    V[pi][qj] = sj * vpp + cj * vpq;
+                    V[qi][pj] = cj * vqp - sj * vqq;
+                    V[qi][qj] = sj * vqp + cj * vqq;
                 }
             }
-            prev = step;
+            cur ^= 1;
             __syncthreads();
         }
         double off = 0.0;
-        for (int i = ty; i < n; i += 16)
-            for (int j = tx; j < n; j += 32)
-                if (i != j) off += A[i][j] * A[i][j];
+        const Mat& A = Ab[cur];
+        for (int e = tid; e < n * n; e += NT) {
+            const int i = e / n, j = e - i * n;
+            if (i != j) off += A[i][j] * A[i][j];
+        }
         off = blk_sum(off, red);
-        if (off <= tol * tot) { ++sweep; break; }
+        if (off <= tol * tot) { RT_DENSE_TRACE_VAL(9, sweep + 1); break; }
     }
-    if (prev >= 0) jacobi_v_update(V, n, half, sched + prev * half, cs + ((gstep - 1) & 1) * CSW);
-    __syncthreads();
-    return sweep;
+    return cur;
 }
 
+
 struct EigShared {
-    Mat A;
+    Mat Ab[2];
     Mat V;
-    double cs[2 * (LMAX + 2)];
-    unsigned short sched[LMAX * LMAX / 2];
     double red[NT];
     int perm[LMAX];
     double lam[LMAX];
@@ -689,10 +695,13 @@ __global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, i
                                                  int* __restrict__ kout, double jtol) {
     __shared__ EigShared S;
     const int tid = threadIdx.x;
-    for (int e = tid; e < ell * ell; e += NT) S.A[e / ell][e % ell] = W[e];
+    for (int e = tid; e < ell * ell; e += NT) S.Ab[0][e / ell][e % ell] = W[e];
     __syncthreads();
-    blk_jacobi_eig(S.A, ell, S.V, jtol, S.cs, S.sched, S.red);
-    blk_sort_desc(S.A, ell, S.perm, S.lam);
+    RT_DENSE_TRACE(1);
+    const int cur = jacobi_1b(S.Ab, ell, S.V, jtol, S.red);
+    RT_DENSE_TRACE(2);
+    blk_sort_desc(S.Ab[cur], ell, S.perm, S.lam);
+    RT_DENSE_TRACE(3);
     if (tid == 0) {
         int k;
         if (r_fixed >= 0) {
@@ -718,69 +727,78 @@ __global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, i
     }
 }
 
-// A = Q Us[:, :k] for rows 64 b .. 64 b + 63 (one row per thread); part[b] =
-// per column the (|a|, a, row) of the entry of largest magnitude of these rows
+// A = Q Us[:, :k] for rows 64 b .. 64 b + 63: lane l of every wave owns row
+// 64 b + l (its row of Q in registers) and wave w the columns j = w, w + 4, ...
+// (Us transposed in LDS, read with broadcast 16-byte loads); part[b] = per
+// column the (|a|, a, row) of the entry of largest magnitude of these rows
 // (lowest row on ties).  A is stored before the sign fix.
 template <int NR>
-__global__ __launch_bounds__(64) void factor_rows_kernel(const double* __restrict__ Q, int64_t ldq, int64_t J,
-                                                         int ell, const double* __restrict__ Us,
-                                                         const int* __restrict__ kdev, void* __restrict__ Aout,
-                                                         int a_is_f64, double* __restrict__ part) {
-    __shared__ double us[NR][NR];
+__global__ __launch_bounds__(256) void factor_rows_kernel(const double* __restrict__ Q, int64_t ldq, int64_t J,
+                                                          int ell, const double* __restrict__ Us,
+                                                          const int* __restrict__ kdev, void* __restrict__ Aout,
+                                                          int a_is_f64, double* __restrict__ part) {
+    __shared__ __align__(16) double ust[NR][NR + 2];     // ust[j][t] = Us[t][j]
     __shared__ double qs[64][NR + 1];
     const int k = kdev[0];
     if (k <= 0) return;
-    const int lane = threadIdx.x;
-    for (int e = lane; e < NR * NR; e += 64) {
-        const int t = e / NR, j = e % NR;
-        us[t][j] = (t < ell && j < k) ? Us[t * ell + j] : 0.0;
-    }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < NR * NR; e += 256) ust[e / NR][e % NR] = 0.0;
+    __syncthreads();
+    batched_copy<8>(ell * k, tid, 256, [&](int e) { return Us[(e / k) * ell + e % k]; },
+                    [&](int e, double v) { ust[e % k][e / k] = v; });
     const int64_t row0 = (int64_t)blockIdx.x * 64;
     const int rows = (int)(J - row0 < 64 ? J - row0 : 64);
-    for (int e = lane; e < rows * ell; e += 64) {
-        const int r = e / ell, t = e - r * ell;
-        qs[r][t] = Q[(row0 + r) * ldq + t];
-    }
+    batched_copy<8>(rows * ell, tid, 256, [&](int e) { return Q[(row0 + e / ell) * ldq + e % ell]; },
+                    [&](int e, double v) { qs[e / ell][e % ell] = v; });
     __syncthreads();
     const bool valid = lane < rows;
     const int64_t i = row0 + lane;
-    double a[NR];
+    double q[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) a[j] = 0.0;
+    for (int t = 0; t < NR; ++t) q[t] = (valid && t < ell) ? qs[lane][t] : 0.0;
+    constexpr int NJ = (NR + 3) / 4;
+    double a[NJ];
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-        if (t < ell) {
-            const double q = valid ? qs[lane][t] : 0.0;
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        a[jj] = 0.0;
+        if (j < k) {
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) a[j] = fma(q, us[t][j], a[j]);
+            for (int t = 0; t < NR; t += 2) {
+                const double2 u = *reinterpret_cast<const double2*>(&ust[j][t]);
+                s0 = fma(q[t], u.x, s0);
+                s1 = fma(q[t + 1], u.y, s1);
+            }
+            a[jj] = s0 + s1;
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
     double* A64 = (double*)Aout;
     float* A32 = (float*)Aout;
-    __syncthreads();                         // every lane is done reading its row of qs
+    __syncthreads();                         // every lane is done reading qs
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
         if (j < k) {
-            qs[lane][j] = a[j];
+            qs[lane][j] = a[jj];
             if (valid && Aout) {
-                if (a_is_f64) A64[i * k + j] = a[j];
-                else A32[i * k + j] = (float)a[j];
+                if (a_is_f64) A64[i * k + j] = a[jj];
+                else A32[i * k + j] = (float)a[jj];
             }
         }
     }
     __syncthreads();
-    if (lane < k) {
+    if (tid < k) {
         double b = -1.0, v = 0.0;
         int64_t ix = INT64_MAX;
         for (int r = 0; r < rows; ++r) {
-            const double x = qs[r][lane];
+            const double x = qs[r][tid];
             if (fabs(x) > b) { b = fabs(x); v = x; ix = row0 + r; }
         }
         double* pb = part + (int64_t)blockIdx.x * 3 * LMAX;
-        pb[lane] = b;
-        pb[LMAX + lane] = v;
-        pb[2 * LMAX + lane] = (double)ix;
+        pb[tid] = b;
+        pb[LMAX + tid] = v;
+        pb[2 * LMAX + tid] = (double)ix;
     }
 }
 
@@ -837,7 +855,7 @@ hipError_t truncate_multi(const double* W, int ell, const double* Q, int64_t ldq
     double* part = Us + (int64_t)ell * ell;
     const int64_t nsign = (J * ell + 4095) / 4096;
     hipLaunchKernelGGL(eig_kernel, dim3(1), dim3(NT), 0, stream, W, ell, r_fixed, E_dev, tau2, Us, lam, kout, jtol);
-    hipLaunchKernelGGL(factor_rows_kernel<NR>, dim3(nwg), dim3(64), 0, stream, Q, ldq, J, ell, (const double*)Us,
+    hipLaunchKernelGGL(factor_rows_kernel<NR>, dim3(nwg), dim3(256), 0, stream, Q, ldq, J, ell, (const double*)Us,
                        (const int*)kout, A, da == Dt::F64 ? 1 : 0, part);
     hipLaunchKernelGGL(sign_kernel, dim3((unsigned)(nsign < 1 ? 1 : nsign)), dim3(256), 0, stream,
                        (const double*)part, nwg, (const int*)kout, J, (const double*)Us, ell, A,
@@ -855,152 +873,293 @@ hipError_t truncate_multi(const double* W, int ell, const double* Q, int64_t ldq
 
 constexpr int OG_ROWS = 32;   // rows per partial Gram
 
-// part[b] = Y[rows of b]^T Y[rows of b] (ell x ell); with stats, stats[2 b] =
-// sum of squares of the finite entries and stats[2 b + 1] = count of the others.
+// Quad-wide sum (lanes 4 q .. 4 q + 3) of a double through DPP quad permutes.
+__device__ __forceinline__ double quad_sum(double v, int G) {
+    if (G >= 2) {
+        const unsigned long long u = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0xb1, 0xf, 0xf, false);  // [1,0,3,2]
+        const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0xb1, 0xf, 0xf, false);
+        v += __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+    if (G >= 4) {
+        const unsigned long long u = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0x4e, 0xf, 0xf, false);  // [2,3,0,1]
+        const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x4e, 0xf, 0xf, false);
+        v += __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    }
+    return v;
+}
+
+// part[b] = Y[rows of b]^T Y[rows of b] (ell x ell) for OG_ROWS rows staged in
+// LDS; each thread owns a 4 x 4 tile of the upper triangle and every G-th row
+// (G <= 4 threads of a tile in one quad, summed with DPP).  With stats,
+// stats[2 b] = sum of squares of the finite entries and stats[2 b + 1] = count
+// of the others.
 __global__ __launch_bounds__(256) void gram_rows_kernel(const double* __restrict__ Y, int64_t J, int ell,
                                                         const int* __restrict__ gate, double* __restrict__ part,
                                                         double* __restrict__ stats) {
     if (gate && gate[0] != 0) return;
-    __shared__ double ys[OG_ROWS][LMAX + 1];
+    __shared__ __align__(16) double ys[OG_ROWS][LMAX + 4];
     __shared__ double red[8];
     const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * OG_ROWS;
     const int rows = (int)(J - row0 < OG_ROWS ? J - row0 : OG_ROWS);
+    const int nt = (ell + 3) / 4;
     double fro = 0.0, bad = 0.0;
-    for (int e = tid; e < rows * ell; e += 256) {
-        const int r = e / ell, c = e - r * ell;
-        const double y = Y[(row0 + r) * ell + c];
+    for (int e = tid; e < OG_ROWS * 4 * nt; e += 256) {
+        const int r = e / (4 * nt), c = e - r * (4 * nt);
+        double y = 0.0;
+        if (r < rows && c < ell) {
+            y = Y[(row0 + r) * ell + c];
+            if (isfinite(y)) fro += y * y;
+            else bad += 1.0;
+        }
         ys[r][c] = y;
-        if (isfinite(y)) fro += y * y;
-        else bad += 1.0;
     }
     __syncthreads();
     if (stats) {
         fro = wave_sum(fro);
         bad = wave_sum(bad);
         if ((tid & 63) == 0) { red[tid >> 6] = fro; red[4 + (tid >> 6)] = bad; }
+    }
+    const int npt = nt * (nt + 1) / 2;
+    int G = 4;
+    while (G > 1 && G * npt > 256) G >>= 1;
+    const int pr = tid / G, g = tid % G;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    int ti = 0, tj = 0;
+    if (pr < npt) {
+        int rem = pr;
+        while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
+        tj = ti + rem;
+        for (int r = g; r < OG_ROWS; r += G) {
+            const double2 x0 = *reinterpret_cast<const double2*>(&ys[r][4 * ti]);
+            const double2 x1 = *reinterpret_cast<const double2*>(&ys[r][4 * ti + 2]);
+            const double2 y0 = *reinterpret_cast<const double2*>(&ys[r][4 * tj]);
+            const double2 y1 = *reinterpret_cast<const double2*>(&ys[r][4 * tj + 2]);
+            const double x[4] = {x0.x, x0.y, x1.x, x1.y}, y[4] = {y0.x, y0.y, y1.x, y1.y};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = quad_sum(acc[u][v], G);
+    double* out = part + (int64_t)blockIdx.x * ell * ell;
+    if (pr < npt && g == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 4 * ti + u, c = 4 * tj + v;
+                if (r < ell && c < ell) { out[r * ell + c] = acc[u][v]; out[c * ell + r] = acc[u][v]; }
+            }
+    }
+    if (stats) {
         __syncthreads();
         if (tid == 0) {
             stats[2 * blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
             stats[2 * blockIdx.x + 1] = (red[4] + red[5]) + (red[6] + red[7]);
         }
     }
-    double* out = part + (int64_t)blockIdx.x * ell * ell;
-    for (int e = tid; e < ell * ell; e += 256) {
-        const int i = e / ell, j = e - i * ell;
-        if (j < i) continue;
-        double a0 = 0.0, a1 = 0.0;
-        int r = 0;
-        for (; r + 2 <= rows; r += 2) {
-            a0 = fma(ys[r][i], ys[r][j], a0);
-            a1 = fma(ys[r + 1][i], ys[r + 1][j], a1);
-        }
-        if (r < rows) a0 = fma(ys[r][i], ys[r][j], a0);
-        const double v = a0 + a1;
-        out[i * ell + j] = v;
-        out[j * ell + i] = v;
-    }
 }
 
-struct CholShared {
-    Mat W;
-    double diag0[LMAX];
-    double invd[LMAX];
-    double minr[1];
-    int flag[4];
-};
+__device__ __forceinline__ double readlane64(double v, int l) {
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-// Sums the nparts partial Grams, factors W = L L^T and tests the pivots:
-// accepted when every pivot ratio is >= min_ratio (and, with stats, the sketch
-// is finite and non-zero).  Writes L (lower, ell x ell) and invd = 1 / diag(L),
-// and gate[0] = 0 (accepted) or 1.  With skip_if_gated, an earlier rejection
-// stands and nothing is done.
-__global__ __launch_bounds__(NT) void chol_gate_kernel(const double* __restrict__ part, int nparts, int ell,
-                                                       const double* __restrict__ stats, double min_ratio,
-                                                       double* __restrict__ L, double* __restrict__ invd,
-                                                       int* __restrict__ gate, int skip_if_gated,
-                                                       uint32_t* __restrict__ status) {
+// Sums the nparts partial Grams (fixed order), factors W = L L^T and tests the
+// pivots: accepted when every pivot ratio pivot_k / W_kk is >= min_ratio (and,
+// with stats, the sketch is finite and non-zero).  On acceptance writes
+// Linv = L^-1 (lower, ell x ell, row-major), so that Y R^-1 = Y Linv^T, and
+// gate[0] = 0; otherwise gate[0] = 1.  With skip_if_gated, an earlier rejection
+// stands and nothing is done.  The factorisation and the inverse are computed
+// by wave 0 with row i of W (then column i of Linv) in the registers of lane i
+// and the current column (row) broadcast through LDS; LDS accesses of one wave
+// complete in order, so no barrier is needed between steps.
+template <int NR>
+__global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict__ part, int nparts, int ell,
+                                                        const double* __restrict__ stats, double min_ratio,
+                                                        double* __restrict__ Linv, double* __restrict__ unused,
+                                                        int* __restrict__ gate, int skip_if_gated,
+                                                        uint32_t* __restrict__ status) {
+    (void)unused;
     if (skip_if_gated && gate[0] != 0) return;
-    __shared__ CholShared S;
+    __shared__ double W[NR][NR + 1];
+    __shared__ __align__(16) double Lb[NR][NR + 2];
+    __shared__ __align__(16) double colb[NR];
+    __shared__ double d0[NR], idg[NR];
+    __shared__ int okflag;
     const int tid = threadIdx.x;
-    for (int e = tid; e < ell * ell; e += NT) {
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        int b = 0;
-        for (; b + 4 <= nparts; b += 4) {
+    // lower triangle of the summed Gram, the nparts loads of an entry in flight together
+    const int ntri = ell * (ell + 1) / 2;
+    for (int e = tid; e < ntri; e += 256) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        const int j = e - i * (i + 1) / 2;
+        const int64_t off = (int64_t)i * ell + j;
+        double acc = 0.0;
+        for (int b0 = 0; b0 < nparts; b0 += 8) {
+            double v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] += part[(int64_t)(b + u) * ell * ell + e];
+            for (int u = 0; u < 8; ++u) v[u] = (b0 + u < nparts) ? part[(int64_t)(b0 + u) * ell * ell + off] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
         }
-        for (; b < nparts; ++b) a[0] += part[(int64_t)b * ell * ell + e];
-        S.W[e / ell][e % ell] = (a[0] + a[1]) + (a[2] + a[3]);
-    }
-    bool ok = true;
-    if (stats) {
-        if (tid == 0) {
-            double fro = 0.0, bad = 0.0;
-            for (int b = 0; b < nparts; ++b) { fro += stats[2 * b]; bad += stats[2 * b + 1]; }
-            S.flag[2] = (bad == 0.0 && fro > 0.0) ? 1 : 0;
-        }
-        __syncthreads();
-        ok = S.flag[2] != 0;
-    }
-    if (ok) ok = blk_cholesky(S.W, ell, 0.0, S.diag0, S.minr, S.flag, S.invd) && S.minr[0] >= min_ratio;
-    __syncthreads();
-    if (ok) {
-        for (int e = tid; e < ell * ell; e += NT) L[e] = S.W[e / ell][e % ell];
-        if (tid < ell) invd[tid] = S.invd[tid];
+        W[i][j] = acc;
     }
     if (tid == 0) {
-        gate[0] = ok ? 0 : 1;
-        if (status) status[0] = 0u;
+        bool ok = true;
+        if (stats) {
+            double fro = 0.0, bad = 0.0;
+            for (int b = 0; b < nparts; ++b) { fro += stats[2 * b]; bad += stats[2 * b + 1]; }
+            ok = bad == 0.0 && fro > 0.0;
+        }
+        okflag = ok ? 1 : 0;
     }
+    __syncthreads();
+    if (tid >= 64) return;
+    const int lane = tid;
+    if (lane < ell) d0[lane] = W[lane][lane];
+    double w[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) w[j] = (lane < ell && j <= lane && j < ell) ? W[lane][j] : 0.0;
+    bool ok = okflag != 0;
+    double mr = 1.0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (k < ell) {
+            const double piv = readlane64(w[k], k);
+            const double dk = d0[k];
+            const bool bad = !(piv > 0.0) || !isfinite(piv) || !(dk > 0.0);
+            ok = ok && !bad;
+            const double pv = bad ? 1.0 : piv;
+            mr = fmin(mr, bad ? 0.0 : pv / dk);
+            const double d = sqrt(pv);
+            const double l = (lane == k) ? d : w[k] / d;
+            if (lane >= k) w[k] = l;
+            if (lane < NR) colb[lane] = (lane > k && lane < ell) ? l : 0.0;
+            double cb[NR];
+#pragma unroll
+            for (int j = 0; j < NR; j += 2) {
+                if (j + 1 > k) {
+                    const double2 c = *reinterpret_cast<const double2*>(&colb[j]);
+                    cb[j] = c.x; cb[j + 1] = c.y;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                if (j > k) w[j] = fma(-l, cb[j], w[j]);
+        }
+    }
+    ok = ok && mr >= min_ratio;
+    if (!ok) {
+        if (lane == 0) { gate[0] = 1; if (status) status[0] = 0u; }
+        return;
+    }
+    // L (row lane) to LDS, then column lane of Linv: x_i = (delta_i,lane - sum_{k<i} L[i][k] x_k) / L[i][i]
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (lane < NR) Lb[lane][j] = (lane < ell && j <= lane) ? w[j] : 0.0;
+    double dl = 1.0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (j == lane) dl = w[j];
+    if (lane < ell) idg[lane] = 1.0 / dl;
+    double x[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i < ell) {
+            double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k2 = 0; k2 < NR; k2 += 2) {
+                if (k2 < i) {
+                    const double2 l2 = *reinterpret_cast<const double2*>(&Lb[i][k2]);
+                    s0 = fma(-l2.x, x[k2], s0);
+                    if (k2 + 1 < i) s1 = fma(-l2.y, x[k2 + 1], s1);
+                }
+            }
+            x[i] = (s0 + s1) * idg[i];
+        } else {
+            x[i] = 0.0;
+        }
+    }
+    // Linv[i][lane] = x_i (zero above the diagonal)
+    if (lane < ell) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (i < ell) Linv[(int64_t)i * ell + lane] = (i >= lane) ? x[i] : 0.0;
+    }
+    if (lane == 0) { gate[0] = 0; if (status) status[0] = 0u; }
 }
 
-// Yout = Yin R^-1 (R = L^T), one row per thread, when gate[0] == 0; also the
-// float copy Qf when given.
+// Yout = Yin R^-1 = Yin Linv^T when gate[0] == 0 (z_j = sum_{k<=j} y_k Linv[j][k]),
+// rows 64 b .. 64 b + 63: lane l of every wave owns a row (in registers) and
+// wave w the columns j = w, w + 4, ... (Linv in LDS, broadcast 16-byte loads);
+// also the float copy Qf when given.
 template <int NR>
-__global__ __launch_bounds__(64) void trsm_rows_kernel(const double* __restrict__ Yin, double* __restrict__ Yout,
-                                                       float* __restrict__ Qf, int64_t J, int ell,
-                                                       const double* __restrict__ L, const double* __restrict__ invd,
-                                                       const int* __restrict__ gate) {
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const double* __restrict__ Yin, double* __restrict__ Yout,
+                                                        float* __restrict__ Qf, int64_t J, int ell,
+                                                        const double* __restrict__ Linv,
+                                                        const double* __restrict__ unused,
+                                                        const int* __restrict__ gate) {
+    (void)unused;
     if (gate[0] != 0) return;
-    __shared__ double Ls[NR][NR + 1];
+    __shared__ __align__(16) double Ls[NR][NR + 2];
     __shared__ double ys[64][NR + 1];
-    __shared__ double id[NR];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NR * NR; e += 64) {
-        const int i = e / NR, j = e - i * NR;
-        Ls[i][j] = (i < ell && j <= i) ? L[i * ell + j] : 0.0;
-    }
-    if (tid < ell) id[tid] = invd[tid];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < NR * (NR + 2); e += 256) (&Ls[0][0])[e] = 0.0;
+    __syncthreads();
+    batched_copy<8>(ell * ell, tid, 256, [&](int e) { return Linv[e]; },
+                    [&](int e, double v) { Ls[e / ell][e % ell] = v; });
     const int64_t row0 = (int64_t)blockIdx.x * 64;
     const int rows = (int)(J - row0 < 64 ? J - row0 : 64);
     const double* src = Yin + row0 * ell;
-    for (int e = tid; e < rows * ell; e += 64) ys[e / ell][e % ell] = src[e];
+    batched_copy<8>(rows * ell, tid, 256, [&](int e) { return src[e]; },
+                    [&](int e, double v) { ys[e / ell][e % ell] = v; });
     __syncthreads();
     double y[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) y[j] = (j < ell && tid < rows) ? ys[tid][j] : 0.0;
+    for (int t = 0; t < NR; ++t) y[t] = (t < ell && lane < rows) ? ys[lane][t] : 0.0;
+    constexpr int NJ = (NR + 3) / 4;
+    double z[NJ];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        double s0 = 0.0, s1 = 0.0;
         if (j < ell) {
-            const double zj = y[j] * id[j];
-            y[j] = zj;
 #pragma unroll
-            for (int k = j + 1; k < NR; ++k) {
-                y[k] -= zj * Ls[k][j];   // entries k >= ell are never stored
-                if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            for (int t = 0; t < NR; t += 2) {
+                if (t <= 4 * jj + 3) {                        // t <= j for every wave
+                    const double2 l2 = *reinterpret_cast<const double2*>(&Ls[j][t]);
+                    s0 = fma(y[t], l2.x, s0);
+                    s1 = fma(y[t + 1], l2.y, s1);
+                }
             }
         }
-        __builtin_amdgcn_sched_barrier(0);
+        z[jj] = s0 + s1;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NR; ++j)
-        if (j < ell) ys[tid][j] = y[j];
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = wave + 4 * jj;
+        if (j < ell) ys[lane][j] = z[jj];
+    }
     __syncthreads();
     double* dst = Yout + row0 * ell;
     float* dstf = Qf ? Qf + row0 * ell : nullptr;
-    for (int e = tid; e < rows * ell; e += 64) {
+    for (int e = tid; e < rows * ell; e += 256) {
         const double v = ys[e / ell][e % ell];
         dst[e] = v;
         if (dstf) dstf[e] = (float)v;
@@ -1021,22 +1180,23 @@ hipError_t orth_multi(double* Y, int64_t J, int ell, float* Qf, double accept_ra
     // pass 1 on the sketch
     hipLaunchKernelGGL(gram_rows_kernel, dim3(nb), dim3(256), 0, stream, (const double*)Y, J, ell,
                        (const int*)nullptr, part, stats);
-    hipLaunchKernelGGL(chol_gate_kernel, dim3(1), dim3(NT), 0, stream, (const double*)part, nb, ell,
+    hipLaunchKernelGGL(chol_gate_kernel<NR>, dim3(1), dim3(256), 0, stream, (const double*)part, nb, ell,
                        (const double*)stats, accept_ratio, L, invd, gate, 0, status);
-    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(64), 0, stream, (const double*)Y, T1, (float*)nullptr, J,
+    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(256), 0, stream, (const double*)Y, T1, (float*)nullptr, J,
                        ell, (const double*)L, (const double*)invd, (const int*)gate);
     // pass 2 on its result (Y is overwritten only if both passes are accepted)
     hipLaunchKernelGGL(gram_rows_kernel, dim3(nb), dim3(256), 0, stream, (const double*)T1, J, ell,
                        (const int*)gate, part, (double*)nullptr);
-    hipLaunchKernelGGL(chol_gate_kernel, dim3(1), dim3(NT), 0, stream, (const double*)part, nb, ell,
+    hipLaunchKernelGGL(chol_gate_kernel<NR>, dim3(1), dim3(256), 0, stream, (const double*)part, nb, ell,
                        (const double*)nullptr, 0.5, L, invd, gate, 1, (uint32_t*)nullptr);
-    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(64), 0, stream, (const double*)T1, Y, Qf, J, ell,
+    hipLaunchKernelGGL(trsm_rows_kernel<NR>, dim3(nr), dim3(256), 0, stream, (const double*)T1, Y, Qf, J, ell,
                        (const double*)L, (const double*)invd, (const int*)gate);
     // fallback on the untouched sketch
     hipLaunchKernelGGL(orth_kernel<NR>, dim3(1), dim3(NT), 0, stream, Y, J, ell, Qf, scratch, accept_ratio, status,
                        (const int*)gate);
     return hipGetLastError();
 }
+
 
 }  // namespace
 
