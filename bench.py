@@ -281,7 +281,9 @@ def main():
     for _ in range(args.warmup):
         run_step(ctx, args.workload, X)
     torch.cuda.synchronize()
-    ctx.timing(True)
+    # timed steps: HIP events on the library's stream bracket the sketch launches only
+    # (the dominant kernel of the roofline), so the other launches run back to back
+    ctx.timing(True, kinds=["sketch"])
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -292,12 +294,19 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log = ctx.timing_log()
+    # a few more steps with every launch kind bracketed, for the per-kind breakdown
+    ctx.timing(True)
+    for _ in range(min(3, args.steps)):
+        run_step(ctx, args.workload, X)
+    torch.cuda.synchronize()
+    log_all = ctx.timing_log()
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
     if w["algo"] == "rsthosvd":
         flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])))
     else:
-        flops = sum(e["flops"] for e in log) / args.steps
+        nsteps_all = min(3, args.steps)
+        flops = sum(e["flops"] for e in log_all) / nsteps_all
     value = flops / (ms * 1e-3) / 1e12
     # dominant kernel: the largest sketch launch (mode-1 sketch over the whole tensor)
     sk = [e for e in log if e["kind"] == "sketch"]
@@ -307,7 +316,7 @@ def main():
     gbs = dom[0]["bytes"] / (avg_ms * 1e-3) / 1e9
     tfl = dom[0]["flops"] / (avg_ms * 1e-3) / 1e12
     mpeak = {"f32": FP32_MFMA_PEAK, "f64": FP64_MFMA_PEAK, "bf16": BF16_MFMA_PEAK}[w["prec"]]
-    pj = [e for e in log if e["kind"] == "project"]
+    pj = [e for e in log_all if e["kind"] == "project"]
     pbig = max(e["bytes"] for e in pj)
     pdom = [e for e in pj if e["bytes"] == pbig]
     p_ms = sum(e["ms"] for e in pdom) / len(pdom)
@@ -328,6 +337,8 @@ def main():
         "sketch_ttm": {"avg_ms": round(avg_ms, 5), "launches": len(dom), "tflops": round(tfl, 3),
                        "mfma_frac": round(tfl / mpeak, 4), "gbs": round(gbs, 1)},
         "projection_ttm": {"avg_ms": round(p_ms, 5), "gbs": round(pdom[0]["bytes"] / (p_ms * 1e-3) / 1e9, 1)},
+        "kind_ms_per_step": {k: round(sum(e["ms"] for e in log_all if e["kind"] == k) / min(3, args.steps), 4)
+                             for k in ("sketch", "orth", "project", "gram", "truncate")},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "sketch TTM, mode 1", "bytes_per_launch": dom[0]["bytes"]},

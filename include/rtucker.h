@@ -189,10 +189,12 @@ rt_status rt_philox_words(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, 
 #define RT_KIND_TRUNCATE 3  /* single-workgroup eigensolver + factor */
 #define RT_KIND_GRAM 4      /* fp64 Gram of B for the truncation (unfused variant) */
 
-/* Turn the per-launch timing log on (enable != 0) or off, clearing it.  While on,
- * every sketch, projection, orth and truncation launch of this context is
- * bracketed by HIP events on the context's stream. */
-rt_status rt_timing(rt_ctx* ctx, int32_t enable);
+/* Set the per-launch timing log and clear it.  `kinds` is a bit mask over the
+ * RT_KIND_* values (bit k records launches of kind k; 0 turns the log off,
+ * RT_TIMING_ALL records every kind).  A recorded launch is bracketed by HIP
+ * events on the context's stream. */
+#define RT_TIMING_ALL 0x1f
+rt_status rt_timing(rt_ctx* ctx, int32_t kinds);
 
 /* Number of entries in the timing log. */
 rt_status rt_timing_count(rt_ctx* ctx, int64_t* n);

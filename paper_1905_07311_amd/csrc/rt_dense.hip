@@ -612,7 +612,15 @@ __device__ __forceinline__ void jrot_nb(double app, double aqq, double apq, doub
     s = skip ? 0.0 : t * y;
 }
 
-__device__ __forceinline__ int jacobi_1b(Mat* Ab, int n, Mat& V, double tol, double* red) {
+// Parallel cyclic Jacobi, two phases per step: wave 0 computes the rotations
+// of the step's pairs from their diagonal blocks (once per pair) into LDS, then
+// every thread applies R^T A R to its 2 x 2 blocks of A and V R to its 2 x 2
+// blocks of V in place (rows of pair bi, columns of pair bj; the blocks of a
+// step are disjoint).  When n is odd, index n is a phantom whose row and column
+// stay zero, so its rotations are the identity.  Stops when the off-diagonal sum
+// of squares is <= tol ||A||_F^2 (checked once per sweep).  A's diagonal then
+// holds the eigenvalues and V's columns the eigenvectors.
+__device__ __forceinline__ int jacobi_2p(Mat& A, int n, Mat& V, double tol, double* red, double* cs, int* pq) {
     const int tid = threadIdx.x;
     const int m = (n % 2) ? n + 1 : n;
     const int half = m / 2;
@@ -620,66 +628,71 @@ __device__ __forceinline__ int jacobi_1b(Mat* Ab, int n, Mat& V, double tol, dou
     for (int e = tid; e < m * m; e += NT) {
         const int i = e / m, j = e % m;
         V[i][j] = (i == j && i < n) ? 1.0 : 0.0;
-        if (i >= n || j >= n) { Ab[0][i][j] = 0.0; Ab[1][i][j] = 0.0; }
+        if (i >= n || j >= n) A[i][j] = 0.0;
     }
     double tot = 0.0;
-    for (int e = tid; e < n * n; e += NT) tot += Ab[0][e / n][e % n] * Ab[0][e / n][e % n];
+    for (int e = tid; e < n * n; e += NT) tot += A[e / n][e % n] * A[e / n][e % n];
     tot = blk_sum(tot, red);
     if (tot == 0.0 || n < 2) return 0;
-    // a thread owns blocks tid and tid + NT (nblk <= 1024)
     const bool own0 = tid < nblk, own1 = tid + NT < nblk;
     const int bi0 = own0 ? tid / half : 0, bj0 = own0 ? tid % half : 0;
     const int bi1 = own1 ? (tid + NT) / half : 0, bj1 = own1 ? (tid + NT) % half : 0;
-    int cur = 0;
+    int sweeps = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
         for (int step = 0; step < m - 1; ++step) {
-            const Mat& A = Ab[cur];
-            Mat& B = Ab[cur ^ 1];
+            if (tid < half) {
+                int p, q;
+                jpair(step, tid, m, p, q);
+                double c, sn;
+                jrot_nb(A[p][p], A[q][q], A[p][q], c, sn);
+                cs[2 * tid] = c;
+                cs[2 * tid + 1] = sn;
+                pq[tid] = p | (q << 8);
+            }
+            __syncthreads();
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (u == 0 ? own0 : own1) {
                     const int bi = u == 0 ? bi0 : bi1, bj = u == 0 ? bj0 : bj1;
-                    int pi, qi, pj, qj;
-                    jpair(step, bi, m, pi, qi);
-                    jpair(step, bj, m, pj, qj);
-                    const double aipp = A[pi][pi], aiqq = A[qi][qi], aipq = A[pi][qi];
-                    const double ajpp = A[pj][pj], ajqq = A[qj][qj], ajpq = A[pj][qj];
+                    const int pqi = pq[bi], pqj = pq[bj];
+                    const int pi = pqi & 255, qi = pqi >> 8, pj = pqj & 255, qj = pqj >> 8;
+                    const double2 rsi = *reinterpret_cast<const double2*>(&cs[2 * bi]);
+                    const double2 rsj = *reinterpret_cast<const double2*>(&cs[2 * bj]);
+                    const double ci = rsi.x, si = rsi.y, cj = rsj.x, sj = rsj.y;
                     const double a = A[pi][pj], b = A[pi][qj], c = A[qi][pj], d = A[qi][qj];
                     const double vpp = V[pi][pj], vpq = V[pi][qj], vqp = V[qi][pj], vqq = V[qi][qj];
-                    double ci, si, cj, sj;
-                    jrot_nb(aipp, aiqq, aipq, ci, si);
-                    jrot_nb(ajpp, ajqq, ajpq, cj, sj);
                     const double a1 = ci * a - si * c, b1 = ci * b - si * d;
                     const double c1 = si * a + ci * c, d1 = si * b + ci * d;
-                    B[pi][pj] = a1 * cj - b1 * sj;
-                    B[pi][qj] = a1 * sj + b1 * cj;
-                    B[qi][pj] = c1 * cj - d1 * sj;
-                    B[qi][qj] = c1 * sj + d1 * cj;
+                    A[pi][pj] = a1 * cj - b1 * sj;
+                    A[pi][qj] = a1 * sj + b1 * cj;
+                    A[qi][pj] = c1 * cj - d1 * sj;
+                    A[qi][qj] = c1 * sj + d1 * cj;
                     V[pi][pj] = cj * vpp - sj * vpq;
                     V[pi][qj] = sj * vpp + cj * vpq;
                     V[qi][pj] = cj * vqp - sj * vqq;
                     V[qi][qj] = sj * vqp + cj * vqq;
                 }
             }
-            cur ^= 1;
             __syncthreads();
         }
+        ++sweeps;
         double off = 0.0;
-        const Mat& A = Ab[cur];
         for (int e = tid; e < n * n; e += NT) {
             const int i = e / n, j = e - i * n;
             if (i != j) off += A[i][j] * A[i][j];
         }
         off = blk_sum(off, red);
-        if (off <= tol * tot) { RT_DENSE_TRACE_VAL(9, sweep + 1); break; }
+        if (off <= tol * tot) break;
     }
-    return cur;
+    RT_DENSE_TRACE_VAL(9, sweeps);
+    return sweeps;
 }
 
-
 struct EigShared {
-    Mat Ab[2];
+    Mat A;
     Mat V;
+    __attribute__((aligned(16))) double cs[2 * (LMAX / 2 + 1)];
+    int pq[LMAX / 2 + 1];
     double red[NT];
     int perm[LMAX];
     double lam[LMAX];
@@ -695,12 +708,12 @@ __global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, i
                                                  int* __restrict__ kout, double jtol) {
     __shared__ EigShared S;
     const int tid = threadIdx.x;
-    for (int e = tid; e < ell * ell; e += NT) S.Ab[0][e / ell][e % ell] = W[e];
+    for (int e = tid; e < ell * ell; e += NT) S.A[e / ell][e % ell] = W[e];
     __syncthreads();
     RT_DENSE_TRACE(1);
-    const int cur = jacobi_1b(S.Ab, ell, S.V, jtol, S.red);
+    jacobi_2p(S.A, ell, S.V, jtol, S.red, S.cs, S.pq);
     RT_DENSE_TRACE(2);
-    blk_sort_desc(S.Ab[cur], ell, S.perm, S.lam);
+    blk_sort_desc(S.A, ell, S.perm, S.lam);
     RT_DENSE_TRACE(3);
     if (tid == 0) {
         int k;

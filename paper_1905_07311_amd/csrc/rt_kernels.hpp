@@ -71,7 +71,20 @@ size_t orth_scratch(int64_t J, int ell);
 // If gram_partial != nullptr, each workgroup adds the fp64 Gram sum_c B[:, c] B[:, c]^T
 // of its columns to gram_partial[wg][ell][ell]; if nrm2_partial != nullptr, sum B^2
 // (fp64) per workgroup.  `nwg_out` receives the workgroup count.
-struct ProjectPlan { int nwg; int64_t ntiles; int kind; };  // kind 0 generic, 1 MFMA strips, 2 MFMA rows (R == 1)
+// kind 0 generic, 1 MFMA strips, 2 MFMA rows (R == 1).  The MFMA kinds may split
+// the contraction over nsplit workgroup rows (jchunk mode rows each) into float
+// partials [nsplit][L][ell][R] (partial_elems floats of workspace) that
+// launch_project_reduce adds in a fixed order.
+struct ProjectPlan {
+    int nwg;
+    int64_t ntiles;
+    int kind;
+    int sets = 1;
+    int nsplit = 1;
+    int64_t jchunk = 0;
+    int64_t split_stride = 0;
+    size_t partial_elems = 0;
+};
 ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 // ldj: stride of the mode index in G (= s.J for a plain tensor; larger when only
 // the first s.J rows of a wider buffer are contracted).  B is written at
@@ -121,13 +134,19 @@ hipError_t launch_sketch_bf16_rows(const SketchPlan& p, const float* X, Shape3 s
 hipError_t launch_sketch_bf16_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
                                    uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff);
-int plan_project_mfma(Shape3 s, int ell);
-hipError_t launch_project_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
-                               float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
+void plan_project_mfma(ProjectPlan& p, Shape3 s, int ell);
+// with p.nsplit > 1, B is the partial buffer (ldk = ell, koff = 0) and nrm2 must be null
+hipError_t launch_project_mfma(const ProjectPlan& p, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq,
+                               int ell, float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
 // last mode (R == 1): B (L x ldk, columns koff..) = G (L x J, row stride ldj) Q
-int plan_project_r1_mfma(Shape3 s);
-hipError_t launch_project_r1_mfma(int nwg, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
-                                  float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream);
+void plan_project_r1_mfma(ProjectPlan& p, Shape3 s, int ell);
+hipError_t launch_project_r1_mfma(const ProjectPlan& p, const float* G, Shape3 s, int64_t ldj, const float* Q,
+                                  int64_t ldq, int ell, float* B, int64_t ldk, int64_t koff, double* nrm2,
+                                  hipStream_t stream);
+// B (L, ldk, R) at koff = sum of the nsplit float partials; nrm2 partials per workgroup (nwg)
+int plan_project_reduce(int64_t n);
+hipError_t launch_project_reduce(const float* part, int nsplit, Shape3 s, int ell, float* B, int64_t ldk, int64_t koff,
+                                 double* nrm2, int nwg, hipStream_t stream);
 
 // ---- misc ------------------------------------------------------------------------------
 // sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)

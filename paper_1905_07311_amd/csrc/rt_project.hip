@@ -183,13 +183,13 @@ ProjectPlan plan_project(Dt dx, Dt dq, Shape3 s, int ell, const void* G, const v
     ProjectPlan p{};
     if (dx == Dt::F32 && dq == Dt::F32 && project_mfma_ok(s, ell, G, B, koff)) {
         p.kind = 1;
-        p.nwg = plan_project_mfma(s, ell);
+        plan_project_mfma(p, s, ell);
         p.ntiles = 0;
         return p;
     }
     if (dx == Dt::F32 && dq == Dt::F32 && s.R == 1 && ell <= LMAX) {
         p.kind = 2;
-        p.nwg = plan_project_r1_mfma(s);
+        plan_project_r1_mfma(p, s, ell);
         p.ntiles = 0;
         return p;
     }
@@ -207,9 +207,9 @@ hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Sha
     if (p.kind == 1 || p.kind == 2) {
         if (gram_partial) return hipErrorInvalidValue;   // the MFMA variants have no fused Gram
         if (p.kind == 2)
-            return launch_project_r1_mfma(p.nwg, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk,
+            return launch_project_r1_mfma(p, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk,
                                           koff, nrm2_partial, stream);
-        return launch_project_mfma(p.nwg, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk, koff,
+        return launch_project_mfma(p, (const float*)G, s, ldj, (const float*)Q, ldq, ell, (float*)B, ldk, koff,
                                    nrm2_partial, stream);
     }
     dim3 grid(p.nwg);
@@ -232,63 +232,124 @@ hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Sha
 
 // fp64 Gram of the first k mode rows of a (L, ldk, R) tensor: per-workgroup
 // partials W_wg[a][b] = sum over the workgroup's columns c of B[l, a, r] B[l, b, r].
+// Tiles of 64 columns are staged in LDS as doubles (bs[c][a]); every thread owns
+// an 8 x 8 block of the upper triangle of W and every G-th column of a tile, and
+// the G partial blocks are added through LDS at the end (16 entries per round).
+constexpr int G3_NC = 64;
+constexpr int G3_LD = LMAX + 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int64_t L, int64_t ldk, int64_t R,
                                                     int k, double* __restrict__ partial) {
-    __shared__ double bs[LMAX][PJ_NC + 1];
+    __shared__ __align__(16) double bs[G3_NC * G3_LD];
     const int tid = threadIdx.x;
     const int64_t K = L * R;
-    const int64_t ntiles = (K + PJ_NC - 1) / PJ_NC;
-    const int npairs = k * (k + 1) / 2;
-    double gacc[9];
-    int pa[9], pb[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        gacc[m] = 0.0;
-        const int t = tid + 256 * m;
-        int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((a + 1) * (a + 2) / 2 <= t) ++a;
-        while (a * (a + 1) / 2 > t) --a;
-        pa[m] = a;
-        pb[m] = t - a * (a + 1) / 2;
+    const int64_t ntiles = (K + G3_NC - 1) / G3_NC;
+    const int nt = (k + 7) / 8, kpad = 8 * nt;
+    const int npt = nt * (nt + 1) / 2;
+    int G = 64;
+    while (G > 1 && G * npt > 256) G >>= 1;
+    const int pr = tid / G, g = tid % G;
+    int ti = 0, tj = 0;
+    if (pr < npt) {
+        int rem = pr;
+        while (rem >= nt - ti) { rem -= nt - ti; ++ti; }
+        tj = ti + rem;
     }
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t cbase = tile * PJ_NC;
-        __syncthreads();
-        for (int e = tid; e < k * PJ_NC; e += 256) {
-            int a, cc;
-            if (R == 1) { a = e % k; cc = e / k; }
-            else        { cc = e % PJ_NC; a = e / PJ_NC; }
-            const int64_t c = cbase + cc;
+    double acc[8][8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = 0.0;
+    // staging of a tile: each thread loads up to G3_PER elements into registers
+    // (the next tile's loads are issued before the current tile is used)
+    constexpr int G3_PER = (G3_NC * (LMAX + 8) + 255) / 256;
+    const int nst = G3_NC * kpad;
+    double pre[G3_PER];
+    // per-thread element -> (mode row aa, column cc of the tile), fixed across tiles
+    int e_aa[G3_PER], e_cc[G3_PER];
+#pragma unroll
+    for (int u = 0; u < G3_PER; ++u) {
+        const int e = u * 256 + tid;
+        if (R == 1) { e_aa[u] = e % kpad; e_cc[u] = e / kpad; }
+        else        { e_cc[u] = e % G3_NC; e_aa[u] = e / G3_NC; }
+    }
+    auto load_tile = [&](int64_t tile) {
+        const int64_t cbase = tile * G3_NC;
+        // column c = l R + r: one division per tile, then at most one wrap when
+        // R >= G3_NC (else a 32-bit division per element)
+        const int64_t l0 = cbase / R, r0 = cbase - l0 * R;
+#pragma unroll
+        for (int u = 0; u < G3_PER; ++u) {
+            const int e = u * 256 + tid;
+            const int aa = e_aa[u], cc = e_cc[u];
+            int64_t l = l0, r = r0 + cc;
+            if (R >= G3_NC) {
+                if (r >= R) { r -= R; ++l; }
+            } else {
+                const uint32_t q = (uint32_t)r / (uint32_t)R;
+                l += q;
+                r -= (int64_t)q * R;
+            }
             double v = 0.0;
-            if (c < K) {
-                const int64_t l = c / R, r = c - l * R;
-                v = (double)B[(l * ldk + a) * R + r];
-            }
-            bs[a][cc] = v;
+            if (e < nst && aa < k && cbase + cc < K) v = (double)B[(l * ldk + aa) * R + r];
+            pre[u] = v;
         }
-        __syncthreads();
+    };
+    auto store_tile = [&]() {
 #pragma unroll
-        for (int m = 0; m < 9; ++m) {
-            if (tid + 256 * m < npairs) {
-                double s = 0.0;
-                for (int q = 0; q < PJ_NC; ++q) s += bs[pa[m]][q] * bs[pb[m]][q];
-                gacc[m] += s;
+        for (int u = 0; u < G3_PER; ++u)
+            if (u * 256 + tid < nst) bs[e_cc[u] * G3_LD + e_aa[u]] = pre[u];
+    };
+    if ((int64_t)blockIdx.x < ntiles) load_tile(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();
+        store_tile();
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) load_tile(tile + gridDim.x);
+        if (pr < npt) {
+            for (int c = g; c < G3_NC; c += G) {
+                const double* row = bs + c * G3_LD;
+                double x[8], y[8];
+#pragma unroll
+                for (int q = 0; q < 8; q += 2) {
+                    const double2 vx = *reinterpret_cast<const double2*>(row + 8 * ti + q);
+                    const double2 vy = *reinterpret_cast<const double2*>(row + 8 * tj + q);
+                    x[q] = vx.x; x[q + 1] = vx.y; y[q] = vy.x; y[q + 1] = vy.y;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int w = 0; w < 8; ++w) acc[u][w] = fma(x[u], y[w], acc[u][w]);
             }
         }
     }
+    __syncthreads();
     double* gp = partial + (int64_t)blockIdx.x * k * k;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        if (tid + 256 * m < npairs) {
-            gp[pa[m] * k + pb[m]] = gacc[m];
-            gp[pb[m] * k + pa[m]] = gacc[m];
+    for (int round = 0; round < 4; ++round) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) bs[tid * 16 + v] = acc[2 * round + v / 8][v % 8];
+        __syncthreads();
+        for (int t = tid; t < npt * 16; t += 256) {
+            const int tile = t / 16, v = t % 16;
+            double s0 = 0.0, s1 = 0.0;
+            for (int gg = 0; gg < G; gg += 2) {
+                s0 += bs[(tile * G + gg) * 16 + v];
+                if (gg + 1 < G) s1 += bs[(tile * G + gg + 1) * 16 + v];
+            }
+            int ti2 = 0, rem = tile;
+            while (rem >= nt - ti2) { rem -= nt - ti2; ++ti2; }
+            const int tj2 = ti2 + rem;
+            const int r = 8 * ti2 + 2 * round + v / 8, c = 8 * tj2 + v % 8;
+            if (r < k && c < k) { gp[r * k + c] = s0 + s1; gp[c * k + r] = s0 + s1; }
         }
+        __syncthreads();
     }
 }
 
 int plan_gram3(int64_t L, int64_t R) {
-    const int64_t nt = (L * R + PJ_NC - 1) / PJ_NC;
+    const int64_t nt = (L * R + G3_NC - 1) / G3_NC;
     return (int)(nt < 512 ? (nt < 1 ? 1 : nt) : 512);
 }
 

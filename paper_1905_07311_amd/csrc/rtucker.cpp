@@ -62,7 +62,7 @@ struct rt_ctx {
     std::vector<void*> outputs;   // outputs handed to the caller (for release)
     // optional per-launch timing log (HIP events on the context's stream)
     struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; };
-    bool timing = false;
+    uint32_t timing = 0;          // bit k: record launches of kind k
     std::vector<Timed> tlog;
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
@@ -115,7 +115,7 @@ struct TimeScope {
     rt_ctx::Timed t{};
     bool on;
     TimeScope(rt_ctx* ctx, int kind, double bytes, double flops, int64_t rows, int64_t cols, int ell)
-        : c(ctx), on(ctx->timing) {
+        : c(ctx), on(((ctx->timing >> kind) & 1u) != 0) {
         if (!on) return;
         t = rt_ctx::Timed{kind, c->next_event(), c->next_event(), bytes, flops, rows, cols, ell};
         if (!t.a || !t.b) { on = false; return; }
@@ -228,13 +228,24 @@ rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj
                      int ell, void* B, int64_t ldk, int64_t koff, double* W, double* nrm2) {
     rt::ProjectPlan plan = rt::plan_project(dx, dq, s, ell, G, B, koff);
     const bool fused_gram = W && plan.kind == 0;
+    const bool split = plan.nsplit > 1;
+    const int nred = split ? rt::plan_project_reduce(s.L * (int64_t)ell * s.R) : 0;
+    const int nnrm = split ? nred : plan.nwg;
     double* gp = fused_gram ? k.ws<double>((size_t)plan.nwg * ell * ell) : nullptr;
-    double* np = nrm2 ? k.ws<double>(plan.nwg) : nullptr;
-    if ((fused_gram && !gp) || (nrm2 && !np)) return fail(RT_ENOMEM, "workspace allocation failed");
+    double* np = nrm2 ? k.ws<double>(nnrm) : nullptr;
+    float* part = split ? k.ws<float>(plan.partial_elems) : nullptr;
+    if ((fused_gram && !gp) || (nrm2 && !np) || (split && !part)) return fail(RT_ENOMEM, "workspace allocation failed");
     {
         const double n = (double)s.L * s.J * s.R, es = dx == Dt::F64 ? 8 : 4;
         TimeScope ts(k.c, 1, n * es + (double)s.L * ell * s.R * es, 2.0 * ell * n, s.J, s.L * s.R, ell);
-        RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, B, ldk, koff, gp, np, k.c->stream));
+        if (split) {
+            // contraction split: float partials, then their fixed-order sum into B
+            RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, part, ell, 0, nullptr, nullptr,
+                                      k.c->stream));
+            RT_HIP(rt::launch_project_reduce(part, plan.nsplit, s, ell, (float*)B, ldk, koff, np, nred, k.c->stream));
+        } else {
+            RT_HIP(rt::launch_project(plan, dx, dq, G, s, ldj, Q, ldq, ell, B, ldk, koff, gp, np, k.c->stream));
+        }
     }
     if (fused_gram) {
         double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nwg, (int64_t)ell * ell) + 1);
@@ -256,7 +267,7 @@ rt_status do_project(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj
         if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
         RT_HIP(rt::launch_reduce_partials(g3, true, nwg, (int64_t)ell * ell, W, k.c->stream, rtmp));
     }
-    if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
+    if (nrm2) RT_HIP(rt::launch_sum_scalar(np, nnrm, nrm2, k.c->stream));
     return RT_OK;
 }
 
@@ -457,7 +468,7 @@ rt_status rt_destroy(rt_ctx* ctx) {
 rt_status rt_timing(rt_ctx* ctx, int32_t enable) {
     if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
     RT_HIP(hipStreamSynchronize(ctx->stream));
-    ctx->timing = enable != 0;
+    ctx->timing = (uint32_t)enable & 0x1fu;
     ctx->tlog.clear();
     ctx->evused = 0;
     return RT_OK;

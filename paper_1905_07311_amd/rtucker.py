@@ -327,8 +327,13 @@ class Context:
     def sync(self):
         _check(_lib.rt_sync(self.ctx))
 
-    def timing(self, enable):
-        _check(_lib.rt_timing(self.ctx, 1 if enable else 0))
+    def timing(self, enable, kinds=None):
+        """Turn the per-launch timing log on (all kinds, or the named ones) or off."""
+        mask = 0
+        if enable:
+            names = {v: k for k, v in self.KINDS.items()}
+            mask = 0x1f if kinds is None else sum(1 << names[k] for k in kinds)
+        _check(_lib.rt_timing(self.ctx, mask))
 
     KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate", 4: "gram"}
 
