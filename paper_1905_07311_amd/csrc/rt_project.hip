@@ -238,10 +238,9 @@ hipError_t launch_project(const ProjectPlan& p, Dt dx, Dt dq, const void* G, Sha
 constexpr int G3_NC = 64;
 constexpr int G3_LD = LMAX + 4;
 
-template <typename T>
-__global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int64_t L, int64_t ldk, int64_t R,
-                                                    int k, double* __restrict__ partial) {
-    __shared__ __align__(16) double bs[G3_NC * G3_LD];
+template <typename T, bool WIDE>
+__device__ __forceinline__ void gram3_body(const T* __restrict__ B, int64_t L, int64_t ldk, int64_t R, int k,
+                                           double* __restrict__ partial, double* bs) {
     const int tid = threadIdx.x;
     const int64_t K = L * R;
     const int64_t ntiles = (K + G3_NC - 1) / G3_NC;
@@ -262,11 +261,12 @@ __global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int
 #pragma unroll
         for (int y = 0; y < 8; ++y) acc[x][y] = 0.0;
     // staging of a tile: each thread loads up to G3_PER elements into registers
-    // (the next tile's loads are issued before the current tile is used)
+    // (the next tile's loads are issued before the current tile is used); the
+    // loads are unconditional (offset clamped into B, out-of-range values
+    // replaced by zero) so that they all stay in flight together
     constexpr int G3_PER = (G3_NC * (LMAX + 8) + 255) / 256;
     const int nst = G3_NC * kpad;
-    double pre[G3_PER];
-    // per-thread element -> (mode row aa, column cc of the tile), fixed across tiles
+    const int64_t maxoff = L * ldk * R - 1;
     int e_aa[G3_PER], e_cc[G3_PER];
 #pragma unroll
     for (int u = 0; u < G3_PER; ++u) {
@@ -274,26 +274,34 @@ __global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int
         if (R == 1) { e_aa[u] = e % kpad; e_cc[u] = e / kpad; }
         else        { e_cc[u] = e % G3_NC; e_aa[u] = e / G3_NC; }
     }
+    double pre[G3_PER];
     auto load_tile = [&](int64_t tile) {
         const int64_t cbase = tile * G3_NC;
-        // column c = l R + r: one division per tile, then at most one wrap when
-        // R >= G3_NC (else a 32-bit division per element)
+        // column c = l R + r: one division per tile, then at most one wrap (WIDE,
+        // R >= G3_NC) or a 32-bit division per element
         const int64_t l0 = cbase / R, r0 = cbase - l0 * R;
+        float raw[G3_PER];
 #pragma unroll
         for (int u = 0; u < G3_PER; ++u) {
-            const int e = u * 256 + tid;
             const int aa = e_aa[u], cc = e_cc[u];
             int64_t l = l0, r = r0 + cc;
-            if (R >= G3_NC) {
-                if (r >= R) { r -= R; ++l; }
+            if (WIDE) {
+                const bool w = r >= R;
+                r = w ? r - R : r;
+                l = w ? l + 1 : l;
             } else {
                 const uint32_t q = (uint32_t)r / (uint32_t)R;
                 l += q;
                 r -= (int64_t)q * R;
             }
-            double v = 0.0;
-            if (e < nst && aa < k && cbase + cc < K) v = (double)B[(l * ldk + aa) * R + r];
-            pre[u] = v;
+            int64_t off = (l * ldk + aa) * R + r;
+            off = off < maxoff ? off : maxoff;
+            raw[u] = (float)B[off];
+        }
+#pragma unroll
+        for (int u = 0; u < G3_PER; ++u) {
+            const bool ok = u * 256 + tid < nst && e_aa[u] < k && cbase + e_cc[u] < K;
+            pre[u] = ok ? (double)raw[u] : 0.0;
         }
     };
     auto store_tile = [&]() {
@@ -346,6 +354,14 @@ __global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int
         }
         __syncthreads();
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int64_t L, int64_t ldk, int64_t R,
+                                                    int k, double* __restrict__ partial) {
+    __shared__ __align__(16) double bs[G3_NC * G3_LD];
+    if (R >= G3_NC) gram3_body<T, true>(B, L, ldk, R, k, partial, bs);
+    else gram3_body<T, false>(B, L, ldk, R, k, partial, bs);
 }
 
 int plan_gram3(int64_t L, int64_t R) {

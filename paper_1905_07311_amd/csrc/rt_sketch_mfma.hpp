@@ -36,6 +36,14 @@ enum { LOAD_ROWS = 0, LOAD_COLS = 1 };
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS operations
+// (lgkmcnt) but leaves its global loads in flight, unlike __syncthreads(), whose
+// fence also waits for every outstanding vector memory operation and so would
+// drain the prefetched tile at each barrier.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
@@ -216,11 +224,11 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
         gen_omega(t_begin, 1);
     }
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
-        __syncthreads();
+        lds_barrier();
         store_tile();
         if (nrm2_partial) norm_tile();
         store_omega();
-        __syncthreads();
+        lds_barrier();
         const bool more = tile + 1 < t_end;
         if (more) load_tile(tile + 1);
 #pragma unroll
