@@ -1008,6 +1008,7 @@ __global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict
                                                         uint32_t* __restrict__ status) {
     (void)unused;
     if (skip_if_gated && gate[0] != 0) return;
+    RT_DENSE_TRACE(1);
     __shared__ double W[NR][NR + 1];
     __shared__ __align__(16) double Lb[NR][NR + 2];
     __shared__ __align__(16) double colb[NR];
@@ -1016,32 +1017,48 @@ __global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict
     const int tid = threadIdx.x;
     // lower triangle of the summed Gram, the nparts loads of an entry in flight together
     const int ntri = ell * (ell + 1) / 2;
-    for (int e = tid; e < ntri; e += 256) {
+    constexpr int EPT = (NR * (NR + 1) / 2 + 255) / 256;    // triangle entries per thread
+    int eoff[EPT], ei[EPT], ej[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 256 * u;
         int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
         while ((i + 1) * (i + 2) / 2 <= e) ++i;
         while (i * (i + 1) / 2 > e) --i;
-        const int j = e - i * (i + 1) / 2;
-        const int64_t off = (int64_t)i * ell + j;
-        double acc = 0.0;
-        for (int b0 = 0; b0 < nparts; b0 += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = (b0 + u < nparts) ? part[(int64_t)(b0 + u) * ell * ell + off] : 0.0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += v[u];
-        }
-        W[i][j] = acc;
+        ei[u] = e < ntri ? i : -1;
+        ej[u] = e - i * (i + 1) / 2;
+        eoff[u] = e < ntri ? i * ell + ej[u] : 0;
     }
-    if (tid == 0) {
-        bool ok = true;
-        if (stats) {
-            double fro = 0.0, bad = 0.0;
-            for (int b = 0; b < nparts; ++b) { fro += stats[2 * b]; bad += stats[2 * b + 1]; }
-            ok = bad == 0.0 && fro > 0.0;
-        }
-        okflag = ok ? 1 : 0;
+    // the partial sums of all of a thread's entries, 8 parts at a time, in flight together
+    double acc[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
+    for (int b0 = 0; b0 < nparts; b0 += 8) {
+        double v[EPT][8];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                v[u][q] = (b0 + q < nparts) ? part[(int64_t)(b0 + q) * ell * ell + eoff[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[u] += v[u][q];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u)
+        if (ei[u] >= 0) W[ei[u]][ej[u]] = acc[u];
+    if (tid < 64) {
+        // finiteness and norm of the sketch from the per-part statistics (wave 0)
+        double fro = 0.0, bad = 0.0;
+        if (stats)
+            for (int b = tid; b < nparts; b += 64) { fro += stats[2 * b]; bad += stats[2 * b + 1]; }
+        fro = wave_sum(fro);
+        bad = wave_sum(bad);
+        if (tid == 0) okflag = (!stats || (bad == 0.0 && fro > 0.0)) ? 1 : 0;
     }
     __syncthreads();
+    RT_DENSE_TRACE(2);
     if (tid >= 64) return;
     const int lane = tid;
     if (lane < ell) d0[lane] = W[lane][lane];
@@ -1059,8 +1076,13 @@ __global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict
             ok = ok && !bad;
             const double pv = bad ? 1.0 : piv;
             mr = fmin(mr, bad ? 0.0 : pv / dk);
-            const double d = sqrt(pv);
-            const double l = (lane == k) ? d : w[k] / d;
+            // 1/sqrt(pv): hardware estimate refined by two Newton steps (relative
+            // error ~1e-16), d = pv / sqrt(pv)
+            double rs = __builtin_amdgcn_rsq(pv);
+            rs = rs * fma(-0.5 * pv, rs * rs, 1.5);
+            rs = rs * fma(-0.5 * pv, rs * rs, 1.5);
+            const double d = pv * rs;
+            const double l = (lane == k) ? d : w[k] * rs;
             if (lane >= k) w[k] = l;
             if (lane < NR) colb[lane] = (lane > k && lane < ell) ? l : 0.0;
             double cb[NR];
@@ -1077,6 +1099,7 @@ __global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict
         }
     }
     ok = ok && mr >= min_ratio;
+    RT_DENSE_TRACE(3);
     if (!ok) {
         if (lane == 0) { gate[0] = 1; if (status) status[0] = 0u; }
         return;
@@ -1108,6 +1131,7 @@ __global__ __launch_bounds__(256) void chol_gate_kernel(const double* __restrict
             x[i] = 0.0;
         }
     }
+    RT_DENSE_TRACE(4);
     // Linv[i][lane] = x_i (zero above the diagonal)
     if (lane < ell) {
 #pragma unroll
