@@ -117,17 +117,18 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
     }
 }
 
-// out[chunk][e] = sum of in[p][e] over p in [chunk * PC, min(nparts, (chunk+1) * PC)),
+// out[chunk][e] = sum of in[p][e] over p in [chunk * pc, min(nparts, (chunk+1) * pc)),
 // summed in fp64 in a fixed order (eight independent running sums combined
 // pairwise), so the result does not depend on the launch shape.
 constexpr int RP_PC = 32;
 
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const T* __restrict__ in, int64_t nparts, int64_t n,
-                                                              int64_t cols, int64_t ldin, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const T* __restrict__ in, int64_t nparts, int64_t pc,
+                                                              int64_t n, int64_t cols, int64_t ldin,
+                                                              double* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.y * RP_PC;
-    const int64_t p1 = p0 + RP_PC < nparts ? p0 + RP_PC : nparts;
+    const int64_t p0 = (int64_t)blockIdx.y * pc;
+    const int64_t p1 = p0 + pc < nparts ? p0 + pc : nparts;
     if (e >= n) return;
     const int64_t src = ldin == cols ? e : (e / cols) * ldin + e % cols;
     const int64_t ps = ldin == cols ? n : n / cols * ldin;   // elements per part
@@ -267,22 +268,22 @@ hipError_t launch_reduce_rows(const void* in, bool in_is_f64, int64_t nparts, in
         // one pass over all parts (fixed order)
         if (in_is_f64)
             hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)in,
-                               nparts, n, cols, ldin, out);
+                               nparts, nparts, n, cols, ldin, out);
         else
             hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, 1), dim3(256), 0, stream, (const float*)in,
-                               nparts, n, cols, ldin, out);
+                               nparts, nparts, n, cols, ldin, out);
         return hipGetLastError();
     }
     if (tmp == nullptr) return hipErrorInvalidValue;
-    // two passes: chunks of RP_PC parts, then the chunk sums
+    // two passes: chunks of RP_PC parts, then all nchunk chunk sums in one run
     if (in_is_f64)
         hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
-                           (const double*)in, nparts, n, cols, ldin, tmp);
+                           (const double*)in, nparts, (int64_t)RP_PC, n, cols, ldin, tmp);
     else
         hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(ex, (unsigned)nchunk), dim3(256), 0, stream,
-                           (const float*)in, nparts, n, cols, ldin, tmp);
+                           (const float*)in, nparts, (int64_t)RP_PC, n, cols, ldin, tmp);
     hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(ex, 1), dim3(256), 0, stream, (const double*)tmp, nchunk,
-                       n, n, n, out);
+                       nchunk, n, n, n, out);
     return hipGetLastError();
 }
 

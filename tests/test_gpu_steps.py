@@ -74,6 +74,22 @@ def test_sketch_large_k_sampled_rows(ctx):
     assert rel(Y, ref) < 2e-6
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sketch_many_split_chunks(ctx, dtype):
+    # 24 x 70000 and 24 x 331776 unfoldings: the generic kernel splits K over
+    # more than 32 x 32 workgroups, so its partial sums take both reduction
+    # passes with more than 32 chunk sums in the second
+    rng = np.random.default_rng(21)
+    for shape, n in (((24, 70000), 0), ((24, 24, 24, 24, 24), 3), ((24, 24, 24, 24, 24), 0)):
+        Xh = rng.standard_normal(shape).astype(np.float64 if dtype == torch.float64 else np.float32)
+        X = torch.from_numpy(Xh).cuda()
+        M = oracle.unfold(Xh.astype(np.float64), n)
+        for col0 in (0, 8):
+            Y = to_np(ctx.sketch(X, n, 8, seed=3, col0=col0))
+            ref = M @ oracle.omega(3, n, M.shape[1], range(col0, col0 + 8))
+            assert rel(Y, ref) < (1e-13 if dtype == torch.float64 else 2e-6), (shape, n, col0)
+
+
 def _orth_checks(Y, Q):
     assert np.allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-13)
     # range(Y) inside range(Q)

@@ -224,3 +224,17 @@ def test_adaptive_parity(ctx, dtype, b):
     Xf = Xs.astype(np.float64)
     _adaptive_check(g, o, Xf, eps, 1e-10 if dtype == torch.float64 else 1e-5,
                     2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adaptive_five_way_odeco(ctx, dtype):
+    # 24^5 orthogonally decomposable tensor, mode spectra 0.7^k: every later mode
+    # sketches unfoldings of 10^5 .. 3 10^5 columns, ranks about 21 per mode
+    rng = np.random.default_rng(3)
+    X = inputs.odeco(rng, (24,) * 5, 0.7)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    g = ctx.rsthosvd_adaptive(torch.from_numpy(Xs).cuda(), 1e-3, 8, seed=3)
+    o = oracle.adaptive_rsthosvd(Xs.astype(np.float64), 1e-3, 8, seed=3,
+                                 delta=1e-10 if dtype == torch.float64 else 1e-5)
+    _adaptive_check(g, o, Xs.astype(np.float64), 1e-3, 1e-10 if dtype == torch.float64 else 1e-5,
+                    2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
