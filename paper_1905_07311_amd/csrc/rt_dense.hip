@@ -39,6 +39,37 @@ __device__ double wave_sum(double v) {
     return v;
 }
 
+__device__ __forceinline__ double readlane64(double v, int l) {
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v moved across lanes by the DPP control CTRL for the rows in RMASK; lanes of
+// the other rows get 0.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, RMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, RMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wave through DPP (every lane active), returned to
+// every lane: quad swaps, half-row and row mirrors give every lane its row's
+// sum; row_bcast:15 and row_bcast:31 carry rows 0-2 into row 3, whose lane 63
+// ends with the total (a fixed order, so the same bits on every call).
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_f64<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xf>(v);    // row_half_mirror
+    v += dpp_f64<0x140, 0xf>(v);    // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return readlane64(v, 63);
+}
+
 
 // dst[e] = src(e) for e < n by `nthr` threads with PER loads in flight per
 // thread (all issued before the first store), for the small staging copies.
@@ -458,7 +489,8 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
 // vectors of Y are appended to Qall (ld = ldq) at column k.
 __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, int64_t J, int b,
                                                         double* __restrict__ Qall, int ldq, int k, double drop,
-                                                        double* __restrict__ V, int* __restrict__ knew) {
+                                                        double* __restrict__ V, int* __restrict__ knew,
+                                                        float* __restrict__ Qf) {
     __shared__ DenseShared S;
     const int tid = threadIdx.x;
     // y0 = ||Y||_F before the projections
@@ -558,6 +590,7 @@ __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, 
         double c = 0.0;
         for (int a = 0; a < b; ++a) c += Y[i * b + a] * S.W[a][j];
         Qall[i * ldq + k + t] = c;
+        if (Qf) Qf[i * ldq + k + t] = (float)c;
     }
     if (tid == 0) knew[0] = kept;
 }
@@ -686,6 +719,139 @@ __device__ __forceinline__ int jacobi_2p(Mat& A, int n, Mat& V, double tol, doub
     }
     RT_DENSE_TRACE_VAL(9, sweeps);
     return sweeps;
+}
+
+// ---- adaptive block step for blocks of at most 16 columns ----------------------------
+// The same result as block_orth_kernel, with Y (J x b) staged in LDS (row stride
+// b | 1): y0 = ||Y||_F, two passes of block Gram-Schmidt against Qall[:, :k],
+// then a parallel one-sided (Hestenes) Jacobi on the columns of Y: in each step
+// of the round-robin schedule wave t rotates the columns of pair t (sums of
+// squares and the inner product over the rows reduced through DPP) so that they
+// become orthogonal; a sweep without a rotation ends it.  The columns of Y are
+// then Y's left singular vectors times its singular values (the column norms);
+// those with sigma > drop * y0 are appended, normalised, in decreasing order.
+constexpr int BO_MAXB = 16;
+constexpr int BO_MAXE = 8192;    // J * (b | 1) doubles staged
+
+struct BlockOrthShared {
+    double Y[BO_MAXE];
+    double C[LMAX][BO_MAXB + 1];
+    double red[NT];
+    double sig[BO_MAXB];
+    int perm[BO_MAXB];
+    int flag[3];
+};
+
+__global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __restrict__ Yin, int64_t J, int b,
+                                                              double* __restrict__ Qall, int ldq, int k,
+                                                              double drop, int* __restrict__ knew,
+                                                              float* __restrict__ Qf) {
+    __shared__ BlockOrthShared S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ldy = b | 1;
+    const int Ji = (int)J;
+    double s = 0.0;
+    for (int e = tid; e < Ji * b; e += NT) {
+        const double v = Yin[e];
+        S.Y[(e / b) * ldy + e % b] = v;
+        s += v * v;
+    }
+    if (tid < 3) S.flag[tid] = 0;
+    const double y0 = sqrt(blk_sum(s, S.red));     // barrier inside: Y staged
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        // C = Qall[:, :k]^T Y
+        for (int e = tid; e < k * b; e += NT) {
+            const int a = e / b, j = e - (e / b) * b;
+            double c0 = 0.0, c1 = 0.0;
+            int i = 0;
+            for (; i + 2 <= Ji; i += 2) {
+                c0 = fma(Qall[(int64_t)i * ldq + a], S.Y[i * ldy + j], c0);
+                c1 = fma(Qall[(int64_t)(i + 1) * ldq + a], S.Y[(i + 1) * ldy + j], c1);
+            }
+            if (i < Ji) c0 = fma(Qall[(int64_t)i * ldq + a], S.Y[i * ldy + j], c0);
+            S.C[a][j] = c0 + c1;
+        }
+        __syncthreads();
+        // Y -= Qall[:, :k] C
+        for (int e = tid; e < Ji * b; e += NT) {
+            const int i = e / b, j = e - (e / b) * b;
+            const double* q = Qall + (int64_t)i * ldq;
+            double c = 0.0;
+            for (int a = 0; a < k; ++a) c = fma(q[a], S.C[a][j], c);
+            S.Y[i * ldy + j] -= c;
+        }
+        __syncthreads();
+    }
+    // one-sided Jacobi, pair t of a step on wave t
+    const int m = (b % 2) ? b + 1 : b;
+    const int half = m / 2;
+    for (int sweep = 0; sweep < 60 && b > 1; ++sweep) {
+        for (int step = 0; step < m - 1; ++step) {
+            int p = 0, q = 0;
+            if (wave < half) jpair(step, wave, m, p, q);
+            if (wave < half && q < b) {                  // wave-uniform
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = lane; i < Ji; i += 64) {
+                    const double yp = S.Y[i * ldy + p], yq = S.Y[i * ldy + q];
+                    al = fma(yp, yp, al);
+                    be = fma(yq, yq, be);
+                    ga = fma(yp, yq, ga);
+                }
+                al = wave_total(al);
+                be = wave_total(be);
+                ga = wave_total(ga);
+                if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al) * sqrt(be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = fabs(zeta) > 1e100 ? 0.5 / zeta
+                                                         : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    for (int i = lane; i < Ji; i += 64) {
+                        const double yp = S.Y[i * ldy + p], yq = S.Y[i * ldy + q];
+                        S.Y[i * ldy + p] = c * yp - sn * yq;
+                        S.Y[i * ldy + q] = sn * yp + c * yq;
+                    }
+                    if (lane == 0) S.flag[sweep % 3] = 1;
+                }
+            }
+            __syncthreads();
+        }
+        // flag[s % 3] is set during sweep s and read after its last barrier; the
+        // flag of sweep s + 2 is cleared now: its last readers (end of sweep s - 1)
+        // are done, and its first writer waits for the barriers of sweep s + 1
+        const int rotated = S.flag[sweep % 3];
+        if (tid == 0) S.flag[(sweep + 2) % 3] = 0;
+        if (!rotated) break;
+    }
+    // singular values = column norms
+    for (int j = wave; j < b; j += NT / 64) {
+        double n2 = 0.0;
+        for (int i = lane; i < Ji; i += 64) n2 = fma(S.Y[i * ldy + j], S.Y[i * ldy + j], n2);
+        n2 = wave_total(n2);
+        if (lane == 0) S.sig[j] = sqrt(n2);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned used = 0u;                                 // bit j: column j placed
+        int kept = 0;
+        for (int t = 0; t < b; ++t) {
+            int best = -1;
+            for (int j = 0; j < b; ++j)
+                if (!((used >> j) & 1u) && (best < 0 || S.sig[j] > S.sig[best])) best = j;
+            used |= 1u << best;
+            if (S.sig[best] > drop * y0 && y0 > 0.0) S.perm[kept++] = best;
+        }
+        S.flag[0] = kept;
+    }
+    __syncthreads();
+    const int kept = S.flag[0];
+    for (int e = tid; e < Ji * kept; e += NT) {
+        const int i = e / kept, t = e - (e / kept) * kept;
+        const int j = S.perm[t];
+        const double v = S.Y[i * ldy + j] / S.sig[j];
+        Qall[(int64_t)i * ldq + k + t] = v;
+        if (Qf) Qf[(int64_t)i * ldq + k + t] = (float)v;
+    }
+    if (tid == 0) knew[0] = kept;
 }
 
 struct EigShared {
@@ -984,13 +1150,6 @@ __global__ __launch_bounds__(256) void gram_rows_kernel(const double* __restrict
     }
 }
 
-__device__ __forceinline__ double readlane64(double v, int l) {
-    const unsigned long long u = __double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Sums the nparts partial Grams (fixed order), factors W = L L^T and tests the
 // pivots: accepted when every pivot ratio pivot_k / W_kk is >= min_ratio (and,
 // with stats, the sketch is finite and non-zero).  On acceptance writes
@@ -1275,9 +1434,14 @@ size_t truncate_scratch(int64_t J, int ell) {
 }
 
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k, double drop, int* knew,
-                             double* scratch, hipStream_t stream) {
+                             float* Qf, double* scratch, hipStream_t stream) {
+    if (b <= BO_MAXB && J * (int64_t)(b | 1) <= BO_MAXE && k <= LMAX) {
+        hipLaunchKernelGGL(block_orth_small_kernel, dim3(1), dim3(NT), 0, stream, (const double*)Y, J, b, Qall, ldq,
+                           k, drop, knew, Qf);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(block_orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, b, Qall, ldq, k, drop,
-                       scratch, knew);
+                       scratch, knew, Qf);
     return hipGetLastError();
 }
 

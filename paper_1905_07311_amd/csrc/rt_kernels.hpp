@@ -116,10 +116,10 @@ size_t truncate_scratch(int64_t J, int ell);
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
 // then orthonormalised with a rank-revealing drop (singular values <= drop * ||Y_in||_F
 // are dropped).  The kept columns are appended to Qall at column k; knew[0] = number
-// appended; Qf (optional) gets the float copy of the appended columns.
+// appended; Qf (optional, J x ld floats) gets the float copy of the appended columns.
 // `scratch`: 2 J b doubles.
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k,
-                             double drop, int* knew, double* scratch, hipStream_t stream);
+                             double drop, int* knew, float* Qf, double* scratch, hipStream_t stream);
 // one-time per-device set-up of the single-workgroup dense kernels (LDS > 64 KiB)
 hipError_t dense_init();
 

@@ -690,12 +690,15 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX);
         if (max_rank) cap = std::min(cap, (int)max_rank[n]);
         double* Qall = k.ws<double>((size_t)J * cap);
+        // float copy of the basis: float32 data is projected on MFMA with a float Q
+        // (||B_i||^2 is still summed in fp64)
+        float* Qallf = dt == Dt::F32 ? k.ws<float>((size_t)J * cap) : nullptr;
         void* Bbuf = k.c->ws((size_t)s.L * cap * s.R * es);
         double* Y = k.ws<double>((size_t)J * block);
         double* scratch = k.ws<double>((size_t)2 * J * block);
         double* W = k.ws<double>((size_t)cap * cap);
         double* Edev = k.ws<double>(1);
-        if (!Qall || !Bbuf || !Y || !scratch || !W || !Edev) {
+        if (!Qall || !Bbuf || !Y || !scratch || !W || !Edev || (dt == Dt::F32 && !Qallf)) {
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "workspace allocation failed");
         }
@@ -714,8 +717,12 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                 const int bi = std::min(block, cap - kcols);
                 rt_status rs = do_sketch(k, dt, prec_cur, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y, nullptr);
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
-                RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop,
-                                             kdev, scratch, st));
+                {
+                    TimeScope ts(k.c, 2, 8.0 * J * (bi + 2.0 * kcols), 8.0 * J * bi * kcols, J, kcols, bi);
+                    RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols,
+                                                 prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop, kdev, Qallf,
+                                                 scratch, st));
+                }
                 RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
                 int kn = 0;
@@ -726,7 +733,8 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                     continue;
                 }
                 if (kn <= 0) break;                              // range exhausted
-                rs = do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
+                rs = Qallf ? do_project(k, dt, Dt::F32, cur, s, s.J, Qallf + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp)
+                           : do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
                 RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
