@@ -167,7 +167,7 @@ bool sketch_mfma_ok(Shape3 s, int ell, int64_t col0, const void* X) {
     if (ell > 64) return false;
     if (((uintptr_t)X & 15) != 0) return false;
     if ((col0 + ell - 1) / 4 - col0 / 4 + 1 > 16) return false;   // Omega blocks per tile row: 2 per thread
-    if (s.R % 32 == 0) return true;
+    if (s.R % 4 == 0) return true;
     if (s.R == 1 && s.J % 4 == 0) return true;
     return false;
 }
@@ -234,7 +234,7 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                          double* nrm2_partial, hipStream_t stream) {
     if (p.kind == 1 || p.kind == 2) {
         const bool bf = p.kind == 2;
-        if (s.R % 32 == 0)
+        if (s.R % 4 == 0)
             return (bf ? launch_sketch_bf16_rows : launch_sketch_f32_rows)(p, (const float*)X, s, ell, col0, seed,
                                                                          mode, (float*)partial, nrm2_partial, stream);
         return (bf ? launch_sketch_bf16_cols : launch_sketch_f32_cols)(p, (const float*)X, s, ell, col0, seed, mode,

@@ -15,7 +15,7 @@
 // the columns of each tile and their sums are added through LDS at the end.
 //
 // Per 32-column tile: X is loaded one tile ahead into registers with coalesced
-// 16-byte loads (rows contiguous when R % 32 == 0, columns contiguous when
+// 16-byte loads (along the rows when R % 4 == 0, along the columns when
 // R == 1) and stored to LDS; Omega for the next tile is generated into
 // registers by the whole workgroup, one or two Philox blocks per thread.
 // Partial sums per split of the unfolding columns go to
@@ -76,7 +76,7 @@ struct TileShape {
 // X viewed as (L, J, R) row-major; unfolding column c = l R + r.
 // BF: the products are formed in bfloat16 (X and Omega rounded to nearest) with
 // float32 accumulation; otherwise in float32.
-// LOAD_ROWS needs R % 32 == 0 (a tile lies in one l-slab); LOAD_COLS needs
+// LOAD_ROWS needs R % 4 == 0 (four columns of a load lie in one l-slab); LOAD_COLS needs
 // R == 1 and J % 4 == 0.  16-byte alignment of X; ell <= 4 NQ <= 64; the
 // Omega blocks of columns [col0, col0 + ell) number at most 16.
 template <int RB, int RW, int NQ, int LOADER, bool BF>
@@ -122,28 +122,39 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
     // whole tiles (all MT rows present, all KC columns inside K) load without
     // per-element guards
     const bool rows_full = row0 + MT <= J;
+    // LOAD_ROWS: a thread always loads the four columns 4 (tid & 7) .. + 3 of a
+    // tile, which lie in one l-slab since R % 4 == 0; their (l, r) is advanced by
+    // KC per tile (tiles are loaded in order)
+    int64_t cur_l = 0, cur_r = 0;
+    if (LOADER == LOAD_ROWS) {
+        const int64_t cg = t_begin * KC + 4 * (tid & 7);
+        cur_l = cg / R;
+        cur_r = cg - cur_l * R;
+    }
     auto load_tile = [&](int64_t tile) {
         const int64_t c0 = tile * KC;
         const bool full = rows_full && c0 + KC <= K;
         if (LOADER == LOAD_ROWS) {
-            const int64_t l = c0 / R;
-            const float* base = X + l * J * R + (c0 - l * R) + row0 * R;
+            const float* base = X + (cur_l * J + row0) * R + cur_r;
+            const int cc = 4 * (tid & 7);
             if (full) {
 #pragma unroll
                 for (int it = 0; it < NLOAD; ++it) {
                     const int e = tid + 256 * it;
-                    pre[it] = *reinterpret_cast<const f4*>(base + (int64_t)(e >> 3) * R + 4 * (e & 7));
+                    pre[it] = *reinterpret_cast<const f4*>(base + (int64_t)(e >> 3) * R);
                 }
             } else {
 #pragma unroll
                 for (int it = 0; it < NLOAD; ++it) {
                     const int e = tid + 256 * it;
-                    const int rr = e >> 3, cc = 4 * (e & 7);
+                    const int rr = e >> 3;
                     f4 v = f4{0.f, 0.f, 0.f, 0.f};
-                    if (row0 + rr < J && c0 + cc < K) v = *reinterpret_cast<const f4*>(base + (int64_t)rr * R + cc);
+                    if (row0 + rr < J && c0 + cc < K) v = *reinterpret_cast<const f4*>(base + (int64_t)rr * R);
                     pre[it] = v;
                 }
             }
+            cur_r += KC;
+            while (cur_r >= R) { cur_r -= R; ++cur_l; }
         } else {
             const float* base = X + c0 * J + row0;
             if (full) {

@@ -1,5 +1,5 @@
 // Instantiations of the bfloat16 MFMA sketch for unfoldings whose rows are
-// contiguous in memory (R % 32 == 0).
+// loaded along the rows (R % 4 == 0).
 #include "rt_sketch_mfma_launch.hpp"
 
 namespace rt {

@@ -1,5 +1,5 @@
 // Instantiations of the float32 MFMA sketch for unfoldings whose rows are
-// contiguous in memory (R % 32 == 0).
+// loaded along the rows (R % 4 == 0).
 #include "rt_sketch_mfma_launch.hpp"
 
 namespace rt {

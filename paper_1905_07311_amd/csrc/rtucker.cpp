@@ -331,7 +331,7 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
         const size_t es = dt == Dt::F64 ? 8 : 4;
         if (!*core_out) *core_out = k.c->ws((size_t)sb.L * kk * sb.R * es);
         if (!*core_out) return fail(RT_ENOMEM, "workspace allocation failed");
-        const bool f64q = dt == Dt::F64 || refine || r_fixed < 0;
+        const bool f64q = dt == Dt::F64 || refine;
         RT_TRY(do_project(k, dt, f64q ? Dt::F64 : Dt::F32, Bcur, sb, ldcur, f64q ? (const void*)U : (const void*)Uf,
                           kk, kk, *core_out, kk, 0, nullptr, k.c->last_nrm2));
     }

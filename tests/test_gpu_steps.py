@@ -157,9 +157,12 @@ def test_projection_and_gram(ctx, shape, dtype):
             assert rel(to_np(B64), ref64) < 1e-7
 
 
-# shapes that take the MFMA (float32) kernels: R % 32 == 0 or R == 1 with J % 4 == 0
-# for the sketch; R even for the projection (four columns per lane when R % 4 == 0)
-MFMA_SHAPES = [(40, 96, 64), (300, 32, 64), (600, 32, 32), (8, 1024, 32), (16, 24, 6)]
+# shapes that take the MFMA (float32) kernels: R % 4 == 0 or R == 1 with J % 4 == 0
+# for the sketch (tiles of 32 unfolding columns that cross l-slabs when R % 32 != 0,
+# several times per tile when R < 32); R even for the projection (four columns per
+# lane when R % 4 == 0)
+MFMA_SHAPES = [(40, 96, 64), (300, 32, 64), (600, 32, 32), (8, 1024, 32), (16, 24, 6),
+               (50, 37, 4), (33, 70, 8), (9, 100, 20), (6, 65, 44), (30, 48, 48)]
 
 
 @pytest.mark.parametrize("shape", MFMA_SHAPES)
