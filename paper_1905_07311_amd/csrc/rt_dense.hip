@@ -70,6 +70,17 @@ __device__ __forceinline__ double wave_total(double v) {
     return readlane64(v, 63);
 }
 
+// Sum over aligned groups of G = 8 or 16 lanes through DPP, returned to every
+// lane of the group.
+template <int G>
+__device__ __forceinline__ double group_total(double v) {
+    v += dpp_f64<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xf>(v);    // row_half_mirror: 8-lane sums
+    if (G == 16) v += dpp_f64<0x140, 0xf>(v);    // row_mirror: 16-lane sums
+    return v;
+}
+
 
 // dst[e] = src(e) for e < n by `nthr` threads with PER loads in flight per
 // thread (all issued before the first store), for the small staging copies.
@@ -582,13 +593,16 @@ __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, 
     }
     __syncthreads();
     const int kept = S.flag[0];
-    // new basis columns: Qy * Vr[:, perm[t]]  (Qy in Y, J x b)
-    for (int64_t e = tid; e < J * kept; e += NT) {
-        const int64_t i = e / kept;
-        const int t = (int)(e % kept);
-        const int j = S.perm[t];
+    // new basis columns: Qy * Vr[:, perm[t]]  (Qy in Y, J x b); columns
+    // k + kept .. k + b - 1 are zero-filled
+    for (int64_t e = tid; e < J * b; e += NT) {
+        const int64_t i = e / b;
+        const int t = (int)(e % b);
         double c = 0.0;
-        for (int a = 0; a < b; ++a) c += Y[i * b + a] * S.W[a][j];
+        if (t < kept) {
+            const int j = S.perm[t];
+            for (int a = 0; a < b; ++a) c += Y[i * b + a] * S.W[a][j];
+        }
         Qall[i * ldq + k + t] = c;
         if (Qf) Qf[i * ldq + k + t] = (float)c;
     }
@@ -742,6 +756,38 @@ struct BlockOrthShared {
     int flag[3];
 };
 
+// Rotation (c, s) of the one-sided Jacobi step for columns p, q with Gram
+// entries al = |y_p|^2, be = |y_q|^2, ga = y_p . y_q (ga != 0):
+// t = 2 ga / (d + sign(d) sqrt(d^2 + 4 ga^2)), d = be - al, the smaller of the
+// two angles that make the rotated columns orthogonal; c = 1 / sqrt(1 + t^2),
+// s = c t.  d and 2 ga are scaled by a power of two first; square root and
+// reciprocal are the hardware approximations refined by Newton steps in fp64.
+__device__ __forceinline__ void hestenes_rot(double al, double be, double ga, double& c, double& s) {
+    double d = be - al, a2 = 2.0 * ga;
+    const int e = ilogb(fmax(fabs(d), fabs(a2)));
+    d = ldexp(d, -e);
+    a2 = ldexp(a2, -e);
+    const double x = fma(d, d, a2 * a2);                     // in [1, 8)
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    const double r = x * y;
+    const double den = d >= 0.0 ? d + r : d - r;            // |den| >= r >= 1
+    double q = __builtin_amdgcn_rcp(den);
+    q = q * fma(-den, q, 2.0);
+    q = q * fma(-den, q, 2.0);
+    const double t = a2 * q;                                 // |t| <= 1
+    const double x2 = fma(t, t, 1.0);
+    double w = __builtin_amdgcn_rsq(x2);
+    w = w * fma(-0.5 * x2, w * w, 1.5);
+    w = w * fma(-0.5 * x2, w * w, 1.5);
+    c = w;
+    s = w * t;
+}
+
+// Jacobi layout: G = 8 or 16: one wave, G lanes per pair, RW rows per lane
+// (J <= G RW, b <= 128 / G); G = 0: one wave per pair, RW rows per lane (J <= 64 RW).
+template <int G, int RW>
 __global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __restrict__ Yin, int64_t J, int b,
                                                               double* __restrict__ Qall, int ldq, int k,
                                                               double drop, int* __restrict__ knew,
@@ -758,70 +804,139 @@ __global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __re
     }
     if (tid < 3) S.flag[tid] = 0;
     const double y0 = sqrt(blk_sum(s, S.red));     // barrier inside: Y staged
+    RT_DENSE_TRACE(1);
     for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        // C = Qall[:, :k]^T Y
+        // C = Qall[:, :k]^T Y (eight running sums per thread, fixed order)
         for (int e = tid; e < k * b; e += NT) {
             const int a = e / b, j = e - (e / b) * b;
-            double c0 = 0.0, c1 = 0.0;
+            double c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = 0.0;
             int i = 0;
-            for (; i + 2 <= Ji; i += 2) {
-                c0 = fma(Qall[(int64_t)i * ldq + a], S.Y[i * ldy + j], c0);
-                c1 = fma(Qall[(int64_t)(i + 1) * ldq + a], S.Y[(i + 1) * ldy + j], c1);
+            for (; i + 8 <= Ji; i += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = fma(Qall[(int64_t)(i + u) * ldq + a], S.Y[(i + u) * ldy + j], c[u]);
             }
-            if (i < Ji) c0 = fma(Qall[(int64_t)i * ldq + a], S.Y[i * ldy + j], c0);
-            S.C[a][j] = c0 + c1;
+            for (; i < Ji; ++i) c[0] = fma(Qall[(int64_t)i * ldq + a], S.Y[i * ldy + j], c[0]);
+            S.C[a][j] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
         }
         __syncthreads();
         // Y -= Qall[:, :k] C
         for (int e = tid; e < Ji * b; e += NT) {
             const int i = e / b, j = e - (e / b) * b;
-            const double* q = Qall + (int64_t)i * ldq;
-            double c = 0.0;
-            for (int a = 0; a < k; ++a) c = fma(q[a], S.C[a][j], c);
-            S.Y[i * ldy + j] -= c;
+            const double* qr = Qall + (int64_t)i * ldq;
+            double c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = 0.0;
+            int a = 0;
+            for (; a + 8 <= k; a += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = fma(qr[a + u], S.C[a + u][j], c[u]);
+            }
+            for (; a < k; ++a) c[0] = fma(qr[a], S.C[a][j], c[0]);
+            S.Y[i * ldy + j] -= ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
         }
         __syncthreads();
     }
-    // one-sided Jacobi, pair t of a step on wave t
+    RT_DENSE_TRACE(2);
     const int m = (b % 2) ? b + 1 : b;
     const int half = m / 2;
-    for (int sweep = 0; sweep < 60 && b > 1; ++sweep) {
-        for (int step = 0; step < m - 1; ++step) {
-            int p = 0, q = 0;
-            if (wave < half) jpair(step, wave, m, p, q);
-            if (wave < half && q < b) {                  // wave-uniform
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < Ji; i += 64) {
-                    const double yp = S.Y[i * ldy + p], yq = S.Y[i * ldy + q];
-                    al = fma(yp, yp, al);
-                    be = fma(yq, yq, be);
-                    ga = fma(yp, yq, ga);
-                }
-                al = wave_total(al);
-                be = wave_total(be);
-                ga = wave_total(ga);
-                if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al) * sqrt(be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = fabs(zeta) > 1e100 ? 0.5 / zeta
-                                                         : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                    for (int i = lane; i < Ji; i += 64) {
-                        const double yp = S.Y[i * ldy + p], yq = S.Y[i * ldy + q];
-                        S.Y[i * ldy + p] = c * yp - sn * yq;
-                        S.Y[i * ldy + q] = sn * yp + c * yq;
+    int sweeps = 0;
+    if (G > 0) {
+        // one wave: pair slot g = lane / G of every step on lanes g G .. g G + G - 1,
+        // rows sub + G r (r < RW) of the pair in registers; LDS writes of a step are
+        // seen by the next step's reads in program order
+        if (wave == 0) {
+            const int g = lane / (G > 0 ? G : 1), sub = lane % (G > 0 ? G : 1);
+            for (int sweep = 0; sweep < 60 && b > 1; ++sweep) {
+                ++sweeps;
+                bool any = false;
+                for (int step = 0; step < m - 1; ++step) {
+                    int p = 0, q = 0;
+                    if (g < half) jpair(step, g, m, p, q);
+                    const bool ok = g < half && q < b;
+                    double yp[RW], yq[RW];
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RW; ++r) {
+                        const int i = sub + G * r;
+                        const bool v = ok && i < Ji;
+                        yp[r] = v ? S.Y[i * ldy + p] : 0.0;
+                        yq[r] = v ? S.Y[i * ldy + q] : 0.0;
+                        al = fma(yp[r], yp[r], al);
+                        be = fma(yq[r], yq[r], be);
+                        ga = fma(yp[r], yq[r], ga);
                     }
-                    if (lane == 0) S.flag[sweep % 3] = 1;
+                    al = group_total<G>(al);
+                    be = group_total<G>(be);
+                    ga = group_total<G>(ga);
+                    if (ok && ga != 0.0 && ga * ga > 1e-30 * (al * be)) {
+                        double c, sn;
+                        hestenes_rot(al, be, ga, c, sn);
+#pragma unroll
+                        for (int r = 0; r < RW; ++r) {
+                            const int i = sub + G * r;
+                            if (i < Ji) {
+                                S.Y[i * ldy + p] = c * yp[r] - sn * yq[r];
+                                S.Y[i * ldy + q] = sn * yp[r] + c * yq[r];
+                            }
+                        }
+                        any = true;
+                    }
                 }
+                if (!__any(any)) break;
             }
-            __syncthreads();
         }
-        // flag[s % 3] is set during sweep s and read after its last barrier; the
-        // flag of sweep s + 2 is cleared now: its last readers (end of sweep s - 1)
-        // are done, and its first writer waits for the barriers of sweep s + 1
-        const int rotated = S.flag[sweep % 3];
-        if (tid == 0) S.flag[(sweep + 2) % 3] = 0;
-        if (!rotated) break;
+        __syncthreads();
+    } else {
+        // pair t of a step on wave t, rows lane + 64 r (r < RW) in registers; one
+        // barrier per step
+        for (int sweep = 0; sweep < 60 && b > 1; ++sweep) {
+            ++sweeps;
+            for (int step = 0; step < m - 1; ++step) {
+                int p = 0, q = 0;
+                if (wave < half) jpair(step, wave, m, p, q);
+                if (wave < half && q < b) {                  // wave-uniform
+                    double yp[RW], yq[RW];
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RW; ++r) {
+                        const int i = lane + 64 * r;
+                        yp[r] = i < Ji ? S.Y[i * ldy + p] : 0.0;
+                        yq[r] = i < Ji ? S.Y[i * ldy + q] : 0.0;
+                        al = fma(yp[r], yp[r], al);
+                        be = fma(yq[r], yq[r], be);
+                        ga = fma(yp[r], yq[r], ga);
+                    }
+                    al = wave_total(al);
+                    be = wave_total(be);
+                    ga = wave_total(ga);
+                    if (ga != 0.0 && ga * ga > 1e-30 * (al * be)) {
+                        double c, sn;
+                        hestenes_rot(al, be, ga, c, sn);
+#pragma unroll
+                        for (int r = 0; r < RW; ++r) {
+                            const int i = lane + 64 * r;
+                            if (i < Ji) {
+                                S.Y[i * ldy + p] = c * yp[r] - sn * yq[r];
+                                S.Y[i * ldy + q] = sn * yp[r] + c * yq[r];
+                            }
+                        }
+                        if (lane == 0) S.flag[sweep % 3] = 1;
+                    }
+                }
+                __syncthreads();
+            }
+            // flag[s % 3] is set during sweep s and read after its last barrier; the
+            // flag of sweep s + 2 is cleared now: its last readers (end of sweep s - 1)
+            // are done, and its first writer waits for the barriers of sweep s + 1
+            const int rotated = S.flag[sweep % 3];
+            if (tid == 0) S.flag[(sweep + 2) % 3] = 0;
+            if (!rotated) break;
+        }
     }
+    RT_DENSE_TRACE(3);
+    RT_DENSE_TRACE_VAL(9, sweeps);
     // singular values = column norms
     for (int j = wave; j < b; j += NT / 64) {
         double n2 = 0.0;
@@ -844,14 +959,16 @@ __global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __re
     }
     __syncthreads();
     const int kept = S.flag[0];
-    for (int e = tid; e < Ji * kept; e += NT) {
-        const int i = e / kept, t = e - (e / kept) * kept;
-        const int j = S.perm[t];
-        const double v = S.Y[i * ldy + j] / S.sig[j];
+    // columns k + kept .. k + b - 1 are zero-filled (a projection over all b
+    // columns then gives zero rows of B for them)
+    for (int e = tid; e < Ji * b; e += NT) {
+        const int i = e / b, t = e - (e / b) * b;
+        const double v = t < kept ? S.Y[i * ldy + S.perm[t]] / S.sig[S.perm[t]] : 0.0;
         Qall[(int64_t)i * ldq + k + t] = v;
         if (Qf) Qf[(int64_t)i * ldq + k + t] = (float)v;
     }
     if (tid == 0) knew[0] = kept;
+    RT_DENSE_TRACE(4);
 }
 
 struct EigShared {
@@ -1435,9 +1552,24 @@ size_t truncate_scratch(int64_t J, int ell) {
 
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k, double drop, int* knew,
                              float* Qf, double* scratch, hipStream_t stream) {
-    if (b <= BO_MAXB && J * (int64_t)(b | 1) <= BO_MAXE && k <= LMAX) {
-        hipLaunchKernelGGL(block_orth_small_kernel, dim3(1), dim3(NT), 0, stream, (const double*)Y, J, b, Qall, ldq,
-                           k, drop, knew, Qf);
+    if (b <= BO_MAXB && J * (int64_t)(b | 1) <= BO_MAXE && k <= LMAX && J <= 1024) {
+#define RT_BO(GV, RWV)                                                                                          \
+    hipLaunchKernelGGL((block_orth_small_kernel<GV, RWV>), dim3(1), dim3(NT), 0, stream, (const double*)Y, J, b, \
+                       Qall, ldq, k, drop, knew, Qf)
+        const int G = b <= 8 ? 16 : 8;
+        if (G == 16 && J <= 16) RT_BO(16, 1);
+        else if (G == 16 && J <= 32) RT_BO(16, 2);
+        else if (G == 16 && J <= 64) RT_BO(16, 4);
+        else if (G == 16 && J <= 128) RT_BO(16, 8);
+        else if (G == 8 && J <= 8) RT_BO(8, 1);
+        else if (G == 8 && J <= 16) RT_BO(8, 2);
+        else if (G == 8 && J <= 32) RT_BO(8, 4);
+        else if (G == 8 && J <= 64) RT_BO(8, 8);
+        else if (J <= 128) RT_BO(0, 2);
+        else if (J <= 256) RT_BO(0, 4);
+        else if (J <= 512) RT_BO(0, 8);
+        else RT_BO(0, 16);
+#undef RT_BO
         return hipGetLastError();
     }
     hipLaunchKernelGGL(block_orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, b, Qall, ldq, k, drop,

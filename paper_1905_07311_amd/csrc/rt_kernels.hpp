@@ -115,8 +115,9 @@ size_t truncate_scratch(int64_t J, int ell);
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
 // then orthonormalised with a rank-revealing drop (singular values <= drop * ||Y_in||_F
-// are dropped).  The kept columns are appended to Qall at column k; knew[0] = number
-// appended; Qf (optional, J x ld floats) gets the float copy of the appended columns.
+// are dropped).  The kept columns are appended to Qall at column k and columns
+// k + kept .. k + b - 1 are zeroed; knew[0] = kept; Qf (optional, J x ld floats)
+// gets the float copy of these b columns.
 // `scratch`: 2 J b doubles.
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k,
                              double drop, int* knew, float* Qf, double* scratch, hipStream_t stream);

@@ -723,7 +723,13 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                                                  prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop, kdev, Qallf,
                                                  scratch, st));
                 }
+                // B_i over all bi columns (the dropped ones are zero), then kn and
+                // ||B_i||^2 come back together
+                rs = Qallf ? do_project(k, dt, Dt::F32, cur, s, s.J, Qallf + kcols, cap, bi, Bbuf, cap, kcols, nullptr, tmp)
+                           : do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, bi, Bbuf, cap, kcols, nullptr, tmp);
+                if (rs != RT_OK) { release_partial(ctx, out); return rs; }
                 RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
+                RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
                 int kn = 0;
                 std::memcpy(&kn, h + 1, sizeof(int));
@@ -733,11 +739,6 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                     continue;
                 }
                 if (kn <= 0) break;                              // range exhausted
-                rs = Qallf ? do_project(k, dt, Dt::F32, cur, s, s.J, Qallf + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp)
-                           : do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, kn, Bbuf, cap, kcols, nullptr, tmp);
-                if (rs != RT_OK) { release_partial(ctx, out); return rs; }
-                RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
-                RT_HIP(hipStreamSynchronize(st));
                 E -= h[2];                                       // E <- E - ||B_i||^2
                 kcols += kn;
             }
