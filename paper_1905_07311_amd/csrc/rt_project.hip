@@ -364,6 +364,118 @@ __global__ __launch_bounds__(256) void gram3_kernel(const T* __restrict__ B, int
     else gram3_body<T, false>(B, L, ldk, R, k, partial, bs);
 }
 
+// fp64 Gram of the first k <= 64 mode rows of a float (L, ldk, R) tensor with
+// R % 4 == 0 on the fp64 matrix cores: W = sum over unfolding columns c of
+// b_c b_c^T, b_c = B[l, 0:k, r], c = l R + r.  Rows are taken in blocks of 16;
+// v_mfma_f64_16x16x4f64 forms D += A_i A_j^T for every block pair i <= j, lane
+// 16 q + s supplying row s of its block at column q of the four (both operands
+// have this layout, since the second factor is a transposed row block), and
+// lane 16 q + s of the result holding D[4 v + q][s] in component v.  A lane
+// loads the four consecutive columns 4 q .. 4 q + 3 of a 16-column chunk as one
+// float4 (one l-slab, since R % 4 == 0) and feeds component u to the u-th MFMA
+// of the chunk: each MFMA then sums over columns {u, 4 + u, 8 + u, 12 + u},
+// the same set for both operands.  Float products are exact in fp64 and the
+// sums are fp64.  A wave takes a contiguous run of chunks; the four waves of a
+// workgroup add their blocks in a fixed order into partial[wg] (k x k).
+typedef double gd4 __attribute__((ext_vector_type(4)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
+static __global__ __launch_bounds__(256) void gram_mfma_kernel(const float* __restrict__ B, int64_t L, int64_t ldk,
+                                                        int64_t R, int k, int64_t chunks_per_wave,
+                                                        double* __restrict__ partial) {
+    constexpr int NP = NB * (NB + 1) / 2;
+    __shared__ double red[3][NP * 256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = lane >> 4, srow = lane & 15;
+    const int64_t K = L * R;
+    const int64_t nchunks = (K + 15) / 16;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t c_begin = gw * chunks_per_wave;
+    const int64_t c_end = c_begin + chunks_per_wave < nchunks ? c_begin + chunks_per_wave : nchunks;
+    gd4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = gd4{0.0, 0.0, 0.0, 0.0};
+    bool rowok[NB];
+    int64_t rowoff[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int a = 16 * b + srow;
+        rowok[b] = a < k;
+        rowoff[b] = (int64_t)(a < k ? a : 0) * R;
+    }
+    const int64_t maxoff = L * ldk * R - 4;
+    // (l, r) of this lane's first column, advanced by 16 columns per chunk
+    int64_t cl = 0, cr = 0;
+    if (c_begin < c_end) {
+        const int64_t c0 = 16 * c_begin + 4 * q;
+        cl = c0 / R;
+        cr = c0 - cl * R;
+    }
+    auto load = [&](int64_t chunk, gf4 (&v)[NB]) {
+        const bool colok = 16 * chunk + 4 * q < K;
+        const int64_t base = cl * ldk * R + cr;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            int64_t off = base + rowoff[b];
+            off = off < maxoff ? off : maxoff;
+            const gf4 x = *reinterpret_cast<const gf4*>(B + off);
+            v[b] = (rowok[b] && colok) ? x : gf4{0.f, 0.f, 0.f, 0.f};
+        }
+        cr += 16;
+        while (cr >= R) { cr -= R; ++cl; }
+    };
+    gf4 cur[NB], nxt[NB];
+    if (c_begin < c_end) load(c_begin, cur);
+    for (int64_t ch = c_begin; ch < c_end; ++ch) {
+        if (ch + 1 < c_end) load(ch + 1, nxt);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double x[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) x[b] = (double)cur[b][u];
+            int p = 0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = bi; bj < NB; ++bj) {
+                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[bi], x[bj], acc[p], 0, 0, 0);
+                    ++p;
+                }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) cur[b] = nxt[b];
+    }
+    // waves 1..3 hand their blocks to wave 0, which adds them in wave order
+    if (wave > 0) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[wave - 1][p * 256 + v * 64 + lane] = acc[p][v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* gp = partial + (int64_t)blockIdx.x * k * k;
+        int p = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double sum = ((acc[p][v] + red[0][p * 256 + v * 64 + lane]) + red[1][p * 256 + v * 64 + lane]) +
+                                       red[2][p * 256 + v * 64 + lane];
+                    const int i = 16 * bi + 4 * v + q, j = 16 * bj + srow;
+                    if (i < k && j < k) {
+                        gp[i * k + j] = sum;
+                        if (bi != bj) gp[j * k + i] = sum;
+                    }
+                }
+                ++p;
+            }
+    }
+}
+
 int plan_gram3(int64_t L, int64_t R) {
     const int64_t nt = (L * R + G3_NC - 1) / G3_NC;
     return (int)(nt < 512 ? (nt < 1 ? 1 : nt) : 512);
@@ -371,6 +483,20 @@ int plan_gram3(int64_t L, int64_t R) {
 
 hipError_t launch_gram3(const void* B, Dt dt, int64_t L, int64_t ldk, int64_t R, int k, double* partial, int nwg,
                         hipStream_t stream) {
+    if (dt == Dt::F32 && R % 4 == 0 && k <= 64 && ((uintptr_t)B & 15) == 0) {
+        const int64_t nchunks = (L * R + 15) / 16;
+        const int64_t waves = 4 * (int64_t)nwg;
+        const int64_t cpw = (nchunks + waves - 1) / waves;
+#define RT_GM(NBV)                                                                                                \
+    hipLaunchKernelGGL(gram_mfma_kernel<NBV>, dim3(nwg), dim3(256), 0, stream, (const float*)B, L, ldk, R, k, cpw, \
+                       partial)
+        if (k <= 16) RT_GM(1);
+        else if (k <= 32) RT_GM(2);
+        else if (k <= 48) RT_GM(3);
+        else RT_GM(4);
+#undef RT_GM
+        return hipGetLastError();
+    }
     if (dt == Dt::F64)
         hipLaunchKernelGGL(gram3_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)B, L, ldk, R, k,
                            partial);
