@@ -134,10 +134,37 @@ __global__ __launch_bounds__(256) void project_generic_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void norm2_kernel(const T* __restrict__ X, int64_t n, double* __restrict__ partial) {
     __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const double v = (double)X[e];
-        s += v * v;
+    // 16-byte loads, four in flight per thread, over the 16-byte-aligned body;
+    // the scalar head and tail go to the first threads of workgroup 0
+    constexpr int V = 16 / sizeof(T);
+    typedef T tv __attribute__((ext_vector_type(V)));
+    const int64_t head = (int64_t)(((16 - ((uintptr_t)X & 15)) & 15) / sizeof(T));
+    const int64_t h = head < n ? head : n;
+    const int64_t nv = (n - h) / V;
+    const tv* Xv = reinterpret_cast<const tv*>(X + h);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; e + 3 * stride < nv; e += 4 * stride) {
+        const tv a = Xv[e], b = Xv[e + stride], c = Xv[e + 2 * stride], d = Xv[e + 3 * stride];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            s0 = fma((double)a[u], (double)a[u], s0);
+            s1 = fma((double)b[u], (double)b[u], s1);
+            s2 = fma((double)c[u], (double)c[u], s2);
+            s3 = fma((double)d[u], (double)d[u], s3);
+        }
+    }
+    for (; e < nv; e += stride) {
+        const tv a = Xv[e];
+#pragma unroll
+        for (int u = 0; u < V; ++u) s0 = fma((double)a[u], (double)a[u], s0);
+    }
+    double s = (s0 + s1) + (s2 + s3);
+    if (blockIdx.x == 0) {
+        const int64_t t0 = h + nv * V;
+        if ((int64_t)threadIdx.x < h) { const double v = (double)X[threadIdx.x]; s = fma(v, v, s); }
+        if (t0 + (int64_t)threadIdx.x < n) { const double v = (double)X[t0 + threadIdx.x]; s = fma(v, v, s); }
     }
     red[threadIdx.x] = s;
     __syncthreads();

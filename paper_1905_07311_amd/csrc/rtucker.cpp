@@ -670,21 +670,17 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     int* kdev = k.ws<int>(4);
     if (!nx2 || !tmp || !status || !kdev) return fail(RT_ENOMEM, "workspace allocation failed");
     RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, st));
-    int64_t ntot = 1;
-    for (auto v : dims) ntot *= v;
-    RT_TRY(do_norm2(k, X->data, dt, ntot, nx2));
     double* h = ctx->host;
-    RT_HIP(hipMemcpyAsync(h, nx2, sizeof(double), hipMemcpyDeviceToHost, st));
-    RT_HIP(hipStreamSynchronize(st));
-    const double normx2 = h[0];
-    if (!std::isfinite(normx2)) return fail(RT_ENONFINITE, "input holds NaN or Inf");
-    const double normx = std::sqrt(normx2);
+    // ||X||^2 is summed by the first sketch (which reads every entry of X) and read
+    // back with that block's results; no separate pass over X
+    bool have_norm = false;
+    double normx2 = 0.0, normx = 0.0;
     const void* cur = X->data;
-    double cur_norm2 = normx2;
+    double cur_norm2 = 0.0;
     bool capped = false;
     for (int n : order) {
         if (epsn[n] == 0.0) continue;
-        const double tau2 = (epsn[n] * normx) * (epsn[n] * normx);
+        double tau2 = (epsn[n] * normx) * (epsn[n] * normx);
         Shape3 s = shape3(dims, n);
         const int64_t J = s.J, K = s.L * s.R;
         int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX);
@@ -712,10 +708,11 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
             blk = 0;
             stop_cap = false;
             prec_cur = attempt == 0 ? prec : (int)RT_PREC_F32;
-            while (E > tau2) {                                  // AdaptRangeFinder block loop
+            while (!have_norm || E > tau2) {                    // AdaptRangeFinder block loop
                 if (kcols >= cap) { stop_cap = true; break; }
                 const int bi = std::min(block, cap - kcols);
-                rt_status rs = do_sketch(k, dt, prec_cur, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y, nullptr);
+                rt_status rs = do_sketch(k, dt, prec_cur, cur, s, bi, (int64_t)blk * block, opts->seed, n, Y,
+                                         have_norm ? nullptr : nx2);
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
                 {
                     TimeScope ts(k.c, 2, 8.0 * J * (bi + 2.0 * kcols), 8.0 * J * bi * kcols, J, kcols, bi);
@@ -730,7 +727,22 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
                 RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
+                if (!have_norm) RT_HIP(hipMemcpyAsync(h, nx2, sizeof(double), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
+                if (!have_norm) {
+                    // the loop test for the first block, now that ||X|| is known
+                    normx2 = h[0];
+                    if (!std::isfinite(normx2)) {
+                        release_partial(ctx, out);
+                        return fail(RT_ENONFINITE, "input holds NaN or Inf");
+                    }
+                    normx = std::sqrt(normx2);
+                    have_norm = true;
+                    cur_norm2 = normx2;
+                    E = normx2;
+                    tau2 = (epsn[n] * normx) * (epsn[n] * normx);
+                    if (!(E > tau2)) break;                      // no block: this one is discarded
+                }
                 int kn = 0;
                 std::memcpy(&kn, h + 1, sizeof(int));
                 ++blk;
@@ -785,6 +797,11 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         out->ranks[n] = kfinal;
         dims[n] = kfinal;
         cur = core;
+    }
+    if (!have_norm) {                                    // every mode kept whole (eps 0)
+        int64_t ntot = 1;
+        for (int j = 0; j < d; ++j) ntot *= X->dims[j];
+        RT_TRY(do_norm2(k, X->data, dt, ntot, nx2));
     }
     rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
     if (rs != RT_OK && rs != RT_ENONFINITE) { release_partial(ctx, out); return rs; }
