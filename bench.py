@@ -24,6 +24,7 @@ latency of an open-loop run with Poisson arrivals at 400/s.  Every result of
 both paths is checked against a direct fp64 residual <= 1e-3.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu]
+                      [--copy-calib]
 """
 import argparse
 import json
@@ -114,6 +115,61 @@ def run_step(ctx, name, X):
     return ctx.rsthosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
 
 
+# HBM traffic of the dominant kernel, from the committed rocprofv3 counter summary
+# (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy of
+# known size); reported only while the kernel's sources are those it was taken on.
+TRAFFIC_FILE = {"c2": "profiles/sketch_f32_rows_mode1_512cube_traffic.md"}
+TRAFFIC_SOURCES = ["paper_1905_07311_amd/csrc/rt_sketch_mfma.hpp",
+                   "paper_1905_07311_amd/csrc/rt_sketch_mfma_launch.hpp",
+                   "paper_1905_07311_amd/csrc/rt_sketch_mfma_f32_rows.hip",
+                   "paper_1905_07311_amd/csrc/rt_philox.hpp",
+                   "paper_1905_07311_amd/csrc/rt_kernels.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """Bytes per launch from the counter summary, or None (absent or stale)."""
+    path = TRAFFIC_FILE.get(name)
+    if not path:
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        lines = open(os.path.join(root, path)).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ":" in ln and ln.startswith("- "):
+            k, v = ln[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of 2^27 float32 (512 MiB read + 512 MiB written), three
+    times: the reference the counter passes are scaled by."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def cpu_baseline(name, X_host):
     """The FP64 oracle, as it stands, on the host cores: one full call."""
     import numpy as np
@@ -122,7 +178,8 @@ def cpu_baseline(name, X_host):
     w = WORKLOADS[name]
     Xf = np.asarray(X_host, dtype=np.float64)
     times = []
-    for _ in range(3):
+    # a bounded sample: whole calls until about 10 s of host work (3 to 30 calls)
+    while len(times) < 3 or (sum(times) < 10.0 and len(times) < 30):
         t0 = time.perf_counter()
         if w["algo"] == "rsthosvd":
             oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))))
@@ -134,8 +191,8 @@ def cpu_baseline(name, X_host):
     dt = float(np.median(times))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"the same workload, full size, 3 calls, median {dt:.2f} s per call (float64 NumPy/LAPACK, "
-                      f"explicit Omega generation included)", "seconds_per_call": dt}
+            "sample": f"the same workload, full size, {len(times)} calls, median {dt:.2f} s per call "
+                      f"(float64 NumPy/LAPACK, explicit Omega generation included)", "seconds_per_call": dt}
 
 
 def run_serving(args):
@@ -261,6 +318,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for the HBM counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the multi-GPU layout is design-only "
@@ -340,9 +399,11 @@ def main():
         "kind_ms_per_step": {k: round(sum(e["ms"] for e in log_all if e["kind"] == k) / min(3, args.steps), 4)
                              for k in ("sketch", "orth", "project", "gram", "truncate")},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                      "kernel": "sketch TTM, mode 1", "bytes_per_launch": dom[0]["bytes"]},
     }
+    if args.copy_calib:
+        copy_calibration()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, X.cpu().numpy())
     print(json.dumps(out), flush=True)
