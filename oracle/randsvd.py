@@ -16,10 +16,19 @@ Readings where the paper is silent:
   With tied singular values several bases are correct; tests therefore compare
   projectors and reconstructions, not raw factors.
 
+Randomized subspace iteration (q >= 1): the range-finding variant the paper
+names in its remarks on range finding (§5 variants, citing Halko, Martinsson and
+Tropp) and applies, one step, to the Olivetti pixels (§6).  Reading: the
+re-orthonormalised form, q times Q <- orth(X orth(X^T Q)) after step 2, whose
+range equals that of (X X^T)^q X Omega in exact arithmetic while rounding does
+not wash out the small directions.
+
 Pinned by tests/test_oracle_randsvd.py: with r + p equal to the number of rows
 Q is square orthogonal and the result equals LAPACK's truncated SVD; on an
 exactly rank-r matrix the reconstruction is exact; the expectation bound of
-thm:randsvd_err holds as a sample mean over many seeds.
+thm:randsvd_err holds as a sample mean over many seeds; with q >= 1 the range
+converges to the dominant singular subspace at the rate (s_{r+p+1}/s_r)^(2q+1)
+and the error falls towards the optimal truncation error.
 """
 import numpy as np
 
@@ -48,10 +57,11 @@ def orth_householder(Y):
     return Q * s, R * s[:, None]
 
 
-def randsvd(X, r, p, Omega, sketch_round=None):
+def randsvd(X, r, p, Omega, sketch_round=None, q=0):
     """Alg. 1.  X: (m, n) matrix, Omega: (n, r + p).  Returns (U, S, V, Q).
     sketch_round: optional rounding applied to both operands of step 1 only
-    (the reduced-precision sketch variant)."""
+    (the reduced-precision sketch variant).  q: steps of subspace iteration
+    after step 2 (see above)."""
     X = np.asarray(X, dtype=np.float64)
     Omega = np.asarray(Omega, dtype=np.float64)
     assert Omega.shape == (X.shape[1], r + p)
@@ -60,6 +70,9 @@ def randsvd(X, r, p, Omega, sketch_round=None):
     else:
         Y = sketch_round(X) @ sketch_round(Omega)
     Q, _ = orth_householder(Y)          # step 2
+    for _ in range(q):                  # subspace iteration
+        Qt, _ = orth_householder(X.T @ Q)
+        Q, _ = orth_householder(X @ Qt)
     B = Q.T @ X                         # step 3
     UB, s, Vt = np.linalg.svd(B, full_matrices=False)   # step 4
     U = Q @ UB[:, :r]                   # step 5

@@ -84,9 +84,9 @@ def check_ranks(shape, ranks, p):
             raise ValueError(f"mode {j}: r + p = {r + p} exceeds min(I_j, prod_(i!=j) I_i)")
 
 
-def rhosvd(X, ranks, p, seed, sketch_round=None):
-    """Alg. 2 with Omega_j from the counter stream (seed, mode j).  sketch_round:
-    see randsvd."""
+def rhosvd(X, ranks, p, seed, sketch_round=None, q=0):
+    """Alg. 2 with Omega_j from the counter stream (seed, mode j).  sketch_round,
+    q (subspace iteration steps): see randsvd."""
     X = np.asarray(X, dtype=np.float64)
     check_ranks(X.shape, ranks, p)
     factors = []
@@ -96,7 +96,7 @@ def rhosvd(X, ranks, p, seed, sketch_round=None):
             continue
         M = unfold(X, j)
         Om = omega(seed, j, M.shape[1], ranks[j] + p)      # Alg. 2, draw Omega_j
-        U, _, _, _ = randsvd(M, ranks[j], p, Om, sketch_round)   # Alg. 2, RandSVD
+        U, _, _, _ = randsvd(M, ranks[j], p, Om, sketch_round, q)   # Alg. 2, RandSVD
         factors.append(U)                                   # A_j = U_hat
     G = X
     for j, A in enumerate(factors):                         # G = X x_j A_j^T
@@ -107,9 +107,9 @@ def rhosvd(X, ranks, p, seed, sketch_round=None):
                         norm_x=float(np.sqrt(fro2(X))), order=list(range(X.ndim)))
 
 
-def rsthosvd(X, ranks, p, seed, order=None, sketch_round=None):
+def rsthosvd(X, ranks, p, seed, order=None, sketch_round=None, q=0):
     """Alg. 3 with Omega_{rho_j} from the counter stream (seed, mode rho_j).
-    sketch_round: see randsvd."""
+    sketch_round, q (subspace iteration steps): see randsvd."""
     X = np.asarray(X, dtype=np.float64)
     check_ranks(X.shape, ranks, p)
     order = default_order(X.shape) if order is None else list(order)
@@ -121,7 +121,7 @@ def rsthosvd(X, ranks, p, seed, order=None, sketch_round=None):
             continue
         M = unfold(G, n)
         Om = omega(seed, n, M.shape[1], ranks[n] + p)       # Alg. 3, draw Omega
-        U, S, V, _ = randsvd(M, ranks[n], p, Om, sketch_round)   # Alg. 3, RandSVD
+        U, S, V, _ = randsvd(M, ranks[n], p, Om, sketch_round, q)   # Alg. 3, RandSVD
         factors[n] = U                                      # A = U_hat
         shape = list(G.shape)
         shape[n] = U.shape[1]

@@ -142,3 +142,24 @@ def test_expectation_bound_over_seeds(alg):
     assert errs.mean() - 3 * errs.std() / np.sqrt(errs.size) <= bound
     # each run is at least as bad as the best deterministic bound's ingredients allow
     assert errs.min() >= np.sqrt(D.max()) * (1 - 1e-9)
+
+
+def test_subspace_iteration_tucker():
+    # r + p = I_j in every mode: the ranges are complete for any q, so R-STHOSVD
+    # with subspace iteration is STHOSVD
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((6, 7, 8))
+    st = oracle.sthosvd(X, [3, 4, 5], order=[0, 1, 2])
+    for q in (1, 2):
+        res = oracle.rsthosvd(X, [3, 4, 5], 3, 9, q=q, order=[0, 1, 2])
+        np.testing.assert_allclose(res.reconstruct(), st.reconstruct(), atol=1e-11)
+    # slowly decaying tensor: one step lowers the error of R-STHOSVD and R-HOSVD
+    # (mean over seeds) to within a few per cent of STHOSVD's
+    Y = inputs.hilbert((20, 20, 20)) + 1e-3 * rng.standard_normal((20, 20, 20))
+    nx = np.linalg.norm(Y)
+    e_st = np.linalg.norm(oracle.sthosvd(Y, [4, 4, 4]).reconstruct() - Y) / nx
+    for alg in (oracle.rsthosvd, oracle.rhosvd):
+        e0 = np.mean([np.linalg.norm(alg(Y, [4, 4, 4], 2, sd).reconstruct() - Y) / nx for sd in range(6)])
+        e1 = np.mean([np.linalg.norm(alg(Y, [4, 4, 4], 2, sd, q=1).reconstruct() - Y) / nx for sd in range(6)])
+        assert e_st * (1 - 1e-9) <= e1 < e0
+        assert e1 < 1.05 * e_st
