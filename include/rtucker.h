@@ -86,12 +86,25 @@ typedef struct {
     const void* data;         /* device, dense row-major */
 } rt_tensor;
 
+#define RT_MAX_POWER_ITERS 16
+
 typedef struct {
     int32_t oversample;       /* p >= 0 */
     uint64_t seed;            /* Omega seed */
     const int32_t* order;     /* host, ndim mode indices (a permutation), or NULL:
                                  largest modes first, ties by index (§3.3) */
     rt_precision prec;        /* must match the input dtype: F64 <-> RT_F64 */
+    int32_t power_iters;      /* q in [0, RT_MAX_POWER_ITERS]: steps of randomized
+                                 subspace iteration inside every RandSVD of
+                                 rt_rhosvd / rt_rsthosvd (the range-finding variant
+                                 of §5 and §6: after Q = orth(G_(n) Omega), q times
+                                 Q <- orth(G_(n) orth(G_(n)^T Q)), the inner orth by
+                                 the eigendecomposition of the fp64 Gram, directions
+                                 below 1e-13 (fp64) / 1e-6 (fp32) of the largest
+                                 singular value dropped); 0 = Alg. 1 as printed.
+                                 Each step adds two reads of the current core and
+                                 one core-sized write.  Must be 0 for
+                                 rt_rsthosvd_adaptive. */
 } rt_opts;
 
 typedef struct {

@@ -1023,6 +1023,28 @@ __global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, i
     }
 }
 
+// Subspace iteration: T = V diag(lam)^-1/2 from the eigendecomposition of the
+// Gram W = B B^T (columns with lam_k <= drop lam_max set to zero), so that T^T B
+// has orthonormal rows (the eigenvalue form of orthonormalisation, Stathopoulos
+// and Wu's SVQB).
+__global__ __launch_bounds__(NT) void svqb_kernel(const double* __restrict__ W, int ell, double drop,
+                                                  double* __restrict__ T, float* __restrict__ Tf, double jtol) {
+    __shared__ EigShared S;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < ell * ell; e += NT) S.A[e / ell][e % ell] = W[e];
+    __syncthreads();
+    jacobi_2p(S.A, ell, S.V, jtol, S.red, S.cs, S.pq);
+    blk_sort_desc(S.A, ell, S.perm, S.lam);
+    const double lmax = S.lam[0];
+    for (int e = tid; e < ell * ell; e += NT) {
+        const int i = e / ell, j = e % ell;
+        const double lam = S.lam[j];
+        const double v = (lmax > 0.0 && lam > drop * lmax) ? S.V[i][S.perm[j]] / sqrt(lam) : 0.0;
+        T[e] = v;
+        if (Tf) Tf[e] = (float)v;
+    }
+}
+
 // A = Q Us[:, :k] for rows 64 b .. 64 b + 63: lane l of every wave owns row
 // 64 b + l (its row of Q in registers) and wave w the columns j = w, w + 4, ...
 // (Us transposed in LDS, read with broadcast 16-byte loads); part[b] = per
@@ -1574,6 +1596,11 @@ hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq,
     }
     hipLaunchKernelGGL(block_orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, b, Qall, ldq, k, drop,
                        scratch, knew, Qf);
+    return hipGetLastError();
+}
+
+hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* Tf, double jtol, hipStream_t stream) {
+    hipLaunchKernelGGL(svqb_kernel, dim3(1), dim3(NT), 0, stream, W, ell, drop, T, Tf, jtol);
     return hipGetLastError();
 }
 

@@ -37,6 +37,12 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                          int64_t col0, uint64_t seed, uint32_t mode, void* partial,
                          double* nrm2_partial, hipStream_t stream);
 
+// Y = X_(n) Z with Z[l R + r][k] = Om[(l ell + k) R + r] (Om: (L, ell, R), dtype dt),
+// split-K partials as launch_sketch (plan from plan_sketch with prec 0: the
+// generic kernel).
+hipError_t launch_sketch_explicit(const SketchPlan& p, Dt dt, const void* X, Shape3 s, int ell, const void* Om,
+                                  void* partial, hipStream_t stream);
+
 // out[e] = sum_{s < nparts} in[s * n + e] (in float or double, summed in fp64 in
 // the order s = 0, 1, ...).  out is double.
 // tmp: ceil(nparts / 32) * n doubles of scratch (needed when nparts > 32)
@@ -111,6 +117,13 @@ hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ld
                            const double* E_dev, double tau2, double* U, float* Uf, void* A, Dt da,
                            double* lam, int* kout, double jtol, double* scratch, hipStream_t stream);
 size_t truncate_scratch(int64_t J, int ell);
+
+// ---- subspace iteration: orthonormal rows of B via the eigendecomposition of W = B B^T --
+// W (ell x ell fp64, symmetric PSD) = V diag(lam) V^T; T[i][k] = V[i][k] / sqrt(lam_k)
+// for lam_k > drop lam_max, else 0 (T and the float copy Tf, row-major ell x ell), so
+// that T^T B has orthonormal rows spanning the retained directions.
+// jtol as launch_truncate.
+hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* Tf, double jtol, hipStream_t stream);
 
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),

@@ -27,11 +27,14 @@ __device__ __forceinline__ float round_bf16(float x) {
 }
 
 // BFR: X and Omega are rounded to bfloat16 before the products (float32 data).
-template <typename TX, typename TA, bool BFR>
+// EXPL: Omega is not generated but read from Om, an (L, ell, R) row-major tensor
+// with Omega[l R + r][k] = Om[(l ell + k) R + r] (the subspace-iteration product
+// Y = X_(n) Z with Z = Om_(n)^T); seed, mode and col0 are unused.
+template <typename TX, typename TA, bool BFR, bool EXPL = false>
 __global__ __launch_bounds__(256) void sketch_generic_kernel(
     const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
     uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
-    double* __restrict__ nrm2_partial) {
+    double* __restrict__ nrm2_partial, const TX* __restrict__ Om = nullptr) {
     __shared__ TA xs[SK_KC][SK_MT + 1];
     __shared__ TA om[SK_KC][LMAX + 4];
     __shared__ double red[256];
@@ -73,8 +76,20 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
             }
             xs[cl][rl] = v;
         }
-        // generate the Omega slab for these 64 unfolding columns
-        for (int e = tid; e < SK_KC * nq; e += 256) {
+        // generate (or, EXPL, load) the Omega slab for these 64 unfolding columns
+        if (EXPL) {
+            for (int e = tid; e < SK_KC * ell; e += 256) {
+                const int cl = e % SK_KC, k = e / SK_KC;
+                const int64_t c = cbase + cl;
+                TA v = TA(0);
+                if (c < K) {
+                    const int64_t l = c / R;
+                    v = (TA)Om[(l * ell + k) * R + (c - l * R)];
+                }
+                om[cl][k] = v;
+            }
+        }
+        for (int e = tid; !EXPL && e < SK_KC * nq; e += 256) {
             const int cl = e % SK_KC;
             const int qi = e / SK_KC;
             const int64_t q = q_first + qi;
@@ -255,6 +270,21 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                                (const float*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
                                (float*)partial, nrm2_partial);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sketch_explicit(const SketchPlan& p, Dt dt, const void* X, Shape3 s, int ell, const void* Om,
+                                  void* partial, hipStream_t stream) {
+    if (p.kind != 0) return hipErrorInvalidValue;
+    dim3 grid(p.nsplit, p.nrowtile);
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL((sketch_generic_kernel<double, double, false, true>), grid, dim3(256), 0, stream,
+                           (const double*)X, s.L, s.J, s.R, ell, (int64_t)0, (uint64_t)0, 0u, p.tiles_per_split,
+                           (double*)partial, (double*)nullptr, (const double*)Om);
+    else
+        hipLaunchKernelGGL((sketch_generic_kernel<float, float, false, true>), grid, dim3(256), 0, stream,
+                           (const float*)X, s.L, s.J, s.R, ell, (int64_t)0, (uint64_t)0, 0u, p.tiles_per_split,
+                           (float*)partial, (double*)nullptr, (const float*)Om);
     return hipGetLastError();
 }
 

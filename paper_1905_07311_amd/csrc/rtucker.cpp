@@ -214,6 +214,23 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
     return RT_OK;
 }
 
+// Y = G_(n) Z, Z[l R + r][k] = Om[(l ell + k) R + r] (Om: (L, ell, R) in dtype dt)
+rt_status do_sketch_explicit(Call& k, Dt dt, const void* G, Shape3 s, int ell, const void* Om, double* Y) {
+    rt::SketchPlan plan = rt::plan_sketch(dt, 0, s, ell, 0, G);
+    const bool f64acc = dt == Dt::F64;
+    void* partial = k.c->ws(plan.partial_elems * (f64acc ? 8 : 4));
+    double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
+    if (!partial || !rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
+    {
+        const double n = (double)s.L * s.J * s.R;
+        TimeScope ts(k.c, 0, n * (dt == Dt::F64 ? 8 : 4) * (1.0 + (double)ell / s.J), 2.0 * ell * n, s.J, s.L * s.R,
+                     ell);
+        RT_HIP(rt::launch_sketch_explicit(plan, dt, G, s, ell, Om, partial, k.c->stream));
+    }
+    RT_HIP(rt::launch_reduce_rows(partial, f64acc, plan.nsplit, s.J, ell, plan.ldp, Y, k.c->stream, rtmp));
+    return RT_OK;
+}
+
 rt_status do_norm2(Call& k, const void* X, Dt dt, int64_t n, double* out) {
     int nwg = rt::plan_norm(n);
     double* part = k.ws<double>(nwg);
@@ -341,7 +358,7 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
 // One fixed-rank RandSVD step (Alg. 1) on the mode-n unfolding of G:
 // A_out (J x r, dtype dt) and, if core_out != NULL, the truncated core (L, r, R).
 rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode, int ell, int r, uint64_t seed,
-                     void* A_out, void* core_out, double* nrm2_dev, uint32_t* status_dev) {
+                     int power_iters, void* A_out, void* core_out, double* nrm2_dev, uint32_t* status_dev) {
     hipStream_t st = k.c->stream;
     const int64_t J = s.J;
     double* Y = k.ws<double>((size_t)J * ell);
@@ -357,6 +374,31 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
     double* W = k.ws<double>((size_t)ell * ell);
     if (!B || !W) return fail(RT_ENOMEM, "workspace allocation failed");
     const void* Qp = dt == Dt::F64 ? (const void*)Y : (const void*)Qf;
+    if (power_iters > 0) {
+        // subspace iteration, power_iters times: Z = G_(n)^T Q (stored as B = G x_n Q^T),
+        // Z <- orth(Z) by the eigendecomposition of its fp64 Gram (rows of T^T B
+        // orthonormal), then Y = G_(n) Z and Q = orth(Y)
+        void* B2 = k.c->ws((size_t)s.L * ell * s.R * (dt == Dt::F64 ? 8 : 4));
+        double* T = k.ws<double>((size_t)ell * ell);
+        float* Tf = k.ws<float>((size_t)ell * ell);
+        const int nwg = rt::plan_gram3(s.L, s.R);
+        double* gp = k.ws<double>((size_t)nwg * ell * ell);
+        double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)ell * ell) + 1);
+        if (!B2 || !T || !Tf || !gp || !rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
+        const Shape3 sb{s.L, ell, s.R};
+        const double drop = dt == Dt::F64 ? 1e-26 : 1e-12;     // relative to the largest eigenvalue
+        for (int it = 0; it < power_iters; ++it) {
+            RT_TRY(do_project(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell, 0, nullptr, nullptr));
+            RT_HIP(rt::launch_gram3(B, dt, s.L, ell, s.R, ell, gp, nwg, st));
+            RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)ell * ell, W, st, rtmp));
+            RT_HIP(rt::launch_svqb(W, ell, drop, T, Tf, dt == Dt::F64 ? 1e-30 : 1e-24, st));
+            RT_TRY(do_project(k, dt, dt, B, sb, ell, dt == Dt::F64 ? (const void*)T : (const void*)Tf, ell, ell, B2,
+                              ell, 0, nullptr, nullptr));
+            RT_TRY(do_sketch_explicit(k, dt, G, s, ell, B2, Y));
+            TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
+            RT_HIP(rt::launch_orth(Y, J, ell, Qf, orth_accept_ratio(), status_dev, scratch, st));
+        }
+    }
     RT_TRY(do_project(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell, 0, W, nullptr));               // step 3
     k.c->cur_J = J;
     k.c->last_nrm2 = nullptr;
@@ -515,6 +557,8 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
     if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
     RT_TRY(check_tensor(X));
     RT_TRY(check_prec(X, opts->prec));
+    if (opts->power_iters < 0 || opts->power_iters > RT_MAX_POWER_ITERS)
+        return fail(RT_EINVAL, "power_iters must be in [0, RT_MAX_POWER_ITERS]");
     RT_TRY(check_ranks(X, ranks, opts->oversample));
     std::vector<int> order;
     RT_TRY(make_order(X, opts->order, order));
@@ -542,8 +586,8 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "allocation failed");
         }
-        rt_status rs = fixed_mode(k, dt, prec, cur, s, n, ell, r, opts->seed, out->factors[n], core,
-                                  have_norm ? nullptr : nx2, status + n);
+        rt_status rs = fixed_mode(k, dt, prec, cur, s, n, ell, r, opts->seed, opts->power_iters, out->factors[n],
+                                  core, have_norm ? nullptr : nx2, status + n);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
         have_norm = true;
         out->ranks[n] = r;
@@ -565,6 +609,8 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
     if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
     RT_TRY(check_tensor(X));
     RT_TRY(check_prec(X, opts->prec));
+    if (opts->power_iters < 0 || opts->power_iters > RT_MAX_POWER_ITERS)
+        return fail(RT_EINVAL, "power_iters must be in [0, RT_MAX_POWER_ITERS]");
     RT_TRY(check_ranks(X, ranks, opts->oversample));
     RT_HIP(hipSetDevice(ctx->device));
     Call k(ctx);
@@ -592,8 +638,8 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "allocation failed");
         }
-        rt_status rs = fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, out->factors[j], core,
-                                  first < 0 ? nx2 : nullptr, status + j);
+        rt_status rs = fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, opts->power_iters,
+                                  out->factors[j], core, first < 0 ? nx2 : nullptr, status + j);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
         if (first < 0) { first = j; core0 = core; }
         out->ranks[j] = r;
@@ -631,6 +677,7 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
     RT_TRY(check_tensor(X));
     RT_TRY(check_prec(X, opts->prec));
+    if (opts->power_iters != 0) return fail(RT_EINVAL, "power_iters must be 0 for the adaptive call");
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(RT_EINVAL, "eps must be finite and >= 0");
     if (block < 1 || block > RT_LMAX) return fail(RT_EINVAL, "block must be in [1, RT_LMAX]");
     const int d = X->ndim;

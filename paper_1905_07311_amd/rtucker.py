@@ -44,7 +44,7 @@ class rt_tensor(ctypes.Structure):
 
 class rt_opts(ctypes.Structure):
     _fields_ = [("oversample", ctypes.c_int32), ("seed", ctypes.c_uint64), ("order", ctypes.POINTER(ctypes.c_int32)),
-                ("prec", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("power_iters", ctypes.c_int32)]
 
 
 class rt_tucker(ctypes.Structure):
@@ -236,9 +236,10 @@ class Context:
             return PREC["f64"] if X.dtype == torch.float64 else PREC["f32"]
         return PREC[prec] if isinstance(prec, str) else int(prec)
 
-    def _opts(self, X, p, seed, order, prec):
+    def _opts(self, X, p, seed, order, prec, power_iters=0):
         o = rt_opts()
         o.oversample = int(p)
+        o.power_iters = int(power_iters)
         o.seed = int(seed) & ((1 << 64) - 1)
         if order is not None:
             arr = (ctypes.c_int32 * X.dim())(*[int(v) for v in order])
@@ -248,17 +249,17 @@ class Context:
         return o
 
     # -- decompositions ----------------------------------------------------------
-    def rsthosvd(self, X, ranks, p, seed, order=None, prec=None):
-        return self._fixed("rt_rsthosvd", X, ranks, p, seed, order, prec)
+    def rsthosvd(self, X, ranks, p, seed, order=None, prec=None, power_iters=0):
+        return self._fixed("rt_rsthosvd", X, ranks, p, seed, order, prec, power_iters)
 
-    def rhosvd(self, X, ranks, p, seed, prec=None):
-        return self._fixed("rt_rhosvd", X, ranks, p, seed, None, prec)
+    def rhosvd(self, X, ranks, p, seed, prec=None, power_iters=0):
+        return self._fixed("rt_rhosvd", X, ranks, p, seed, None, prec, power_iters)
 
-    def _fixed(self, fn, X, ranks, p, seed, order, prec):
+    def _fixed(self, fn, X, ranks, p, seed, order, prec, power_iters=0):
         self._sync_stream()
         t = self._tensor(X)
         rk = (ctypes.c_int32 * X.dim())(*[RT_KEEP if (r is None or r < 0) else int(r) for r in ranks])
-        o = self._opts(X, p, seed, order, prec)
+        o = self._opts(X, p, seed, order, prec, power_iters)
         out = rt_tucker()
         st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), rk, ctypes.byref(o), ctypes.byref(out)))
         return self._result(out, X, st)
@@ -365,12 +366,12 @@ def context(device=None):
     return _default[idx]
 
 
-def rsthosvd(X, ranks, p, seed, order=None, prec=None):
-    return context(X.device.index).rsthosvd(X, ranks, p, seed, order, prec)
+def rsthosvd(X, ranks, p, seed, order=None, prec=None, power_iters=0):
+    return context(X.device.index).rsthosvd(X, ranks, p, seed, order, prec, power_iters)
 
 
-def rhosvd(X, ranks, p, seed, prec=None):
-    return context(X.device.index).rhosvd(X, ranks, p, seed, prec)
+def rhosvd(X, ranks, p, seed, prec=None, power_iters=0):
+    return context(X.device.index).rhosvd(X, ranks, p, seed, prec, power_iters)
 
 
 def rsthosvd_adaptive(X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):

@@ -72,7 +72,8 @@ def test_struct_layout_matches_header(tmp_path):
 #include "rtucker.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(rt_tensor), offsetof(rt_tensor, dtype), offsetof(rt_tensor, data));
-  printf("%zu %zu %zu\\n", sizeof(rt_opts), offsetof(rt_opts, order), offsetof(rt_opts, prec));
+  printf("%zu %zu %zu %zu\\n", sizeof(rt_opts), offsetof(rt_opts, order), offsetof(rt_opts, prec),
+         offsetof(rt_opts, power_iters));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_tucker), offsetof(rt_tucker, core), offsetof(rt_tucker, factors),
          offsetof(rt_tucker, norm_x), offsetof(rt_tucker, flags));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_server_opts), offsetof(rt_server_opts, hbm_budget),
@@ -87,7 +88,8 @@ int main(void) {
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     T, O, K = rtucker.rt_tensor, rtucker.rt_opts, rtucker.rt_tucker
     assert [int(v) for v in lines[0].split()] == [ctypes.sizeof(T), T.dtype.offset, T.data.offset]
-    assert [int(v) for v in lines[1].split()] == [ctypes.sizeof(O), O.order.offset, O.prec.offset]
+    assert [int(v) for v in lines[1].split()] == [ctypes.sizeof(O), O.order.offset, O.prec.offset,
+                                                 O.power_iters.offset]
     assert [int(v) for v in lines[2].split()] == [ctypes.sizeof(K), K.core.offset, K.factors.offset,
                                                  K.norm_x.offset, K.flags.offset]
     S, R = rtucker.rt_server_opts, rtucker.rt_result

@@ -238,3 +238,37 @@ def test_adaptive_five_way_odeco(ctx, dtype):
                                  delta=1e-10 if dtype == torch.float64 else 1e-5)
     _adaptive_check(g, o, Xs.astype(np.float64), 1e-3, 1e-10 if dtype == torch.float64 else 1e-5,
                     2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("alg", ["rsthosvd", "rhosvd"])
+@pytest.mark.parametrize("q", [1, 2])
+def test_subspace_iteration_parity(ctx, dtype, alg, q):
+    # graded spectrum (core 0.7^(i+j+k) of Tucker rank (14, 13, 12)) truncated to
+    # (6, 5, 4): one step of subspace iteration moves the result by ~1e-1, the
+    # second by ~1e-3, far above the parity bar
+    rng = np.random.default_rng(31)
+    X = inputs.lowrank_tensor(rng, (40, 33, 27), (14, 13, 12), noise=1e-4,
+                              core_scale=inputs.graded_scale((14, 13, 12), 0.7))
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xd = torch.from_numpy(Xs).cuda()
+    g = getattr(ctx, alg)(Xd, [6, 5, 4], 3, 5, power_iters=q)
+    o = getattr(oracle, alg)(Xs.astype(np.float64), [6, 5, 4], 3, 5, q=q)
+    _check(g, o, Xs.astype(np.float64), 1e-10 if dtype == torch.float64 else 1e-5)
+    g0 = getattr(ctx, alg)(Xd, [6, 5, 4], 3, 5)
+    nx = np.linalg.norm(X)
+    assert np.linalg.norm(to_np(g0.reconstruct()) - to_np(g.reconstruct())) / nx > 1e-2
+
+
+def test_subspace_iteration_errors(ctx):
+    X = torch.zeros((8, 9, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(rtucker.RtError):
+        ctx.rsthosvd(X, [2, 2, 2], 1, 0, power_iters=-1)
+    with pytest.raises(rtucker.RtError):
+        ctx.rhosvd(X, [2, 2, 2], 1, 0, power_iters=17)
+    # zero tensor: the iteration keeps the padded, orthonormal factors
+    g = ctx.rsthosvd(X, [2, 2, 2], 1, 0, power_iters=1)
+    assert g.core_norm == 0.0
+    for A in g.factors:
+        A = to_np(A)
+        assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
