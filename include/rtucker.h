@@ -99,9 +99,9 @@ typedef struct {
                                  rt_rhosvd / rt_rsthosvd (the range-finding variant
                                  of §5 and §6: after Q = orth(G_(n) Omega), q times
                                  Q <- orth(G_(n) orth(G_(n)^T Q)), the inner orth by
-                                 the eigendecomposition of the fp64 Gram, directions
-                                 below 1e-13 (fp64) / 1e-6 (fp32) of the largest
-                                 singular value dropped); 0 = Alg. 1 as printed.
+                                 the eigendecomposition of the fp64 Gram, singular
+                                 values below 1e-13 (fp64) / 1e-6 (fp32) of the
+                                 largest raised to that floor); 0 = Alg. 1 as printed.
                                  Each step adds two reads of the current core and
                                  one core-sized write.  Must be 0 for
                                  rt_rsthosvd_adaptive. */

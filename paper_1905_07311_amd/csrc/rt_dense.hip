@@ -1023,10 +1023,12 @@ __global__ __launch_bounds__(NT) void eig_kernel(const double* __restrict__ W, i
     }
 }
 
-// Subspace iteration: T = V diag(lam)^-1/2 from the eigendecomposition of the
-// Gram W = B B^T (columns with lam_k <= drop lam_max set to zero), so that T^T B
-// has orthonormal rows (the eigenvalue form of orthonormalisation, Stathopoulos
-// and Wu's SVQB).
+// Subspace iteration: T = V diag(max(lam, drop lam_max))^-1/2 from the
+// eigendecomposition of the Gram W = B B^T, so that T^T B has orthonormal rows
+// along the directions above the floor (the eigenvalue form of
+// orthonormalisation, Stathopoulos and Wu's SVQB).  Directions below the floor
+// are rounding noise; they are scaled by the floor instead of dropped, so that
+// they stay noise-sized rather than exactly zero, as in a plain sketch.
 __global__ __launch_bounds__(NT) void svqb_kernel(const double* __restrict__ W, int ell, double drop,
                                                   double* __restrict__ T, float* __restrict__ Tf, double jtol) {
     __shared__ EigShared S;
@@ -1039,7 +1041,7 @@ __global__ __launch_bounds__(NT) void svqb_kernel(const double* __restrict__ W, 
     for (int e = tid; e < ell * ell; e += NT) {
         const int i = e / ell, j = e % ell;
         const double lam = S.lam[j];
-        const double v = (lmax > 0.0 && lam > drop * lmax) ? S.V[i][S.perm[j]] / sqrt(lam) : 0.0;
+        const double v = lmax > 0.0 ? S.V[i][S.perm[j]] / sqrt(fmax(lam, drop * lmax)) : 0.0;
         T[e] = v;
         if (Tf) Tf[e] = (float)v;
     }

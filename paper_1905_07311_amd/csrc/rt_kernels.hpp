@@ -38,8 +38,9 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
                          double* nrm2_partial, hipStream_t stream);
 
 // Y = X_(n) Z with Z[l R + r][k] = Om[(l ell + k) R + r] (Om: (L, ell, R), dtype dt),
-// split-K partials as launch_sketch (plan from plan_sketch with prec 0: the
-// generic kernel).
+// split-K partials as launch_sketch.  Plan: plan_sketch with prec 0 (the generic
+// kernel) or, for float data with R % 4 == 0 and a 16-byte aligned Om, prec 1
+// (the MFMA rows kernel).
 hipError_t launch_sketch_explicit(const SketchPlan& p, Dt dt, const void* X, Shape3 s, int ell, const void* Om,
                                   void* partial, hipStream_t stream);
 
@@ -119,9 +120,9 @@ hipError_t launch_truncate(const double* W, int ell, const double* Q, int64_t ld
 size_t truncate_scratch(int64_t J, int ell);
 
 // ---- subspace iteration: orthonormal rows of B via the eigendecomposition of W = B B^T --
-// W (ell x ell fp64, symmetric PSD) = V diag(lam) V^T; T[i][k] = V[i][k] / sqrt(lam_k)
-// for lam_k > drop lam_max, else 0 (T and the float copy Tf, row-major ell x ell), so
-// that T^T B has orthonormal rows spanning the retained directions.
+// W (ell x ell fp64, symmetric PSD) = V diag(lam) V^T; T[i][k] = V[i][k] /
+// sqrt(max(lam_k, drop lam_max)) (T and the float copy Tf, row-major ell x ell; zero
+// when W = 0), so that T^T B has orthonormal rows along the directions above the floor.
 // jtol as launch_truncate.
 hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* Tf, double jtol, hipStream_t stream);
 
@@ -147,6 +148,9 @@ hipError_t launch_sketch_bf16_rows(const SketchPlan& p, const float* X, Shape3 s
                                    uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 hipError_t launch_sketch_bf16_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
                                    uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
+// explicit Omega from Om ((L, ell, R) float tensor, 16-byte aligned); needs R % 4 == 0
+hipError_t launch_sketch_f32_rows_explicit(const SketchPlan& p, const float* X, Shape3 s, int ell, const float* Om,
+                                           float* partial, hipStream_t stream);
 bool project_mfma_ok(Shape3 s, int ell, const void* G, const void* B, int64_t koff);
 void plan_project_mfma(ProjectPlan& p, Shape3 s, int ell);
 // with p.nsplit > 1, B is the partial buffer (ldk = ell, koff = 0) and nrm2 must be null

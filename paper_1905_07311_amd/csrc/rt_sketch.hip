@@ -275,6 +275,10 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
 
 hipError_t launch_sketch_explicit(const SketchPlan& p, Dt dt, const void* X, Shape3 s, int ell, const void* Om,
                                   void* partial, hipStream_t stream) {
+    if (p.kind == 1) {
+        if (s.R % 4 != 0 || ((uintptr_t)Om & 15) != 0) return hipErrorInvalidValue;
+        return launch_sketch_f32_rows_explicit(p, (const float*)X, s, ell, (const float*)Om, (float*)partial, stream);
+    }
     if (p.kind != 0) return hipErrorInvalidValue;
     dim3 grid(p.nsplit, p.nrowtile);
     if (dt == Dt::F64)

@@ -79,12 +79,17 @@ struct TileShape {
 // LOAD_ROWS needs R % 4 == 0 (four columns of a load lie in one l-slab); LOAD_COLS needs
 // R == 1 and J % 4 == 0.  16-byte alignment of X; ell <= 4 NQ <= 64; the
 // Omega blocks of columns [col0, col0 + ell) number at most 16.
-template <int RB, int RW, int NQ, int LOADER, bool BF>
+// EXPL (LOAD_ROWS, float32 only): Omega is read from Om, an (L, ell, R) tensor with
+// Omega[l R + r][k] = Om[(l ell + k) R + r] (the subspace-iteration product
+// Y = X_(n) Z, Z = Om_(n)^T), instead of generated; seed, mode and col0 unused.
+template <int RB, int RW, int NQ, int LOADER, bool BF, bool EXPL = false>
 __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict__ X, int64_t L, int64_t J,
                                                          int64_t R, int ell, int64_t col0, uint64_t seed,
                                                          uint32_t mode, int64_t tiles_per_split,
                                                          float* __restrict__ partial,
-                                                         double* __restrict__ nrm2_partial) {
+                                                         double* __restrict__ nrm2_partial,
+                                                         const float* __restrict__ Om = nullptr) {
+    static_assert(!EXPL || (LOADER == LOAD_ROWS && !BF), "explicit Omega: float32 rows loader only");
     typedef TileShape<RB, RW, LOADER> S;
     constexpr int CW = S::CW, MT = S::MT, NLOAD = S::NLOAD, TLD = S::TLD, JC = S::JC;
     constexpr int NQP = (NQ + 3) / 4 * 4;  // Omega row length in LDS (16-byte reads)
@@ -199,6 +204,26 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
     };
     auto gen_omega = [&](int64_t tile, int h) {
         const int e = tid + 256 * h;
+        if (EXPL) {
+            // row k = e / 8 of Om, columns 4 (e % 8) .. + 3 of the tile (one l-slab)
+            const int k = e >> 3;
+            const int64_t c = tile * KC + 4 * (tid & 7);
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            if (k < ell && c < K) {
+                int64_t l, r;
+                if (K <= 0xffffffffll) {
+                    const uint32_t q = (uint32_t)c / (uint32_t)R;
+                    l = q;
+                    r = c - (int64_t)q * R;
+                } else {
+                    l = c / R;
+                    r = c - l * R;
+                }
+                v = *reinterpret_cast<const f4*>(Om + (l * ell + k) * R + r);
+            }
+            opre[4 * h + 0] = v.x; opre[4 * h + 1] = v.y; opre[4 * h + 2] = v.z; opre[4 * h + 3] = v.w;
+            return;
+        }
         if (e < KC * nqblk) {
             const int cc = e % KC, qi = e / KC;
             float z[4];
@@ -208,6 +233,17 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
     };
     // columns outside [0, ell) of a generated block go to the sink slot
     auto store_omega = [&]() {
+        if (EXPL) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = (tid + 256 * h) >> 3, cq = tid & 7;
+                if (k < ell) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) os[((4 * cq + u) * 4 + (k & 3)) * NQP + (k >> 2)] = opre[4 * h + u];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int e = tid + 256 * h;

@@ -216,7 +216,9 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
 
 // Y = G_(n) Z, Z[l R + r][k] = Om[(l ell + k) R + r] (Om: (L, ell, R) in dtype dt)
 rt_status do_sketch_explicit(Call& k, Dt dt, const void* G, Shape3 s, int ell, const void* Om, double* Y) {
-    rt::SketchPlan plan = rt::plan_sketch(dt, 0, s, ell, 0, G);
+    const bool mfma = dt == Dt::F32 && s.R % 4 == 0 && ((uintptr_t)Om & 15) == 0;
+    rt::SketchPlan plan = rt::plan_sketch(dt, mfma ? 1 : 0, s, ell, 0, G);
+    if (plan.kind == 1 && s.R % 4 != 0) plan = rt::plan_sketch(dt, 0, s, ell, 0, G);
     const bool f64acc = dt == Dt::F64;
     void* partial = k.c->ws(plan.partial_elems * (f64acc ? 8 : 4));
     double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
@@ -377,7 +379,8 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
     if (power_iters > 0) {
         // subspace iteration, power_iters times: Z = G_(n)^T Q (stored as B = G x_n Q^T),
         // Z <- orth(Z) by the eigendecomposition of its fp64 Gram (rows of T^T B
-        // orthonormal), then Y = G_(n) Z and Q = orth(Y)
+        // orthonormal above a floor of the largest eigenvalue), then Y = G_(n) Z and
+        // Q = orth(Y)
         void* B2 = k.c->ws((size_t)s.L * ell * s.R * (dt == Dt::F64 ? 8 : 4));
         double* T = k.ws<double>((size_t)ell * ell);
         float* Tf = k.ws<float>((size_t)ell * ell);
@@ -386,7 +389,7 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
         double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)ell * ell) + 1);
         if (!B2 || !T || !Tf || !gp || !rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
         const Shape3 sb{s.L, ell, s.R};
-        const double drop = dt == Dt::F64 ? 1e-26 : 1e-12;     // relative to the largest eigenvalue
+        const double drop = dt == Dt::F64 ? 1e-26 : 1e-12;     // eigenvalue floor, relative to the largest
         for (int it = 0; it < power_iters; ++it) {
             RT_TRY(do_project(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell, 0, nullptr, nullptr));
             RT_HIP(rt::launch_gram3(B, dt, s.L, ell, s.R, ell, gp, nwg, st));

@@ -240,16 +240,23 @@ def test_adaptive_five_way_odeco(ctx, dtype):
                     2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
 
 
+# (dims, core ranks): the second shape has R % 4 == 0 in modes 0 and 1 (R = 640,
+# 20), so its float32 products Y = X_(n) Z take the MFMA kernel with Z read
+# from memory (tiles crossing l-slabs in mode 1)
+SUBSPACE_SHAPES = [((40, 33, 27), (14, 13, 12)), ((36, 32, 20), (12, 12, 10))]
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("alg", ["rsthosvd", "rhosvd"])
 @pytest.mark.parametrize("q", [1, 2])
-def test_subspace_iteration_parity(ctx, dtype, alg, q):
-    # graded spectrum (core 0.7^(i+j+k) of Tucker rank (14, 13, 12)) truncated to
-    # (6, 5, 4): one step of subspace iteration moves the result by ~1e-1, the
-    # second by ~1e-3, far above the parity bar
+@pytest.mark.parametrize("shape", SUBSPACE_SHAPES)
+def test_subspace_iteration_parity(ctx, dtype, alg, q, shape):
+    # graded spectrum (core 0.7^(i+j+k)) truncated to (6, 5, 4): one step of
+    # subspace iteration moves the result by ~1e-1, the second by ~1e-3, far
+    # above the parity bar
     rng = np.random.default_rng(31)
-    X = inputs.lowrank_tensor(rng, (40, 33, 27), (14, 13, 12), noise=1e-4,
-                              core_scale=inputs.graded_scale((14, 13, 12), 0.7))
+    dims, core = shape
+    X = inputs.lowrank_tensor(rng, dims, core, noise=1e-4, core_scale=inputs.graded_scale(core, 0.7))
     Xs = X.astype(np.float32) if dtype == torch.float32 else X
     Xd = torch.from_numpy(Xs).cuda()
     g = getattr(ctx, alg)(Xd, [6, 5, 4], 3, 5, power_iters=q)
