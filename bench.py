@@ -43,8 +43,10 @@ FP64_MFMA_PEAK = 78.6
 BF16_MFMA_PEAK = 2500.0
 
 
-def flop_model(dims, ranks, p, order, algo="rsthosvd"):
-    """Algorithmic flops of the method (sketch + projection + truncation), §3.3."""
+def flop_model(dims, ranks, p, order, algo="rsthosvd", q=0):
+    """Algorithmic flops of the method (sketch + projection + truncation), §3.3;
+    q steps of subspace iteration add per mode a projection, the Gram of B, the
+    orthonormalisation T^T B and a product with the result."""
     dims = list(dims)
     total = 0.0
     if algo == "rsthosvd":
@@ -52,6 +54,7 @@ def flop_model(dims, ranks, p, order, algo="rsthosvd"):
             N = math.prod(dims)
             ell = ranks[n] + p
             K = N // dims[n]
+            total += q * (2 * ell * N * 2 + 2 * ell * ell * K * 2)
             total += 2 * ell * N * 2                  # sketch + projection
             total += 2 * ell * ell * K                # Gram of B
             total += 2 * ranks[n] * ell * K           # U_r^T B
@@ -77,6 +80,9 @@ WORKLOADS = {
     "c2": dict(desc="R-STHOSVD, dense 512^3 float32 X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, "
                     "order 1-2-3, Omega seed 1", dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1,
                prec="f32", algo="rsthosvd"),
+    "c2q1": dict(desc="R-STHOSVD with one step of randomized subspace iteration per mode, dense 512^3 float32 "
+                      "X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, order 1-2-3, Omega seed 1",
+                 dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="rsthosvd", q=1),
     "c1": dict(desc="R-STHOSVD, dense 64^3 float64 Gaussian 8^3 core x Haar factors + 1e-8 N(0,1), rank (8,8,8), "
                     "p=5, Omega seed 0", dims=(64, 64, 64), ranks=(8, 8, 8), p=5, seed=0, prec="f64",
                algo="rsthosvd"),
@@ -95,7 +101,7 @@ def make_input(name, device):
     import torch
     from paper_1905_07311_amd import inputs
     w = WORKLOADS[name]
-    if name == "c2":
+    if name in ("c2", "c2q1"):
         return inputs.hilbert0_device(w["dims"], device, torch.float32)
     if name == "c1":
         return torch.from_numpy(inputs.config1()).to(device)
@@ -111,7 +117,7 @@ def run_step(ctx, name, X):
     w = WORKLOADS[name]
     if w["algo"] == "rsthosvd":
         return ctx.rsthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
-                            prec=w["prec"])
+                            prec=w["prec"], power_iters=w.get("q", 0))
     return ctx.rsthosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
 
 
@@ -182,8 +188,9 @@ def cpu_baseline(name, X_host):
     while len(times) < 3 or (sum(times) < 10.0 and len(times) < 30):
         t0 = time.perf_counter()
         if w["algo"] == "rsthosvd":
-            oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))))
-            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])))
+            oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
+                            q=w.get("q", 0))
+            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
         else:
             res = oracle.adaptive_rsthosvd(Xf, w["eps"], w["block"], w["seed"])
             flops = float("nan")
@@ -362,7 +369,7 @@ def main():
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
     if w["algo"] == "rsthosvd":
-        flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])))
+        flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
     else:
         nsteps_all = min(3, args.steps)
         flops = sum(e["flops"] for e in log_all) / nsteps_all
@@ -400,7 +407,9 @@ def main():
                              for k in ("sketch", "orth", "project", "gram", "truncate")},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
-                     "kernel": "sketch TTM, mode 1", "bytes_per_launch": dom[0]["bytes"]},
+                     "kernel": "sketch TTM, mode 1" + (" (largest: the subspace-iteration product with Z read "
+                                                        "from memory)" if w.get("q") else ""),
+                     "bytes_per_launch": dom[0]["bytes"]},
     }
     if args.copy_calib:
         copy_calibration()
