@@ -7,6 +7,7 @@
  *   rt_rhosvd            - R-HOSVD, Alg. 2 (§3.1)
  *   rt_rsthosvd          - R-STHOSVD, Alg. 3 (§3.1)
  *   rt_rsthosvd_adaptive - adaptive R-STHOSVD, Alg. 5 (§4)
+ *   rt_rhosvd_adaptive   - adaptive R-HOSVD, Alg. 4 (§4)
  * and exposes the steps of their hot path for testing: the on-the-fly Gaussian
  * sketch Y = X_(n) Omega (Alg. 1 step 1), Q = orth(Y) (Alg. 1 step 2) and the
  * projection B = X x_n Q^T (Alg. 1 step 3).
@@ -103,8 +104,8 @@ typedef struct {
                                  values below 1e-13 (fp64) / 1e-6 (fp32) of the
                                  largest raised to that floor); 0 = Alg. 1 as printed.
                                  Each step adds two reads of the current core and
-                                 one core-sized write.  Must be 0 for
-                                 rt_rsthosvd_adaptive. */
+                                 one core-sized write.  Must be 0 for the
+                                 adaptive calls. */
 } rt_opts;
 
 typedef struct {
@@ -158,6 +159,15 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
  * a cap stops a mode before its tolerance.  opts->oversample is ignored. */
 rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
                                int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out);
+
+/* Adaptive R-HOSVD (Alg. 4, §4): the same block range finder and truncation on
+ * the mode-n unfolding of X itself for every mode (tolerance eps_n ||X||_F, so
+ * that the error of X x_j A_j A_j^T is at most eps ||X||_F), then the core
+ * X x_1 A_1^T ... x_d A_d^T.  Arguments, ownership and errors as for
+ * rt_rsthosvd_adaptive (opts->order only sets the order the modes are
+ * processed in). */
+rt_status rt_rhosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
+                             int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out);
 
 /* Release the core and factors of a result produced by this context. */
 rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t);

@@ -146,16 +146,22 @@ def adaptive_rhosvd(X, eps, b, seed, eps_per_mode=None, delta=1e-10):
     nx = float(np.sqrt(fro2(X)))
     epsn = _mode_tolerances(d, eps, eps_per_mode)
     factors = [None] * d
+    info = []
     for n in range(d):
         if epsn[n] == 0.0:
             continue
         tau = epsn[n] * nx
-        Q, B, E, _ = adapt_range_finder(unfold(X, n), tau, b, seed, n, delta)
-        A, _, _, _ = truncate_qb(Q, B, E, tau)
+        Q, B, E, inf = adapt_range_finder(unfold(X, n), tau, b, seed, n, delta)
+        A, _, k, s = truncate_qb(Q, B, E, tau)
         factors[n] = A
+        inf.update({"mode": n, "E": E, "k": k, "qb_cols": Q.shape[1], "tau2": tau * tau,
+                    "sv2": (s ** 2).tolist()})
+        info.append(inf)
     G = X
     for j, A in enumerate(factors):
         if A is not None:
             G = ttm(G, A.T, j)
     ranks = [X.shape[j] if factors[j] is None else factors[j].shape[1] for j in range(d)]
-    return TuckerResult(core=G, factors=factors, ranks=ranks, norm_x=nx, order=list(range(d)))
+    res = TuckerResult(core=G, factors=factors, ranks=ranks, norm_x=nx, order=list(range(d)))
+    res.info = info
+    return res

@@ -675,8 +675,12 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
     return rs;
 }
 
-rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode, int32_t block,
-                               const int32_t* max_rank, const rt_opts* opts, rt_tucker* out) {
+// Adaptive R-STHOSVD (Alg. 5, sequential: every mode works on the core left by
+// the previous one) or adaptive R-HOSVD (Alg. 4: every mode works on X, the
+// core is X x_j A_j^T at the end).
+static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
+                               int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out,
+                               bool sequential) {
     if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
     RT_TRY(check_tensor(X));
     RT_TRY(check_prec(X, opts->prec));
@@ -826,27 +830,50 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
             if (!rtmp) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
             RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)kcols * kcols, W, st, rtmp));
             k.c->cur_J = J;
-            k.c->last_nrm2 = tmp;
+            k.c->last_nrm2 = sequential ? tmp : nullptr;
             rt_status rs = do_truncate(k, dt, Bbuf, Shape3{s.L, kcols, s.R}, cap, W, Qall, cap, -1, Edev, tau2,
-                                       dt == Dt::F64, A, &core, &kfinal);
+                                       dt == Dt::F64, A, sequential ? &core : nullptr, &kfinal);
             k.c->last_nrm2 = nullptr;
             if (rs != RT_OK) { release_partial(ctx, out); return rs; }
         }
         out->factors[n] = ctx->raw_alloc((size_t)J * std::max(kfinal, 1) * es);
-        if (!core) core = k.c->ws((size_t)s.L * std::max(kfinal, 1) * s.R * es);
-        if (!out->factors[n] || !core) { release_partial(ctx, out); return fail(RT_ENOMEM, "allocation failed"); }
+        if (sequential && !core) core = k.c->ws((size_t)s.L * std::max(kfinal, 1) * s.R * es);
+        if (!out->factors[n] || (sequential && !core)) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "allocation failed");
+        }
         if (kfinal > 0) {
             // A was written with leading dimension kfinal by the truncation kernel
             RT_HIP(hipMemcpyAsync(out->factors[n], A, (size_t)J * kfinal * es, hipMemcpyDeviceToDevice, st));
-            RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
-            RT_HIP(hipStreamSynchronize(st));
-            cur_norm2 = h[2];
-        } else {
-            cur_norm2 = 0.0;
         }
         out->ranks[n] = kfinal;
-        dims[n] = kfinal;
-        cur = core;
+        if (sequential) {
+            if (kfinal > 0) {
+                RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
+                RT_HIP(hipStreamSynchronize(st));
+                cur_norm2 = h[2];
+            } else {
+                cur_norm2 = 0.0;
+            }
+            dims[n] = kfinal;
+            cur = core;
+        }
+    }
+    if (!sequential) {
+        // Alg. 4: G = X x_1 A_1^T ... x_d A_d^T over the compressed modes
+        for (int j = 0; j < d; ++j) {
+            if (epsn[j] == 0.0) continue;
+            const int r = out->ranks[j];
+            const Shape3 s = shape3(dims, j);
+            void* nc = k.c->ws((size_t)s.L * std::max(r, 1) * s.R * es);
+            if (!nc) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
+            if (r > 0) {
+                rt_status rs = do_project(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r, 0, nullptr, nullptr);
+                if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+            }
+            dims[j] = r;
+            cur = nc;
+        }
     }
     if (!have_norm) {                                    // every mode kept whole (eps 0)
         int64_t ntot = 1;
@@ -857,6 +884,16 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     if (rs != RT_OK && rs != RT_ENONFINITE) { release_partial(ctx, out); return rs; }
     if (rs == RT_OK && capped) return fail(RT_ECAP, "a mode reached its rank cap before the tolerance");
     return rs;
+}
+
+rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode, int32_t block,
+                               const int32_t* max_rank, const rt_opts* opts, rt_tucker* out) {
+    return adaptive_impl(ctx, X, eps, eps_per_mode, block, max_rank, opts, out, true);
+}
+
+rt_status rt_rhosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode, int32_t block,
+                             const int32_t* max_rank, const rt_opts* opts, rt_tucker* out) {
+    return adaptive_impl(ctx, X, eps, eps_per_mode, block, max_rank, opts, out, false);
 }
 
 // ---- step entry points -------------------------------------------------------------------

@@ -25,7 +25,7 @@ RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
-            "rt_rsthosvd_adaptive", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
+            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_destroy"]
@@ -91,9 +91,10 @@ def load(path=None):
     for fn in ("rt_rhosvd", "rt_rsthosvd"):
         getattr(lib, fn).argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(rt_opts), ctypes.POINTER(rt_tucker)]
-    lib.rt_rsthosvd_adaptive.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
-                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_opts),
-                                         ctypes.POINTER(rt_tucker)]
+    for fn in ("rt_rsthosvd_adaptive", "rt_rhosvd_adaptive"):
+        getattr(lib, fn).argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_opts),
+                                     ctypes.POINTER(rt_tucker)]
     lib.rt_tucker_release.argtypes = [P, ctypes.POINTER(rt_tucker)]
     lib.rt_sketch.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                               ctypes.c_uint64, ctypes.c_int, P, P]
@@ -264,15 +265,21 @@ class Context:
         st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), rk, ctypes.byref(o), ctypes.byref(out)))
         return self._result(out, X, st)
 
+    def rhosvd_adaptive(self, X, eps, block, seed, eps_per_mode=None, max_rank=None, prec=None):
+        return self._adaptive("rt_rhosvd_adaptive", X, eps, block, seed, None, eps_per_mode, max_rank, prec)
+
     def rsthosvd_adaptive(self, X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):
+        return self._adaptive("rt_rsthosvd_adaptive", X, eps, block, seed, order, eps_per_mode, max_rank, prec)
+
+    def _adaptive(self, fn, X, eps, block, seed, order, eps_per_mode, max_rank, prec):
         self._sync_stream()
         t = self._tensor(X)
         o = self._opts(X, 0, seed, order, prec)
         epm = (ctypes.c_double * X.dim())(*eps_per_mode) if eps_per_mode is not None else None
         mr = (ctypes.c_int32 * X.dim())(*max_rank) if max_rank is not None else None
         out = rt_tucker()
-        st = _check(_lib.rt_rsthosvd_adaptive(self.ctx, ctypes.byref(t), float(eps), epm, int(block), mr,
-                                              ctypes.byref(o), ctypes.byref(out)), allow=(RT_ECAP,))
+        st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), float(eps), epm, int(block), mr,
+                                      ctypes.byref(o), ctypes.byref(out)), allow=(RT_ECAP,))
         return self._result(out, X, st)
 
     # -- steps ----------------------------------------------------------------------
@@ -376,6 +383,10 @@ def rhosvd(X, ranks, p, seed, prec=None, power_iters=0):
 
 def rsthosvd_adaptive(X, eps, block, seed, order=None, eps_per_mode=None, max_rank=None, prec=None):
     return context(X.device.index).rsthosvd_adaptive(X, eps, block, seed, order, eps_per_mode, max_rank, prec)
+
+
+def rhosvd_adaptive(X, eps, block, seed, eps_per_mode=None, max_rank=None, prec=None):
+    return context(X.device.index).rhosvd_adaptive(X, eps, block, seed, eps_per_mode, max_rank, prec)
 
 
 @dataclass

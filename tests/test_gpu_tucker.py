@@ -279,3 +279,34 @@ def test_subspace_iteration_errors(ctx):
     for A in g.factors:
         A = to_np(A)
         assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("b", [1, 8])
+def test_adaptive_rhosvd_parity(ctx, dtype, b):
+    # Alg. 4: the range finder on every unfolding of X, then the core X x_j A_j^T
+    rng = np.random.default_rng(17 + b)
+    X = inputs.lowrank_tensor(rng, (40, 33, 27), (10, 9, 8), noise=1e-6,
+                              core_scale=inputs.graded_scale((10, 9, 8), 0.6))
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xd = torch.from_numpy(Xs).cuda()
+    eps = 1e-3
+    g = ctx.rhosvd_adaptive(Xd, eps, b, seed=3)
+    o = oracle.adaptive_rhosvd(Xs.astype(np.float64), eps, b, seed=3,
+                               delta=1e-10 if dtype == torch.float64 else 1e-5)
+    _adaptive_check(g, o, Xs.astype(np.float64), eps, 1e-10 if dtype == torch.float64 else 1e-5,
+                    2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
+
+
+def test_adaptive_rhosvd_per_mode_and_zero(ctx):
+    rng = np.random.default_rng(23)
+    X = inputs.lowrank_tensor(rng, (30, 20, 25), (6, 5, 4), noise=1e-7)
+    Xd = torch.from_numpy(X).cuda()
+    epm = [1e-3 / np.sqrt(2), 0.0, 1e-3 / np.sqrt(2)]          # mode 1 kept whole
+    g = ctx.rhosvd_adaptive(Xd, 1e-3, 4, seed=5, eps_per_mode=epm)
+    o = oracle.adaptive_rhosvd(X, 1e-3, 4, seed=5, eps_per_mode=epm)
+    assert g.ranks == o.ranks and g.ranks[1] == 20 and g.factors[1] is None
+    assert np.linalg.norm(to_np(g.reconstruct()) - o.reconstruct()) / np.linalg.norm(X) < 1e-10
+    Z = torch.zeros((12, 10, 8), dtype=torch.float64, device="cuda")
+    gz = ctx.rhosvd_adaptive(Z, 1e-3, 4, seed=0)
+    assert gz.ranks == [0, 0, 0] and gz.core_norm == 0.0
