@@ -91,6 +91,8 @@ WORKLOADS = {
                p=10, seed=2, prec="bf16", algo="rsthosvd"),
     "c4": dict(desc="adaptive R-STHOSVD, dense 48^5 float32 odeco tensor with mode spectra 0.7^k, eps=1e-3, b=8",
                dims=(48,) * 5, eps=1e-3, block=8, seed=3, prec="f32", algo="adaptive"),
+    "c4h": dict(desc="adaptive R-HOSVD, dense 48^5 float32 odeco tensor with mode spectra 0.7^k, eps=1e-3, b=8",
+                dims=(48,) * 5, eps=1e-3, block=8, seed=3, prec="f32", algo="adaptive_hosvd"),
     "c5": dict(desc="serving: 1024 adaptive R-STHOSVD requests, dense 3-way float32, sides U[32,256], exact Tucker "
                     "ranks U[4,32] + 1e-6 N(0,1), eps=1e-3, b=8, BF16 sketch, Poisson arrivals at 400/s",
                nreq=1024, rate=400.0, eps=1e-3, block=8, prec="bf16", slots=8, pool=256, algo="serving"),
@@ -108,7 +110,7 @@ def make_input(name, device):
     if name == "c3":
         return inputs.lowrank_device(inputs.config_seed(3), w["dims"], w["ranks"], device, torch.float32,
                                      noise=1e-6, core_base=0.8)
-    if name == "c4":
+    if name in ("c4", "c4h"):
         return inputs.odeco_device(inputs.config_seed(4), w["dims"], 0.7, device, torch.float32)
     raise ValueError(name)
 
@@ -118,6 +120,8 @@ def run_step(ctx, name, X):
     if w["algo"] == "rsthosvd":
         return ctx.rsthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                             prec=w["prec"], power_iters=w.get("q", 0))
+    if w["algo"] == "adaptive_hosvd":
+        return ctx.rhosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
     return ctx.rsthosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
 
 
@@ -176,12 +180,32 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
-def cpu_baseline(name, X_host):
-    """The FP64 oracle, as it stands, on the host cores: one full call."""
+def cpu_baseline(name, X_host, ctx=None):
+    """The FP64 oracle, as it stands, on the host cores, over a bounded sample:
+    whole calls of the same workload (fixed rank), or for the adaptive workloads
+    whole calls on the same recipe at side 24 (1/32 of the entries), whose
+    algorithmic flops are read from the library's per-launch log of one device
+    call on that sample."""
     import numpy as np
     import oracle
     from threadpoolctl import threadpool_info
     w = WORKLOADS[name]
+    sample = "the same workload, full size"
+    if w["algo"] in ("adaptive", "adaptive_hosvd"):
+        import torch
+        from paper_1905_07311_amd import inputs
+        dims = (24,) * len(w["dims"])
+        Xs = inputs.odeco_device(inputs.config_seed(4), dims, 0.7, torch.device("cuda", 0), torch.float32)
+        ctx.timing(True)
+        if w["algo"] == "adaptive_hosvd":
+            ctx.rhosvd_adaptive(Xs, w["eps"], w["block"], w["seed"], prec=w["prec"])
+        else:
+            ctx.rsthosvd_adaptive(Xs, w["eps"], w["block"], w["seed"], prec=w["prec"])
+        torch.cuda.synchronize()
+        sample_flops = sum(e["flops"] for e in ctx.timing_log())
+        ctx.timing(False)
+        X_host = Xs.cpu().numpy()
+        sample = "the same recipe at 24^%d (1/32 of the entries)" % len(dims)
     Xf = np.asarray(X_host, dtype=np.float64)
     times = []
     # a bounded sample: whole calls until about 10 s of host work (3 to 30 calls)
@@ -192,13 +216,14 @@ def cpu_baseline(name, X_host):
                             q=w.get("q", 0))
             flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
         else:
-            res = oracle.adaptive_rsthosvd(Xf, w["eps"], w["block"], w["seed"])
-            flops = float("nan")
+            fn = oracle.adaptive_rhosvd if w["algo"] == "adaptive_hosvd" else oracle.adaptive_rsthosvd
+            fn(Xf, w["eps"], w["block"], w["seed"])
+            flops = sample_flops
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"the same workload, full size, {len(times)} calls, median {dt:.2f} s per call "
+            "sample": f"{sample}, {len(times)} calls, median {dt:.2f} s per call "
                       f"(float64 NumPy/LAPACK, explicit Omega generation included)", "seconds_per_call": dt}
 
 
@@ -414,7 +439,7 @@ def main():
     if args.copy_calib:
         copy_calibration()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.workload, X.cpu().numpy())
+        out["cpu_baseline"] = cpu_baseline(args.workload, X.cpu().numpy(), ctx)
     print(json.dumps(out), flush=True)
 
 
