@@ -174,6 +174,17 @@ rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t);
 
 /* ---- hot-path steps, exposed for testing --------------------------------------- */
 
+/* Tucker reconstruction (decompression) X_hat = G x_1 A_1 x_2 ... x_d A_d (§2.1,
+ * the approximation every decomposition call defines).  t: a result of the calls
+ * above or any tensor of the same form (core: row-major ranks[0] x ... x
+ * ranks[d-1] in t->dtype, factors[j]: row-major dims[j] x ranks[j], or NULL for a
+ * mode kept whole, whose rank must equal its dimension, or of rank 0; norms and
+ * flags are ignored; a rank 0 gives a zero result).  out: device buffer of dims[0] x ... x dims[d-1] elements of
+ * t->dtype, written in full (row-major).  Float data runs on the MFMA projection
+ * kernels with the factor transposed, float64 on the fp64 kernels.  Returns after
+ * the stream has finished. */
+rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out);
+
 /* Y = X_(mode) Omega_mode[:, col0 : col0 + ell] (Alg. 1 step 1) for a row-major
  * tensor X, written to Y (device, float64, dims[mode] x ell, row-major).
  * prec selects the arithmetic (F64 needs an RT_F64 tensor).  If nrm2 is not NULL

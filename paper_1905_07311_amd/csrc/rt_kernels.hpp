@@ -170,6 +170,8 @@ hipError_t launch_project_reduce(const float* part, int nsplit, Shape3 s, int el
 // sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)
 int plan_norm(int64_t n);
 hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream);
+// AT (cols x rows) = A^T for a row-major rows x cols matrix A, in dtype dt
+hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT, Dt dt, hipStream_t stream);
 // dst (dtype) <- src (double), n elements
 hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream);
 // explicit Omega (testing): out[i][j] = Omega[c0 + i, col0 + j], fp32 or fp64 transform

@@ -548,6 +548,29 @@ hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nw
     return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ A, int64_t rows, int64_t cols,
+                                                        T* __restrict__ AT) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows * cols; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / cols, k = e - (e / cols) * cols;
+        AT[k * rows + i] = A[e];
+    }
+}
+
+hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT, Dt dt, hipStream_t stream) {
+    const int64_t n = rows * cols;
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(transpose_kernel<double>, dim3((unsigned)g), dim3(256), 0, stream, (const double*)A, rows,
+                           cols, (double*)AT);
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, dim3((unsigned)g), dim3(256), 0, stream, (const float*)A, rows,
+                           cols, (float*)AT);
+    return hipGetLastError();
+}
+
 hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     int64_t g = (n + 255) / 256;

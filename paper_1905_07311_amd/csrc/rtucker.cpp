@@ -896,6 +896,67 @@ rt_status rt_rhosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const 
     return adaptive_impl(ctx, X, eps, eps_per_mode, block, max_rank, opts, out, false);
 }
 
+// ---- Tucker reconstruction ------------------------------------------------------------------
+
+rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
+    if (!ctx || !t || !out) return fail(RT_EINVAL, "NULL argument");
+    const int d = t->ndim;
+    if (d < 2 || d > RT_MAXD) return fail(RT_EINVAL, "ndim must be in [2, RT_MAXD]");
+    if (t->dtype != RT_F32 && t->dtype != RT_F64) return fail(RT_EINVAL, "unknown dtype");
+    int64_t ncore = 1, nout = 1;
+    for (int j = 0; j < d; ++j) {
+        if (t->dims[j] < 1) return fail(RT_EINVAL, "dims must be >= 1");
+        if (t->ranks[j] < 0 || t->ranks[j] > t->dims[j]) return fail(RT_EINVAL, "ranks must be in [0, dims]");
+        if (!t->factors[j] && t->ranks[j] != t->dims[j] && t->ranks[j] != 0)
+            return fail(RT_EINVAL, "a mode without a factor must keep its dimension");
+        ncore *= t->ranks[j];
+        nout *= t->dims[j];
+    }
+    if (ncore > 0 && !t->core) return fail(RT_EINVAL, "NULL core");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    hipStream_t st = ctx->stream;
+    const Dt dt = dt_of(t->dtype);
+    const size_t es = dsize(t->dtype);
+    if (ncore == 0) {
+        RT_HIP(hipMemsetAsync(out, 0, (size_t)nout * es, st));
+        RT_HIP(hipStreamSynchronize(st));
+        return RT_OK;
+    }
+    int last = -1;
+    for (int j = 0; j < d; ++j)
+        if (t->factors[j]) last = j;
+    if (last < 0) {
+        RT_HIP(hipMemcpyAsync(out, t->core, (size_t)nout * es, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipStreamSynchronize(st));
+        return RT_OK;
+    }
+    // G x_j A_j one mode at a time: out[l, i, r] = sum_k A_j[i, k] G[l, k, r], i.e. the
+    // projection kernels with Q = A_j^T (r_j x I_j), in column blocks of at most
+    // RT_LMAX written at their offset in the wider mode
+    std::vector<int64_t> cur_dims(t->ranks, t->ranks + d);
+    const void* cur = t->core;
+    for (int j = 0; j < d; ++j) {
+        if (!t->factors[j]) continue;
+        const int64_t I = t->dims[j];
+        const int r = t->ranks[j];
+        const Shape3 s = shape3(cur_dims, j);
+        void* AT = k.c->ws((size_t)r * I * es);
+        void* dst = j == last ? out : k.c->ws((size_t)s.L * I * s.R * es);
+        if (!AT || !dst) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_transpose(t->factors[j], I, r, AT, dt, st));
+        for (int64_t i0 = 0; i0 < I; i0 += RT_LMAX) {
+            const int e = (int)std::min<int64_t>(RT_LMAX, I - i0);
+            RT_TRY(do_project(k, dt, dt, cur, s, s.J, (const char*)AT + (size_t)i0 * es, I, e, dst, I, i0, nullptr,
+                              nullptr));
+        }
+        cur_dims[j] = I;
+        cur = dst;
+    }
+    RT_HIP(hipStreamSynchronize(st));
+    return RT_OK;
+}
+
 // ---- step entry points -------------------------------------------------------------------
 
 rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,

@@ -25,7 +25,7 @@ RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
-            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
+            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_destroy"]
@@ -96,6 +96,7 @@ def load(path=None):
                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_opts),
                                      ctypes.POINTER(rt_tucker)]
     lib.rt_tucker_release.argtypes = [P, ctypes.POINTER(rt_tucker)]
+    lib.rt_reconstruct.argtypes = [P, ctypes.POINTER(rt_tucker), P]
     lib.rt_sketch.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                               ctypes.c_uint64, ctypes.c_int, P, P]
     lib.rt_orth.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]
@@ -281,6 +282,31 @@ class Context:
         st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), float(eps), epm, int(block), mr,
                                       ctypes.byref(o), ctypes.byref(out)), allow=(RT_ECAP,))
         return self._result(out, X, st)
+
+    def reconstruct(self, t):
+        """X_hat = G x_1 A_1 ... x_d A_d on the device (rt_reconstruct) for a Tucker result."""
+        torch = self.torch
+        self._sync_stream()
+        core = t.core.contiguous()
+        d = core.dim()
+        dims = [int(A.shape[0]) if A is not None else int(core.shape[j]) for j, A in enumerate(t.factors)]
+        s = rt_tucker()
+        s.ndim = d
+        keep = [core]
+        for j in range(d):
+            s.dims[j] = dims[j]
+            s.ranks[j] = int(core.shape[j])
+            A = t.factors[j]
+            if A is not None:
+                A = A.contiguous()
+                keep.append(A)
+                s.factors[j] = A.data_ptr() if A.numel() > 0 else None
+        s.dtype = RT_F64 if core.dtype == torch.float64 else RT_F32
+        s.core = core.data_ptr() if core.numel() > 0 else None
+        out = torch.empty(dims, dtype=core.dtype, device=self.device)
+        _check(_lib.rt_reconstruct(self.ctx, ctypes.byref(s), out.data_ptr()))
+        del keep
+        return out
 
     # -- steps ----------------------------------------------------------------------
     def sketch(self, X, mode, ell, seed, col0=0, prec=None, want_norm=False):

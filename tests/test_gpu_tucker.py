@@ -310,3 +310,22 @@ def test_adaptive_rhosvd_per_mode_and_zero(ctx):
     Z = torch.zeros((12, 10, 8), dtype=torch.float64, device="cuda")
     gz = ctx.rhosvd_adaptive(Z, 1e-3, 4, seed=0)
     assert gz.ranks == [0, 0, 0] and gz.core_norm == 0.0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_reconstruct_device(ctx, dtype):
+    # rt_reconstruct against the oracle's mode products: dims above 64 (several
+    # column blocks per expansion), a mode kept whole, R = 1 in the last mode
+    rng = np.random.default_rng(41)
+    for dims, ranks in (((130, 70, 9), [20, 64, 9]), ((33, 150, 64), [7, 5, 3]), ((40, 33, 27), [6, None, 4])):
+        X = inputs.lowrank_tensor(rng, dims, [r or d for r, d in zip(ranks, dims)], noise=1e-3)
+        Xs = X.astype(np.float32) if dtype == torch.float32 else X
+        g = ctx.rsthosvd(torch.from_numpy(Xs).cuda(), ranks, 0, 2)
+        ref = oracle.reconstruct(to_np(g.core), [None if A is None else to_np(A) for A in g.factors])
+        Xh = to_np(ctx.reconstruct(g))
+        assert Xh.shape == tuple(dims)
+        assert rel(Xh, ref) < (1e-13 if dtype == torch.float64 else 2e-6), dims
+    # rank 0 (adaptive on a zero tensor): zeros
+    Z = torch.zeros((12, 10, 8), dtype=dtype, device="cuda")
+    gz = ctx.rsthosvd_adaptive(Z, 1e-3, 4, seed=0)
+    assert float(ctx.reconstruct(gz).abs().max()) == 0.0
