@@ -20,6 +20,7 @@ from .tucker import (rhosvd, rsthosvd, hosvd, sthosvd, default_order, TuckerResu
                      per_mode_residuals)
 from .adaptive import adapt_range_finder, adaptive_rsthosvd, adaptive_rhosvd
 from .precision import round_bf16
+from .structure import pivoted_rows, select_rows, sp_sthosvd
 
 __all__ = [
     "philox4x32_10", "omega_block", "omega", "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
@@ -28,5 +29,6 @@ __all__ = [
     "rhosvd", "rsthosvd", "hosvd", "sthosvd", "default_order", "TuckerResult",
     "per_mode_residuals",
     "adapt_range_finder", "adaptive_rsthosvd", "adaptive_rhosvd",
+    "pivoted_rows", "select_rows", "sp_sthosvd",
     "round_bf16",
 ]
