@@ -8,6 +8,7 @@
  *   rt_rsthosvd          - R-STHOSVD, Alg. 3 (§3.1)
  *   rt_rsthosvd_adaptive - adaptive R-STHOSVD, Alg. 5 (§4)
  *   rt_rhosvd_adaptive   - adaptive R-HOSVD, Alg. 4 (§4)
+ *   rt_sp_sthosvd        - structure-preserving STHOSVD, Alg. 6 (§5)
  * and exposes the steps of their hot path for testing: the on-the-fly Gaussian
  * sketch Y = X_(n) Omega (Alg. 1 step 1), Q = orth(Y) (Alg. 1 step 2) and the
  * projection B = X x_n Q^T (Alg. 1 step 3).
@@ -148,6 +149,17 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
 /* R-STHOSVD (Alg. 3, §3.1): modes in the order opts->order; the core shrinks
  * after each mode.  Arguments as for rt_rhosvd. */
 rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out);
+
+/* Structure-preserving STHOSVD (Alg. 6, §5), dense tensors: for every mode in
+ * opts->order, Y = G_(n) Omega (ell = r_n + p columns), Q = orth(Y), a selection
+ * P of ell rows of Q, A_n = Q (P^T Q)^-1 and G <- P^T G.  The selection is the
+ * column-pivoted QR order of Q^T followed by strong rank-revealing QR exchanges
+ * (parameter eta = 2) until every entry of A_n is at most 2 in magnitude, so A_n
+ * holds the ell x ell identity and ||A_n||_2 <= sqrt(1 + 4 ell (I_n - ell)); the
+ * core holds entries of X (dims ell_n; RT_KEEP modes keep theirs).  The factors
+ * are not orthonormal: rel_err_est is set to -1.  Other arguments, ownership and
+ * errors as rt_rsthosvd (opts->power_iters must be 0). */
+rt_status rt_sp_sthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out);
 
 /* Adaptive R-STHOSVD (Alg. 5, §4): the rank of each mode is grown `block`
  * columns at a time until ||G_(n) - Q Q^T G_(n)||_F <= eps_n ||X||_F, with

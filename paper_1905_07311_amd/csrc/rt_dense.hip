@@ -1047,6 +1047,165 @@ __global__ __launch_bounds__(NT) void svqb_kernel(const double* __restrict__ W, 
     }
 }
 
+// ---- structure-preserving STHOSVD: selection of ell rows of Q (Alg. 6) -----------------
+// One workgroup.  First set: the column-pivoted QR order of Q^T, i.e. ell greedy
+// steps of Gram-Schmidt on the rows of Q (R, J x ell fp64 scratch, holds the
+// residual rows): the unselected row of largest residual norm (lowest index on
+// ties) is chosen and projected out of every row.  Then strong-RRQR exchanges
+// with k = ell: A = Q Q[sel]^-1 (Gauss-Jordan inverse with partial pivoting); while
+// the largest |A[j][i]| over unselected rows j (first in row-major order) exceeds
+// eta, sel[i] <- j.  Outputs sel (ell ints), A (J x ell, fp64 in Ad, and in dtype
+// at Aout) and the number of exchanges.
+struct SelectShared {
+    Mat M;                 // Q[sel] being inverted (Gauss-Jordan, left block)
+    Mat Inv;               // its inverse (right block)
+    double v[LMAX];
+    double redv[NT / 64];
+    int64_t redi[NT / 64];
+    int sel[LMAX];
+    int piv;
+    int done;
+};
+
+// block argmax of (val, idx): largest val, smallest idx on ties; every thread gets it
+__device__ __forceinline__ void blk_argmax(double& val, int64_t& idx, double* redv, int64_t* redi) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(val, off, 64);
+        const int64_t oi = __shfl_xor(idx, off, 64);
+        if (ov > val || (ov == val && oi < idx)) { val = ov; idx = oi; }
+    }
+    __syncthreads();
+    if (lane == 0) { redv[wave] = val; redi[wave] = idx; }
+    __syncthreads();
+    val = redv[0];
+    idx = redi[0];
+    for (int w = 1; w < NT / 64; ++w)
+        if (redv[w] > val || (redv[w] == val && redi[w] < idx)) { val = redv[w]; idx = redi[w]; }
+}
+
+__global__ __launch_bounds__(NT) void select_rows_kernel(const double* __restrict__ Q, int64_t J, int ell, double eta,
+                                                         int max_swaps, double* __restrict__ R,
+                                                         double* __restrict__ Ad, void* __restrict__ Aout,
+                                                         int a_is_f64, int* __restrict__ sel_out,
+                                                         int* __restrict__ swaps_out) {
+    __shared__ SelectShared S;
+    const int tid = threadIdx.x;
+    for (int64_t e = tid; e < J * ell; e += NT) R[e] = Q[e];
+    __syncthreads();
+    // greedy pivoted Gram-Schmidt on the rows
+    for (int k = 0; k < ell; ++k) {
+        double best = -2.0;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = tid; i < J; i += NT) {
+            bool used = false;
+            for (int t = 0; t < k; ++t) used = used || (S.sel[t] == (int)i);
+            double n2 = 0.0;
+            for (int c = 0; c < ell; ++c) n2 = fma(R[i * ell + c], R[i * ell + c], n2);
+            const double val = used ? -1.0 : n2;
+            if (val > best) { best = val; bi = i; }
+        }
+        blk_argmax(best, bi, S.redv, S.redi);
+        const int p = (int)bi;
+        if (tid == 0) S.sel[k] = p;
+        if (tid < ell) S.v[tid] = best > 0.0 ? R[(int64_t)p * ell + tid] / sqrt(best) : 0.0;
+        __syncthreads();
+        for (int64_t i = tid; i < J; i += NT) {
+            double dot = 0.0;
+            for (int c = 0; c < ell; ++c) dot = fma(R[i * ell + c], S.v[c], dot);
+            for (int c = 0; c < ell; ++c) R[i * ell + c] = fma(-dot, S.v[c], R[i * ell + c]);
+        }
+        __syncthreads();
+    }
+    // exchanges
+    int swaps = 0;
+    for (;;) {
+        // Inv = Q[sel]^-1 by Gauss-Jordan with partial pivoting
+        for (int e = tid; e < ell * ell; e += NT) {
+            const int r = e / ell, c = e % ell;
+            S.M[r][c] = Q[(int64_t)S.sel[r] * ell + c];
+            S.Inv[r][c] = r == c ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int c = 0; c < ell; ++c) {
+            if (tid < 64) {
+                double bv = -1.0;
+                int br = c;
+                for (int r = c + tid; r < ell; r += 64) {
+                    const double a = fabs(S.M[r][c]);
+                    if (a > bv) { bv = a; br = r; }
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off, 64);
+                    const int orr = __shfl_xor(br, off, 64);
+                    if (ov > bv || (ov == bv && orr < br)) { bv = ov; br = orr; }
+                }
+                if (tid == 0) S.piv = br;
+            }
+            __syncthreads();
+            const int pr = S.piv;
+            if (pr != c)
+                for (int e = tid; e < 2 * ell; e += NT) {
+                    const int col = e % ell;
+                    double* a = e < ell ? &S.M[c][col] : &S.Inv[c][col];
+                    double* b = e < ell ? &S.M[pr][col] : &S.Inv[pr][col];
+                    const double t = *a;
+                    *a = *b;
+                    *b = t;
+                }
+            __syncthreads();
+            const double d = S.M[c][c];
+            __syncthreads();
+            for (int e = tid; e < 2 * ell; e += NT) {
+                const int col = e % ell;
+                if (e < ell) S.M[c][col] /= d;
+                else S.Inv[c][col] /= d;
+            }
+            __syncthreads();
+            for (int e = tid; e < ell * 2 * ell; e += NT) {
+                const int r = e / (2 * ell), cc = e % (2 * ell);
+                if (r != c) {
+                    const double f = S.M[r][c];
+                    if (cc < ell) { if (cc != c) S.M[r][cc] = fma(-f, S.M[c][cc], S.M[r][cc]); }
+                    else S.Inv[r][cc - ell] = fma(-f, S.Inv[c][cc - ell], S.Inv[r][cc - ell]);
+                }
+            }
+            __syncthreads();
+            for (int r = tid; r < ell; r += NT)
+                if (r != c) S.M[r][c] = 0.0;
+            __syncthreads();
+        }
+        // A = Q Inv, and the largest |A| over unselected rows
+        double best = -1.0;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = tid; i < J; i += NT) {
+            bool used = false;
+            for (int t = 0; t < ell; ++t) used = used || (S.sel[t] == (int)i);
+            for (int c = 0; c < ell; ++c) {
+                double a = 0.0;
+                for (int t = 0; t < ell; ++t) a = fma(Q[i * ell + t], S.Inv[t][c], a);
+                Ad[i * ell + c] = a;
+                if (!used && fabs(a) > best) { best = fabs(a); bi = i * ell + c; }
+            }
+        }
+        blk_argmax(best, bi, S.redv, S.redi);
+        if (!(best > eta) || swaps >= max_swaps) break;
+        if (tid == 0) S.sel[bi % ell] = (int)(bi / ell);
+        ++swaps;
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < J * ell; e += NT) {
+        const double a = Ad[e];
+        if (a_is_f64) ((double*)Aout)[e] = a;
+        else ((float*)Aout)[e] = (float)a;
+    }
+    if (tid < ell) sel_out[tid] = S.sel[tid];
+    if (tid == 0) swaps_out[0] = swaps;
+}
+
 // A = Q Us[:, :k] for rows 64 b .. 64 b + 63: lane l of every wave owns row
 // 64 b + l (its row of Q in registers) and wave w the columns j = w, w + 4, ...
 // (Us transposed in LDS, read with broadcast 16-byte loads); part[b] = per
@@ -1598,6 +1757,16 @@ hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq,
     }
     hipLaunchKernelGGL(block_orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, b, Qall, ldq, k, drop,
                        scratch, knew, Qf);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, int max_swaps, double* scratch,
+                              void* Aout, Dt da, int* sel, int* swaps, hipStream_t stream) {
+    if (ell < 1 || ell > LMAX || J < ell) return hipErrorInvalidValue;
+    double* R = scratch;
+    double* Ad = scratch + J * ell;
+    hipLaunchKernelGGL(select_rows_kernel, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad, Aout,
+                       da == Dt::F64 ? 1 : 0, sel, swaps);
     return hipGetLastError();
 }
 

@@ -126,6 +126,15 @@ size_t truncate_scratch(int64_t J, int ell);
 // jtol as launch_truncate.
 hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* Tf, double jtol, hipStream_t stream);
 
+// ---- structure-preserving STHOSVD (Alg. 6): row selection on Q -------------------------
+// Q: J x ell fp64 with orthonormal columns.  sel (ell ints, device): the pivoted-QR
+// rows of Q then strong-RRQR exchanges until every |A| <= eta, A = Q Q[sel]^-1 written
+// to Aout (J x ell, dtype da); swaps[0] = exchanges made.  scratch: 2 J ell doubles.
+hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, int max_swaps, double* scratch,
+                              void* Aout, Dt da, int* sel, int* swaps, hipStream_t stream);
+// out (L, ell, R) = G (L, J, R) at the mode indices sel[0..ell) (dtype dt)
+hipError_t launch_gather_mode(const void* G, Dt dt, Shape3 s, const int* sel, int ell, void* out, hipStream_t stream);
+
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
 // then orthonormalised with a rank-revealing drop (singular values <= drop * ||Y_in||_F

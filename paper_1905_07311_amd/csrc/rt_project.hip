@@ -571,6 +571,35 @@ hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT,
     return hipGetLastError();
 }
 
+// out[(l ell + k) R + r] = G[(l J + sel[k]) R + r]: one output row of R elements per
+// (l, k), rows strided over the grid
+template <typename T>
+__global__ __launch_bounds__(256) void gather_mode_kernel(const T* __restrict__ G, int64_t L, int64_t J, int64_t R,
+                                                          const int* __restrict__ sel, int ell, T* __restrict__ out) {
+    const int64_t rows = L * ell;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int64_t l = row / ell;
+        const int k = (int)(row - l * ell);
+        const T* src = G + (l * J + sel[k]) * R;
+        T* dst = out + row * R;
+        for (int64_t r = threadIdx.x; r < R; r += 256) dst[r] = src[r];
+    }
+}
+
+hipError_t launch_gather_mode(const void* G, Dt dt, Shape3 s, const int* sel, int ell, void* out,
+                              hipStream_t stream) {
+    const int64_t rows = s.L * ell;
+    if (rows <= 0 || s.R <= 0) return hipSuccess;
+    const unsigned g = (unsigned)(rows < 8192 ? rows : 8192);
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(gather_mode_kernel<double>, dim3(g), dim3(256), 0, stream, (const double*)G, s.L, s.J,
+                           s.R, sel, ell, (double*)out);
+    else
+        hipLaunchKernelGGL(gather_mode_kernel<float>, dim3(g), dim3(256), 0, stream, (const float*)G, s.L, s.J, s.R,
+                           sel, ell, (float*)out);
+    return hipGetLastError();
+}
+
 hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     int64_t g = (n + 255) / 256;

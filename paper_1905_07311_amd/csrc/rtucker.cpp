@@ -608,6 +608,70 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
     return rs;
 }
 
+rt_status rt_sp_sthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out) {
+    if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, opts->prec));
+    if (opts->power_iters != 0) return fail(RT_EINVAL, "power_iters must be 0 for rt_sp_sthosvd");
+    RT_TRY(check_ranks(X, ranks, opts->oversample));
+    std::vector<int> order;
+    RT_TRY(make_order(X, opts->order, order));
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    hipStream_t st = ctx->stream;
+    const Dt dt = dt_of(X->dtype);
+    const int prec = (int)opts->prec;
+    const size_t es = dsize(X->dtype);
+    init_out(out, X);
+    std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
+    double* nx2 = k.ws<double>(1);
+    uint32_t* status = k.ws<uint32_t>(RT_MAXD);
+    int* sel = k.ws<int>(RT_LMAX);
+    int* swaps = k.ws<int>(1);
+    if (!nx2 || !status || !sel || !swaps) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, st));
+    const void* cur = X->data;
+    bool have_norm = false;
+    for (int n : order) {
+        if (ranks[n] == RT_KEEP) continue;
+        const int ell = ranks[n] + opts->oversample;
+        const Shape3 s = shape3(dims, n);
+        const int64_t J = s.J;
+        double* Y = k.ws<double>((size_t)J * ell);
+        double* oscr = k.ws<double>(rt::orth_scratch(J, ell));
+        double* sscr = k.ws<double>((size_t)2 * J * ell);
+        out->factors[n] = ctx->raw_alloc((size_t)J * ell * es);
+        void* core = k.c->ws((size_t)s.L * ell * s.R * es);
+        if (!Y || !oscr || !sscr || !out->factors[n] || !core) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "allocation failed");
+        }
+        // Alg. 6: Y = G_(n) Omega, Q = orth(Y), selection P, A = Q (P^T Q)^-1, G <- P^T G
+        rt_status rs = do_sketch(k, dt, prec, cur, s, ell, 0, opts->seed, n, Y, have_norm ? nullptr : nx2);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        {
+            TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
+            RT_HIP(rt::launch_orth(Y, J, ell, nullptr, orth_accept_ratio(), status + n, oscr, st));
+            RT_HIP(rt::launch_select_rows(Y, J, ell, 2.0, 1000, sscr, out->factors[n], dt, sel, swaps, st));
+        }
+        RT_HIP(rt::launch_gather_mode(cur, dt, s, sel, ell, core, st));
+        have_norm = true;
+        out->ranks[n] = ell;
+        dims[n] = ell;
+        cur = core;
+    }
+    if (!have_norm) {
+        int64_t n = 1;
+        for (auto v : dims) n *= v;
+        rt_status rs = do_norm2(k, X->data, dt, n, nx2);
+        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+    }
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    out->rel_err_est = -1.0;                 // no identity: the projections are oblique
+    if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
+    return rs;
+}
+
 rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out) {
     if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
     RT_TRY(check_tensor(X));

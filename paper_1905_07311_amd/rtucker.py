@@ -25,7 +25,7 @@ RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
-            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
+            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_destroy"]
@@ -88,7 +88,7 @@ def load(path=None):
     lib.rt_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P, ALLOC_FN, FREE_FN, P]
     lib.rt_set_stream.argtypes = [P, P]
     lib.rt_destroy.argtypes = [P]
-    for fn in ("rt_rhosvd", "rt_rsthosvd"):
+    for fn in ("rt_rhosvd", "rt_rsthosvd", "rt_sp_sthosvd"):
         getattr(lib, fn).argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(rt_opts), ctypes.POINTER(rt_tucker)]
     for fn in ("rt_rsthosvd_adaptive", "rt_rhosvd_adaptive"):
@@ -256,6 +256,9 @@ class Context:
 
     def rhosvd(self, X, ranks, p, seed, prec=None, power_iters=0):
         return self._fixed("rt_rhosvd", X, ranks, p, seed, None, prec, power_iters)
+
+    def sp_sthosvd(self, X, ranks, p, seed, order=None, prec=None):
+        return self._fixed("rt_sp_sthosvd", X, ranks, p, seed, order, prec)
 
     def _fixed(self, fn, X, ranks, p, seed, order, prec, power_iters=0):
         self._sync_stream()

@@ -329,3 +329,29 @@ def test_reconstruct_device(ctx, dtype):
     Z = torch.zeros((12, 10, 8), dtype=dtype, device="cuda")
     gz = ctx.rsthosvd_adaptive(Z, 1e-3, 4, seed=0)
     assert float(ctx.reconstruct(gz).abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dims,core,ranks,p", [((40, 33, 27), (10, 9, 8), [6, 5, 4], 3),
+                                               ((64, 48, 20), (12, 12, 10), [10, 8, 6], 4)])
+def test_sp_sthosvd_parity(ctx, dtype, dims, core, ranks, p):
+    # Alg. 6: same selections as the oracle (index work: exact), factors
+    # A = Q (P^T Q)^-1 (independent of the basis Q), core = X at the selections
+    rng = np.random.default_rng(51)
+    X = inputs.lowrank_tensor(rng, dims, core, noise=1e-3, core_scale=inputs.graded_scale(core, 0.8))
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    g = ctx.sp_sthosvd(torch.from_numpy(Xs).cuda(), ranks, p, 4, order=[0, 1, 2])
+    o = oracle.sp_sthosvd(Xs.astype(np.float64), ranks, p, 4, order=[0, 1, 2])
+    assert g.ranks == o.ranks == [r + p for r in ranks]
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    for A, Ao in zip(g.factors, o.factors):
+        assert rel(to_np(A), Ao) < tol
+    s0, s1, s2 = o.selections
+    np.testing.assert_array_equal(to_np(g.core), Xs[np.ix_(s0, s1, s2)])
+    for A, s in zip(g.factors, o.selections):
+        A = to_np(A)
+        np.testing.assert_allclose(A[s], np.eye(A.shape[1]), atol=10 * tol)
+        assert np.max(np.abs(A)) <= 2.0 + 10 * tol
+    nx = np.linalg.norm(X)
+    assert np.linalg.norm(to_np(ctx.reconstruct(g)) - o.reconstruct()) / nx < (1e-10 if dtype == torch.float64 else 1e-4)
+    assert g.rel_err_est == -1.0
