@@ -49,6 +49,12 @@ def flop_model(dims, ranks, p, order, algo="rsthosvd", q=0):
     orthonormalisation T^T B and a product with the result."""
     dims = list(dims)
     total = 0.0
+    if algo == "sp_sthosvd":
+        for n in order:                                # sketch of the current core per mode
+            ell = ranks[n] + p
+            total += 2 * ell * math.prod(dims)
+            dims[n] = ell
+        return total
     if algo == "rsthosvd":
         for n in order:
             N = math.prod(dims)
@@ -83,6 +89,9 @@ WORKLOADS = {
     "c2q1": dict(desc="R-STHOSVD with one step of randomized subspace iteration per mode, dense 512^3 float32 "
                       "X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, order 1-2-3, Omega seed 1",
                  dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="rsthosvd", q=1),
+    "c2sp": dict(desc="structure-preserving STHOSVD (core of X entries), dense 512^3 float32 X[i,j,k]=1/(i+j+k+1) "
+                      "(0-based), rank (25,25,25), p=10 (core 35^3), order 1-2-3, Omega seed 1",
+                 dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="sp_sthosvd"),
     "c1": dict(desc="R-STHOSVD, dense 64^3 float64 Gaussian 8^3 core x Haar factors + 1e-8 N(0,1), rank (8,8,8), "
                     "p=5, Omega seed 0", dims=(64, 64, 64), ranks=(8, 8, 8), p=5, seed=0, prec="f64",
                algo="rsthosvd"),
@@ -103,7 +112,7 @@ def make_input(name, device):
     import torch
     from paper_1905_07311_amd import inputs
     w = WORKLOADS[name]
-    if name in ("c2", "c2q1"):
+    if name in ("c2", "c2q1", "c2sp"):
         return inputs.hilbert0_device(w["dims"], device, torch.float32)
     if name == "c1":
         return torch.from_numpy(inputs.config1()).to(device)
@@ -120,6 +129,9 @@ def run_step(ctx, name, X):
     if w["algo"] == "rsthosvd":
         return ctx.rsthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                             prec=w["prec"], power_iters=w.get("q", 0))
+    if w["algo"] == "sp_sthosvd":
+        return ctx.sp_sthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
+                              prec=w["prec"])
     if w["algo"] == "adaptive_hosvd":
         return ctx.rhosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
     return ctx.rsthosvd_adaptive(X, w["eps"], w["block"], w["seed"], prec=w["prec"])
@@ -215,6 +227,9 @@ def cpu_baseline(name, X_host, ctx=None):
             oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                             q=w.get("q", 0))
             flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
+        elif w["algo"] == "sp_sthosvd":
+            oracle.sp_sthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))))
+            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo="sp_sthosvd")
         else:
             fn = oracle.adaptive_rhosvd if w["algo"] == "adaptive_hosvd" else oracle.adaptive_rsthosvd
             fn(Xf, w["eps"], w["block"], w["seed"])
@@ -393,8 +408,8 @@ def main():
     log_all = ctx.timing_log()
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
-    if w["algo"] == "rsthosvd":
-        flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
+    if w["algo"] in ("rsthosvd", "sp_sthosvd"):
+        flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo=w["algo"], q=w.get("q", 0))
     else:
         nsteps_all = min(3, args.steps)
         flops = sum(e["flops"] for e in log_all) / nsteps_all
@@ -408,9 +423,13 @@ def main():
     tfl = dom[0]["flops"] / (avg_ms * 1e-3) / 1e12
     mpeak = {"f32": FP32_MFMA_PEAK, "f64": FP64_MFMA_PEAK, "bf16": BF16_MFMA_PEAK}[w["prec"]]
     pj = [e for e in log_all if e["kind"] == "project"]
-    pbig = max(e["bytes"] for e in pj)
-    pdom = [e for e in pj if e["bytes"] == pbig]
-    p_ms = sum(e["ms"] for e in pdom) / len(pdom)
+    if pj:
+        pbig = max(e["bytes"] for e in pj)
+        pdom = [e for e in pj if e["bytes"] == pbig]
+        p_ms = sum(e["ms"] for e in pdom) / len(pdom)
+        proj = {"avg_ms": round(p_ms, 5), "gbs": round(pdom[0]["bytes"] / (p_ms * 1e-3) / 1e9, 1)}
+    else:                                           # SP-STHOSVD gathers instead of projecting
+        proj = None
     # decompression X_hat = G x_j A_j on the device (rt_reconstruct), timed, then the
     # correctness of the measured result (direct residual, fp64)
     ctx.reconstruct(res)
@@ -435,7 +454,7 @@ def main():
         "rel_err_direct": rel_err, "rel_err_est": res.rel_err_est, "ranks": res.ranks,
         "sketch_ttm": {"avg_ms": round(avg_ms, 5), "launches": len(dom), "tflops": round(tfl, 3),
                        "mfma_frac": round(tfl / mpeak, 4), "gbs": round(gbs, 1)},
-        "projection_ttm": {"avg_ms": round(p_ms, 5), "gbs": round(pdom[0]["bytes"] / (p_ms * 1e-3) / 1e9, 1)},
+        "projection_ttm": proj,
         "reconstruct": {"ms": round(rec_ms, 4),
                         "output_gbs": round(X.numel() * X.element_size() / (rec_ms * 1e-3) / 1e9, 1)},
         "kind_ms_per_step": {k: round(sum(e["ms"] for e in log_all if e["kind"] == k) / min(3, args.steps), 4)
