@@ -1085,6 +1085,8 @@ __device__ __forceinline__ void blk_argmax(double& val, int64_t& idx, double* re
         if (redv[w] > val || (redv[w] == val && redi[w] < idx)) { val = redv[w]; idx = redi[w]; }
 }
 
+// REG (J <= NT): a thread's single row of R, and later of Q, is kept in registers.
+template <bool REG>
 __global__ __launch_bounds__(NT) void select_rows_kernel(const double* __restrict__ Q, int64_t J, int ell, double eta,
                                                          int max_swaps, double* __restrict__ R,
                                                          double* __restrict__ Ad, void* __restrict__ Aout,
@@ -1092,6 +1094,40 @@ __global__ __launch_bounds__(NT) void select_rows_kernel(const double* __restric
                                                          int* __restrict__ swaps_out) {
     __shared__ SelectShared S;
     const int tid = threadIdx.x;
+    double rr[REG ? LMAX : 1];
+    if (REG) {
+        // greedy pivoted Gram-Schmidt on the rows, row tid in registers
+        const bool mine = tid < J;
+#pragma unroll
+        for (int c = 0; c < (REG ? LMAX : 1); ++c) rr[c] = (mine && c < ell) ? Q[(int64_t)tid * ell + c] : 0.0;
+        bool used = !mine;
+        for (int k = 0; k < ell; ++k) {
+            double n2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < (REG ? LMAX : 1); ++c) n2 = fma(rr[c], rr[c], n2);
+            double best = used ? -1.0 : n2;
+            if (!mine) best = -2.0;
+            int64_t bi = mine ? tid : INT64_MAX;
+            blk_argmax(best, bi, S.redv, S.redi);
+            const double rs = best > 0.0 ? 1.0 / sqrt(best) : 0.0;
+            if (tid == (int)bi) {
+                S.sel[k] = tid;
+                used = true;
+#pragma unroll
+                for (int c = 0; c < (REG ? LMAX : 1); ++c)
+                    if (c < ell) S.v[c] = rr[c] * rs;
+            }
+            __syncthreads();
+            double dot = 0.0;
+#pragma unroll
+            for (int c = 0; c < (REG ? LMAX : 1); ++c)
+                if (c < ell) dot = fma(rr[c], S.v[c], dot);
+#pragma unroll
+            for (int c = 0; c < (REG ? LMAX : 1); ++c)
+                if (c < ell) rr[c] = fma(-dot, S.v[c], rr[c]);
+            __syncthreads();
+        }
+    } else {
     for (int64_t e = tid; e < J * ell; e += NT) R[e] = Q[e];
     __syncthreads();
     // greedy pivoted Gram-Schmidt on the rows
@@ -1118,7 +1154,13 @@ __global__ __launch_bounds__(NT) void select_rows_kernel(const double* __restric
         }
         __syncthreads();
     }
-    // exchanges
+    }
+    // exchanges: the Q row of a REG thread in registers
+    if (REG) {
+        const bool mine = tid < J;
+#pragma unroll
+        for (int c = 0; c < (REG ? LMAX : 1); ++c) rr[c] = (mine && c < ell) ? Q[(int64_t)tid * ell + c] : 0.0;
+    }
     int swaps = 0;
     for (;;) {
         // Inv = Q[sel]^-1 by Gauss-Jordan with partial pivoting
@@ -1180,14 +1222,30 @@ __global__ __launch_bounds__(NT) void select_rows_kernel(const double* __restric
         // A = Q Inv, and the largest |A| over unselected rows
         double best = -1.0;
         int64_t bi = INT64_MAX;
-        for (int64_t i = tid; i < J; i += NT) {
-            bool used = false;
-            for (int t = 0; t < ell; ++t) used = used || (S.sel[t] == (int)i);
-            for (int c = 0; c < ell; ++c) {
-                double a = 0.0;
-                for (int t = 0; t < ell; ++t) a = fma(Q[i * ell + t], S.Inv[t][c], a);
-                Ad[i * ell + c] = a;
-                if (!used && fabs(a) > best) { best = fabs(a); bi = i * ell + c; }
+        if (REG) {
+            if (tid < J) {
+                const int64_t i = tid;
+                bool used = false;
+                for (int t = 0; t < ell; ++t) used = used || (S.sel[t] == (int)i);
+                for (int c = 0; c < ell; ++c) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int t = 0; t < (REG ? LMAX : 1); ++t)
+                        if (t < ell) a = fma(rr[t], S.Inv[t][c], a);
+                    Ad[i * ell + c] = a;
+                    if (!used && fabs(a) > best) { best = fabs(a); bi = i * ell + c; }
+                }
+            }
+        } else {
+            for (int64_t i = tid; i < J; i += NT) {
+                bool used = false;
+                for (int t = 0; t < ell; ++t) used = used || (S.sel[t] == (int)i);
+                for (int c = 0; c < ell; ++c) {
+                    double a = 0.0;
+                    for (int t = 0; t < ell; ++t) a = fma(Q[i * ell + t], S.Inv[t][c], a);
+                    Ad[i * ell + c] = a;
+                    if (!used && fabs(a) > best) { best = fabs(a); bi = i * ell + c; }
+                }
             }
         }
         blk_argmax(best, bi, S.redv, S.redi);
@@ -1765,8 +1823,12 @@ hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, i
     if (ell < 1 || ell > LMAX || J < ell) return hipErrorInvalidValue;
     double* R = scratch;
     double* Ad = scratch + J * ell;
-    hipLaunchKernelGGL(select_rows_kernel, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad, Aout,
-                       da == Dt::F64 ? 1 : 0, sel, swaps);
+    if (J <= NT)
+        hipLaunchKernelGGL(select_rows_kernel<true>, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad,
+                           Aout, da == Dt::F64 ? 1 : 0, sel, swaps);
+    else
+        hipLaunchKernelGGL(select_rows_kernel<false>, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad,
+                           Aout, da == Dt::F64 ? 1 : 0, sel, swaps);
     return hipGetLastError();
 }
 
