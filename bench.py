@@ -86,6 +86,9 @@ WORKLOADS = {
     "c2": dict(desc="R-STHOSVD, dense 512^3 float32 X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, "
                     "order 1-2-3, Omega seed 1", dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1,
                prec="f32", algo="rsthosvd"),
+    "c2h": dict(desc="R-HOSVD, dense 512^3 float32 X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, "
+                     "Omega seed 1", dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32",
+                algo="rhosvd"),
     "c2q1": dict(desc="R-STHOSVD with one step of randomized subspace iteration per mode, dense 512^3 float32 "
                       "X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, order 1-2-3, Omega seed 1",
                  dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="rsthosvd", q=1),
@@ -112,7 +115,7 @@ def make_input(name, device):
     import torch
     from paper_1905_07311_amd import inputs
     w = WORKLOADS[name]
-    if name in ("c2", "c2q1", "c2sp"):
+    if name in ("c2", "c2h", "c2q1", "c2sp"):
         return inputs.hilbert0_device(w["dims"], device, torch.float32)
     if name == "c1":
         return torch.from_numpy(inputs.config1()).to(device)
@@ -129,6 +132,8 @@ def run_step(ctx, name, X):
     if w["algo"] == "rsthosvd":
         return ctx.rsthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                             prec=w["prec"], power_iters=w.get("q", 0))
+    if w["algo"] == "rhosvd":
+        return ctx.rhosvd(X, list(w["ranks"]), w["p"], w["seed"], prec=w["prec"], power_iters=w.get("q", 0))
     if w["algo"] == "sp_sthosvd":
         return ctx.sp_sthosvd(X, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                               prec=w["prec"])
@@ -227,6 +232,9 @@ def cpu_baseline(name, X_host, ctx=None):
             oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
                             q=w.get("q", 0))
             flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
+        elif w["algo"] == "rhosvd":
+            oracle.rhosvd(Xf, list(w["ranks"]), w["p"], w["seed"], q=w.get("q", 0))
+            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo="rhosvd")
         elif w["algo"] == "sp_sthosvd":
             oracle.sp_sthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))))
             flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo="sp_sthosvd")
@@ -408,7 +416,7 @@ def main():
     log_all = ctx.timing_log()
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
-    if w["algo"] in ("rsthosvd", "sp_sthosvd"):
+    if w["algo"] in ("rsthosvd", "rhosvd", "sp_sthosvd"):
         flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo=w["algo"], q=w.get("q", 0))
     else:
         nsteps_all = min(3, args.steps)
