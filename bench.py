@@ -430,6 +430,17 @@ def main():
     gbs = dom[0]["bytes"] / (avg_ms * 1e-3) / 1e9
     tfl = dom[0]["flops"] / (avg_ms * 1e-3) / 1e12
     mpeak = {"f32": FP32_MFMA_PEAK, "f64": FP64_MFMA_PEAK, "bf16": BF16_MFMA_PEAK}[w["prec"]]
+    # matrix-core use of the dominant sketch: the float32 kernel built on bfloat16
+    # pieces issues six bfloat16 products per float32 product
+    variant = dom[0].get("variant", -1)
+    if variant == 3:
+        mfrac, mdesc = 6.0 * tfl / BF16_MFMA_PEAK, "bf16 MFMA, 6 piece products per fp32 product"
+    elif variant == 2:
+        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA"
+    elif variant == 1:
+        mfrac, mdesc = tfl / mpeak, "fp32 MFMA"
+    else:
+        mfrac, mdesc = tfl / mpeak, "vector ALU (no MFMA)"
     pj = [e for e in log_all if e["kind"] == "project"]
     if pj:
         pbig = max(e["bytes"] for e in pj)
@@ -461,7 +472,7 @@ def main():
         "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
         "rel_err_direct": rel_err, "rel_err_est": res.rel_err_est, "ranks": res.ranks,
         "sketch_ttm": {"avg_ms": round(avg_ms, 5), "launches": len(dom), "tflops": round(tfl, 3),
-                       "mfma_frac": round(tfl / mpeak, 4), "gbs": round(gbs, 1)},
+                       "mfma_frac": round(mfrac, 4), "matrix_cores": mdesc, "gbs": round(gbs, 1)},
         "projection_ttm": proj,
         "reconstruct": {"ms": round(rec_ms, 4),
                         "output_gbs": round(X.numel() * X.element_size() / (rec_ms * 1e-3) / 1e9, 1)},

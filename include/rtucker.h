@@ -251,6 +251,18 @@ rt_status rt_timing_count(rt_ctx* ctx, int64_t* n);
 rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, double* bytes, double* flops,
                           int64_t* rows, int64_t* cols, int32_t* ell);
 
+/* Kernel variant of entry i of the timing log (host output).  For sketches:
+ * RT_SKETCH_GENERIC (LDS-staged vector ALU), RT_SKETCH_MFMA_F32 (float32
+ * MFMA), RT_SKETCH_MFMA_BF16 (products of bfloat16-rounded operands),
+ * RT_SKETCH_SPLIT_BF16 (float32 products formed from three bfloat16 pieces per
+ * operand, six piece products on the bfloat16 MFMA, float32 accuracy); 0 for
+ * the other kinds. */
+#define RT_SKETCH_GENERIC 0
+#define RT_SKETCH_MFMA_F32 1
+#define RT_SKETCH_MFMA_BF16 2
+#define RT_SKETCH_SPLIT_BF16 3
+rt_status rt_timing_variant(rt_ctx* ctx, int64_t i, int32_t* variant);
+
 /* Block until the context's stream is idle. */
 rt_status rt_sync(rt_ctx* ctx);
 

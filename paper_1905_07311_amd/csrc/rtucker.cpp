@@ -61,7 +61,7 @@ struct rt_ctx {
     double* host = nullptr;       // pinned scratch for small read-backs
     std::vector<void*> outputs;   // outputs handed to the caller (for release)
     // optional per-launch timing log (HIP events on the context's stream)
-    struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; };
+    struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; int variant; };
     uint32_t timing = 0;          // bit k: record launches of kind k
     std::vector<Timed> tlog;
     std::vector<hipEvent_t> evpool;
@@ -117,7 +117,7 @@ struct TimeScope {
     TimeScope(rt_ctx* ctx, int kind, double bytes, double flops, int64_t rows, int64_t cols, int ell)
         : c(ctx), on(((ctx->timing >> kind) & 1u) != 0) {
         if (!on) return;
-        t = rt_ctx::Timed{kind, c->next_event(), c->next_event(), bytes, flops, rows, cols, ell};
+        t = rt_ctx::Timed{kind, c->next_event(), c->next_event(), bytes, flops, rows, cols, ell, 0};
         if (!t.a || !t.b) { on = false; return; }
         (void)hipEventRecord(t.a, c->stream);
     }
@@ -205,6 +205,7 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
     {
         const double n = (double)s.L * s.J * s.R;
         TimeScope ts(k.c, 0, n * (dt == Dt::F64 ? 8 : 4), 2.0 * ell * n, s.J, s.L * s.R, ell);
+        ts.t.variant = plan.kind;
         RT_HIP(rt::launch_sketch(plan, dt, prec, G, s, ell, col0, seed, (uint32_t)mode, partial, np, k.c->stream));
     }
     double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
@@ -217,7 +218,7 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
 // Y = G_(n) Z, Z[l R + r][k] = Om[(l ell + k) R + r] (Om: (L, ell, R) in dtype dt)
 rt_status do_sketch_explicit(Call& k, Dt dt, const void* G, Shape3 s, int ell, const void* Om, double* Y) {
     const bool mfma = dt == Dt::F32 && s.R % 4 == 0 && ((uintptr_t)Om & 15) == 0;
-    rt::SketchPlan plan = rt::plan_sketch(dt, mfma ? 1 : 0, s, ell, 0, G);
+    rt::SketchPlan plan = rt::plan_sketch(dt, mfma ? 1 : 0, s, ell, 0, G, false);
     if (plan.kind == 1 && s.R % 4 != 0) plan = rt::plan_sketch(dt, 0, s, ell, 0, G);
     const bool f64acc = dt == Dt::F64;
     void* partial = k.c->ws(plan.partial_elems * (f64acc ? 8 : 4));
@@ -227,6 +228,7 @@ rt_status do_sketch_explicit(Call& k, Dt dt, const void* G, Shape3 s, int ell, c
         const double n = (double)s.L * s.J * s.R;
         TimeScope ts(k.c, 0, n * (dt == Dt::F64 ? 8 : 4) * (1.0 + (double)ell / s.J), 2.0 * ell * n, s.J, s.L * s.R,
                      ell);
+        ts.t.variant = plan.kind;
         RT_HIP(rt::launch_sketch_explicit(plan, dt, G, s, ell, Om, partial, k.c->stream));
     }
     RT_HIP(rt::launch_reduce_rows(partial, f64acc, plan.nsplit, s.J, ell, plan.ldp, Y, k.c->stream, rtmp));
@@ -522,6 +524,13 @@ rt_status rt_timing(rt_ctx* ctx, int32_t enable) {
 rt_status rt_timing_count(rt_ctx* ctx, int64_t* n) {
     if (!ctx || !n) return fail(RT_EINVAL, "NULL argument");
     *n = (int64_t)ctx->tlog.size();
+    return RT_OK;
+}
+
+rt_status rt_timing_variant(rt_ctx* ctx, int64_t i, int32_t* variant) {
+    if (!ctx || !variant) return fail(RT_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int64_t)ctx->tlog.size()) return fail(RT_EINVAL, "entry index out of range");
+    *variant = ctx->tlog[(size_t)i].variant;
     return RT_OK;
 }
 

@@ -26,7 +26,7 @@ RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
             "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
-            "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry",
+            "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_destroy"]
 
@@ -108,6 +108,7 @@ def load(path=None):
     lib.rt_sync.argtypes = [P]
     lib.rt_timing.argtypes = [P, ctypes.c_int32]
     lib.rt_timing_count.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.rt_timing_variant.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
     lib.rt_timing_entry.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -375,7 +376,8 @@ class Context:
     KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate", 4: "gram"}
 
     def timing_log(self):
-        """List of dicts, one per timed launch (kind, ms, bytes, flops, rows, cols, ell)."""
+        """List of dicts, one per timed launch (kind, ms, bytes, flops, rows, cols, ell,
+        variant: the sketch kernel variant, RT_SKETCH_* of the header)."""
         n = ctypes.c_int64(0)
         _check(_lib.rt_timing_count(self.ctx, ctypes.byref(n)))
         out = []
@@ -385,8 +387,11 @@ class Context:
             rows, cols = ctypes.c_int64(), ctypes.c_int64()
             _check(_lib.rt_timing_entry(self.ctx, i, ctypes.byref(kind), ctypes.byref(ms), ctypes.byref(by),
                                         ctypes.byref(fl), ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(ell)))
+            var = ctypes.c_int32()
+            _check(_lib.rt_timing_variant(self.ctx, i, ctypes.byref(var)))
             out.append({"kind": self.KINDS.get(kind.value, str(kind.value)), "ms": ms.value, "bytes": by.value,
-                        "flops": fl.value, "rows": rows.value, "cols": cols.value, "ell": ell.value})
+                        "flops": fl.value, "rows": rows.value, "cols": cols.value, "ell": ell.value,
+                        "variant": var.value})
         return out
 
 

@@ -217,3 +217,36 @@ def test_projection_mfma_shapes(ctx, shape):
             assert rel(to_np(B), ref) < 2e-6, (shape, n, ell)
             Bn = oracle.unfold(to_np(B), n)
             assert rel(to_np(W), Bn @ Bn.T) < 1e-12
+
+
+# float32 sketch on the bfloat16 matrix cores (each operand split exactly into
+# three bfloat16 pieces, six piece products): modes with J > 64 and R % 8 == 0,
+# column offsets that are multiples of 4.  Rows past the last 16-row block,
+# 32-column tiles crossing l-slabs (R = 8, 24) and a ragged last tile, every
+# compiled width (ell up to 16, 32, 48, 64), and rows scaled by 1e-30 and 1e30:
+# each row must carry float32 accuracy relative to its own size.
+SPLIT_SHAPES = [(33, 70, 8), (5, 129, 24), (300, 40, 16), (3, 1000, 40)]
+
+
+@pytest.mark.parametrize("shape", SPLIT_SHAPES)
+def test_sketch_split_bf16_rows(ctx, shape):
+    rng = np.random.default_rng(sum(shape) + 7)
+    Xh = rng.standard_normal(shape).astype(np.float32)
+    n = 1 if shape[1] > 64 else 0
+    idx = [slice(None)] * 3
+    idx[n] = 0
+    Xh[tuple(idx)] *= np.float32(1e-30)
+    idx[n] = shape[n] - 1
+    Xh[tuple(idx)] *= np.float32(1e30)
+    X = torch.from_numpy(Xh).cuda()
+    M = oracle.unfold(Xh.astype(np.float64), n)
+    for ell, col0 in ((1, 0), (16, 4), (17, 0), (35, 8), (48, 0), (64, 12)):
+        Y, nrm = ctx.sketch(X, n, ell, seed=23, col0=col0, want_norm=True)
+        Yg = to_np(Y)
+        ref = M @ oracle.omega(23, n, M.shape[1], range(col0, col0 + ell))
+        # a row of Y is ||M[i]|| sqrt(ell) in size (Omega has N(0, 1) entries);
+        # the bar is taken against that, not against a draw that cancels
+        for i in range(M.shape[0]):
+            scale = np.linalg.norm(M[i]) * np.sqrt(ell)
+            assert np.linalg.norm(Yg[i] - ref[i]) <= 2e-6 * scale, (shape, ell, col0, i)
+        assert abs(float(nrm.item()) - oracle.fro2(Xh)) <= 1e-12 * oracle.fro2(Xh)
