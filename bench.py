@@ -145,10 +145,8 @@ def run_step(ctx, name, X):
 # HBM traffic of the dominant kernel, from the committed rocprofv3 counter summary
 # (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy of
 # known size); reported only while the kernel's sources are those it was taken on.
-TRAFFIC_FILE = {"c2": "profiles/sketch_f32_rows_mode1_512cube_traffic.md"}
-TRAFFIC_SOURCES = ["paper_1905_07311_amd/csrc/rt_sketch_mfma.hpp",
-                   "paper_1905_07311_amd/csrc/rt_sketch_mfma_launch.hpp",
-                   "paper_1905_07311_amd/csrc/rt_sketch_mfma_f32_rows.hip",
+TRAFFIC_FILE = {"c2": "profiles/sketch_split_bf16_mode1_512cube_traffic.md"}
+TRAFFIC_SOURCES = ["paper_1905_07311_amd/csrc/rt_sketch_x6.hip",
                    "paper_1905_07311_amd/csrc/rt_philox.hpp",
                    "paper_1905_07311_amd/csrc/rt_kernels.hpp"]
 
