@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rtucker.h"
+
 namespace rt {
 
 constexpr int LMAX = 64;     // largest sketch width / rank handled by the dense FP64 kernels
@@ -188,6 +190,18 @@ hipError_t launch_project_reduce(const float* part, int nsplit, Shape3 s, int el
 // ---- misc ------------------------------------------------------------------------------
 // sum x^2 (fp64) of n elements, per workgroup partials (nwg <= 1024)
 int plan_norm(int64_t n);
+// Scalars read back at the end of a decomposition (one pinned, device-mapped block).
+struct FinishScalars { double nx2, ng2; uint32_t status[RT_MAXD]; };
+// End of a decomposition in one workgroup: copies the core (n elements) from
+// `core` to `out` when copy is set, sums its squares in fp64 (over the npart
+// per-workgroup partials of launch_norm2 when `partial` is given, else over the
+// elements, in a fixed order) and writes {*nx2, that sum, status[0 .. RT_MAXD)}
+// into `hs`, a pinned host block mapped for the device; visible to the host
+// once the stream has been synchronised.  Serves cores of up to
+// FINISH_DIRECT_MAX elements directly (larger ones: copy and launch_norm2 first).
+constexpr int64_t FINISH_DIRECT_MAX = 1 << 16;
+hipError_t launch_finish(const void* core, void* out, Dt dt, int64_t n, bool copy, const double* partial, int npart,
+                         const double* nx2, const uint32_t* status, FinishScalars* hs, hipStream_t stream);
 hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream);
 // AT (cols x rows) = A^T for a row-major rows x cols matrix A, in dtype dt
 hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT, Dt dt, hipStream_t stream);

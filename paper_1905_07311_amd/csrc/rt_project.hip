@@ -540,6 +540,49 @@ int plan_norm(int64_t n) {
     return (int)g;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void finish_kernel(const T* __restrict__ core, T* __restrict__ out, int64_t n,
+                                                     int copy, const double* __restrict__ partial, int npart,
+                                                     const double* __restrict__ nx2,
+                                                     const uint32_t* __restrict__ status, FinishScalars* hs) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    if (partial) {
+        for (int e = tid; e < npart; e += 256) s += partial[e];
+    } else {
+        for (int64_t e = tid; e < n; e += 256) {
+            const T v = core[e];
+            if (copy) out[e] = v;
+            s = fma((double)v, (double)v, s);
+        }
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid < RT_MAXD) hs->status[tid] = status[tid];
+    if (tid == 0) {
+        hs->nx2 = nx2[0];
+        hs->ng2 = red[0];
+    }
+    __threadfence_system();
+}
+
+hipError_t launch_finish(const void* core, void* out, Dt dt, int64_t n, bool copy, const double* partial, int npart,
+                         const double* nx2, const uint32_t* status, FinishScalars* hs, hipStream_t stream) {
+    if (!partial && n > FINISH_DIRECT_MAX) return hipErrorInvalidValue;
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(finish_kernel<double>, dim3(1), dim3(256), 0, stream, (const double*)core, (double*)out, n,
+                           copy ? 1 : 0, partial, npart, nx2, status, hs);
+    else
+        hipLaunchKernelGGL(finish_kernel<float>, dim3(1), dim3(256), 0, stream, (const float*)core, (float*)out, n,
+                           copy ? 1 : 0, partial, npart, nx2, status, hs);
+    return hipGetLastError();
+}
+
 hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream) {
     if (dt == Dt::F64)
         hipLaunchKernelGGL(norm2_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)X, n, partial);

@@ -59,6 +59,7 @@ struct rt_ctx {
     struct Chunk { char* p; size_t size; size_t used; };
     std::vector<Chunk> chunks;
     double* host = nullptr;       // pinned scratch for small read-backs
+    double* host_dev = nullptr;   // the same block as the device addresses it
     std::vector<void*> outputs;   // outputs handed to the caller (for release)
     // optional per-launch timing log (HIP events on the context's stream)
     struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; int variant; };
@@ -432,9 +433,6 @@ void release_partial(rt_ctx* ctx, rt_tucker* out) {
     }
 }
 
-// Scalars read back at the end of a decomposition (pinned host).
-struct Scalars { double nx2, ng2; uint32_t status[RT_MAXD]; };
-
 rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vector<int64_t>& cdims, Dt dt,
                  double* nx2_dev, uint32_t* status_dev) {
     int64_t n = 1;
@@ -442,16 +440,23 @@ rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vecto
     const size_t bytes = (size_t)n * (dt == Dt::F64 ? 8 : 4);
     out->core = k.c->raw_alloc(bytes);
     if (!out->core) return fail(RT_ENOMEM, "core allocation failed");
-    if (n > 0) RT_HIP(hipMemcpyAsync(out->core, core_dev, bytes, hipMemcpyDeviceToDevice, k.c->stream));
-    double* ng2 = k.ws<double>(1);
-    if (!ng2) return fail(RT_ENOMEM, "workspace allocation failed");
-    if (n > 0) RT_TRY(do_norm2(k, out->core, dt, n, ng2));
-    else RT_HIP(hipMemsetAsync(ng2, 0, sizeof(double), k.c->stream));
-    Scalars* h = (Scalars*)k.c->host;
-    RT_HIP(hipMemcpyAsync(&h->nx2, nx2_dev, sizeof(double), hipMemcpyDeviceToHost, k.c->stream));
-    RT_HIP(hipMemcpyAsync(&h->ng2, ng2, sizeof(double), hipMemcpyDeviceToHost, k.c->stream));
-    RT_HIP(hipMemcpyAsync(h->status, status_dev, sizeof(uint32_t) * RT_MAXD, hipMemcpyDeviceToHost, k.c->stream));
+    // one launch copies the core, sums its squares and writes the scalars into
+    // the mapped pinned block; a large core is copied and its partial sums taken
+    // first
+    rt::FinishScalars* hd = (rt::FinishScalars*)k.c->host_dev;
+    if (n <= rt::FINISH_DIRECT_MAX) {
+        RT_HIP(rt::launch_finish(core_dev, out->core, dt, n, true, nullptr, 0, nx2_dev, status_dev, hd,
+                                 k.c->stream));
+    } else {
+        RT_HIP(hipMemcpyAsync(out->core, core_dev, bytes, hipMemcpyDeviceToDevice, k.c->stream));
+        const int nwg = rt::plan_norm(n);
+        double* part = k.ws<double>(nwg);
+        if (!part) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_norm2(out->core, dt, n, part, nwg, k.c->stream));
+        RT_HIP(rt::launch_finish(nullptr, nullptr, dt, 0, false, part, nwg, nx2_dev, status_dev, hd, k.c->stream));
+    }
     RT_HIP(hipStreamSynchronize(k.c->stream));
+    const rt::FinishScalars* h = (const rt::FinishScalars*)k.c->host;
     out->norm_x = std::sqrt(std::max(h->nx2, 0.0));
     out->core_norm = std::sqrt(std::max(h->ng2, 0.0));
     out->rel_err_est = out->norm_x > 0 ? std::sqrt(std::max(0.0, h->nx2 - h->ng2)) / out->norm_x : 0.0;
@@ -489,6 +494,11 @@ rt_status rt_create(rt_ctx** ctx, int device, void* stream, rt_alloc_fn alloc, r
     if (hipHostMalloc((void**)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(RT_ENOMEM, "pinned host allocation failed");
+    }
+    if (hipHostGetDevicePointer((void**)&c->host_dev, c->host, 0) != hipSuccess || !c->host_dev) {
+        (void)hipHostFree(c->host);
+        delete c;
+        return fail(RT_EHIP, "pinned host block is not mapped for the device");
     }
     *ctx = c;
     return RT_OK;
