@@ -255,12 +255,14 @@ rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, dou
  * RT_SKETCH_GENERIC (LDS-staged vector ALU), RT_SKETCH_MFMA_F32 (float32
  * MFMA), RT_SKETCH_MFMA_BF16 (products of bfloat16-rounded operands),
  * RT_SKETCH_SPLIT_BF16 (float32 products formed from three bfloat16 pieces per
- * operand, six piece products on the bfloat16 MFMA, float32 accuracy); 0 for
- * the other kinds. */
+ * operand, six piece products on the bfloat16 MFMA, float32 accuracy),
+ * RT_SKETCH_BF16_16X16 (the products of bfloat16-rounded operands on the
+ * 16x16x32 bfloat16 MFMA); 0 for the other kinds. */
 #define RT_SKETCH_GENERIC 0
 #define RT_SKETCH_MFMA_F32 1
 #define RT_SKETCH_MFMA_BF16 2
 #define RT_SKETCH_SPLIT_BF16 3
+#define RT_SKETCH_BF16_16X16 4
 rt_status rt_timing_variant(rt_ctx* ctx, int64_t i, int32_t* variant);
 
 /* Block until the context's stream is idle. */

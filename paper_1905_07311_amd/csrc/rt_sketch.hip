@@ -211,8 +211,8 @@ int64_t sketch_target_wg(const SketchPlan&) { return 1024; }
 SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3) {
     SketchPlan p{};
     const int64_t K = s.L * s.R;
-    if (dt == Dt::F32 && prec == 1 && split3 && sketch_x6_ok(s, ell, col0, X)) {
-        plan_sketch_x6(p, s, ell);
+    if (dt == Dt::F32 && (prec == 1 || prec == 2) && split3 && sketch_x6_ok(s, ell, col0, X)) {
+        plan_sketch_x6(p, s, ell, prec == 2);
         return p;
     }
     if (dt == Dt::F32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X)) {
@@ -251,7 +251,7 @@ SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const v
 hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,
                          int64_t col0, uint64_t seed, uint32_t mode, void* partial,
                          double* nrm2_partial, hipStream_t stream) {
-    if (p.kind == 3)
+    if (p.kind == 3 || p.kind == 4)
         return launch_sketch_f32_x6(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
                                     stream);
     if (p.kind == 1 || p.kind == 2) {

@@ -50,10 +50,19 @@ __device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32
     m = __float_as_uint(r) & 0xffff0000u;
     l = __float_as_uint(r - __uint_as_float(m));
 }
+// x rounded to the nearest bfloat16 (ties to even), as a float32 bit pattern
+__device__ __forceinline__ uint32_t rne16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u & 0xffff0000u;
+}
 // two bfloat16 (the high halves of a and b) in one word, a in the low half
 __device__ __forceinline__ uint32_t pack2(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
-template <int NB, int RM>
+// NP = 3: the float32 products from three pieces per operand (above); NP = 1:
+// the products of X and Omega each rounded to the nearest bfloat16 (the
+// bfloat16 sketch), one MFMA per block.
+template <int NB, int RM, int NP>
 __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __restrict__ X, int64_t L, int64_t J, int64_t R,
                                                         int ell, int64_t col0, uint64_t seed, uint32_t mode,
                                                         int64_t tiles_per_split, float* __restrict__ partial,
@@ -63,7 +72,7 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     // words per bfloat16 plane: row n (16 k pairs) at n * 16 + (n / 2) * 4, the
     // padding keeps the generation's stores and the 16-byte reads apart in the banks
     constexpr int PL = NB * 16 * (X6_KC / 2) + NB * 8 * 4;
-    __shared__ __align__(16) uint32_t om[2][3 * PL];
+    __shared__ __align__(16) uint32_t om[2][NP * PL];
     __shared__ double red[X6_WPG];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
@@ -75,7 +84,7 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     const int64_t qbase = col0 / 4;                  // col0 % 4 == 0
     const int nq4 = (ell + 3) / 4;
 
-    for (int e = tid; e < 2 * 3 * PL; e += NTH) (&om[0][0])[e] = 0u;
+    for (int e = tid; e < 2 * NP * PL; e += NTH) (&om[0][0])[e] = 0u;
 
     const __amdgpu_buffer_rsrc_t xr =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), (short)0, (int)(K * J * 4), 0x00020000);
@@ -114,13 +123,17 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int n = 4 * q + u;
-                uint32_t ha, ma, la, hb, mb, lb;
-                split3(za[u], ha, ma, la);
-                split3(zb[u], hb, mb, lb);
                 const int w = n * 16 + (n >> 1) * 4 + kp;
-                om[buf][w] = pack2(ha, hb);
-                om[buf][PL + w] = pack2(ma, mb);
-                om[buf][2 * PL + w] = pack2(la, lb);
+                if (NP == 1) {
+                    om[buf][w] = pack2(rne16(za[u]), rne16(zb[u]));
+                } else {
+                    uint32_t ha, ma, la, hb, mb, lb;
+                    split3(za[u], ha, ma, la);
+                    split3(zb[u], hb, mb, lb);
+                    om[buf][w] = pack2(ha, hb);
+                    om[buf][PL + w] = pack2(ma, mb);
+                    om[buf][2 * PL + w] = pack2(la, lb);
+                }
             }
         }
     };
@@ -139,49 +152,58 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
             const int n = nb * 16 + i16;
             const int w = n * 16 + (n >> 1) * 4 + 4 * g;
             bh[nb] = *reinterpret_cast<const u4*>(&om[buf][w]);
-            bm[nb] = *reinterpret_cast<const u4*>(&om[buf][PL + w]);
-            bl[nb] = *reinterpret_cast<const u4*>(&om[buf][2 * PL + w]);
+            if (NP == 3) {
+                bm[nb] = *reinterpret_cast<const u4*>(&om[buf][PL + w]);
+                bl[nb] = *reinterpret_cast<const u4*>(&om[buf][2 * PL + w]);
+            }
         }
         u4 ah[RM], am[RM], al[RM];
 #pragma unroll
         for (int rm = 0; rm < RM; ++rm) {
             const float x[8] = {v[rm][0].x, v[rm][0].y, v[rm][0].z, v[rm][0].w,
                                 v[rm][1].x, v[rm][1].y, v[rm][1].z, v[rm][1].w};
-            uint32_t h[8], m[8], l[8];
+            if (NP == 1) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) split3(x[e], h[e], m[e], l[e]);
+                for (int j = 0; j < 4; ++j) ah[rm][j] = pack2(rne16(x[2 * j]), rne16(x[2 * j + 1]));
+            } else {
+                uint32_t h[8], m[8], l[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                ah[rm][j] = pack2(h[2 * j], h[2 * j + 1]);
-                am[rm][j] = pack2(m[2 * j], m[2 * j + 1]);
-                al[rm][j] = pack2(l[2 * j], l[2 * j + 1]);
+                for (int e = 0; e < 8; ++e) split3(x[e], h[e], m[e], l[e]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ah[rm][j] = pack2(h[2 * j], h[2 * j + 1]);
+                    am[rm][j] = pack2(m[2 * j], m[2 * j + 1]);
+                    al[rm][j] = pack2(l[2 * j], l[2 * j + 1]);
+                }
             }
             if (nrm2_partial) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) nrm = fma((double)x[e], (double)x[e], nrm);
             }
         }
-        // six products per block, the accumulators of all blocks in between
+        if (NP == 3) {
+            // the five smaller products first, the accumulators of all blocks in between
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm)
+            for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(am[rm], bm[nb], acc[rm][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(am[rm], bm[nb], acc[rm][nb]);
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm)
+            for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(al[rm], bh[nb], acc[rm][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(al[rm], bh[nb], acc[rm][nb]);
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm)
+            for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bl[nb], acc[rm][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bl[nb], acc[rm][nb]);
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm)
+            for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(am[rm], bh[nb], acc[rm][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(am[rm], bh[nb], acc[rm][nb]);
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm)
+            for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bm[nb], acc[rm][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bm[nb], acc[rm][nb]);
+        }
 #pragma unroll
         for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
@@ -239,20 +261,20 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     }
 }
 
-template <int NB>
+template <int NB, int NP>
 hipError_t x6_by_rm(int rm, dim3 grid, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed, uint32_t mode,
                     int64_t tps, float* partial, double* nrm2, hipStream_t st) {
     switch (rm) {
         case 1:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 1>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 1, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
                                mode, tps, partial, nrm2);
             return hipGetLastError();
         case 2:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 2>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 2, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
                                mode, tps, partial, nrm2);
             return hipGetLastError();
         case 4:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 4>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 4, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
                                mode, tps, partial, nrm2);
             return hipGetLastError();
         default:
@@ -270,8 +292,8 @@ bool sketch_x6_ok(Shape3 s, int ell, int64_t col0, const void* X) {
            bytes <= 0x7fff0000LL;
 }
 
-void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell) {
-    p.kind = 3;
+void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16_rounded) {
+    p.kind = bf16_rounded ? 4 : 3;
     p.rb = s.J <= 128 ? 1 : 2;                        // 16-row blocks per wave
     p.rw = 0;
     p.nq = (ell + 15) / 16;
@@ -291,15 +313,20 @@ void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell) {
 
 hipError_t launch_sketch_f32_x6(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed,
                                 uint32_t mode, float* partial, double* nrm2, hipStream_t stream) {
-    if (p.kind != 3 || !sketch_x6_ok(s, ell, col0, X)) return hipErrorInvalidValue;
+    if ((p.kind != 3 && p.kind != 4) || !sketch_x6_ok(s, ell, col0, X)) return hipErrorInvalidValue;
     const dim3 grid(p.nsplit, p.nrowtile);
+    const int64_t tps = p.tiles_per_split;
+#define RT_X6(NBV)                                                                                               \
+    return p.kind == 3 ? x6_by_rm<NBV, 3>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream) \
+                       : x6_by_rm<NBV, 1>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream)
     switch (p.nq) {
-        case 1: return x6_by_rm<1>(p.rb, grid, X, s, ell, col0, seed, mode, p.tiles_per_split, partial, nrm2, stream);
-        case 2: return x6_by_rm<2>(p.rb, grid, X, s, ell, col0, seed, mode, p.tiles_per_split, partial, nrm2, stream);
-        case 3: return x6_by_rm<3>(p.rb, grid, X, s, ell, col0, seed, mode, p.tiles_per_split, partial, nrm2, stream);
-        case 4: return x6_by_rm<4>(p.rb, grid, X, s, ell, col0, seed, mode, p.tiles_per_split, partial, nrm2, stream);
+        case 1: RT_X6(1);
+        case 2: RT_X6(2);
+        case 3: RT_X6(3);
+        case 4: RT_X6(4);
         default: return hipErrorInvalidValue;
     }
+#undef RT_X6
 }
 
 }  // namespace rt
