@@ -276,10 +276,14 @@ def run_serving(args):
                                               dims=([1], [n])), 0, n)
         return float(torch.linalg.norm((H - Xg).reshape(-1)) / torch.linalg.norm(Xg.reshape(-1)))
 
+    # every path is warmed up on one pass over the distinct tensors (all shapes
+    # seen once, so workspaces and cached device memory are in place), then timed
+    # on all requests
+    warm = reqs[:len(pool)]
     # plain per-tensor float32 path: one request after another on one stream, host copies included
     ctx = rtucker.Context(0)
-    for X, s in reqs[:4]:
-        ctx.rsthosvd_adaptive(X.to(dev, non_blocking=True), w["eps"], w["block"], s)
+    for X, s in warm:
+        ctx.rsthosvd_adaptive(X.to(dev, non_blocking=True), w["eps"], w["block"], s, prec="f32")
     torch.cuda.synchronize()
     plain_err = 0.0
     t0 = time.perf_counter()
@@ -296,8 +300,8 @@ def run_serving(args):
 
     # server, closed loop: every request queued at once
     srv = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec=w["prec"])
-    for X, s in reqs[:2 * w["slots"]]:
-        srv.wait(srv.submit(X, s))
+    for t in [srv.submit(X, s) for X, s in warm]:
+        srv.wait(t)
     t0 = time.perf_counter()
     tickets = [srv.submit(X, s) for X, s in reqs]
     served = [srv.wait(t) for t in tickets]
@@ -320,8 +324,8 @@ def run_serving(args):
     srv.close()
     # the same server with float32 sketches
     srv32 = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec="f32")
-    for X, s in reqs[:2 * w["slots"]]:
-        srv32.wait(srv32.submit(X, s))
+    for t in [srv32.submit(X, s) for X, s in warm]:
+        srv32.wait(t)
     t0 = time.perf_counter()
     tickets = [srv32.submit(X, s) for X, s in reqs]
     served32 = [srv32.wait(t) for t in tickets]
@@ -433,8 +437,10 @@ def main():
     variant = dom[0].get("variant", -1)
     if variant == 3:
         mfrac, mdesc = 6.0 * tfl / BF16_MFMA_PEAK, "bf16 MFMA, 6 piece products per fp32 product"
+    elif variant == 4:
+        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA (16x16x32)"
     elif variant == 2:
-        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA"
+        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA (4x4x4)"
     elif variant == 1:
         mfrac, mdesc = tfl / mpeak, "fp32 MFMA"
     else:
