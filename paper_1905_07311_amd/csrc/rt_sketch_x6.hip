@@ -1,15 +1,16 @@
-// FP32 sketch Y = X_(n) Omega (§2.4 Alg. 1 step 1; Alg. 3 step 4) on the
-// bfloat16 matrix cores, at FP32 accuracy.
+// Sketch Y = X_(n) Omega (§2.4 Alg. 1 step 1; Alg. 3 step 4) of float32 data on
+// the bfloat16 matrix cores: at float32 accuracy (NP = 3), or as the bfloat16
+// sketch with X and Omega rounded to the nearest bfloat16 (NP = 1).
 //
-// Every float32 operand is split exactly into three bfloat16 pieces,
+// NP = 3: every float32 operand is split exactly into three bfloat16 pieces,
 // x = h + m + l: h keeps the top 8 significant bits of x (truncation), m the top
 // 8 of the remainder x - h, l the remaining at most 8 bits.  The product x w is
 // formed from the six piece products whose weight is at least 2^-16 of it
 // (hh, hm, mh, hl, lh, mm); each is exact in the float32 accumulator, and the
 // three dropped ones (ml, lm, ll) together stay below 3 * 2^-24 |x w|, so the
-// result carries float32 accuracy.  v_mfma_f32_16x16x32_bf16 then does the
-// work: 2^4 x more flops per instruction than the float32 MFMA, which leaves the
-// kernel bound by HBM rather than by the matrix cores.
+// result carries float32 accuracy.  v_mfma_f32_16x16x32_bf16 runs at 16 x the
+// rate of the float32 MFMA, so even six products per product leave the kernel
+// bound by its memory traffic rather than by the matrix cores.
 //
 // Layout.  A wave owns RM blocks of 16 rows; a workgroup (eight waves) shares
 // the Omega tile.  For an MFMA, lane l = 16 g + i supplies row i of X at the
@@ -18,13 +19,14 @@
 // as the B operand, Omega at the same eight columns for sketch column i of a
 // 16-column block; the accumulator of lane l holds Y[4 g + v][i], v = 0..3.
 // Omega is generated once per tile per workgroup (Philox4x32-10 + Box-Muller,
-// the same values as every other sketch kernel), split, and stored as three
-// bfloat16 planes [piece][block][column][k] (k pairs packed in a word; one
-// 16-byte LDS read per operand).  X is read through a buffer descriptor sized
-// to the tensor (at most 0x7fff0000 bytes), so rows past J and columns past
-// L R load zeros: their offsets are pushed past the end without wrapping.  Split-K
-// partial sums go to partial[split][row][0 .. ell) and are added in a fixed
-// order afterwards, like those of the other sketch kernels.
+// the same values as every other sketch kernel), split or rounded, and stored as
+// NP bfloat16 planes, each [sketch column n][k] (k pairs packed in a word, four
+// words of padding after every two columns; one 16-byte LDS read per operand).
+// X is read through a buffer descriptor sized to the tensor (at most 0x7fff0000
+// bytes), so rows past J and columns past L R load zeros: their offsets are
+// pushed past the end without wrapping.  Split-K partial sums go to
+// partial[split][row][0 .. ell) and are added in a fixed order afterwards, like
+// those of the other sketch kernels.
 #include "rt_kernels.hpp"
 #include "rt_philox.hpp"
 
