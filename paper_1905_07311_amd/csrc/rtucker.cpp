@@ -338,9 +338,14 @@ rt_status do_truncate(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, con
         if (!U) return fail(RT_ENOMEM, "workspace allocation failed");
     }
     {
+        // Jacobi stops at an off-diagonal sum of squares of jtol ||W||_F^2.  For
+        // float data W is the Gram of a float32 B, whose entries already carry a
+        // relative rounding of 2^-24: W and its eigenvectors are fixed only to
+        // about 1e-7 ||W||, so the sweeps stop there (jtol = 1e-14); fp64 data
+        // sweeps to 1e-15 ||W||.
         TimeScope ts(k.c, 3, 0.0, 0.0, Jq, kb, kb);
         RT_HIP(rt::launch_truncate(Wcur, kb, Qcur, ldqcur, Jq, r_fixed, Edev, tau2, U, Uf, A_out, dt, lam, kdev,
-                                   dt == Dt::F64 ? 1e-30 : 1e-24, tscr, st));
+                                   dt == Dt::F64 ? 1e-30 : 1e-14, tscr, st));
     }
     int kk = r_fixed;
     if (r_fixed < 0) {
