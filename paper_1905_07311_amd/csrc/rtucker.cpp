@@ -402,7 +402,8 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
             RT_TRY(do_project(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell, 0, nullptr, nullptr));
             RT_HIP(rt::launch_gram3(B, dt, s.L, ell, s.R, ell, gp, nwg, st));
             RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)ell * ell, W, st, rtmp));
-            RT_HIP(rt::launch_svqb(W, ell, drop, T, Tf, dt == Dt::F64 ? 1e-30 : 1e-24, st));
+            // Jacobi tolerance as for the truncation: float data fixes W only to ~2^-24 ||W||
+            RT_HIP(rt::launch_svqb(W, ell, drop, T, Tf, dt == Dt::F64 ? 1e-30 : 1e-14, st));
             RT_TRY(do_project(k, dt, dt, B, sb, ell, dt == Dt::F64 ? (const void*)T : (const void*)Tf, ell, ell, B2,
                               ell, 0, nullptr, nullptr));
             RT_TRY(do_sketch_explicit(k, dt, G, s, ell, B2, Y));
