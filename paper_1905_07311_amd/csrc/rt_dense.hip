@@ -618,17 +618,10 @@ __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, 
 // fix (each column of A and U flipped so that its largest-|.| entry, lowest
 // row on ties, is positive) applied to A and written into U.
 
-// ---- Jacobi with one barrier per step ------------------------------------------------
-// Parallel cyclic Jacobi on the symmetric n x n matrix in Ab[0] (round-robin
-// pairing of m = n + (n odd) indices; when n is odd, index n is a phantom whose
-// row and column are kept zero, so its rotations are the identity).  The matrix
-// is double buffered: in a step every thread owns 2 x 2 blocks (rows of pair bi,
-// columns of pair bj), loads the diagonal blocks of both pairs, its block and
-// its block of V in one batch, computes both rotations (the same values, so the
-// same bits, in every thread), writes R^T A R of its block to the other buffer
-// and V R in place; one barrier ends the step.  Stops when the off-diagonal sum
-// of squares is <= tol ||A||_F^2 (checked once per sweep).  Returns the buffer
-// that holds the result; V's columns are the eigenvectors.
+// ---- parallel cyclic Jacobi -----------------------------------------------------------
+// Round-robin pairing of m = n + (n odd) indices: in step `step` (0 .. m - 2)
+// pair t joins indices a and b as below (index m - 1 stays fixed, the others
+// rotate), every index once per step; p < q.
 __device__ __forceinline__ void jpair(int step, int t, int m, int& p, int& q) {
     int a, b;
     if (t == 0) { a = m - 1; b = step; }
