@@ -75,6 +75,26 @@ struct rt_ctx {
         ++evused;
         return e;
     }
+    // streams (default priority) and events for work forked off `stream` and
+    // joined back into it within one call
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> sync_ev;
+    hipStream_t side_stream(size_t i) {
+        while (side.size() <= i) {
+            hipStream_t s = nullptr;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+            side.push_back(s);
+        }
+        return side[i];
+    }
+    hipEvent_t sync_event(size_t i) {
+        while (sync_ev.size() <= i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+            sync_ev.push_back(e);
+        }
+        return sync_ev[i];
+    }
     int64_t cur_J = 0;            // rows of the basis Q of the mode being truncated
     double* last_nrm2 = nullptr;  // optional: receives ||core||^2 of the truncation's core update
 
@@ -523,6 +543,13 @@ rt_status rt_destroy(rt_ctx* ctx) {
     ctx->chunks.clear();
     for (auto e : ctx->evpool) (void)hipEventDestroy(e);
     ctx->evpool.clear();
+    for (auto sd : ctx->side) {
+        (void)hipStreamSynchronize(sd);
+        (void)hipStreamDestroy(sd);
+    }
+    ctx->side.clear();
+    for (auto e : ctx->sync_ev) (void)hipEventDestroy(e);
+    ctx->sync_ev.clear();
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;
     return RT_OK;
@@ -718,6 +745,16 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
     RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, ctx->stream));
     int first = -1;
     void* core0 = nullptr;
+    // Alg. 2's modes are independent: each runs on a stream of its own, forked
+    // from the context's stream and joined back into it before the core, so the
+    // single-workgroup steps of one mode overlap the sweeps over X of another.
+    // Every mode's workspace is its own (the arena is bump-allocated within a
+    // call); the host enqueues the modes one after another.
+    hipStream_t main_st = ctx->stream;
+    hipEvent_t fork = ctx->sync_event(0);
+    if (!fork) return fail(RT_EHIP, "event creation failed");
+    RT_HIP(hipEventRecord(fork, main_st));
+    int nside = 0;
     for (int j = 0; j < d; ++j) {                          // Alg. 2: every mode from X itself
         if (ranks[j] == RT_KEEP) continue;
         const int r = ranks[j];
@@ -730,9 +767,22 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "allocation failed");
         }
+        hipStream_t sj = ctx->side_stream((size_t)nside);
+        hipEvent_t done = ctx->sync_event((size_t)nside + 1);
+        if (!sj || !done) { release_partial(ctx, out); return fail(RT_EHIP, "stream creation failed"); }
+        RT_HIP(hipStreamWaitEvent(sj, fork, 0));
+        ctx->stream = sj;
         rt_status rs = fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, opts->power_iters,
                                   out->factors[j], core, first < 0 ? nx2 : nullptr, status + j);
-        if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        ctx->stream = main_st;
+        RT_HIP(hipEventRecord(done, sj));
+        RT_HIP(hipStreamWaitEvent(main_st, done, 0));
+        ++nside;
+        if (rs != RT_OK) {
+            (void)hipStreamSynchronize(main_st);
+            release_partial(ctx, out);
+            return rs;
+        }
         if (first < 0) { first = j; core0 = core; }
         out->ranks[j] = r;
     }
