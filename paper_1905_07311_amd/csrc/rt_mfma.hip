@@ -48,7 +48,7 @@ constexpr int PR1_QCH = 128;  // the same for the last-mode kernel
 // gridDim.y > 1 splits the contraction: block row y sums the rows
 // [y jchunk, (y + 1) jchunk) of the mode and writes its partial result at
 // B + y * split_stride (the caller then adds the partials in a fixed order).
-template <int NQ, int SETS, int DEPTH = PM_DEPTH>
+template <int NQ, int SETS, int DEPTH = PM_DEPTH, bool ROLL = false>
 __global__ __launch_bounds__(256) void project_mfma_kernel(const float* __restrict__ G, int64_t L, int64_t Jfull,
                                                            int64_t ldj, int64_t R, const float* __restrict__ Qfull,
                                                            int64_t ldq, int ell, float* __restrict__ Bbase, int64_t ldk,
@@ -70,6 +70,91 @@ __global__ __launch_bounds__(256) void project_mfma_kernel(const float* __restri
     constexpr int SW = 64 * SETS;                           // strip width (columns)
     const int64_t nstrips = (K + SW - 1) / SW;
     double nrm = 0.0;
+    // set s of lane l holds B[4 j + v][c + s] in register v of acc[s][j]
+    auto store = [&](const f4 (&acc)[SETS][NQ], int64_t l, int64_t r) {
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = 4 * j + v;
+                if (k < ell) {
+                    vec o;
+#pragma unroll
+                    for (int s = 0; s < SETS; ++s) o[s] = acc[s][j][v];
+                    *reinterpret_cast<vec*>(B + (l * ldk + koff + k) * R + r) = o;
+                    if (nrm2_partial)
+#pragma unroll
+                        for (int s = 0; s < SETS; ++s) nrm += (double)o[s] * o[s];
+                }
+            }
+        }
+    };
+    // ROLL, for short modes (the launch checks: no contraction split, J <= 64,
+    // all of Q staged at once, J a multiple of the ring depth): Q is staged once,
+    // and the load ring rolls on from one strip of the wave into its next, so the
+    // loads never drain between strips.  The ring slot d always holds row d of
+    // the current group of DEPTH rows.
+    if constexpr (ROLL) {
+        for (int e = tid; e < PM_QCH * 4 * QW; e += 256) {
+            const int ii = e / (4 * QW), tt = (e / QW) & 3, j = e % QW;
+            const int k = 4 * j + tt;
+            qs[e] = (ii < J && k < ell) ? Q[ii * ldq + k] : 0.f;
+        }
+        __syncthreads();
+        const int64_t sstep = (int64_t)gridDim.x * 4;
+        // the strip's first-row pointer (G itself for a strip past the end: its
+        // loads stay inside the first J rows and are never used)
+        auto strip_ptr = [&](int64_t strip, bool& ok, int64_t& l, int64_t& r) -> const float* {
+            const int64_t c = strip * SW + SETS * lane;
+            ok = strip < nstrips && c < K;
+            l = 0;
+            r = 0;
+            if (ok) { l = c / R; r = c - l * R; }
+            return ok ? G + l * ldj * R + r : G;
+        };
+        int64_t strip = (int64_t)blockIdx.x * 4 + wave;
+        bool ok;
+        int64_t l, r;
+        const float* gq = strip_ptr(strip, ok, l, r);
+        vec ring[DEPTH];
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) ring[d] = *reinterpret_cast<const vec*>(gq + (int64_t)d * R);
+        for (; strip < nstrips; strip += sstep) {
+            bool okn;
+            int64_t ln, rn;
+            const float* gn = strip_ptr(strip + sstep, okn, ln, rn);
+            f4 acc[SETS][NQ];
+#pragma unroll
+            for (int s = 0; s < SETS; ++s)
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) acc[s][j] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int ii = 0; ii < J; ii += DEPTH) {
+                const bool last = ii + DEPTH >= J;
+#pragma unroll
+                for (int d = 0; d < DEPTH; ++d) {
+                    const vec x = ring[d];
+                    const float* src = last ? gn + (int64_t)d * R : gq + (int64_t)(ii + DEPTH + d) * R;
+                    ring[d] = *reinterpret_cast<const vec*>(src);
+                    const float* qrow = &qs[((ii + d) * 4 + t) * QW];
+                    float av[QW];
+#pragma unroll
+                    for (int j4 = 0; j4 < QW; j4 += 4) {
+                        const f4 q = *reinterpret_cast<const f4*>(qrow + j4);
+                        av[j4] = q.x; av[j4 + 1] = q.y; av[j4 + 2] = q.z; av[j4 + 3] = q.w;
+                    }
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j)
+#pragma unroll
+                        for (int s = 0; s < SETS; ++s) acc[s][j] = mfma4(av[j], x[s], acc[s][j]);
+                }
+            }
+            if (ok) store(acc, l, r);
+            gq = gn;
+            ok = okn;
+            l = ln;
+            r = rn;
+        }
+    } else
     for (int64_t s0 = (int64_t)blockIdx.x * 4; s0 < nstrips; s0 += (int64_t)gridDim.x * 4) {
         const int64_t strip = s0 + wave;
         const int64_t c = strip * SW + SETS * lane;          // this lane's columns c .. c + SETS - 1
@@ -127,25 +212,7 @@ __global__ __launch_bounds__(256) void project_mfma_kernel(const float* __restri
             for (int d = 0; d < DEPTH; ++d)
                 if (nfull + d < rows) step(nfull + d, ring[d]);
         }
-        // set s of lane l holds B[4 j + v][c + s] in register v of acc[s][j]
-        if (valid) {
-#pragma unroll
-            for (int j = 0; j < NQ; ++j) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int k = 4 * j + v;
-                    if (k < ell) {
-                        vec o;
-#pragma unroll
-                        for (int s = 0; s < SETS; ++s) o[s] = acc[s][j][v];
-                        *reinterpret_cast<vec*>(B + (l * ldk + koff + k) * R + r) = o;
-                        if (nrm2_partial)
-#pragma unroll
-                            for (int s = 0; s < SETS; ++s) nrm += (double)o[s] * o[s];
-                    }
-                }
-            }
-        }
+        if (valid) store(acc, l, r);
     }
     if (nrm2_partial) {
 #pragma unroll
@@ -165,8 +232,16 @@ struct PmDepth { static constexpr int value = SETS == 2 ? 8 : 16; };
 template <int NQ, int SETS>
 hipError_t launch_pm(const ProjectPlan& p, const float* G, Shape3 s, int64_t ldj, const float* Q, int64_t ldq, int ell,
                      float* B, int64_t ldk, int64_t koff, double* nrm2, hipStream_t stream) {
-    hipLaunchKernelGGL((project_mfma_kernel<NQ, SETS, PmDepth<SETS>::value>), dim3(p.nwg, p.nsplit), dim3(256), 0,
-                       stream, G, s.L, s.J, ldj, s.R, Q, ldq, ell, B, ldk, koff, nrm2, p.jchunk, p.split_stride);
+    constexpr int D = PmDepth<SETS>::value;
+    constexpr int QCH = PmChunk<(NQ + 3) / 4 * 4, SETS>::rows;
+    // the rolling ring pays off for short modes only (measured: 48 rows gain,
+    // 128 and 512 rows lose)
+    if (p.nsplit == 1 && s.J <= 64 && s.J <= QCH && s.J % D == 0)
+        hipLaunchKernelGGL((project_mfma_kernel<NQ, SETS, D, true>), dim3(p.nwg, 1), dim3(256), 0, stream, G, s.L,
+                           s.J, ldj, s.R, Q, ldq, ell, B, ldk, koff, nrm2, p.jchunk, p.split_stride);
+    else
+        hipLaunchKernelGGL((project_mfma_kernel<NQ, SETS, D, false>), dim3(p.nwg, p.nsplit), dim3(256), 0, stream,
+                           G, s.L, s.J, ldj, s.R, Q, ldq, ell, B, ldk, koff, nrm2, p.jchunk, p.split_stride);
     return hipGetLastError();
 }
 
