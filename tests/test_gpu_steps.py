@@ -250,3 +250,23 @@ def test_sketch_split_bf16_rows(ctx, shape):
             scale = np.linalg.norm(M[i]) * np.sqrt(ell)
             assert np.linalg.norm(Yg[i] - ref[i]) <= 2e-6 * scale, (shape, ell, col0, i)
         assert abs(float(nrm.item()) - oracle.fro2(Xh)) <= 1e-12 * oracle.fro2(Xh)
+
+
+def test_projection_short_mode_many_strips(ctx):
+    """Short mode (J = 16, a multiple of the ring depth) over 4,194,452 columns:
+    more 256-column strips than the grid has waves, so each wave's load ring
+    rolls from one strip into the next two or three, and the last strip is
+    ragged.  Columns sampled across the whole range (every wave's first and
+    later strips, the tail) against the fp64 product."""
+    rng = np.random.default_rng(31)
+    J, K, ell = 16, 2 * 8192 * 256 + 4 * 37, 8
+    X = torch.randn((J, K), generator=torch.Generator().manual_seed(5), dtype=torch.float32).cuda()
+    Qh, _ = np.linalg.qr(rng.standard_normal((J, ell)))
+    Qf = Qh.astype(np.float32)
+    B, _ = ctx.project(X, 0, torch.from_numpy(Qf).cuda(), want_gram=True)
+    cols = np.unique(np.concatenate([rng.integers(0, K, 3000), np.arange(K - 300, K), np.arange(0, 300),
+                                     np.arange(2048 * 4 * 256 - 100, 2048 * 4 * 256 + 100)]))
+    Xs = X[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+    ref = Qf.astype(np.float64).T @ Xs
+    got = B[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
+    assert rel(got, ref) < 2e-6
