@@ -204,6 +204,21 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out);
 rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
                     rt_precision prec, double* Y, double* nrm2);
 
+/* rt_sketch for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * result, plan and kernels, with every temporary (split-K partial sums, norm
+ * partials, reduction temporaries) in a static device array of 64 MiB that each
+ * GPU holds from library load until the process ends; it calls no allocator.
+ * Enqueues on the context's stream and returns without waiting (Y and *nrm2 are
+ * valid once the stream has reached that point).  A shape whose temporaries
+ * exceed 64 MiB (float64 sketches of width above about 32 over many columns,
+ * or float sketches of width near 64 over long, non-x8 modes) returns RT_EINVAL
+ * before anything is enqueued.  All calls on one GPU share the array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised by
+ * the caller. */
+rt_status rt_sketch_noalloc(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0,
+                            uint64_t seed, rt_precision prec, double* Y, double* nrm2);
+
 /* Q = orth(Y) (Alg. 1 step 2): Y (device, float64, rows x ell, row-major) is
  * overwritten by an orthonormal Q with range(Y) inside range(Q).  *flags (host)
  * receives RT_FLAG_* bits.  ell <= rows, ell <= RT_LMAX. */

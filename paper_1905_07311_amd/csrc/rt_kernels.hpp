@@ -218,4 +218,15 @@ hipError_t launch_philox_words(uint64_t seed, uint32_t mode, int64_t c0, int64_t
                                uint32_t* out, hipStream_t stream);
 // Tucker reconstruction helper is the projection kernel with the factor in place of Q^T.
 
+// ---- allocation-free entry point ---------------------------------------------------------
+// Device address of the library's static scratch array on `device` (the current
+// device), taken once per device; rt_create calls it.
+hipError_t noalloc_init(int device);
+// Context accessors and the sketch's argument checks, shared by the entry points.
+hipStream_t ctx_stream(const rt_ctx* c);
+int ctx_device(const rt_ctx* c);
+rt_status check_sketch_args(const rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0,
+                            rt_precision prec, const double* Y);
+rt_status set_error(rt_status s, const char* msg);
+
 }  // namespace rt

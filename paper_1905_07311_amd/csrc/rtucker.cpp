@@ -128,6 +128,11 @@ struct rt_ctx {
     }
 };
 
+namespace rt {
+hipStream_t ctx_stream(const rt_ctx* c) { return c->stream; }
+int ctx_device(const rt_ctx* c) { return c->device; }
+}  // namespace rt
+
 namespace {
 
 // Records HIP events around one kernel launch when the context's timing log is on.
@@ -212,6 +217,24 @@ rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
     }
     return RT_OK;
 }
+
+}  // namespace
+
+namespace rt {
+// Arguments of the sketch entry points (rt_sketch and its allocation-free variant).
+rt_status check_sketch_args(const rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0,
+                            rt_precision prec, const double* Y) {
+    if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_tensor(X));
+    RT_TRY(check_prec(X, prec));
+    if (mode < 0 || mode >= X->ndim) return fail(RT_EINVAL, "mode out of range");
+    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
+    if (col0 < 0) return fail(RT_EINVAL, "col0 must be >= 0");
+    return RT_OK;
+}
+}  // namespace rt
+
+namespace {
 
 // ---- building blocks ----------------------------------------------------------------
 
@@ -511,6 +534,7 @@ rt_status rt_create(rt_ctx** ctx, int device, void* stream, rt_alloc_fn alloc, r
     if ((alloc == nullptr) != (free_fn == nullptr)) return fail(RT_EINVAL, "alloc and free must both be set or NULL");
     RT_HIP(hipSetDevice(device));
     RT_HIP(rt::dense_init());
+    RT_HIP(rt::noalloc_init(device));
     rt_ctx* c = new rt_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -1100,12 +1124,7 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
 
 rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
                     rt_precision prec, double* Y, double* nrm2) {
-    if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
-    RT_TRY(check_tensor(X));
-    RT_TRY(check_prec(X, prec));
-    if (mode < 0 || mode >= X->ndim) return fail(RT_EINVAL, "mode out of range");
-    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
-    if (col0 < 0) return fail(RT_EINVAL, "col0 must be >= 0");
+    RT_TRY(rt::check_sketch_args(ctx, X, mode, ell, col0, prec, Y));
     RT_HIP(hipSetDevice(ctx->device));
     Call k(ctx);
     std::vector<int64_t> dims(X->dims, X->dims + X->ndim);

@@ -25,7 +25,7 @@ RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
-            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_orth", "rt_project", "rt_omega",
+            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_destroy"]
@@ -99,6 +99,7 @@ def load(path=None):
     lib.rt_reconstruct.argtypes = [P, ctypes.POINTER(rt_tucker), P]
     lib.rt_sketch.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                               ctypes.c_uint64, ctypes.c_int, P, P]
+    lib.rt_sketch_noalloc.argtypes = lib.rt_sketch.argtypes
     lib.rt_orth.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]
     lib.rt_project.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, P, ctypes.c_int, ctypes.c_int32, P, P]
     lib.rt_omega.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
@@ -322,6 +323,19 @@ class Context:
         _check(_lib.rt_sketch(self.ctx, ctypes.byref(t), int(mode), int(ell), int(col0), int(seed),
                               self._prec(X, prec), Y.data_ptr(), nrm.data_ptr() if nrm is not None else None))
         return (Y, nrm) if want_norm else Y
+
+    def sketch_noalloc(self, X, mode, ell, seed, Y, col0=0, prec=None, nrm2=None):
+        """rt_sketch_noalloc: Y (float64, dims[mode] x ell, caller-allocated) and the
+        optional nrm2 (one float64) are written on the current stream; the library
+        allocates nothing and does not wait."""
+        torch = self.torch
+        self._sync_stream()
+        t = self._tensor(X)
+        if Y.dtype != torch.float64 or not Y.is_contiguous() or tuple(Y.shape) != (int(X.shape[mode]), int(ell)):
+            raise ValueError("Y must be a contiguous float64 (dims[mode], ell) tensor")
+        _check(_lib.rt_sketch_noalloc(self.ctx, ctypes.byref(t), int(mode), int(ell), int(col0), int(seed),
+                                      self._prec(X, prec), Y.data_ptr(), nrm2.data_ptr() if nrm2 is not None else None))
+        return Y
 
     def orth(self, Y):
         torch = self.torch
