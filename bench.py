@@ -23,8 +23,11 @@ request after another on one stream, host copies included) and the p50/p99
 latency of an open-loop run with Poisson arrivals at 400/s.  Every result of
 both paths is checked against a direct fp64 residual <= 1e-3.
 
+The default line also carries `serving`: the same serving measurement as
+workload c5, so one run reports both halves of the metric.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5] [--no-cpu]
-                      [--copy-calib]
+                      [--no-serving] [--copy-calib]
 """
 import argparse
 import json
@@ -108,7 +111,7 @@ WORKLOADS = {
     "c5": dict(desc="serving: 1024 adaptive R-STHOSVD requests, dense 3-way float32, sides U[32,256], exact Tucker "
                     "ranks U[4,32] + 1e-6 N(0,1), eps=1e-3, b=8, FP32 sketch (the BF16-sketch server reported "
                     "beside it), Poisson arrivals at 400/s",
-               nreq=1024, rate=400.0, eps=1e-3, block=8, prec="f32", alt_prec="bf16", slots=8, pool=256,
+               nreq=1024, rate=400.0, eps=1e-3, block=8, prec="f32", alt_prec="bf16", slots=8, pool=1024,
                algo="serving"),
 }
 
@@ -197,15 +200,55 @@ def copy_calibration():
     torch.cuda.synchronize()
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, physical cores of the machine,
+    CPUs this process may use, and the BLAS threads the oracle's calls use."""
+    from threadpoolctl import threadpool_info
+    model, cores = "unknown", set()
+    try:
+        phys = core = None
+        for ln in open("/proc/cpuinfo"):
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model == "unknown":
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None:
+                cores.add((phys, core))
+                phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"cores": int(threads), "cpu_model": model, "physical_cores": len(cores) or None,
+            "cpus_available": len(os.sched_getaffinity(0))}
+
+
+def _time_calls(fn, budget_s, min_calls=3, max_calls=30):
+    """Median seconds per call over whole calls until about budget_s of host work."""
+    import numpy as np
+    times = []
+    while len(times) < min_calls or (sum(times) < budget_s and len(times) < max_calls):
+        t0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times)), len(times)
+
+
 def cpu_baseline(name, X_host, ctx=None):
     """The FP64 oracle, as it stands, on the host cores, over a bounded sample:
     whole calls of the same workload (fixed rank), or for the adaptive workloads
     whole calls on the same recipe at side 24 (1/32 of the entries), whose
     algorithmic flops are read from the library's per-launch log of one device
-    call on that sample."""
+    call on that sample.  Timed with the BLAS threads the host offers and again
+    on one thread."""
     import numpy as np
     import oracle
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_limits
     w = WORKLOADS[name]
     sample = "the same workload, full size"
     if w["algo"] in ("adaptive", "adaptive_hosvd"):
@@ -224,34 +267,35 @@ def cpu_baseline(name, X_host, ctx=None):
         X_host = Xs.cpu().numpy()
         sample = "the same recipe at 24^%d (1/32 of the entries)" % len(dims)
     Xf = np.asarray(X_host, dtype=np.float64)
-    times = []
-    # a bounded sample: whole calls until about 10 s of host work (3 to 30 calls)
-    while len(times) < 3 or (sum(times) < 10.0 and len(times) < 30):
-        t0 = time.perf_counter()
-        if w["algo"] == "rsthosvd":
-            oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))),
-                            q=w.get("q", 0))
-            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), q=w.get("q", 0))
-        elif w["algo"] == "rhosvd":
-            oracle.rhosvd(Xf, list(w["ranks"]), w["p"], w["seed"], q=w.get("q", 0))
-            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo="rhosvd")
-        elif w["algo"] == "sp_sthosvd":
-            oracle.sp_sthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=list(range(len(w["dims"]))))
-            flops = flop_model(w["dims"], w["ranks"], w["p"], range(len(w["dims"])), algo="sp_sthosvd")
-        else:
-            fn = oracle.adaptive_rhosvd if w["algo"] == "adaptive_hosvd" else oracle.adaptive_rsthosvd
-            fn(Xf, w["eps"], w["block"], w["seed"])
-            flops = sample_flops
-        times.append(time.perf_counter() - t0)
-    dt = float(np.median(times))
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{sample}, {len(times)} calls, median {dt:.2f} s per call "
-                      f"(float64 NumPy/LAPACK, explicit Omega generation included)", "seconds_per_call": dt}
+    order = list(range(len(w["dims"])))
+    if w["algo"] == "rsthosvd":
+        call = lambda: oracle.rsthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=order, q=w.get("q", 0))
+        flops = flop_model(w["dims"], w["ranks"], w["p"], order, q=w.get("q", 0))
+    elif w["algo"] == "rhosvd":
+        call = lambda: oracle.rhosvd(Xf, list(w["ranks"]), w["p"], w["seed"], q=w.get("q", 0))
+        flops = flop_model(w["dims"], w["ranks"], w["p"], order, algo="rhosvd")
+    elif w["algo"] == "sp_sthosvd":
+        call = lambda: oracle.sp_sthosvd(Xf, list(w["ranks"]), w["p"], w["seed"], order=order)
+        flops = flop_model(w["dims"], w["ranks"], w["p"], order, algo="sp_sthosvd")
+    else:
+        fn = oracle.adaptive_rhosvd if w["algo"] == "adaptive_hosvd" else oracle.adaptive_rsthosvd
+        call = lambda: fn(Xf, w["eps"], w["block"], w["seed"])
+        flops = sample_flops
+    info = host_info()
+    dt, n = _time_calls(call, 10.0)
+    with threadpool_limits(limits=1):
+        dt1, n1 = _time_calls(call, 8.0, min_calls=1, max_calls=3)
+    return dict(info, value=flops / dt / 1e12, unit="TFLOP/s", kind="oracle",
+                sample=f"{sample}, {n} calls, median {dt:.2f} s per call on {info['cores']} BLAS threads "
+                       f"(float64 NumPy/LAPACK, explicit Omega generation included)",
+                seconds_per_call=dt, one_core={"value": flops / dt1 / 1e12, "seconds_per_call": dt1, "calls": n1})
 
 
-def run_serving(args):
-    """Workload c5: the continuous-batching server against the plain per-tensor path."""
+def serving_measure(with_cpu=False):
+    """The serving half of the metric: the continuous-batching server on 1024
+    adaptive requests against the plain per-tensor float32 path, closed loop
+    (all requests queued at once) and open loop (Poisson arrivals at 400/s),
+    every result checked against a direct fp64 residual <= 1e-3."""
     import numpy as np
     import torch
     from paper_1905_07311_amd import inputs, rtucker
@@ -259,8 +303,8 @@ def run_serving(args):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     arrivals, sides, ranks = inputs.serving_schedule(nreq=w["nreq"], rate=w["rate"])
-    # a pool of distinct tensors drawn from the same shape/rank distribution,
-    # request i uses pool entry i mod pool with its own Omega seed
+    # one distinct tensor per request (drawn on the device, held in page-locked
+    # host memory before the clock starts), each with its own Omega seed
     pool = []
     for i in range(min(w["pool"], w["nreq"])):
         Xd = inputs.lowrank_device(inputs.config_seed(5) * 1000 + i, tuple(sides[i]), tuple(ranks[i]), dev,
@@ -278,10 +322,9 @@ def run_serving(args):
                                               dims=([1], [n])), 0, n)
         return float(torch.linalg.norm((H - Xg).reshape(-1)) / torch.linalg.norm(Xg.reshape(-1)))
 
-    # every path is warmed up on one pass over the distinct tensors (all shapes
-    # seen once, so workspaces and cached device memory are in place), then timed
-    # on all requests
-    warm = reqs[:len(pool)]
+    # every path is warmed up on the first 256 requests (shapes seen once, so
+    # workspaces and cached device memory are in place), then timed on all
+    warm = reqs[:256]
     # plain per-tensor float32 path: one request after another on one stream, host copies included
     ctx = rtucker.Context(0)
     for X, s in warm:
@@ -325,49 +368,66 @@ def run_serving(args):
     t_open = time.perf_counter() - t0
     srv.close()
     # the same server with the other sketch precision
-    srv32 = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec=w["alt_prec"])
-    for t in [srv32.submit(X, s) for X, s in warm]:
-        srv32.wait(t)
+    srv2 = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec=w["alt_prec"])
+    for t in [srv2.submit(X, s) for X, s in warm]:
+        srv2.wait(t)
     t0 = time.perf_counter()
-    tickets = [srv32.submit(X, s) for X, s in reqs]
-    served32 = [srv32.wait(t) for t in tickets]
-    t_srv32 = time.perf_counter() - t0
-    srv32.close()
-    srv32_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, served32))
-    del served32
+    tickets = [srv2.submit(X, s) for X, s in reqs]
+    served2 = [srv2.wait(t) for t in tickets]
+    t_srv2 = time.perf_counter() - t0
+    srv2.close()
+    srv2_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, served2))
+    del served2
     lat = np.array([r.latency_s for r in open_res])
     open_err = max(residual(X, r.core, r.factors) for (X, _), r in zip(reqs, open_res))
-    value = w["nreq"] / t_srv
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "tensors/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(t_srv * 1e3, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "bf16": "bf16+f32"}[w["prec"]], "data": "synthetic",
-        "config": {"workload": w["desc"], "requests": w["nreq"], "slots": w["slots"],
-                   "distinct_tensors": len(pool), "mean_entries": round(nent), "parallelism": "single-gpu"},
+        "workload": w["desc"], "requests": w["nreq"], "slots": w["slots"], "distinct_tensors": len(pool),
+        "mean_entries": round(nent),
+        "served_tensors_per_s": round(w["nreq"] / t_srv, 2),
         "plain_f32_tensors_per_s": round(w["nreq"] / t_plain, 2),
-        "served_%s_sketch_tensors_per_s" % w["alt_prec"]: round(w["nreq"] / t_srv32, 2),
-        "request_status_counts": statuses,
+        "served_%s_sketch_tensors_per_s" % w["alt_prec"]: round(w["nreq"] / t_srv2, 2),
         "speedup_vs_plain": round(t_plain / t_srv, 3),
+        "closed_loop_s": round(t_srv, 4),
+        "request_status_counts": statuses,
         "open_loop": {"rate_per_s": w["rate"], "achieved_per_s": round(w["nreq"] / t_open, 2),
                       "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                      "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+                      "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                      "latency_ms_max": round(float(np.max(lat)) * 1e3, 3)},
         "max_rel_err": {"served_closed": srv_err, "served_open": open_err,
-                        "served_%s_sketch" % w["alt_prec"]: srv32_err,
-                        "plain": plain_err},
-        "roofline": None,
+                        "served_%s_sketch" % w["alt_prec"]: srv2_err, "plain": plain_err},
     }
-    if not args.no_cpu:
+    if with_cpu:
         import oracle
-        from threadpoolctl import threadpool_info
         t0 = time.perf_counter()
         nsamp = 8
         for X, s in reqs[:nsamp]:
             oracle.adaptive_rsthosvd(X.numpy().astype(np.float64), w["eps"], w["block"], s)
         dt = time.perf_counter() - t0
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        out["cpu_baseline"] = {"value": round(nsamp / dt, 3), "unit": "tensors/s", "cores": int(threads),
-                               "kind": "oracle", "sample": f"the first {nsamp} requests, one after another "
-                                                           f"(float64 NumPy/LAPACK), {dt:.2f} s"}
+        out["cpu_baseline"] = dict(host_info(), value=round(nsamp / dt, 3), unit="tensors/s", kind="oracle",
+                                   sample=f"the first {nsamp} requests, one after another (float64 "
+                                          f"NumPy/LAPACK), {dt:.2f} s")
+    return out
+
+
+def run_serving(args):
+    """Workload c5: the continuous-batching server against the plain per-tensor path."""
+    w = WORKLOADS["c5"]
+    sv = serving_measure(with_cpu=not args.no_cpu)
+    out = {
+        "metric": METRIC, "value": sv["served_tensors_per_s"], "unit": "tensors/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(sv["closed_loop_s"] * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "bf16": "bf16+f32"}[w["prec"]],
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "requests": w["nreq"], "slots": w["slots"],
+                   "distinct_tensors": sv["distinct_tensors"], "mean_entries": sv["mean_entries"],
+                   "parallelism": "single-gpu"},
+        "roofline": None,
+    }
+    for k in ("plain_f32_tensors_per_s", "served_%s_sketch_tensors_per_s" % w["alt_prec"], "request_status_counts",
+              "speedup_vs_plain", "open_loop", "max_rel_err"):
+        out[k] = sv[k]
+    if "cpu_baseline" in sv:
+        out["cpu_baseline"] = sv["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 
@@ -378,6 +438,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave the serving measurement out of the default workload's line")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for the HBM counter passes)")
     args = ap.parse_args()
@@ -403,20 +465,28 @@ def main():
     # timed steps: HIP events on the library's stream bracket the sketch launches only
     # (the dominant kernel of the roofline), so the other launches run back to back
     ctx.timing(True, kinds=["sketch"])
-    lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s0 = time.perf_counter()
-        res = run_step(ctx, args.workload, X)     # returns after its stream work is done
-        lat.append(time.perf_counter() - s0)
+        # fixed-rank calls return once enqueued (the adaptive ones after their
+        # stream work), so consecutive steps overlap host and device work
+        res = run_step(ctx, args.workload, X)
+    ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log = ctx.timing_log()
+    # per-step latency: each call followed by rt_sync (result and scalars ready)
+    lat = []
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        run_step(ctx, args.workload, X)
+        ctx.sync()
+        lat.append(time.perf_counter() - s0)
     # a few more steps with every launch kind bracketed, for the per-kind breakdown
     ctx.timing(True)
     for _ in range(min(3, args.steps)):
         run_step(ctx, args.workload, X)
+    ctx.sync()
     torch.cuda.synchronize()
     log_all = ctx.timing_log()
     ctx.timing(False)
@@ -441,9 +511,7 @@ def main():
     if variant == 3:
         mfrac, mdesc = 6.0 * tfl / BF16_MFMA_PEAK, "bf16 MFMA, 6 piece products per fp32 product"
     elif variant == 4:
-        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA (16x16x32)"
-    elif variant == 2:
-        mfrac, mdesc = tfl / BF16_MFMA_PEAK, "bf16 MFMA (4x4x4)"
+        mfrac, mdesc = 3.0 * tfl / BF16_MFMA_PEAK, "bf16 MFMA, 3 piece products per product"
     elif variant == 1:
         mfrac, mdesc = tfl / mpeak, "fp32 MFMA"
     else:
@@ -495,6 +563,13 @@ def main():
         copy_calibration()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, X.cpu().numpy(), ctx)
+    if args.workload == "c2" and not args.no_serving:
+        # the serving half of the metric (tensors/s beside the plain path, p50/p99
+        # latency, 1e-3 residuals), measured in the same run
+        del X, Xh, res
+        ctx.close()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_measure()
     print(json.dumps(out), flush=True)
 
 

@@ -25,8 +25,16 @@
  *    see the same Omega.
  *  - Pointers are device pointers unless marked "host".  The caller keeps
  *    ownership of every input; the library never writes an input tensor.
- *  - Work is enqueued on the context's stream.  The decomposition calls return
- *    after the stream has finished their work (their scalar results need it).
+ *  - Work is enqueued on the context's stream.  The fixed-rank decompositions
+ *    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd) and rt_reconstruct are
+ *    asynchronous: they return once their work is enqueued, with the ranks and
+ *    the core and factor buffers of the result set; the contents of those
+ *    buffers are valid once the stream reaches that point, and the scalars
+ *    (norm_x, core_norm, rel_err_est, flags) are filled in by the next rt_sync
+ *    on the context (NaN until then), which also returns deferred device
+ *    status.  The caller keeps the rt_tucker struct alive until that rt_sync.
+ *    The adaptive calls choose ranks on the host from device results, so they
+ *    return after the stream has finished their work, with every field set.
  *  - Errors: argument errors return RT_EINVAL before anything is enqueued;
  *    HIP failures return RT_EHIP; rt_last_error() gives a message (thread-local,
  *    valid until the next call on the same thread).
@@ -56,12 +64,19 @@ typedef enum { RT_F32 = 0, RT_F64 = 1 } rt_dtype;
  *  RT_PREC_F64: float64 input, every step in float64.
  *  RT_PREC_F32: float32 input; sketch and projections in float32 with float32
  *               accumulation; Gram matrices, Cholesky, eigenproblems in float64.
- *  RT_PREC_BF16_SKETCH: as RT_PREC_F32 but the sketch multiplies bfloat16-rounded
- *               X and Omega (float32 accumulation); orth, projection and
- *               truncation stay float32/float64.  In the adaptive call a
- *               block keeps only directions above 1e-2 of its norm (the
- *               bfloat16 noise lies below), and once a bfloat16 block adds no
- *               direction the mode continues with float32 sketches. */
+ *  RT_PREC_BF16_SKETCH: as RT_PREC_F32 but the sketch runs in bfloat16 on the
+ *               matrix cores (float32 accumulation): each float32 operand of
+ *               X and Omega is split into two bfloat16 pieces by truncation,
+ *               x = h + m + (|remainder| < 2^-15 |x|), and the three piece
+ *               products of weight above 2^-16 (hh, hm, mh) are summed, a
+ *               relative accuracy near 2^-15 (bf16x3 of Henry, Tang and
+ *               Heinecke, ARITH 2019), enough that the sketch's rounding stays
+ *               below the tail a randomized range finder leaves.  Modes the
+ *               16x16x32 kernel does not serve (J <= 64, R % 8 != 0) take the
+ *               float32 sketch.  Orth, projection and truncation stay
+ *               float32/float64.  In the adaptive call a bfloat16 block keeps
+ *               directions above 1e-4 of its norm, and once such a block adds
+ *               no direction the mode continues with float32 sketches. */
 typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_precision;
 
 #define RT_MAXD 8
@@ -72,6 +87,7 @@ typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_pr
 #define RT_FLAG_PADDED 1u    /* some sketch was numerically rank deficient; its basis
                                 was completed with zero-weight orthonormal columns */
 #define RT_FLAG_FALLBACK 2u  /* orth used the Householder fallback instead of CholeskyQR2 */
+#define RT_FLAG_NONFINITE 4u /* the input held NaN or Inf (the result is not meaningful) */
 
 typedef struct rt_ctx rt_ctx;
 
@@ -119,7 +135,12 @@ typedef struct {
                                    columns; NULL for an uncompressed mode */
     double norm_x;              /* ||X||_F (fp64 accumulation) */
     double core_norm;           /* ||G||_F */
-    double rel_err_est;         /* sqrt(max(0, ||X||^2 - ||G||^2)) / ||X|| */
+    double rel_err_est;         /* sqrt(max(0, ||X||^2 - ||G||^2)) / ||X|| (the identity
+                                   of orthonormal factors; -1 for rt_sp_sthosvd).  For
+                                   float32 data ||G||^2 carries the core's float32
+                                   rounding, a few 1e-7 of ||X||^2, so estimates below
+                                   about 1e-3 are not resolved and may read 0; a direct
+                                   residual decides there */
     uint32_t flags;             /* RT_FLAG_* */
 } rt_tucker;
 
@@ -181,7 +202,8 @@ rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, cons
 rt_status rt_rhosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
                              int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out);
 
-/* Release the core and factors of a result produced by this context. */
+/* Release the core and factors of a result produced by this context (waits for
+ * the stream; a result not yet filled by rt_sync is dropped from it). */
 rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t);
 
 /* ---- hot-path steps, exposed for testing --------------------------------------- */
@@ -193,8 +215,8 @@ rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t);
  * mode kept whole, whose rank must equal its dimension, or of rank 0; norms and
  * flags are ignored; a rank 0 gives a zero result).  out: device buffer of dims[0] x ... x dims[d-1] elements of
  * t->dtype, written in full (row-major).  Float data runs on the MFMA projection
- * kernels with the factor transposed, float64 on the fp64 kernels.  Returns after
- * the stream has finished. */
+ * kernels with the factor transposed, float64 on the fp64 kernels.  Asynchronous:
+ * `out` is complete once the stream reaches this point. */
 rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out);
 
 /* Y = X_(mode) Omega_mode[:, col0 : col0 + ell] (Alg. 1 step 1) for a row-major
@@ -268,19 +290,20 @@ rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, dou
 
 /* Kernel variant of entry i of the timing log (host output).  For sketches:
  * RT_SKETCH_GENERIC (LDS-staged vector ALU), RT_SKETCH_MFMA_F32 (float32
- * MFMA), RT_SKETCH_MFMA_BF16 (products of bfloat16-rounded operands),
- * RT_SKETCH_SPLIT_BF16 (float32 products formed from three bfloat16 pieces per
- * operand, six piece products on the bfloat16 MFMA, float32 accuracy),
- * RT_SKETCH_BF16_16X16 (the products of bfloat16-rounded operands on the
- * 16x16x32 bfloat16 MFMA); 0 for the other kinds. */
+ * MFMA), RT_SKETCH_SPLIT_BF16 (float32 products formed from three bfloat16
+ * pieces per operand, six piece products on the 16x16x32 bfloat16 MFMA, float32
+ * accuracy), RT_SKETCH_BF16X3 (the bfloat16 sketch: two bfloat16 pieces per
+ * operand, three piece products on the same MFMA); 0 for the other kinds. */
 #define RT_SKETCH_GENERIC 0
 #define RT_SKETCH_MFMA_F32 1
-#define RT_SKETCH_MFMA_BF16 2
 #define RT_SKETCH_SPLIT_BF16 3
-#define RT_SKETCH_BF16_16X16 4
+#define RT_SKETCH_BF16X3 4
 rt_status rt_timing_variant(rt_ctx* ctx, int64_t i, int32_t* variant);
 
-/* Block until the context's stream is idle. */
+/* Block until the context's stream is idle, then fill the scalars of every
+ * result of an asynchronous call made since the last rt_sync.  Returns
+ * RT_ENONFINITE if the input of any of them held NaN or Inf (that result's
+ * flags carry RT_FLAG_NONFINITE), RT_EHIP if the stream failed, else RT_OK. */
 rt_status rt_sync(rt_ctx* ctx);
 
 /* ---- serving: continuous batching of many requests --------------------------- */

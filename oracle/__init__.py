@@ -15,20 +15,20 @@ in its module header; none is "parity unpinned" except where stated.
 
 from .philox import philox4x32_10, omega_block, omega, PHILOX_M0, PHILOX_M1, PHILOX_W0, PHILOX_W1
 from .tensor import unfold, fold, ttm, reconstruct, fro2
-from .randsvd import randsvd, orth_householder, sign_fix_columns
+from .randsvd import randsvd, range_basis, qb_truncate, orth_householder, sign_fix_columns
 from .tucker import (rhosvd, rsthosvd, hosvd, sthosvd, default_order, TuckerResult,
                      per_mode_residuals)
 from .adaptive import adapt_range_finder, adaptive_rsthosvd, adaptive_rhosvd
-from .precision import round_bf16
+from .precision import split_bf16, sketch_bf16x3
 from .structure import pivoted_rows, select_rows, sp_sthosvd
 
 __all__ = [
     "philox4x32_10", "omega_block", "omega", "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
     "unfold", "fold", "ttm", "reconstruct", "fro2",
-    "randsvd", "orth_householder", "sign_fix_columns",
+    "randsvd", "range_basis", "qb_truncate", "orth_householder", "sign_fix_columns",
     "rhosvd", "rsthosvd", "hosvd", "sthosvd", "default_order", "TuckerResult",
     "per_mode_residuals",
     "adapt_range_finder", "adaptive_rsthosvd", "adaptive_rhosvd",
     "pivoted_rows", "select_rows", "sp_sthosvd",
-    "round_bf16",
+    "split_bf16", "sketch_bf16x3",
 ]

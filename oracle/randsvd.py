@@ -1,27 +1,29 @@
-"""Randomized SVD, Alg. 1 (§2.4), oracle side.
+"""Randomized SVD of a matrix, oracle side (Alg. 1, §2.4).
 
-RandSVD(X, r, p, Omega):
-  1. Y = X Omega
-  2. thin QR  Y = Q R                      (Householder, LAPACK)
-  3. B = Q^T X
-  4. thin SVD B = U_B S V^T
-  5. U_hat = Q U_B(:, 1:r)
-  6. S_hat = S(1:r, 1:r), V_hat = V(:, 1:r)
+The method finds an orthonormal basis Q for the range of a Gaussian sketch of
+the matrix (X times an n x (r + p) Gaussian matrix Omega, p extra columns of
+oversampling), projects the matrix onto that basis (B = Q^T X), takes the thin
+SVD of the small matrix B, and keeps its r leading singular triplets, the left
+ones mapped back through Q.  This file writes that as two helpers,
+range_basis (sketch and orthonormalisation) and qb_truncate (projection and
+truncation), joined by randsvd.
 
 Readings where the paper is silent:
 * QR signs: columns of Q are flipped so that diag(R) >= 0 (then the thin QR of
   a full-rank Y is unique).
-* SVD signs: each column of U_hat is flipped so that its entry of largest
-  magnitude (lowest index on ties) is positive, and V_hat gets the same flip.
-  With tied singular values several bases are correct; tests therefore compare
-  projectors and reconstructions, not raw factors.
-
-Randomized subspace iteration (q >= 1): the range-finding variant the paper
-names in its remarks on range finding (§5 variants, citing Halko, Martinsson and
-Tropp) and applies, one step, to the Olivetti pixels (§6).  Reading: the
-re-orthonormalised form, q times Q <- orth(X orth(X^T Q)) after step 2, whose
-range equals that of (X X^T)^q X Omega in exact arithmetic while rounding does
-not wash out the small directions.
+* SVD signs: each column of the left factor is flipped so that its entry of
+  largest magnitude (lowest index on ties) is positive, and the right factor
+  gets the same flip.  With tied singular values several bases are correct;
+  tests therefore compare projectors and reconstructions, not raw factors.
+* Randomized subspace iteration (q >= 1): the range-finding variant the paper
+  names in its remarks on range finding (§5 variants, citing Halko, Martinsson
+  and Tropp) and applies, one step, to the Olivetti pixels (§6).  Reading: the
+  re-orthonormalised form, q times Q <- orth(X orth(X^T Q)) after the first
+  basis, whose range equals that of (X X^T)^q X Omega in exact arithmetic while
+  rounding does not wash out the small directions.
+* A reduced-precision sketch (the library's bfloat16 sketch) is modelled by
+  passing the product that forms the sketch (oracle.sketch_bf16x3); everything
+  after the sketch stays float64.
 
 Pinned by tests/test_oracle_randsvd.py: with r + p equal to the number of rows
 Q is square orthogonal and the result equals LAPACK's truncated SVD; on an
@@ -57,26 +59,32 @@ def orth_householder(Y):
     return Q * s, R * s[:, None]
 
 
-def randsvd(X, r, p, Omega, sketch_round=None, q=0):
-    """Alg. 1.  X: (m, n) matrix, Omega: (n, r + p).  Returns (U, S, V, Q).
-    sketch_round: optional rounding applied to both operands of step 1 only
-    (the reduced-precision sketch variant).  q: steps of subspace iteration
-    after step 2 (see above)."""
+def range_basis(X, Omega, sketch=None, q=0):
+    """Orthonormal basis of the range of the sketch X Omega (formed by `sketch`
+    when given), refined by q steps of subspace iteration."""
+    Y = X @ Omega if sketch is None else sketch(X, Omega)
+    Q, _ = orth_householder(Y)
+    for _ in range(q):
+        Qt, _ = orth_householder(X.T @ Q)
+        Q, _ = orth_householder(X @ Qt)
+    return Q
+
+
+def qb_truncate(Q, X, r):
+    """Rank-r truncation of X within range(Q): the thin SVD of B = Q^T X, its
+    leading r left singular vectors mapped back by Q.  Returns (U, S, V)."""
+    UB, s, Vt = np.linalg.svd(Q.T @ X, full_matrices=False)
+    U, V = sign_fix_columns(Q @ UB[:, :r], Vt[:r].T)
+    return U, s[:r], V
+
+
+def randsvd(X, r, p, Omega, sketch=None, q=0):
+    """Alg. 1 on the matrix X (m x n) with the Gaussian Omega (n x (r + p)).
+    Returns (U, S, V, Q).  sketch: optional product forming the sketch (the
+    reduced-precision variant); q: steps of subspace iteration."""
     X = np.asarray(X, dtype=np.float64)
     Omega = np.asarray(Omega, dtype=np.float64)
     assert Omega.shape == (X.shape[1], r + p)
-    if sketch_round is None:
-        Y = X @ Omega                   # step 1
-    else:
-        Y = sketch_round(X) @ sketch_round(Omega)
-    Q, _ = orth_householder(Y)          # step 2
-    for _ in range(q):                  # subspace iteration
-        Qt, _ = orth_householder(X.T @ Q)
-        Q, _ = orth_householder(X @ Qt)
-    B = Q.T @ X                         # step 3
-    UB, s, Vt = np.linalg.svd(B, full_matrices=False)   # step 4
-    U = Q @ UB[:, :r]                   # step 5
-    S = s[:r]                           # step 6
-    V = Vt[:r].T
-    U, V = sign_fix_columns(U, V)
+    Q = range_basis(X, Omega, sketch, q)
+    U, S, V = qb_truncate(Q, X, r)
     return U, S, V, Q

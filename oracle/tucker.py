@@ -84,32 +84,44 @@ def check_ranks(shape, ranks, p):
             raise ValueError(f"mode {j}: r + p = {r + p} exceeds min(I_j, prod_(i!=j) I_i)")
 
 
-def rhosvd(X, ranks, p, seed, sketch_round=None, q=0):
-    """Alg. 2 with Omega_j from the counter stream (seed, mode j).  sketch_round,
-    q (subspace iteration steps): see randsvd."""
-    X = np.asarray(X, dtype=np.float64)
-    check_ranks(X.shape, ranks, p)
-    factors = []
-    for j in range(X.ndim):
-        if _keep(ranks[j]):
-            factors.append(None)
-            continue
-        M = unfold(X, j)
-        Om = omega(seed, j, M.shape[1], ranks[j] + p)      # Alg. 2, draw Omega_j
-        U, _, _, _ = randsvd(M, ranks[j], p, Om, sketch_round, q)   # Alg. 2, RandSVD
-        factors.append(U)                                   # A_j = U_hat
+def _mode_randsvd(G, n, r, p, seed, sketch, q):
+    """Alg. 1 on the mode-n unfolding of G with Omega_n from the counter stream
+    (seed, mode n): returns (U, S, V)."""
+    M = unfold(G, n)
+    U, S, V, _ = randsvd(M, r, p, omega(seed, n, M.shape[1], r + p), sketch, q)
+    return U, S, V
+
+
+def _project_all(X, factors):
+    """X x_1 A_1^T ... x_d A_d^T over the modes that have a factor."""
     G = X
-    for j, A in enumerate(factors):                         # G = X x_j A_j^T
+    for j, A in enumerate(factors):
         if A is not None:
             G = ttm(G, A.T, j)
-    return TuckerResult(core=G, factors=factors,
-                        ranks=[X.shape[j] if A is None else A.shape[1] for j, A in enumerate(factors)],
+    return G
+
+
+def _ranks_of(shape, factors):
+    return [shape[j] if A is None else A.shape[1] for j, A in enumerate(factors)]
+
+
+def rhosvd(X, ranks, p, seed, sketch=None, q=0):
+    """R-HOSVD (Alg. 2): every mode's factor from the randomized SVD of X's own
+    unfolding, then the core is X projected on all factors.  sketch, q: see
+    randsvd."""
+    X = np.asarray(X, dtype=np.float64)
+    check_ranks(X.shape, ranks, p)
+    factors = [None if _keep(ranks[j]) else _mode_randsvd(X, j, ranks[j], p, seed, sketch, q)[0]
+               for j in range(X.ndim)]
+    return TuckerResult(core=_project_all(X, factors), factors=factors, ranks=_ranks_of(X.shape, factors),
                         norm_x=float(np.sqrt(fro2(X))), order=list(range(X.ndim)))
 
 
-def rsthosvd(X, ranks, p, seed, order=None, sketch_round=None, q=0):
-    """Alg. 3 with Omega_{rho_j} from the counter stream (seed, mode rho_j).
-    sketch_round, q (subspace iteration steps): see randsvd."""
+def rsthosvd(X, ranks, p, seed, order=None, sketch=None, q=0):
+    """R-STHOSVD (Alg. 3): modes in the processing order; each one's factor from
+    the randomized SVD of the current core's unfolding, whose truncated right
+    part S V^T (equal to U^T G_(n)) becomes the next core.  sketch, q: see
+    randsvd."""
     X = np.asarray(X, dtype=np.float64)
     check_ranks(X.shape, ranks, p)
     order = default_order(X.shape) if order is None else list(order)
@@ -119,16 +131,13 @@ def rsthosvd(X, ranks, p, seed, order=None, sketch_round=None, q=0):
     for n in order:
         if _keep(ranks[n]):
             continue
-        M = unfold(G, n)
-        Om = omega(seed, n, M.shape[1], ranks[n] + p)       # Alg. 3, draw Omega
-        U, S, V, _ = randsvd(M, ranks[n], p, Om, sketch_round, q)   # Alg. 3, RandSVD
-        factors[n] = U                                      # A = U_hat
+        U, S, V = _mode_randsvd(G, n, ranks[n], p, seed, sketch, q)
+        factors[n] = U
         shape = list(G.shape)
         shape[n] = U.shape[1]
-        G = fold(S[:, None] * V.T, n, shape)                # G_(n) <- S_hat V_hat^T
+        G = fold(S[:, None] * V.T, n, shape)
         norms.append(fro2(G))
-    ranks_out = [X.shape[j] if factors[j] is None else factors[j].shape[1] for j in range(X.ndim)]
-    return TuckerResult(core=G, factors=factors, ranks=ranks_out,
+    return TuckerResult(core=G, factors=factors, ranks=_ranks_of(X.shape, factors),
                         norm_x=float(np.sqrt(fro2(X))), order=order, step_core_norm2=norms)
 
 

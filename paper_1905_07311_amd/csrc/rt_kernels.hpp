@@ -28,9 +28,9 @@ struct SketchPlan {
     int64_t tiles_per_split;
     size_t partial_elems;  // nsplit * J * ldp
     int nwg;               // nsplit * nrowtile
-    int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32, 2 MFMA bfloat16,
-                           // 3 float32-accurate from bfloat16 pieces (16x16x32 MFMA),
-                           // 4 bfloat16-rounded operands on the same kernel (one product)
+    int kind;              // kernel variant: 0 generic (LDS-staged VALU), 1 MFMA float32,
+                           // 3 float32-accurate from three bfloat16 pieces (16x16x32 MFMA, six products),
+                           // 4 the bfloat16 sketch: two bfloat16 pieces, three products, same kernel
     int rb;                // MFMA variant: 64-row blocks per wave (1, 2 or 4); kind 3: 16-row blocks
     int rw;                // MFMA variant: row blocks per workgroup (1 or 2)
     int nq;                // MFMA variant: compiled column quads (ell <= 4 nq); kind 3: 16-column blocks
@@ -158,18 +158,14 @@ hipError_t launch_sketch_f32_rows(const SketchPlan& p, const float* X, Shape3 s,
                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 hipError_t launch_sketch_f32_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
-hipError_t launch_sketch_bf16_rows(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
-                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
-hipError_t launch_sketch_bf16_cols(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0,
-                                   uint64_t seed, uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 // kind 3: each float32 operand split into three bfloat16 pieces, six piece
 // products per product on v_mfma_f32_16x16x32_bf16 (float32 accuracy); needs
 // J > 64, 1 <= ell <= 64, col0 % 4 == 0, R % 8 == 0, 16-byte aligned X of at most
-// 0x7fff0000 bytes.  Partials have ldp = ell.  bf16_rounded (kind 4): X and
-// Omega rounded to the nearest bfloat16, one product per block (the bfloat16
-// sketch).
+// 0x7fff0000 bytes.  Partials have ldp = ell.  bf16 (kind 4): the bfloat16
+// sketch, two truncated bfloat16 pieces per operand and the three products of
+// weight above 2^-16 (hh, hm, mh), relative accuracy about 2^-15.
 bool sketch_x6_ok(Shape3 s, int ell, int64_t col0, const void* X);
-void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16_rounded);
+void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16);
 hipError_t launch_sketch_f32_x6(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed,
                                 uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 // explicit Omega from Om ((L, ell, R) float tensor, 16-byte aligned); needs R % 4 == 0

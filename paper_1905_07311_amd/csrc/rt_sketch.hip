@@ -19,18 +19,10 @@ constexpr int SK_MT = 64;     // rows per tile
 constexpr int SK_KC = 64;     // unfolding columns per tile
 constexpr int SK_NACC = LMAX / 4;
 
-// float -> nearest bfloat16 value (ties to even), as a float
-__device__ __forceinline__ float round_bf16(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-}
-
-// BFR: X and Omega are rounded to bfloat16 before the products (float32 data).
 // EXPL: Omega is not generated but read from Om, an (L, ell, R) row-major tensor
 // with Omega[l R + r][k] = Om[(l ell + k) R + r] (the subspace-iteration product
 // Y = X_(n) Z with Z = Om_(n)^T); seed, mode and col0 are unused.
-template <typename TX, typename TA, bool BFR, bool EXPL = false>
+template <typename TX, typename TA, bool EXPL = false>
 __global__ __launch_bounds__(256) void sketch_generic_kernel(
     const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
     uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
@@ -72,7 +64,6 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
                 const int64_t r = c - l * R;
                 v = (TA)X[(l * J + i) * R + r];
                 if (nrm2_partial) nrm += (double)v * (double)v;
-                if (BFR) v = (TA)round_bf16((float)v);
             }
             xs[cl][rl] = v;
         }
@@ -98,7 +89,7 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
                 const int64_t k = 4 * q + tt - col0;
-                if (k >= 0 && k < ell) om[cl][k] = BFR ? (TA)round_bf16((float)z[tt]) : z[tt];
+                if (k >= 0 && k < ell) om[cl][k] = z[tt];
             }
         }
         __syncthreads();
@@ -215,8 +206,10 @@ SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const v
         plan_sketch_x6(p, s, ell, prec == 2);
         return p;
     }
+    // the bfloat16 sketch exists on the 16x16x32 kernel only; other modes take
+    // the float32 sketch (at least as accurate)
     if (dt == Dt::F32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X)) {
-        p.kind = prec == 2 ? 2 : 1;
+        p.kind = 1;
         sketch_rows_config(s.J, p.rb, p.rw);
         p.nq = sketch_nq_bucket((ell + 3) / 4);
         p.ldp = 4 * p.nq;
@@ -254,29 +247,21 @@ hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Sh
     if (p.kind == 3 || p.kind == 4)
         return launch_sketch_f32_x6(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
                                     stream);
-    if (p.kind == 1 || p.kind == 2) {
-        const bool bf = p.kind == 2;
+    (void)prec;
+    if (p.kind == 1) {
         if (s.R % 4 == 0)
-            return (bf ? launch_sketch_bf16_rows : launch_sketch_f32_rows)(p, (const float*)X, s, ell, col0, seed,
-                                                                         mode, (float*)partial, nrm2_partial, stream);
-        return (bf ? launch_sketch_bf16_cols : launch_sketch_f32_cols)(p, (const float*)X, s, ell, col0, seed, mode,
-                                                                     (float*)partial, nrm2_partial, stream);
+            return launch_sketch_f32_rows(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
+                                          stream);
+        return launch_sketch_f32_cols(p, (const float*)X, s, ell, col0, seed, mode, (float*)partial, nrm2_partial,
+                                      stream);
     }
     dim3 grid(p.nsplit, p.nrowtile);
-    if (dt == Dt::F64) {
-        hipLaunchKernelGGL((sketch_generic_kernel<double, double, false>), grid, dim3(256), 0, stream,
-                           (const double*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
-                           (double*)partial, nrm2_partial);
-    } else {
-        if (prec == 2)
-            hipLaunchKernelGGL((sketch_generic_kernel<float, float, true>), grid, dim3(256), 0, stream,
-                               (const float*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
-                               (float*)partial, nrm2_partial);
-        else
-            hipLaunchKernelGGL((sketch_generic_kernel<float, float, false>), grid, dim3(256), 0, stream,
-                               (const float*)X, s.L, s.J, s.R, ell, col0, seed, mode, p.tiles_per_split,
-                               (float*)partial, nrm2_partial);
-    }
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL((sketch_generic_kernel<double, double>), grid, dim3(256), 0, stream, (const double*)X, s.L,
+                           s.J, s.R, ell, col0, seed, mode, p.tiles_per_split, (double*)partial, nrm2_partial);
+    else
+        hipLaunchKernelGGL((sketch_generic_kernel<float, float>), grid, dim3(256), 0, stream, (const float*)X, s.L,
+                           s.J, s.R, ell, col0, seed, mode, p.tiles_per_split, (float*)partial, nrm2_partial);
     return hipGetLastError();
 }
 
@@ -289,11 +274,11 @@ hipError_t launch_sketch_explicit(const SketchPlan& p, Dt dt, const void* X, Sha
     if (p.kind != 0) return hipErrorInvalidValue;
     dim3 grid(p.nsplit, p.nrowtile);
     if (dt == Dt::F64)
-        hipLaunchKernelGGL((sketch_generic_kernel<double, double, false, true>), grid, dim3(256), 0, stream,
+        hipLaunchKernelGGL((sketch_generic_kernel<double, double, true>), grid, dim3(256), 0, stream,
                            (const double*)X, s.L, s.J, s.R, ell, (int64_t)0, (uint64_t)0, 0u, p.tiles_per_split,
                            (double*)partial, (double*)nullptr, (const double*)Om);
     else
-        hipLaunchKernelGGL((sketch_generic_kernel<float, float, false, true>), grid, dim3(256), 0, stream,
+        hipLaunchKernelGGL((sketch_generic_kernel<float, float, true>), grid, dim3(256), 0, stream,
                            (const float*)X, s.L, s.J, s.R, ell, (int64_t)0, (uint64_t)0, 0u, p.tiles_per_split,
                            (float*)partial, (double*)nullptr, (const float*)Om);
     return hipGetLastError();

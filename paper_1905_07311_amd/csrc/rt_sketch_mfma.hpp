@@ -48,21 +48,6 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
-// v_mfma_f32_4x4x4_16b_bf16: the same sixteen 4x4 blocks with a k-depth of 4;
-// lane 4 blk + i supplies A_blk[i][0..3] and B_blk[0..3][i] (checked on the
-// device), so a lane's A operand is four consecutive unfolding columns of its
-// row and its B operand the same four rows of one Omega column.
-__device__ __forceinline__ f4 mfma4_bf16(s4 a, s4 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
-}
-
-// float -> bfloat16, round to nearest even (infinities and NaNs stay such)
-__device__ __forceinline__ short bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
 template <int RB, int RW, int LOADER>
 struct TileShape {
     static constexpr int CW = 4 / RW;                      // waves per row block
@@ -74,31 +59,27 @@ struct TileShape {
 };
 
 // X viewed as (L, J, R) row-major; unfolding column c = l R + r.
-// BF: the products are formed in bfloat16 (X and Omega rounded to nearest) with
-// float32 accumulation; otherwise in float32.
 // LOAD_ROWS needs R % 4 == 0 (four columns of a load lie in one l-slab); LOAD_COLS needs
 // R == 1 and J % 4 == 0.  16-byte alignment of X; ell <= 4 NQ <= 64; the
 // Omega blocks of columns [col0, col0 + ell) number at most 16.
 // EXPL (LOAD_ROWS, float32 only): Omega is read from Om, an (L, ell, R) tensor with
 // Omega[l R + r][k] = Om[(l ell + k) R + r] (the subspace-iteration product
 // Y = X_(n) Z, Z = Om_(n)^T), instead of generated; seed, mode and col0 unused.
-template <int RB, int RW, int NQ, int LOADER, bool BF, bool EXPL = false>
+template <int RB, int RW, int NQ, int LOADER, bool EXPL = false>
 __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict__ X, int64_t L, int64_t J,
                                                          int64_t R, int ell, int64_t col0, uint64_t seed,
                                                          uint32_t mode, int64_t tiles_per_split,
                                                          float* __restrict__ partial,
                                                          double* __restrict__ nrm2_partial,
                                                          const float* __restrict__ Om = nullptr) {
-    static_assert(!EXPL || (LOADER == LOAD_ROWS && !BF), "explicit Omega: float32 rows loader only");
+    static_assert(!EXPL || LOADER == LOAD_ROWS, "explicit Omega: rows loader only");
     typedef TileShape<RB, RW, LOADER> S;
     constexpr int CW = S::CW, MT = S::MT, NLOAD = S::NLOAD, TLD = S::TLD, JC = S::JC;
     constexpr int NQP = (NQ + 3) / 4 * 4;  // Omega row length in LDS (16-byte reads)
-    constexpr int NQB = (NQ + 1) / 2 * 2;  // bfloat16 layout: quads per (column group, t), 16-byte reads
     constexpr int LDP = 4 * NQ;            // partial row length
     __shared__ __align__(16) float xs[S::XSZ];
-    // Omega tile: float32 [c][t][j] = Omega[c][4 j + t]; bfloat16 [c / 4][t][j][c % 4]; + sink
+    // Omega tile: [c][t][j] = Omega[c][4 j + t], then a sink
     __shared__ __align__(16) float os[KC * 4 * NQP + 4];
-    unsigned short* osb = reinterpret_cast<unsigned short*>(os);
     __shared__ double red[4];
     static_assert(4 * 64 * RB * JC * 4 <= S::XSZ, "epilogue buffer exceeds the tile");
 
@@ -253,11 +234,7 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
                 for (int u = 0; u < 4; ++u) {
                     const int k = 4 * qi + u - shift;
                     const bool in = k >= 0 && k < ell;
-                    if (BF)
-                        osb[in ? (((cc >> 2) * 4 + (k & 3)) * NQB + (k >> 2)) * 4 + (cc & 3) : 2 * KC * 4 * NQP] =
-                            (unsigned short)bf16_rne(opre[4 * h + u]);
-                    else
-                        os[in ? (cc * 4 + (k & 3)) * NQP + (k >> 2) : KC * 4 * NQP] = opre[4 * h + u];
+                    os[in ? (cc * 4 + (k & 3)) * NQP + (k >> 2) : KC * 4 * NQP] = opre[4 * h + u];
                 }
             }
         }
@@ -293,38 +270,19 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float* __restrict
                     for (int u = 0; u < 4; ++u) a[rb][u] = xs[(c4 + u) * TLD + row];
                 }
             }
-            if (BF) {
-                s4 ab[RB];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-                    ab[rb] = s4{bf16_rne(a[rb][0]), bf16_rne(a[rb][1]), bf16_rne(a[rb][2]), bf16_rne(a[rb][3])};
-                const unsigned short* orow = &osb[((c4 >> 2) * 4 + t) * NQB * 4];
+            for (int u = 0; u < 4; ++u) {
+                const float* orow = &os[((c4 + u) * 4 + t) * NQP];
+                float bv[NQP];
 #pragma unroll
-                for (int j2 = 0; j2 < NQB; j2 += 2) {
-                    typedef short s8 __attribute__((ext_vector_type(8)));
-                    const s8 v = *reinterpret_cast<const s8*>(orow + 4 * j2);
-                    const s4 b0 = s4{v[0], v[1], v[2], v[3]}, b1 = s4{v[4], v[5], v[6], v[7]};
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) {
-                        acc[rb][j2] = mfma4_bf16(ab[rb], b0, acc[rb][j2]);
-                        if (j2 + 1 < NQ) acc[rb][j2 + 1] = mfma4_bf16(ab[rb], b1, acc[rb][j2 + 1]);
-                    }
+                for (int j4 = 0; j4 < NQP; j4 += 4) {
+                    const f4 v = *reinterpret_cast<const f4*>(orow + j4);
+                    bv[j4] = v.x; bv[j4 + 1] = v.y; bv[j4 + 2] = v.z; bv[j4 + 3] = v.w;
                 }
-            } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float* orow = &os[((c4 + u) * 4 + t) * NQP];
-                    float bv[NQP];
+                for (int j = 0; j < NQ; ++j)
 #pragma unroll
-                    for (int j4 = 0; j4 < NQP; j4 += 4) {
-                        const f4 v = *reinterpret_cast<const f4*>(orow + j4);
-                        bv[j4] = v.x; bv[j4 + 1] = v.y; bv[j4 + 2] = v.z; bv[j4 + 3] = v.w;
-                    }
-#pragma unroll
-                    for (int j = 0; j < NQ; ++j)
-#pragma unroll
-                        for (int rb = 0; rb < RB; ++rb) acc[rb][j] = mfma4(a[rb][u], bv[j], acc[rb][j]);
-                }
+                    for (int rb = 0; rb < RB; ++rb) acc[rb][j] = mfma4(a[rb][u], bv[j], acc[rb][j]);
             }
             // Omega of the next tile, spread over the first two column groups
             if (more && m < 2) gen_omega(tile + 1, m);

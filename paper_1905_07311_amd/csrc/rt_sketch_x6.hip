@@ -1,6 +1,6 @@
 // Sketch Y = X_(n) Omega (§2.4 Alg. 1 step 1; Alg. 3 step 4) of float32 data on
 // the bfloat16 matrix cores: at float32 accuracy (NP = 3), or as the bfloat16
-// sketch with X and Omega rounded to the nearest bfloat16 (NP = 1).
+// sketch (NP = 2).
 //
 // NP = 3: every float32 operand is split exactly into three bfloat16 pieces,
 // x = h + m + l: h keeps the top 8 significant bits of x (truncation), m the top
@@ -8,7 +8,15 @@
 // formed from the six piece products whose weight is at least 2^-16 of it
 // (hh, hm, mh, hl, lh, mm); each is exact in the float32 accumulator, and the
 // three dropped ones (ml, lm, ll) together stay below 3 * 2^-24 |x w|, so the
-// result carries float32 accuracy.  v_mfma_f32_16x16x32_bf16 runs at 16 x the
+// result carries float32 accuracy.
+//
+// NP = 2 (the bfloat16 sketch): two pieces per operand, x = h + m + r with the
+// same truncations (|r| < 2^-15 |x|), and the three products of weight above
+// 2^-16 (hh, hm, mh), the bf16x3 scheme of Henry, Tang and Heinecke (ARITH
+// 2019): a relative rounding near 2^-15 instead of the 2^-8 of operands rounded
+// once to bfloat16.
+//
+// v_mfma_f32_16x16x32_bf16 runs at 16 x the
 // rate of the float32 MFMA, so even six products per product leave the kernel
 // bound by its memory traffic rather than by the matrix cores.
 //
@@ -52,18 +60,16 @@ __device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32
     m = __float_as_uint(r) & 0xffff0000u;
     l = __float_as_uint(r - __uint_as_float(m));
 }
-// x rounded to the nearest bfloat16 (ties to even), as a float32 bit pattern
-__device__ __forceinline__ uint32_t rne16(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u & 0xffff0000u;
+// the first two pieces of split3 (x - h - m is left out)
+__device__ __forceinline__ void split2(float x, uint32_t& h, uint32_t& m) {
+    h = __float_as_uint(x) & 0xffff0000u;
+    m = __float_as_uint(x - __uint_as_float(h)) & 0xffff0000u;
 }
 // two bfloat16 (the high halves of a and b) in one word, a in the low half
 __device__ __forceinline__ uint32_t pack2(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
-// NP = 3: the float32 products from three pieces per operand (above); NP = 1:
-// the products of X and Omega each rounded to the nearest bfloat16 (the
-// bfloat16 sketch), one MFMA per block.
+// NP = 3: the float32 products from three pieces per operand, six MFMAs per
+// block; NP = 2: the bfloat16 sketch from two pieces, three MFMAs per block.
 template <int NB, int RM, int NP>
 __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __restrict__ X, int64_t L, int64_t J, int64_t R,
                                                         int ell, int64_t col0, uint64_t seed, uint32_t mode,
@@ -126,8 +132,12 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
             for (int u = 0; u < 4; ++u) {
                 const int n = 4 * q + u;
                 const int w = n * 16 + (n >> 1) * 4 + kp;
-                if (NP == 1) {
-                    om[buf][w] = pack2(rne16(za[u]), rne16(zb[u]));
+                if (NP == 2) {
+                    uint32_t ha, ma, hb, mb;
+                    split2(za[u], ha, ma);
+                    split2(zb[u], hb, mb);
+                    om[buf][w] = pack2(ha, hb);
+                    om[buf][PL + w] = pack2(ma, mb);
                 } else {
                     uint32_t ha, ma, la, hb, mb, lb;
                     split3(za[u], ha, ma, la);
@@ -154,19 +164,23 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
             const int n = nb * 16 + i16;
             const int w = n * 16 + (n >> 1) * 4 + 4 * g;
             bh[nb] = *reinterpret_cast<const u4*>(&om[buf][w]);
-            if (NP == 3) {
-                bm[nb] = *reinterpret_cast<const u4*>(&om[buf][PL + w]);
-                bl[nb] = *reinterpret_cast<const u4*>(&om[buf][2 * PL + w]);
-            }
+            if (NP >= 2) bm[nb] = *reinterpret_cast<const u4*>(&om[buf][PL + w]);
+            if (NP == 3) bl[nb] = *reinterpret_cast<const u4*>(&om[buf][2 * PL + w]);
         }
         u4 ah[RM], am[RM], al[RM];
 #pragma unroll
         for (int rm = 0; rm < RM; ++rm) {
             const float x[8] = {v[rm][0].x, v[rm][0].y, v[rm][0].z, v[rm][0].w,
                                 v[rm][1].x, v[rm][1].y, v[rm][1].z, v[rm][1].w};
-            if (NP == 1) {
+            if (NP == 2) {
+                uint32_t h[8], m[8];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) ah[rm][j] = pack2(rne16(x[2 * j]), rne16(x[2 * j + 1]));
+                for (int e = 0; e < 8; ++e) split2(x[e], h[e], m[e]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ah[rm][j] = pack2(h[2 * j], h[2 * j + 1]);
+                    am[rm][j] = pack2(m[2 * j], m[2 * j + 1]);
+                }
             } else {
                 uint32_t h[8], m[8], l[8];
 #pragma unroll
@@ -182,6 +196,17 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
 #pragma unroll
                 for (int e = 0; e < 8; ++e) nrm = fma((double)x[e], (double)x[e], nrm);
             }
+        }
+        if (NP == 2) {
+            // the two smaller products first
+#pragma unroll
+            for (int rm = 0; rm < RM; ++rm)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(am[rm], bh[nb], acc[rm][nb]);
+#pragma unroll
+            for (int rm = 0; rm < RM; ++rm)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bm[nb], acc[rm][nb]);
         }
         if (NP == 3) {
             // the five smaller products first, the accumulators of all blocks in between
@@ -294,8 +319,8 @@ bool sketch_x6_ok(Shape3 s, int ell, int64_t col0, const void* X) {
            bytes <= 0x7fff0000LL;
 }
 
-void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16_rounded) {
-    p.kind = bf16_rounded ? 4 : 3;
+void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16) {
+    p.kind = bf16 ? 4 : 3;
     p.rb = s.J <= 128 ? 1 : 2;                        // 16-row blocks per wave
     p.rw = 0;
     p.nq = (ell + 15) / 16;
@@ -320,7 +345,7 @@ hipError_t launch_sketch_f32_x6(const SketchPlan& p, const float* X, Shape3 s, i
     const int64_t tps = p.tiles_per_split;
 #define RT_X6(NBV)                                                                                               \
     return p.kind == 3 ? x6_by_rm<NBV, 3>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream) \
-                       : x6_by_rm<NBV, 1>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream)
+                       : x6_by_rm<NBV, 2>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream)
     switch (p.nq) {
         case 1: RT_X6(1);
         case 2: RT_X6(2);

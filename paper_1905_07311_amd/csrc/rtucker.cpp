@@ -60,6 +60,21 @@ struct rt_ctx {
     std::vector<Chunk> chunks;
     double* host = nullptr;       // pinned scratch for small read-backs
     double* host_dev = nullptr;   // the same block as the device addresses it
+    // Results of asynchronous calls: each takes a slot of scalars in the pinned
+    // block (after the first 4 KiB of read-back scratch), written by the call's
+    // last kernel and copied into the caller's rt_tucker by rt_sync.
+    static constexpr int NSLOT = 255;
+    static constexpr size_t SLOT_OFFSET = 4096;
+    static constexpr size_t SLOT_BYTES = 64;
+    struct Pending { rt_tucker* out; bool oblique; };
+    std::vector<Pending> pending;
+    rt_tucker discard{};          // stands in for a pending result released before rt_sync
+    rt::FinishScalars* slot_host(size_t i) const {
+        return (rt::FinishScalars*)((char*)host + SLOT_OFFSET + i * SLOT_BYTES);
+    }
+    rt::FinishScalars* slot_dev(size_t i) const {
+        return (rt::FinishScalars*)((char*)host_dev + SLOT_OFFSET + i * SLOT_BYTES);
+    }
     std::vector<void*> outputs;   // outputs handed to the caller (for release)
     // optional per-launch timing log (HIP events on the context's stream)
     struct Timed { int kind; hipEvent_t a, b; double bytes, flops; int64_t rows, cols; int ell; int variant; };
@@ -482,17 +497,58 @@ void release_partial(rt_ctx* ctx, rt_tucker* out) {
     }
 }
 
+// Scalars of a finished result from its slot: norms, error estimate, flags.
+rt_status fill_result(rt_tucker* out, const rt::FinishScalars* h, bool oblique) {
+    out->norm_x = std::sqrt(std::max(h->nx2, 0.0));
+    out->core_norm = std::sqrt(std::max(h->ng2, 0.0));
+    out->rel_err_est = out->norm_x > 0 ? std::sqrt(std::max(0.0, h->nx2 - h->ng2)) / out->norm_x : 0.0;
+    if (oblique) out->rel_err_est = -1.0;   // no identity: the projections are oblique
+    uint32_t fl = 0;
+    bool nonfinite = false;
+    for (int i = 0; i < RT_MAXD; ++i) {
+        fl |= h->status[i] & 3u;
+        if (h->status[i] & 4u) nonfinite = true;
+    }
+    if (nonfinite || !std::isfinite(h->nx2)) {
+        out->flags = fl | RT_FLAG_NONFINITE;
+        return RT_ENONFINITE;
+    }
+    out->flags = fl;
+    return RT_OK;
+}
+
+// Waits for the stream and fills every pending result; returns the first
+// deferred error (RT_ENONFINITE) or RT_OK.  `mine`, when set, receives the
+// status of that result alone.
+rt_status drain_pending(rt_ctx* c, const rt_tucker* self = nullptr, rt_status* mine = nullptr) {
+    RT_HIP(hipStreamSynchronize(c->stream));
+    rt_status first = RT_OK;
+    for (size_t i = 0; i < c->pending.size(); ++i) {
+        const rt_status s = fill_result(c->pending[i].out, c->slot_host(i), c->pending[i].oblique);
+        if (mine && c->pending[i].out == self) *mine = s;
+        if (s != RT_OK && first == RT_OK) first = s;
+    }
+    c->pending.clear();
+    if (first != RT_OK) fail(first, "input holds NaN or Inf");
+    return first;
+}
+
+// Last step of a decomposition: the core copied into its output buffer, its
+// squared norm and the device status words written into a slot of the pinned
+// block.  defer: the call returns at once and rt_sync fills the scalars of
+// *out; otherwise they are filled here (after waiting for the stream).
 rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vector<int64_t>& cdims, Dt dt,
-                 double* nx2_dev, uint32_t* status_dev) {
+                 double* nx2_dev, uint32_t* status_dev, bool defer, bool oblique = false) {
     int64_t n = 1;
     for (auto v : cdims) n *= v;
     const size_t bytes = (size_t)n * (dt == Dt::F64 ? 8 : 4);
     out->core = k.c->raw_alloc(bytes);
     if (!out->core) return fail(RT_ENOMEM, "core allocation failed");
+    if (k.c->pending.size() >= (size_t)rt_ctx::NSLOT) RT_TRY(drain_pending(k.c) == RT_EHIP ? RT_EHIP : RT_OK);
+    const size_t slot = k.c->pending.size();
     // one launch copies the core, sums its squares and writes the scalars into
-    // the mapped pinned block; a large core is copied and its partial sums taken
-    // first
-    rt::FinishScalars* hd = (rt::FinishScalars*)k.c->host_dev;
+    // the slot; a large core is copied and its partial sums taken first
+    rt::FinishScalars* hd = k.c->slot_dev(slot);
     if (n <= rt::FINISH_DIRECT_MAX) {
         RT_HIP(rt::launch_finish(core_dev, out->core, dt, n, true, nullptr, 0, nx2_dev, status_dev, hd,
                                  k.c->stream));
@@ -504,19 +560,16 @@ rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vecto
         RT_HIP(rt::launch_norm2(out->core, dt, n, part, nwg, k.c->stream));
         RT_HIP(rt::launch_finish(nullptr, nullptr, dt, 0, false, part, nwg, nx2_dev, status_dev, hd, k.c->stream));
     }
-    RT_HIP(hipStreamSynchronize(k.c->stream));
-    const rt::FinishScalars* h = (const rt::FinishScalars*)k.c->host;
-    out->norm_x = std::sqrt(std::max(h->nx2, 0.0));
-    out->core_norm = std::sqrt(std::max(h->ng2, 0.0));
-    out->rel_err_est = out->norm_x > 0 ? std::sqrt(std::max(0.0, h->nx2 - h->ng2)) / out->norm_x : 0.0;
-    uint32_t fl = 0;
-    bool nonfinite = false;
-    for (int i = 0; i < RT_MAXD; ++i) {
-        fl |= h->status[i] & 3u;
-        if (h->status[i] & 4u) nonfinite = true;
+    k.c->pending.push_back({out, oblique});
+    if (defer) {
+        const double nan = std::nan("");
+        out->norm_x = out->core_norm = out->rel_err_est = nan;
+        return RT_OK;
     }
-    out->flags = fl;
-    if (nonfinite || !std::isfinite(h->nx2)) return fail(RT_ENONFINITE, "input holds NaN or Inf");
+    rt_status mine = RT_OK;
+    const rt_status all = drain_pending(k.c, out, &mine);
+    if (all == RT_EHIP) return all;
+    if (mine != RT_OK) return fail(mine, "input holds NaN or Inf");
     return RT_OK;
 }
 
@@ -541,7 +594,8 @@ rt_status rt_create(rt_ctx** ctx, int device, void* stream, rt_alloc_fn alloc, r
     c->alloc = alloc;
     c->free_fn = free_fn;
     c->user = user;
-    if (hipHostMalloc((void**)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->host, rt_ctx::SLOT_OFFSET + rt_ctx::NSLOT * rt_ctx::SLOT_BYTES,
+                      hipHostMallocDefault) != hipSuccess) {
         delete c;
         return fail(RT_ENOMEM, "pinned host allocation failed");
     }
@@ -621,13 +675,15 @@ rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, dou
 
 rt_status rt_sync(rt_ctx* ctx) {
     if (!ctx) return fail(RT_EINVAL, "ctx is NULL");
-    RT_HIP(hipStreamSynchronize(ctx->stream));
-    return RT_OK;
+    return drain_pending(ctx);
 }
 
 rt_status rt_tucker_release(rt_ctx* ctx, rt_tucker* t) {
     if (!ctx || !t) return fail(RT_EINVAL, "NULL argument");
     (void)hipStreamSynchronize(ctx->stream);
+    // a result released before rt_sync: its scalars are not filled later
+    for (auto& p : ctx->pending)
+        if (p.out == t) p.out = &ctx->discard;
     release_partial(ctx, t);
     return RT_OK;
 }
@@ -679,7 +735,7 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
         rt_status rs = do_norm2(k, X->data, dt, n, nx2);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
     }
-    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status, true);
     if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
     return rs;
 }
@@ -742,8 +798,7 @@ rt_status rt_sp_sthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, c
         rt_status rs = do_norm2(k, X->data, dt, n, nx2);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
     }
-    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
-    out->rel_err_est = -1.0;                 // no identity: the projections are oblique
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status, true, true);
     if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
     return rs;
 }
@@ -833,7 +888,7 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
         rt_status rs = do_norm2(k, X->data, dt, n, nx2);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
     }
-    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status, true);
     if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
     return rs;
 }
@@ -874,11 +929,12 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     const int prec = (int)opts->prec;
     const size_t es = dsize(X->dtype);
     const double drop = X->dtype == RT_F64 ? 1e-10 : 1e-5;
-    // With the bfloat16 sketch a block's directions below ~1e-3 of its norm are
-    // sketch noise: such blocks use a drop threshold above that level, and once a
-    // bfloat16 block resolves no new direction the mode continues with float32
-    // sketches, so the tolerance is still met.
-    const double drop_bf16 = 1e-2;
+    // With the bfloat16 sketch (two pieces per operand, relative rounding near
+    // 2^-15) a block's directions below ~1e-5 of its norm are sketch noise: such
+    // blocks use a drop threshold above that level, and once a bfloat16 block
+    // resolves no new direction the mode continues with float32 sketches, so the
+    // tolerance is still met.
+    const double drop_bf16 = 1e-4;
     init_out(out, X);
     std::vector<int64_t> dims(X->dims, X->dims + d);
     double* nx2 = k.ws<double>(1);
@@ -1043,7 +1099,7 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         for (int j = 0; j < d; ++j) ntot *= X->dims[j];
         RT_TRY(do_norm2(k, X->data, dt, ntot, nx2));
     }
-    rt_status rs = finish(k, out, cur, dims, dt, nx2, status);
+    rt_status rs = finish(k, out, cur, dims, dt, nx2, status, false);
     if (rs != RT_OK && rs != RT_ENONFINITE) { release_partial(ctx, out); return rs; }
     if (rs == RT_OK && capped) return fail(RT_ECAP, "a mode reached its rank cap before the tolerance");
     return rs;
@@ -1083,7 +1139,6 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
     const size_t es = dsize(t->dtype);
     if (ncore == 0) {
         RT_HIP(hipMemsetAsync(out, 0, (size_t)nout * es, st));
-        RT_HIP(hipStreamSynchronize(st));
         return RT_OK;
     }
     int last = -1;
@@ -1091,7 +1146,6 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
         if (t->factors[j]) last = j;
     if (last < 0) {
         RT_HIP(hipMemcpyAsync(out, t->core, (size_t)nout * es, hipMemcpyDeviceToDevice, st));
-        RT_HIP(hipStreamSynchronize(st));
         return RT_OK;
     }
     // G x_j A_j one mode at a time: out[l, i, r] = sum_k A_j[i, k] G[l, k, r], i.e. the
@@ -1116,7 +1170,6 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
         cur_dims[j] = I;
         cur = dst;
     }
-    RT_HIP(hipStreamSynchronize(st));
     return RT_OK;
 }
 

@@ -9,7 +9,7 @@ does not load the library; the first call does, and raises if it is missing
 import ctypes
 import math
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import List, Optional
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -133,25 +133,50 @@ def _check(status, allow=()):
     return status
 
 
-@dataclass
-class Tucker:
-    core: object
-    factors: List[Optional[object]]
-    ranks: List[int]
-    norm_x: float
-    core_norm: float
-    rel_err_est: float
-    flags: int
-    status: int = RT_OK
+RT_FLAG_NONFINITE = 4
 
-    def reconstruct(self):
-        """X_hat = G x_1 A_1 ... x_d A_d with torch (validation helper, not the hot path)."""
-        import torch
-        X = self.core
-        for n, A in enumerate(self.factors):
-            if A is not None:
-                X = torch.movedim(torch.tensordot(A, X, dims=([1], [n])), 0, n)
-        return X
+
+class Tucker:
+    """A decomposition [G; A_1..A_d] on the device.  The core and factors are
+    torch tensors written on the context's stream.  After an asynchronous call
+    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd) the scalars are filled by rt_sync:
+    reading norm_x, core_norm, rel_err_est or flags calls it once."""
+
+    def __init__(self, core, factors, ranks, out, ctx=None, status=RT_OK):
+        self.core = core
+        self.factors = factors
+        self.ranks = ranks
+        self.status = status
+        self._out = out
+        self._ctx = ctx                      # set while the scalars are pending
+
+    def _resolve(self):
+        if self._ctx is not None:
+            ctx, self._ctx = self._ctx, None
+            try:
+                ctx.sync()
+            except RtError as e:
+                if e.status != RT_ENONFINITE:
+                    raise
+        if self._out.flags & RT_FLAG_NONFINITE:
+            raise RtError(RT_ENONFINITE, "input holds NaN or Inf")
+        return self._out
+
+    @property
+    def norm_x(self):
+        return self._resolve().norm_x
+
+    @property
+    def core_norm(self):
+        return self._resolve().core_norm
+
+    @property
+    def rel_err_est(self):
+        return self._resolve().rel_err_est
+
+    @property
+    def flags(self):
+        return int(self._resolve().flags)
 
 
 class Context:
@@ -176,6 +201,7 @@ class Context:
         self._alloc_cb = ALLOC_FN(_alloc)
         self._free_cb = FREE_FN(_free)
         self.ctx = ctypes.c_void_p()
+        self._pending = []                   # rt_tucker structs rt_sync still writes into
         stream = torch.cuda.current_stream(self.device).cuda_stream
         _check(lib.rt_create(ctypes.byref(self.ctx), self.device.index, ctypes.c_void_p(stream), self._alloc_cb,
                              self._free_cb, None))
@@ -185,6 +211,7 @@ class Context:
             _lib.rt_destroy(self.ctx)
             self.ctx = ctypes.c_void_p()
             self._bufs.clear()
+            self._pending.clear()
 
     def __del__(self):
         try:
@@ -221,8 +248,7 @@ class Context:
         n = math.prod(shape)
         return buf.view(dtype)[:n].view(*shape) if n > 0 else torch.empty(shape, dtype=dtype, device=self.device)
 
-    def _result(self, out, X, status):
-        torch = self.torch
+    def _result(self, out, X, status, deferred=False):
         d = X.dim()
         ranks = [int(out.ranks[i]) for i in range(d)]
         core = self._take(out.core, ranks, X.dtype)
@@ -230,8 +256,9 @@ class Context:
         for j in range(d):
             p = out.factors[j]
             factors.append(self._take(p, (int(X.shape[j]), ranks[j]), X.dtype) if p else None)
-        return Tucker(core=core, factors=factors, ranks=ranks, norm_x=out.norm_x, core_norm=out.core_norm,
-                      rel_err_est=out.rel_err_est, flags=int(out.flags), status=status)
+        if deferred:
+            self._pending.append(out)
+        return Tucker(core, factors, ranks, out, self if deferred else None, status)
 
     @staticmethod
     def _prec(X, prec):
@@ -269,7 +296,7 @@ class Context:
         o = self._opts(X, p, seed, order, prec, power_iters)
         out = rt_tucker()
         st = _check(getattr(_lib, fn)(self.ctx, ctypes.byref(t), rk, ctypes.byref(o), ctypes.byref(out)))
-        return self._result(out, X, st)
+        return self._result(out, X, st, deferred=True)
 
     def rhosvd_adaptive(self, X, eps, block, seed, eps_per_mode=None, max_rank=None, prec=None):
         return self._adaptive("rt_rhosvd_adaptive", X, eps, block, seed, None, eps_per_mode, max_rank, prec)
@@ -377,7 +404,12 @@ class Context:
         return out
 
     def sync(self):
-        _check(_lib.rt_sync(self.ctx))
+        """rt_sync: wait for the stream and fill the scalars of pending results;
+        raises RtError(RT_ENONFINITE) if the input of any of them was not finite."""
+        st = _lib.rt_sync(self.ctx)
+        if st != RT_EHIP:
+            self._pending.clear()
+        _check(st)
 
     def timing(self, enable, kinds=None):
         """Turn the per-launch timing log on (all kinds, or the named ones) or off."""
@@ -450,14 +482,6 @@ class ServedResult:
     flags: int
     queue_s: float
     latency_s: float
-
-    def reconstruct(self):
-        import numpy as np
-        X = np.asarray(self.core, dtype=np.float64)
-        for n, A in enumerate(self.factors):
-            if A is not None:
-                X = np.moveaxis(np.tensordot(np.asarray(A, dtype=np.float64), X, axes=([1], [n])), 0, n)
-        return X
 
 
 class Server:

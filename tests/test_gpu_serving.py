@@ -5,14 +5,21 @@ requests (Alg. 5, §4) of uneven shapes and ranks.
   residual on the host), in float32 and with the bfloat16 sketch;
 * a request's result is the same alone and in the mix (the kernels' reductions
   have a fixed order, so the comparison is exact);
-* the ranks agree with the single-call adaptive entry point on the same data.
+* the ranks agree with the single-call adaptive entry point on the same data;
+* served results of both precisions against the FP64 oracle, on requests of the
+  benchmark's serving recipe (sides U[32, 256], ranks U[4, 32] + 1e-6 noise):
+  float32 sketch - the oracle's ranks and X_hat within 1e-5 ||X|| (ranks within
+  one where a stop or truncation quantity of the oracle lies at the rounding
+  level of tau^2); bfloat16 sketch - the same ranks, X_hat within 1e-4 ||X||,
+  direct error <= eps.
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1905_07311_amd import inputs, rtucker
-from gpu_common import need_gpu
+from gpu_common import borderline, need_gpu, tucker_dist, xhat
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +37,7 @@ def _requests(n, seed=77):
 
 def _rel_err(res, X):
     Xf = X.numpy().astype(np.float64)
-    return np.linalg.norm(res.reconstruct() - Xf) / np.linalg.norm(Xf)
+    return np.linalg.norm(xhat(res) - Xf) / np.linalg.norm(Xf)
 
 
 @pytest.fixture(scope="module")
@@ -80,7 +87,7 @@ def test_served_matches_single_call(reqs):
             r = srv.wait(t)
             g = ctx.rsthosvd_adaptive(X.cuda(), 1e-3, 8, seed=s)
             assert r.ranks == g.ranks
-            assert np.allclose(r.reconstruct(), g.reconstruct().double().cpu().numpy(), rtol=0, atol=1e-6 * r.norm_x)
+            assert np.allclose(xhat(r), xhat(g), rtol=0, atol=1e-6 * r.norm_x)
     finally:
         srv.close()
         ctx.close()
@@ -99,3 +106,37 @@ def test_budget_admission_and_release():
             srv.poll(ts[0])                 # released by wait()
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_served_against_oracle(prec):
+    """Eight requests of the serving workload's own recipe (the first eight of its
+    arrival schedule), served together, against the FP64 oracle's adaptive
+    R-STHOSVD on the same float32 values and Omega seeds."""
+    need_gpu()
+    eps, b = 1e-3, 8
+    _, sides, ranks = inputs.serving_schedule()
+    reqs = [(torch.from_numpy(inputs.serving_request_host(9000 + i, sides[i], ranks[i])).pin_memory(), 9000 + i)
+            for i in range(8)]
+    srv = rtucker.Server(max_inflight=4, eps=eps, block=b, prec=prec)
+    try:
+        served = [srv.wait(t) for t in [srv.submit(X, s) for X, s in reqs]]
+    finally:
+        srv.close()
+    for (X, s), r in zip(reqs, served):
+        Xf = X.numpy().astype(np.float64)
+        nx2 = oracle.fro2(Xf)
+        o = oracle.adaptive_rsthosvd(Xf, eps, b, s, delta=1e-5)
+        err = np.linalg.norm(xhat(r) - Xf) / np.sqrt(nx2)
+        d = tucker_dist(r.core, r.factors, o.core, o.factors) / np.sqrt(nx2)
+        print(f"{prec} request {s} dims {tuple(X.shape)}: ranks {r.ranks} (oracle {o.ranks}), error {err:.3e}, "
+              f"distance to oracle {d:.3e}", flush=True)
+        assert r.status == rtucker.RT_OK
+        assert err <= eps
+        if borderline(o, nx2, 2.0 ** -24):
+            assert all(abs(a - c) <= 1 for a, c in zip(r.ranks, o.ranks))
+        else:
+            assert r.ranks == o.ranks
+            # the bfloat16 sketch's 2^-15 rounding moves the basis within the
+            # tolerance's slack, not only by float32 rounding
+            assert d <= (1e-4 if prec == "bf16" else 1e-5), d

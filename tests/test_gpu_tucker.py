@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_1905_07311_amd import inputs, rtucker
-from gpu_common import need_gpu, projector_dist, rel, to_np
+from gpu_common import borderline, need_gpu, projector_dist, rel, to_np, xhat
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,7 +24,7 @@ def ctx():
 
 
 def _check(res_g, res_o, X, tol, check_proj=True):
-    Xh_g = to_np(res_g.reconstruct())
+    Xh_g = xhat(res_g)
     Xh_o = res_o.reconstruct()
     nx = np.linalg.norm(X)
     assert np.linalg.norm(Xh_g - Xh_o) / nx < tol
@@ -87,25 +87,28 @@ def test_four_way_keep_and_order(ctx):
 
 @pytest.mark.parametrize("alg", ["rsthosvd", "rhosvd"])
 def test_bf16_sketch_decomposition(ctx, alg):
-    """BF16 sketch (the precision of the 128^4 workload): the sketch multiplies
-    bfloat16-rounded X and Omega, the rest runs in float32.  Parity with the
-    oracle's rounded-sketch variant (same Omega, same rounding, float64
-    elsewhere); the error stays within 1e-2 of the exact-sketch oracle."""
+    """BF16 sketch (the precision of the 128^4 workload): modes 0 and 1 (J > 64,
+    R % 8 == 0) sketch with two bfloat16 pieces per operand, the other modes in
+    float32, the rest of the method in float32/float64.  Parity with the
+    oracle's bfloat16-sketch variant (same Omega, same split, float64
+    elsewhere); after refinement the error is within 1.1 x the exact-sketch
+    oracle's error + 1e-4."""
     rng = np.random.default_rng(9)
     ranks = [8, 7, 6, 5]
-    X = inputs.lowrank_tensor(rng, (48, 40, 36, 32), ranks, noise=1e-6,
+    X = inputs.lowrank_tensor(rng, (96, 72, 36, 32), ranks, noise=1e-6,
                               core_scale=inputs.graded_scale(ranks, 0.8))
     Xs = X.astype(np.float32)
     Xf = Xs.astype(np.float64)
     g = getattr(ctx, alg)(torch.from_numpy(Xs).cuda(), ranks, 4, seed=12, prec="bf16")
-    o = getattr(oracle, alg)(Xf, ranks, 4, seed=12, sketch_round=oracle.round_bf16)
+    o = getattr(oracle, alg)(Xf, ranks, 4, seed=12, sketch=oracle.sketch_bf16x3)
     assert g.ranks == o.ranks
     nx = np.linalg.norm(Xf)
-    assert np.linalg.norm(to_np(g.reconstruct()) - o.reconstruct()) / nx < 1e-4
+    assert np.linalg.norm(xhat(g) - o.reconstruct()) / nx < 2e-5
     for A, B in zip(g.factors, o.factors):
         assert projector_dist(to_np(A), B) < 1e-3
     exact = getattr(oracle, alg)(Xf, ranks, 4, seed=12)
-    assert np.linalg.norm(to_np(g.reconstruct()) - Xf) / nx < np.linalg.norm(exact.reconstruct() - Xf) / nx + 1e-2
+    err = np.linalg.norm(xhat(g) - Xf) / nx
+    assert err <= 1.1 * np.linalg.norm(exact.reconstruct() - Xf) / nx + 1e-4
 
 
 def test_exact_recovery_f64(ctx):
@@ -114,7 +117,7 @@ def test_exact_recovery_f64(ctx):
     Xd = torch.from_numpy(X).cuda()
     for fn in (ctx.rsthosvd, ctx.rhosvd):
         g = fn(Xd, [3, 4, 5], 4, seed=2)
-        err = np.linalg.norm(to_np(g.reconstruct()) - X) / np.linalg.norm(X)
+        err = np.linalg.norm(xhat(g) - X) / np.linalg.norm(X)
         assert err < 1e-12
         assert g.rel_err_est < 1e-6
 
@@ -124,7 +127,7 @@ def test_identity_and_estimate(ctx):
     X = inputs.lowrank_tensor(rng, (40, 30, 20), (8, 8, 8), noise=1e-2)
     Xd = torch.from_numpy(X).cuda()
     g = ctx.rsthosvd(Xd, [4, 5, 6], 3, seed=0)
-    direct = np.linalg.norm(to_np(g.reconstruct()) - X) / np.linalg.norm(X)
+    direct = np.linalg.norm(xhat(g) - X) / np.linalg.norm(X)
     assert abs(direct - g.rel_err_est) < 1e-10
 
 
@@ -136,9 +139,43 @@ def test_errors(ctx):
         ctx.rsthosvd(X, [2, 2, 2], 1, seed=0, prec="f32")
     Xn = torch.ones((6, 6, 6), dtype=torch.float64, device="cuda")
     Xn[1, 2, 3] = float("nan")
+    # the fixed-rank call is asynchronous: the device status comes back with rt_sync
+    g = ctx.rsthosvd(Xn, [2, 2, 2], 1, seed=0)
     with pytest.raises(rtucker.RtError) as ei:
-        ctx.rsthosvd(Xn, [2, 2, 2], 1, seed=0)
+        ctx.sync()
     assert ei.value.status == rtucker.RT_ENONFINITE
+    assert g._out.flags & rtucker.RT_FLAG_NONFINITE
+    with pytest.raises(rtucker.RtError):
+        g.norm_x
+    with pytest.raises(rtucker.RtError) as ei:
+        ctx.rsthosvd_adaptive(Xn, 1e-3, 2, seed=0)
+    assert ei.value.status == rtucker.RT_ENONFINITE
+
+
+def test_fixed_rank_calls_return_before_the_work_completes(ctx):
+    """rt_rsthosvd / rt_rhosvd / rt_sp_sthosvd / rt_reconstruct enqueue and return:
+    with a long product queued ahead on the same stream, each call comes back
+    while the stream is still busy and the scalars of its result unset (NaN);
+    rt_sync then fills them, equal to a synchronous evaluation."""
+    import math
+    X = torch.from_numpy(inputs.hilbert0((60, 50, 40))).cuda()
+    A = torch.randn((4096, 4096), dtype=torch.float32, device="cuda")
+    for fn in ("rsthosvd", "rhosvd", "sp_sthosvd"):
+        torch.cuda.synchronize()
+        B = A
+        for _ in range(30):                          # ~4 TFLOP queued ahead of the call
+            B = A @ B
+        g = getattr(ctx, fn)(X, [6, 5, 4], 3, seed=1)
+        busy = not torch.cuda.current_stream().query()
+        raw = g._out.norm_x
+        Xr = ctx.reconstruct(g)
+        busy_rec = not torch.cuda.current_stream().query()
+        assert busy and busy_rec, fn
+        assert math.isnan(raw), fn
+        ctx.sync()
+        assert abs(g.norm_x - float(X.norm())) <= 1e-12 * float(X.norm())
+        assert np.allclose(to_np(Xr), xhat(g), rtol=0, atol=1e-12 * g.norm_x)
+        del B
 
 
 def test_zero_tensor_fixed_rank(ctx):
@@ -161,29 +198,11 @@ def load_hilbert_table():
     return rows
 
 
-def borderline(o, nx2, u):
-    """True when one of the oracle's stop or truncation quantities lies within the
-    rounding level of its threshold.  E = ||M||^2 - sum ||B_i||^2 is a difference
-    of fp64 sums (absolute error ~ u64 ||X||^2), and a basis computed in working
-    precision u moves the captured energy near the threshold by ~ u ||X|| tau, so
-    decisions taken that close to tau^2 are not determined by the arithmetic."""
-    for inf in o.info:
-        t2 = inf["tau2"]
-        noise = 64.0 * (2.0 ** -53 * nx2 + u * np.sqrt(nx2 * t2))
-        if any(abs(e - t2) <= noise for e in inf["E_hist"]):
-            return True
-        sv2 = np.array(inf["sv2"])
-        tails = np.concatenate([np.cumsum(sv2[::-1])[::-1], [0.0]]) + max(inf["E"], 0.0)
-        if np.any(np.abs(tails - t2) <= noise) or abs(inf["E"]) <= noise:
-            return True
-    return False
-
-
 def _adaptive_check(g, o, X, eps, tol, u):
     nx2 = float(np.sum(X * X))
-    err = np.linalg.norm(to_np(g.reconstruct()) - X) / np.sqrt(nx2)
+    err = np.linalg.norm(xhat(g) - X) / np.sqrt(nx2)
     assert err <= eps
-    diff = np.linalg.norm(to_np(g.reconstruct()) - o.reconstruct()) / np.sqrt(nx2)
+    diff = np.linalg.norm(xhat(g) - o.reconstruct()) / np.sqrt(nx2)
     if borderline(o, nx2, u):
         # several results are correct: ranks within one, both within the tolerance
         assert all(abs(a - c) <= 1 for a, c in zip(g.ranks, o.ranks))
@@ -264,7 +283,7 @@ def test_subspace_iteration_parity(ctx, dtype, alg, q, shape):
     _check(g, o, Xs.astype(np.float64), 1e-10 if dtype == torch.float64 else 1e-5)
     g0 = getattr(ctx, alg)(Xd, [6, 5, 4], 3, 5)
     nx = np.linalg.norm(X)
-    assert np.linalg.norm(to_np(g0.reconstruct()) - to_np(g.reconstruct())) / nx > 1e-2
+    assert np.linalg.norm(xhat(g0) - xhat(g)) / nx > 1e-2
 
 
 def test_subspace_iteration_errors(ctx):
@@ -306,7 +325,7 @@ def test_adaptive_rhosvd_per_mode_and_zero(ctx):
     g = ctx.rhosvd_adaptive(Xd, 1e-3, 4, seed=5, eps_per_mode=epm)
     o = oracle.adaptive_rhosvd(X, 1e-3, 4, seed=5, eps_per_mode=epm)
     assert g.ranks == o.ranks and g.ranks[1] == 20 and g.factors[1] is None
-    assert np.linalg.norm(to_np(g.reconstruct()) - o.reconstruct()) / np.linalg.norm(X) < 1e-10
+    assert np.linalg.norm(xhat(g) - o.reconstruct()) / np.linalg.norm(X) < 1e-10
     Z = torch.zeros((12, 10, 8), dtype=torch.float64, device="cuda")
     gz = ctx.rhosvd_adaptive(Z, 1e-3, 4, seed=0)
     assert gz.ranks == [0, 0, 0] and gz.core_norm == 0.0
