@@ -308,21 +308,38 @@ rt_status rt_sync(rt_ctx* ctx);
 
 /* ---- serving: continuous batching of many requests --------------------------- */
 /* A server runs adaptive R-STHOSVD (Alg. 5, §4) on a stream of float32 tensors of
- * uneven shapes.  Requests wait in arrival order and are admitted to one of
- * `max_inflight` slots as soon as a slot is free and the estimated device
- * memory of the admitted requests stays within `hbm_budget`; every slot has its
- * own stream, workspace and cached device memory, so the work of admitted
- * requests overlaps on the device while later requests keep arriving.  A
- * request's result does not depend on what else is in flight (the kernels'
- * reductions have a fixed order). */
+ * uneven shapes.  Requests wait in arrival order and are admitted as soon as a
+ * slot is free and their device memory fits in `hbm_budget`.
+ *
+ * RT_SERVE_GROUPED (default): one executor drives every admitted request through
+ * the method's steps in lock-step iterations.  In each iteration the requests in
+ * their block phase share one launch of each step (the block sketch, its sums,
+ * the block orthonormalisation, the projection) and the requests whose mode has
+ * stopped growing share the truncation launches (Gram, eigensolver with rank
+ * choice and factor, core update); the iteration is one captured HIP graph
+ * (descriptor copy plus the launches, replayed every iteration) followed by one
+ * wait, after which the host advances every request (next block, truncation,
+ * next mode, done) and admits new ones.  A request's footprint is the exact
+ * workspace of its shape (input, basis, projections, cores, factors).  A request
+ * whose block step does not fit the grouped kernel (a mode longer than 910 rows
+ * for blocks of 8) runs alone through rt_rsthosvd_adaptive.  Float32 sketches.
+ * RT_SERVE_SLOTS: every slot runs whole requests through rt_rsthosvd_adaptive
+ * on a stream of its own (float32 or bfloat16 sketches).
+ *
+ * Either way a request's result does not depend on what else is in flight (the
+ * work of a request is split by its own shape and every sum has a fixed order). */
 typedef struct rt_server rt_server;
 
+#define RT_SERVE_GROUPED 0
+#define RT_SERVE_SLOTS 1
+
 typedef struct {
-    int32_t max_inflight;     /* slots: 1 .. 64 */
+    int32_t max_inflight;     /* requests in flight (slots): 1 .. 64 */
     size_t hbm_budget;        /* bytes; 0 = 3/4 of the device memory free at creation */
-    rt_precision prec;        /* RT_PREC_F32 or RT_PREC_BF16_SKETCH */
+    rt_precision prec;        /* RT_PREC_F32 (either mode) or RT_PREC_BF16_SKETCH (slots) */
     double eps;               /* relative tolerance of every request (eps_n = eps / sqrt(d)) */
-    int32_t block;            /* adaptive block size, 1 .. RT_LMAX */
+    int32_t block;            /* adaptive block size, 1 .. RT_LMAX (grouped: 1 .. 16) */
+    int32_t mode;             /* RT_SERVE_GROUPED or RT_SERVE_SLOTS */
 } rt_server_opts;
 
 typedef struct {

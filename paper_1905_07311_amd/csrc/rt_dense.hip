@@ -781,10 +781,10 @@ __device__ __forceinline__ void hestenes_rot(double al, double be, double ga, do
 // Jacobi layout: G = 8 or 16: one wave, G lanes per pair, RW rows per lane
 // (J <= G RW, b <= 128 / G); G = 0: one wave per pair, RW rows per lane (J <= 64 RW).
 template <int G, int RW>
-__global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __restrict__ Yin, int64_t J, int b,
-                                                              double* __restrict__ Qall, int ldq, int k,
-                                                              double drop, int* __restrict__ knew,
-                                                              float* __restrict__ Qf) {
+__device__ __forceinline__ void block_orth_small_body(const double* __restrict__ Yin, int64_t J, int b,
+                                                      double* __restrict__ Qall, int ldq, int k, double drop,
+                                                      int* __restrict__ knew, float* __restrict__ Qf,
+                                                      int* __restrict__ knew2) {
     __shared__ BlockOrthShared S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ldy = b | 1;
@@ -960,8 +960,31 @@ __global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __re
         Qall[(int64_t)i * ldq + k + t] = v;
         if (Qf) Qf[(int64_t)i * ldq + k + t] = (float)v;
     }
-    if (tid == 0) knew[0] = kept;
+    if (tid == 0) {
+        knew[0] = kept;
+        if (knew2) knew2[0] = kept;
+    }
     RT_DENSE_TRACE(4);
+}
+
+template <int G, int RW>
+__global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __restrict__ Yin, int64_t J, int b,
+                                                              double* __restrict__ Qall, int ldq, int k,
+                                                              double drop, int* __restrict__ knew,
+                                                              float* __restrict__ Qf) {
+    block_orth_small_body<G, RW>(Yin, J, b, Qall, ldq, k, drop, knew, Qf, nullptr);
+}
+
+// Grouped block steps: workgroup i serves request i of the group when its mode
+// length falls in (jlo, 64 RW] (one wave per column pair, RW rows per lane).
+template <int RW>
+__global__ __launch_bounds__(NT) void block_orth_group_kernel(const GHeader* __restrict__ hdr,
+                                                              const GBlock* __restrict__ d, int64_t jlo) {
+    const int i = blockIdx.x;
+    if (i >= hdr->nblock) return;
+    const GBlock& q = d[i];
+    if (q.J <= jlo || q.J > 64 * RW) return;
+    block_orth_small_body<0, RW>(q.Y, q.J, q.b, q.Qall, q.cap, q.kcols, q.drop, q.knew, q.Qallf, &q.rb->knew);
 }
 
 struct EigShared {
@@ -1391,6 +1414,146 @@ hipError_t truncate_multi(const double* W, int ell, const double* Q, int64_t ldq
                        (const double*)part, nwg, (const int*)kout, J, (const double*)Us, ell, A,
                        da == Dt::F64 ? 1 : 0, U, Uf);
     return hipGetLastError();
+}
+
+// ---- grouped truncation (serving) ----------------------------------------------------------
+// Workgroup i truncates request i of the group: the Gram partials summed in a
+// fixed order, the parallel Jacobi eigensolver (float data: off-diagonal sum of
+// squares down to 1e-14 ||W||^2), eigenvalues sorted in decreasing order, the
+// rank k = the smallest with max(E, 0) + sum_{t >= k} lambda_t <= tau2 (the
+// truncation of the adaptive range finder's QB), A = Qall U_k row chunk by row
+// chunk (lane = row, wave w the columns w, w + 8, ...), each column flipped so
+// that its entry of largest magnitude (lowest row on ties) is positive, and
+// U_k with the same flips as the float operand of the core update.
+struct GTruncShared {
+    Mat A;
+    Mat V;
+    __attribute__((aligned(16))) double cs[2 * (LMAX / 2 + 1)];
+    int pq[LMAX / 2 + 1];
+    double red[NT];
+    int perm[LMAX];
+    double lam[LMAX];
+    __attribute__((aligned(16))) double ust[LMAX][LMAX + 2];
+    __attribute__((aligned(16))) double qs[64][LMAX + 2];
+    double sg[LMAX];
+    int wrow[NT / 64][LMAX];
+    int k;
+};
+
+__global__ __launch_bounds__(NT) void trunc_group_kernel(const GHeader* __restrict__ hdr,
+                                                         const GTrunc* __restrict__ d) {
+    const int i = blockIdx.x;
+    if (i >= hdr->ntrunc) return;
+    __shared__ GTruncShared S;
+    const GTrunc& q = d[i];
+    const int n = q.kcols;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < n * n; e += NT) {
+        double sum = 0.0;
+        for (int c = 0; c < q.nchunk; ++c) sum += q.gpart[(int64_t)c * n * n + e];
+        S.A[e / n][e % n] = sum;
+    }
+    __syncthreads();
+    jacobi_2p(S.A, n, S.V, 1e-14, S.red, S.cs, S.pq);
+    blk_sort_desc(S.A, n, S.perm, S.lam);
+    if (tid == 0) {
+        const double E = fmax(q.E, 0.0);
+        double tail = 0.0;
+        for (int t = n - 1; t >= 0; --t) tail += fmax(S.lam[t], 0.0);
+        int k = n;
+        for (int kk = 0; kk <= n; ++kk) {
+            if (E + tail <= q.tau2) { k = kk; break; }
+            if (kk < n) tail -= fmax(S.lam[kk], 0.0);
+        }
+        S.k = k;
+        q.kout[0] = k;
+        q.rb->kfinal = k;
+    }
+    __syncthreads();
+    const int k = S.k;
+    for (int e = tid; e < LMAX * LMAX; e += NT) {
+        const int j = e / LMAX, t = e % LMAX;
+        S.ust[j][t] = (j < k && t < n) ? S.V[t][S.perm[j]] : 0.0;
+    }
+    __syncthreads();
+    if (k <= 0) return;
+    constexpr int NJ = LMAX / 8;
+    double bmax[NJ];
+    int brow[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) { bmax[jj] = -1.0; brow[jj] = 0x7fffffff; }
+    for (int64_t r0 = 0; r0 < q.J; r0 += 64) {
+        const int rows = (int)(q.J - r0 < 64 ? q.J - r0 : 64);
+        batched_copy<8>(64 * LMAX, tid, NT,
+                        [&](int e) { const int r = e / LMAX, c = e % LMAX;
+                                     return (r < rows && c < n) ? q.Qall[(r0 + r) * q.cap + c] : 0.0; },
+                        [&](int e, double v) { S.qs[e / LMAX][e % LMAX] = v; });
+        __syncthreads();
+        // a_j = sum_t Q[row][t] U[t][j] in two running sums (even and odd t),
+        // the row's entries streamed from LDS once for all of the wave's columns
+        double s0[NJ], s1[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) { s0[jj] = 0.0; s1[jj] = 0.0; }
+        for (int t = 0; t < n; t += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(&S.qs[lane][t]);
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const double2 u2 = *reinterpret_cast<const double2*>(&S.ust[wave + 8 * jj][t]);
+                s0[jj] = fma(v.x, u2.x, s0[jj]);
+                s1[jj] = fma(v.y, u2.y, s1[jj]);
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = wave + 8 * jj;
+            if (j < k) {
+                const double a = s0[jj] + s1[jj];
+                if (lane < rows) {
+                    q.A[(r0 + lane) * k + j] = (float)a;
+                    const double x = fabs(a);
+                    const int row = (int)r0 + lane;
+                    if (x > bmax[jj] || (x == bmax[jj] && row < brow[jj])) {
+                        bmax[jj] = x;
+                        brow[jj] = row;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // sign of each column from its entry of largest magnitude (lowest row on ties)
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        double x = bmax[jj];
+        int row = brow[jj];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ox = __shfl_xor(x, off, 64);
+            const int orow = __shfl_xor(row, off, 64);
+            if (ox > x || (ox == x && orow < row)) { x = ox; row = orow; }
+        }
+        const int j = wave + 8 * jj;
+        if (lane == 0 && j < k) S.wrow[0][j] = row;
+    }
+    __syncthreads();
+    if (tid < k) {
+        // the same two running sums as above for the column's largest entry
+        const int64_t row = S.wrow[0][tid];
+        double s0 = 0.0, s1 = 0.0;
+        for (int t = 0; t < n; t += 2) {
+            const double q0 = q.Qall[row * q.cap + t];
+            const double q1 = t + 1 < n ? q.Qall[row * q.cap + t + 1] : 0.0;
+            s0 = fma(q0, S.ust[tid][t], s0);
+            s1 = fma(q1, S.ust[tid][t + 1], s1);
+        }
+        S.sg[tid] = (s0 + s1) < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();                       // the unsigned A is written and visible to the workgroup
+    for (int64_t e = tid; e < q.J * k; e += NT) q.A[e] *= (float)S.sg[e % k];
+    for (int e = tid; e < n * k; e += NT) {       // U_k as the core update's Q (ld = kcols)
+        const int t = e / k, j = e % k;
+        q.Uf[t * n + j] = (float)(S.ust[j][t] * S.sg[j]);
+    }
 }
 
 // ---- CholeskyQR2 over many workgroups ---------------------------------------------------
@@ -1827,6 +1990,25 @@ hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, i
 
 hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* Tf, double jtol, hipStream_t stream) {
     hipLaunchKernelGGL(svqb_kernel, dim3(1), dim3(NT), 0, stream, W, ell, drop, T, Tf, jtol);
+    return hipGetLastError();
+}
+
+int64_t group_block_maxj(int b) {
+    // one wave per column pair, 16 rows per lane, Y staged with row stride b | 1
+    int64_t jmax = 64 * 16;
+    const int64_t e = BO_MAXE / (b | 1);
+    return b <= BO_MAXB ? (e < jmax ? e : jmax) : 0;
+}
+
+hipError_t launch_group_dense(const GHeader* hdr, const GBlock* blk, const GTrunc* tr, int maxreq, hipStream_t stream,
+                              int stage) {
+    if (stage == 0) {
+        // block steps: modes of at most 256 rows with 4 rows per lane, longer ones with 16
+        hipLaunchKernelGGL(block_orth_group_kernel<4>, dim3(maxreq), dim3(NT), 0, stream, hdr, blk, (int64_t)0);
+        hipLaunchKernelGGL(block_orth_group_kernel<16>, dim3(maxreq), dim3(NT), 0, stream, hdr, blk, (int64_t)256);
+    } else {
+        hipLaunchKernelGGL(trunc_group_kernel, dim3(maxreq), dim3(NT), 0, stream, hdr, tr);
+    }
     return hipGetLastError();
 }
 

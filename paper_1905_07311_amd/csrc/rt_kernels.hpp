@@ -214,6 +214,104 @@ hipError_t launch_philox_words(uint64_t seed, uint32_t mode, int64_t c0, int64_t
                                uint32_t* out, hipStream_t stream);
 // Tucker reconstruction helper is the projection kernel with the factor in place of Q^T.
 
+// ---- grouped execution: one launch serves the same step of many requests ----------------
+// Used by the serving executor.  Every launch has a fixed grid (so one
+// captured graph serves every iteration) and takes its work from descriptor
+// arrays in device memory, refreshed by one host-to-device copy per iteration;
+// a request's work is split by its own shape only, so its result does not
+// depend on the other requests of the group.  Scalars the host needs come back
+// through a mapped pinned slot per request (GRead).
+struct GRead {
+    int knew;              // kept columns of the block step
+    int kfinal;            // rank chosen by the truncation
+    double bnorm2;         // ||B_i||^2 of the block's projection (fp64)
+    double xnorm2;         // ||G||^2 summed by the first block's sketch
+    double gnorm2;         // ||G'||^2 of the truncated core
+};
+// Adaptive block step: Y = G_(n) Omega[:, col0 : col0 + b] (LDS-staged sketch,
+// split-K partials), its fixed-order sum (with ||G||^2 when nrm_partial is set),
+// the block orthonormalisation against Qall[:, :kcols] and the projection of G
+// on the new columns (a GProj entry).
+struct GBlock {
+    const float* G;
+    int64_t L, J, R;
+    int64_t col0;
+    uint64_t seed;
+    uint32_t mode;
+    int b;
+    int nsplit, nrowtile;
+    int64_t tiles_per_split;
+    int64_t wi0;            // first sketch work item (prefix over the group)
+    float* partial;         // nsplit * J * b
+    double* nrm_partial;    // nsplit * nrowtile, or null
+    double* Y;              // J x b
+    double* Qall;           // J x cap (fp64)
+    float* Qallf;           // J x cap (float copy)
+    int cap, kcols;
+    double drop;
+    int* knew;              // device copy of the kept count
+    GRead* rb;
+};
+// B (L, ldo, R) rows koff .. koff + ell = Q^T G over the first J mode rows of G
+// (L, ldj, R), Q float (J x ell, ld ldq); ell from *ell_dev when set (a rank
+// chosen on the device; at most ellmax).  Work items: column tiles of 256 x
+// chunks of 8 output rows; nrm_partial[item] = fp64 sum of squares of the item's
+// outputs, summed into *rb_norm (mapped) by the sum launch.
+struct GProj {
+    const float* G;
+    int64_t L, J, R, ldj;
+    const float* Q;
+    int64_t ldq;
+    int ellmax;
+    const int* ell_dev;
+    float* out;
+    int64_t ldo, koff;
+    int64_t wi0;
+    int nct, nch;
+    double* nrm_partial;
+    double* rb_norm;
+};
+// Truncation of a mode: fp64 Gram of B rows 0 .. kcols (column chunks into
+// partials), its eigendecomposition, the rank (smallest k with max(E, 0) + tail
+// <= tau2), A = Qall U_k with the sign fix (float, J x k), U_k (float, kcols x k).
+struct GTrunc {
+    const float* B;
+    int64_t L, ldk, R;
+    int kcols;
+    const double* Qall;
+    int64_t J;
+    int cap;
+    double E, tau2;
+    int64_t wi0;            // first Gram work item
+    int nchunk;             // Gram column chunks
+    double* gpart;          // nchunk * kcols * kcols
+    float* A;               // J x k
+    float* Uf;              // kcols x k, row stride kcols
+    int* kout;
+    GRead* rb;
+};
+struct GHeader {
+    int nblock, ntrunc, nbproj, ncproj;
+    int64_t sketch_items, bproj_items, gram_items, cproj_items;
+};
+// Layout of the descriptor buffer: GHeader, then maxreq GBlock, maxreq GProj
+// (block projections), maxreq GTrunc, maxreq GProj (core projections).
+size_t group_desc_bytes(int maxreq);
+// The launches of one iteration (fixed grids; empty lists return at once).
+hipError_t launch_group_iteration(const void* desc_dev, int maxreq, hipStream_t stream);
+// Sketch plan of one block (generic kernel): nsplit, nrowtile, tiles_per_split.
+void group_sketch_plan(int64_t L, int64_t J, int64_t R, int b, int& nsplit, int& nrowtile, int64_t& tps);
+// Largest J the grouped block step serves for block width b.
+int64_t group_block_maxj(int b);
+// Gram column chunks of a truncation over K columns.
+int group_gram_chunks(int64_t K);
+// the launches of the iteration, by file
+hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, hipStream_t stream);
+hipError_t launch_group_dense(const GHeader* hdr, const GBlock* blk, const GTrunc* tr, int maxreq, hipStream_t stream,
+                              int stage);
+hipError_t launch_group_tensor(const GHeader* hdr, const GBlock* blk, const GProj* bproj, const GTrunc* tr,
+                               const GProj* cproj, int maxreq, hipStream_t stream, int stage);
+
 // ---- allocation-free entry point ---------------------------------------------------------
 // Device address of the library's static scratch array on `device` (the current
 // device), taken once per device; rt_create calls it.

@@ -1,19 +1,34 @@
 // Serving: a request loop that admits float32 tensors of uneven shapes by
-// device-memory footprint and keeps several of them in flight, each on its own
-// stream, running adaptive R-STHOSVD (Alg. 5, §4) with a common tolerance.
+// device-memory footprint and keeps many of them in flight, running adaptive
+// R-STHOSVD (Alg. 5, §4) with a common tolerance.
 //
-// Requests wait in arrival order.  A slot thread takes the request at the head
-// as soon as it is free and the estimated footprint of the admitted requests
-// stays within the budget (a request is always admitted when nothing else is
-// in flight, so an oversized one cannot block the queue for ever).  Each slot
-// owns a stream (default priority, not synchronising with the null stream), a
-// library context with its workspace, and a cache of device blocks: blocks are
-// reused rather than freed, because freeing device memory synchronises the
-// whole device and would stall the other slots.  Results are copied to host
-// memory owned by the server until the caller releases them.
+// Grouped mode (the default): one executor thread drives all admitted requests
+// through the method in lock-step iterations.  Each request is a small state
+// machine (mode, block loop or truncation, error indicator E, tolerance);
+// every iteration the executor writes one descriptor per request into a pinned
+// buffer and replays one captured HIP graph: the descriptor copy, then grouped
+// launches of the block sketch, its sums, the block orthonormalisation and the
+// projection for the requests in a block loop, and of the Gram, the
+// eigensolver with rank choice and factor, and the core update for the
+// requests whose mode stopped growing (rt_group.hip, the grouped kernels of
+// rt_sketch.hip and rt_dense.hip).  The scalars each request needs (kept
+// columns, ||B_i||^2, ||X||^2, chosen rank, ||G'||^2) come back through mapped
+// pinned slots; after one wait the host applies the same decisions as the
+// single-request driver (rtucker.cpp, adaptive_impl) and admits new requests.
+// Device memory comes from an arena pool; a request is admitted when its exact
+// footprint fits the budget.
+//
+// Slots mode: each slot thread takes whole requests and runs them through
+// rt_rsthosvd_adaptive on a stream of its own (the pipelines overlap on the
+// device).  Its blocks are reused rather than freed, because freeing device
+// memory synchronises the whole device and would stall the other slots.
+//
+// Results are copied to host memory owned by the server until the caller
+// releases them.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <algorithm>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -25,11 +40,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include "rt_kernels.hpp"
 #include "rtucker.h"
-
-namespace rt {
-rt_status set_error(rt_status s, const char* msg);
-}
 
 namespace {
 
@@ -117,7 +129,27 @@ struct rt_server {
     void slot_main(int slot);
     void run(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache, float*& dX, size_t& dX_cap,
              float*& stage, size_t& stage_cap);
+    void complete(Request* r);
+    void exec_main();
 };
+
+// Marks a request done (results in its host vectors) and wakes its waiters.
+void rt_server::complete(Request* r) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        in_use -= r->footprint;
+        --in_flight;
+        r->t_done = Clock::now();
+        r->res.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+        r->res.latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+        r->res.core = r->core.data();
+        for (int i = 0; i < RT_MAXD; ++i)
+            r->res.factors[i] = (i < (int)r->factors.size() && !r->factors[i].empty()) ? r->factors[i].data() : nullptr;
+        r->done = true;
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+}
 
 void rt_server::run(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache, float*& dX, size_t& dX_cap,
                     float*& stage, size_t& stage_cap) {
@@ -229,27 +261,548 @@ void rt_server::slot_main(int slot) {
             r->res.status = RT_EHIP;
             r->err = "slot set-up failed";
         }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            in_use -= r->footprint;
-            --in_flight;
-            r->t_done = Clock::now();
-            r->res.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
-            r->res.latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-            r->res.core = r->core.data();
-            for (int i = 0; i < RT_MAXD; ++i)
-                r->res.factors[i] = (i < (int)r->factors.size() && !r->factors[i].empty()) ? r->factors[i].data()
-                                                                                            : nullptr;
-            r->done = true;
-        }
-        cv_done.notify_all();
-        cv_work.notify_all();
+        complete(r);
     }
     if (st) (void)hipStreamSynchronize(st);
     if (dX) cache.put(dX);
     if (ctx) rt_destroy(ctx);
     if (stage) (void)hipHostFree(stage);
     cache.clear();
+    if (st) (void)hipStreamDestroy(st);
+}
+
+// ---- grouped mode ------------------------------------------------------------------------
+namespace {
+
+constexpr size_t MIB = size_t(1) << 20;
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device memory of the grouped executor: chunks of at least 256 MiB, request
+// arenas placed first-fit in their free segments and merged back when freed.
+struct ArenaPool {
+    struct Chunk { char* base; size_t size; std::map<size_t, size_t> free; };
+    std::vector<Chunk> chunks;
+    size_t reserved = 0;
+    void* get(size_t bytes, size_t limit) {
+        bytes = (bytes + MIB - 1) / MIB * MIB;
+        for (auto& c : chunks)
+            for (auto it = c.free.begin(); it != c.free.end(); ++it)
+                if (it->second >= bytes) {
+                    const size_t off = it->first, sz = it->second;
+                    c.free.erase(it);
+                    if (sz > bytes) c.free[off + bytes] = sz - bytes;
+                    return c.base + off;
+                }
+        const size_t csz = std::max(bytes, size_t(256) * MIB);
+        if (reserved + csz > limit && !chunks.empty()) return nullptr;
+        void* p = nullptr;
+        if (hipMalloc(&p, csz) != hipSuccess) return nullptr;
+        Chunk c{(char*)p, csz, {}};
+        if (csz > bytes) c.free[bytes] = csz - bytes;
+        chunks.push_back(c);
+        reserved += csz;
+        return p;
+    }
+    void put(void* p, size_t bytes) {
+        bytes = (bytes + MIB - 1) / MIB * MIB;
+        for (auto& c : chunks) {
+            if ((char*)p < c.base || (char*)p >= c.base + c.size) continue;
+            size_t off = (char*)p - c.base, sz = bytes;
+            auto nx = c.free.lower_bound(off);
+            if (nx != c.free.end() && off + sz == nx->first) { sz += nx->second; nx = c.free.erase(nx); }
+            if (nx != c.free.begin()) {
+                auto pv = std::prev(nx);
+                if (pv->first + pv->second == off) { off = pv->first; sz += pv->second; c.free.erase(pv); }
+            }
+            c.free[off] = sz;
+            return;
+        }
+    }
+    void clear() {
+        for (auto& c : chunks) (void)hipFree(c.base);
+        chunks.clear();
+        reserved = 0;
+    }
+};
+
+// Per-request state of the grouped executor.
+struct GState {
+    Request* r = nullptr;
+    int slot = -1;
+    char* arena = nullptr;
+    size_t bytes = 0;
+    int d = 0;
+    int64_t dims[RT_MAXD] = {}, cdims[RT_MAXD] = {};
+    int order[RT_MAXD] = {};
+    int mi = 0;
+    const float* cur = nullptr;
+    float* core[2] = {nullptr, nullptr};
+    int pp = 0;
+    float* fac[RT_MAXD] = {};
+    int ranks[RT_MAXD] = {};
+    char* scratch = nullptr;
+    float* B = nullptr;
+    // the mode being processed
+    int n = -1;
+    int64_t L = 0, J = 0, R = 0;
+    int cap = 0, nsplit = 0, nrowtile = 0, nchunk = 0;
+    int64_t tps = 0;
+    int kcols = 0, blk = 0, bi = 0;
+    double E = 0.0, tau2 = 0.0, nx2 = 0.0, cur_norm2 = 0.0;
+    bool have_norm = false, capped = false;
+    enum Phase { BLOCK, TRUNC, DONE } phase = BLOCK;
+    // scratch views of the mode
+    float* partial = nullptr;
+    double* nrm_partial = nullptr;
+    double* Y = nullptr;
+    double* Qall = nullptr;
+    float* Qallf = nullptr;
+    double* bnrm = nullptr;
+    double* gpart = nullptr;
+    float* Uf = nullptr;
+    int* ints = nullptr;
+    double* cnrm = nullptr;
+};
+
+// Sizes of one mode's scratch (bytes) for current dims `cd`; optionally lays
+// the views out from `base`.
+size_t mode_scratch(GState* s, const int64_t* cd, int d, int n, int block, char* base) {
+    int64_t L = 1, R = 1;
+    for (int i = 0; i < n; ++i) L *= cd[i];
+    for (int i = n + 1; i < d; ++i) R *= cd[i];
+    const int64_t J = cd[n], K = L * R;
+    const int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX);
+    int nsplit = 1, nrowtile = 1;
+    int64_t tps = 1;
+    rt::group_sketch_plan(L, J, R, block, nsplit, nrowtile, tps);
+    const int64_t nct = (K + 255) / 256;
+    const int nchunk = rt::group_gram_chunks(K);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += al256(bytes); return base ? base + o : nullptr; };
+    char* partial = take((size_t)nsplit * J * block * 4);
+    char* nrm = take((size_t)nsplit * nrowtile * 8);
+    char* Y = take((size_t)J * block * 8);
+    char* Qall = take((size_t)J * cap * 8);
+    char* Qallf = take((size_t)J * cap * 4);
+    char* bnrm = take((size_t)nct * ((block + 7) / 8) * 8);
+    char* gpart = take((size_t)nchunk * cap * cap * 8);
+    char* Uf = take((size_t)cap * cap * 4);
+    char* ints = take(64);
+    char* cnrm = take((size_t)nct * ((cap + 7) / 8) * 8);
+    if (base && s) {
+        s->L = L; s->J = J; s->R = R; s->cap = cap;
+        s->nsplit = nsplit; s->nrowtile = nrowtile; s->tps = tps; s->nchunk = nchunk;
+        s->partial = (float*)partial; s->nrm_partial = (double*)nrm; s->Y = (double*)Y;
+        s->Qall = (double*)Qall; s->Qallf = (float*)Qallf; s->bnrm = (double*)bnrm;
+        s->gpart = (double*)gpart; s->Uf = (float*)Uf; s->ints = (int*)ints; s->cnrm = (double*)cnrm;
+    }
+    return off;
+}
+
+// Footprint of a request (bytes) and whether the grouped kernels serve it: the
+// input, the largest mode scratch, B and two cores at the largest (L, cap, R),
+// and the factors, with every rank bounded by its cap.
+bool group_footprint(const rt_tensor& X, int block, size_t& bytes, size_t& scratch, size_t& big) {
+    const int d = X.ndim;
+    int64_t cd[RT_MAXD];
+    int order[RT_MAXD];
+    for (int i = 0; i < d; ++i) { cd[i] = X.dims[i]; order[i] = i; }
+    std::stable_sort(order, order + d, [&](int a, int b) { return X.dims[a] > X.dims[b]; });
+    int64_t N = 1;
+    for (int i = 0; i < d; ++i) N *= cd[i];
+    bool ok = block <= 16;
+    scratch = 0;
+    big = 0;
+    size_t fac = 0;
+    for (int m = 0; m < d; ++m) {
+        const int n = order[m];
+        int64_t L = 1, R = 1;
+        for (int i = 0; i < n; ++i) L *= cd[i];
+        for (int i = n + 1; i < d; ++i) R *= cd[i];
+        const int64_t J = cd[n];
+        const int cap = (int)std::min<int64_t>(std::min<int64_t>(J, L * R), RT_LMAX);
+        if (J > rt::group_block_maxj(block)) ok = false;
+        scratch = std::max(scratch, mode_scratch(nullptr, cd, d, n, block, nullptr));
+        big = std::max(big, al256((size_t)L * cap * R * 4));
+        fac += al256((size_t)J * std::max(cap, 1) * 4);
+        cd[n] = cap;
+    }
+    bytes = al256((size_t)N * 4) + scratch + 3 * big + fac;
+    return ok;
+}
+
+}  // namespace
+
+void rt_server::exec_main() {
+    const int maxreq = opts.max_inflight;
+    const int block = opts.block;
+    hipStream_t st = nullptr;
+    char* desc_host = nullptr;
+    char* desc_dev = nullptr;
+    rt::GRead* rb_host = nullptr;
+    rt::GRead* rb_dev = nullptr;
+    float* stage = nullptr;
+    size_t stage_cap = 0;
+    const size_t dbytes = rt::group_desc_bytes(maxreq);
+    // a request the grouped kernels do not serve runs alone on a context of its own
+    BlockCache cache;
+    rt_ctx* ctx = nullptr;
+    float* dX = nullptr;
+    size_t dX_cap = 0;
+    bool ready = hipSetDevice(device) == hipSuccess &&
+                 hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+                 hipHostMalloc((void**)&desc_host, dbytes, hipHostMallocDefault) == hipSuccess &&
+                 hipMalloc((void**)&desc_dev, dbytes) == hipSuccess &&
+                 hipHostMalloc((void**)&rb_host, sizeof(rt::GRead) * maxreq, hipHostMallocMapped) == hipSuccess &&
+                 hipHostGetDevicePointer((void**)&rb_dev, rb_host, 0) == hipSuccess &&
+                 rt_create(&ctx, device, st, cache_alloc, cache_free, &cache) == RT_OK;
+    if (ready) std::memset(desc_host, 0, dbytes);
+    ArenaPool pool;
+    std::vector<GState*> active;
+    std::vector<int> free_slots;
+    for (int i = maxreq - 1; i >= 0; --i) free_slots.push_back(i);
+    hipGraphExec_t gexec = nullptr;
+    bool graph_ok = true;
+    const char* dp = desc_host;
+    rt::GHeader* hdr = (rt::GHeader*)dp;
+    dp += al256(sizeof(rt::GHeader));
+    rt::GBlock* gblk = (rt::GBlock*)dp;
+    dp += al256(sizeof(rt::GBlock) * maxreq);
+    rt::GProj* gbproj = (rt::GProj*)dp;
+    dp += al256(sizeof(rt::GProj) * maxreq);
+    rt::GTrunc* gtr = (rt::GTrunc*)dp;
+    dp += al256(sizeof(rt::GTrunc) * maxreq);
+    rt::GProj* gcproj = (rt::GProj*)dp;
+
+    auto fail = [&](GState* g, rt_status stt, const char* msg) {
+        g->r->res.status = stt;
+        g->r->err = msg;
+        g->phase = GState::DONE;
+    };
+    // the next mode of a request (or done); modes whose core has no entries, or
+    // whose core is already within the tolerance, take rank 0 without work
+    auto next_mode = [&](GState* g) {
+        for (;;) {
+            if (g->mi >= g->d) { g->phase = GState::DONE; return; }
+            const int n = g->order[g->mi];
+            int64_t N = 1;
+            for (int i = 0; i < g->d; ++i) N *= g->cdims[i];
+            if (N == 0 || (g->have_norm && !(g->cur_norm2 > g->tau2))) {
+                g->ranks[n] = 0;
+                g->cdims[n] = 0;
+                g->cur_norm2 = 0.0;
+                ++g->mi;
+                continue;
+            }
+            g->n = n;
+            mode_scratch(g, g->cdims, g->d, n, block, g->scratch);
+            g->kcols = 0;
+            g->blk = 0;
+            g->E = g->cur_norm2;
+            g->phase = GState::BLOCK;
+            return;
+        }
+    };
+    auto end_blocks = [&](GState* g) {
+        if (g->kcols > 0) { g->phase = GState::TRUNC; return; }
+        g->ranks[g->n] = 0;
+        g->cdims[g->n] = 0;
+        g->cur_norm2 = 0.0;
+        ++g->mi;
+        next_mode(g);
+    };
+    auto admit = [&](Request* r) -> bool {      // false: wait for memory
+        size_t bytes = 0, scratch = 0, big = 0;
+        group_footprint(r->X, block, bytes, scratch, big);
+        GState* g = new GState();
+        g->arena = (char*)pool.get(bytes, budget);
+        if (!g->arena) { delete g; return false; }
+        g->r = r;
+        g->bytes = bytes;
+        g->slot = free_slots.back();
+        free_slots.pop_back();
+        g->d = r->X.ndim;
+        for (int i = 0; i < g->d; ++i) { g->dims[i] = g->cdims[i] = r->X.dims[i]; g->order[i] = i; }
+        std::stable_sort(g->order, g->order + g->d, [&](int a, int b) { return g->dims[a] > g->dims[b]; });
+        int64_t N = 1;
+        for (int i = 0; i < g->d; ++i) N *= g->dims[i];
+        char* p = g->arena;
+        float* X = (float*)p;
+        p += al256((size_t)N * 4);
+        g->scratch = p;
+        p += scratch;
+        g->B = (float*)p;
+        p += big;
+        g->core[0] = (float*)p;
+        p += big;
+        g->core[1] = (float*)p;
+        p += big;
+        int64_t cd[RT_MAXD];
+        for (int i = 0; i < g->d; ++i) cd[i] = g->dims[i];
+        for (int m = 0; m < g->d; ++m) {
+            const int n = g->order[m];
+            int64_t K = 1;
+            for (int i = 0; i < g->d; ++i) if (i != n) K *= cd[i];
+            const int cap = (int)std::min<int64_t>(std::min<int64_t>(cd[n], K), RT_LMAX);
+            g->fac[n] = (float*)p;
+            p += al256((size_t)cd[n] * std::max(cap, 1) * 4);
+            cd[n] = cap;
+        }
+        r->res.ndim = g->d;
+        for (int i = 0; i < g->d; ++i) r->res.dims[i] = g->dims[i];
+        r->res.status = RT_OK;
+        if (hipMemcpyAsync(X, r->X.data, (size_t)N * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            fail(g, RT_EHIP, "host to device copy failed");
+        g->cur = X;
+        g->mi = 0;
+        if (g->phase != GState::DONE) next_mode(g);
+        active.push_back(g);
+        return true;
+    };
+    auto finish = [&](GState* g) {
+        Request* r = g->r;
+        if (r->res.status == RT_OK || r->res.status == RT_ECAP) {
+            int64_t ncore = 1;
+            for (int i = 0; i < g->d; ++i) ncore *= g->cdims[i];
+            int64_t total = ncore;
+            for (int i = 0; i < g->d; ++i) total += g->dims[i] * g->ranks[i];
+            bool ok = true;
+            if ((size_t)total > stage_cap) {
+                if (stage) (void)hipHostFree(stage);
+                stage = nullptr;
+                stage_cap = 0;
+                ok = hipHostMalloc((void**)&stage, (size_t)std::max<int64_t>(total, 1) * 4, hipHostMallocDefault) ==
+                     hipSuccess;
+                if (ok) stage_cap = (size_t)std::max<int64_t>(total, 1);
+            }
+            if (ok && ncore > 0)
+                ok = hipMemcpyAsync(stage, g->cur, (size_t)ncore * 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+            int64_t off = ncore;
+            for (int i = 0; i < g->d && ok; ++i) {
+                const int64_t nf = g->dims[i] * g->ranks[i];
+                if (nf > 0)
+                    ok = hipMemcpyAsync(stage + off, g->fac[i], (size_t)nf * 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+                off += nf;
+            }
+            ok = ok && hipStreamSynchronize(st) == hipSuccess;
+            if (!ok) {
+                r->res.status = RT_EHIP;
+                r->err = "device to host copy failed";
+            } else {
+                r->core.assign(stage, stage + ncore);
+                r->factors.assign(g->d, std::vector<float>());
+                off = ncore;
+                for (int i = 0; i < g->d; ++i) {
+                    const int64_t nf = g->dims[i] * g->ranks[i];
+                    r->factors[i].assign(stage + off, stage + off + nf);
+                    off += nf;
+                    r->res.ranks[i] = g->ranks[i];
+                }
+                r->res.norm_x = std::sqrt(std::max(g->nx2, 0.0));
+                r->res.core_norm = std::sqrt(std::max(g->cur_norm2, 0.0));
+                r->res.rel_err_est = r->res.norm_x > 0
+                                         ? std::sqrt(std::max(0.0, g->nx2 - g->cur_norm2)) / r->res.norm_x : 0.0;
+                r->res.flags = 0;
+                if (g->capped) {
+                    r->res.status = RT_ECAP;
+                    r->err = "a mode reached its rank cap before the tolerance";
+                }
+            }
+        }
+        pool.put(g->arena, g->bytes);
+        free_slots.push_back(g->slot);
+        delete g;
+        complete(r);
+    };
+
+    const double eps_n_base = opts.eps;
+    for (;;) {
+        // admission: arrival order, while a slot is free and the footprint fits
+        for (;;) {
+            Request* r = nullptr;
+            bool alone = false;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (active.empty())
+                    cv_work.wait(lk, [&] { return !queue.empty() || stopping; });
+                if (queue.empty() || (int)active.size() >= maxreq) break;
+                Request* h = queue.front();
+                size_t bytes = 0, scratch = 0, big = 0;
+                alone = !group_footprint(h->X, block, bytes, scratch, big);
+                if (!alone && !active.empty() && in_use + bytes > budget) break;
+                queue.pop_front();
+                h->footprint = bytes;
+                in_use += alone ? 0 : bytes;
+                ++in_flight;
+                h->t_admit = Clock::now();
+                r = h;
+            }
+            if (!ready) {
+                r->res.status = RT_EHIP;
+                r->err = "executor set-up failed";
+                complete(r);
+                continue;
+            }
+            if (alone) {
+                r->footprint = 0;
+                run(r, ctx, st, cache, dX, dX_cap, stage, stage_cap);
+                complete(r);
+                continue;
+            }
+            if (!admit(r)) {
+                if (!active.empty()) {
+                    // no memory now: back to the head of the queue until requests finish
+                    std::lock_guard<std::mutex> lk(mu);
+                    in_use -= r->footprint;
+                    --in_flight;
+                    queue.push_front(r);
+                    break;
+                }
+                r->res.status = RT_ENOMEM;
+                r->err = "device allocation failed";
+                complete(r);
+            }
+        }
+        if (active.empty()) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (stopping && queue.empty()) break;
+            continue;
+        }
+        // requests that finished without device work (rank 0 everywhere, failures)
+        for (size_t i = 0; i < active.size();) {
+            if (active[i]->phase == GState::DONE) { finish(active[i]); active.erase(active.begin() + i); }
+            else ++i;
+        }
+        if (active.empty()) continue;
+        // descriptors of this iteration
+        std::memset(hdr, 0, sizeof(rt::GHeader));
+        int nb = 0, nt = 0;
+        int64_t swi = 0, pwi = 0, gwi = 0, cwi = 0;
+        for (GState* g : active) {
+            const int64_t K = g->L * g->R;
+            const int64_t nct = (K + 255) / 256;
+            rt::GRead* rb = rb_dev + g->slot;
+            if (g->phase == GState::BLOCK) {
+                g->bi = std::min(block, g->cap - g->kcols);
+                rt::GBlock& b = gblk[nb];
+                b.G = g->cur; b.L = g->L; b.J = g->J; b.R = g->R;
+                b.col0 = (int64_t)g->blk * block;
+                b.seed = g->r->seed;
+                b.mode = (uint32_t)g->n;
+                b.b = g->bi;
+                b.nsplit = g->nsplit; b.nrowtile = g->nrowtile; b.tiles_per_split = g->tps;
+                b.wi0 = swi;
+                swi += (int64_t)g->nsplit * g->nrowtile;
+                b.partial = g->partial;
+                b.nrm_partial = g->have_norm ? nullptr : g->nrm_partial;
+                b.Y = g->Y; b.Qall = g->Qall; b.Qallf = g->Qallf; b.cap = g->cap; b.kcols = g->kcols;
+                b.drop = 1e-5;
+                b.knew = g->ints;
+                b.rb = rb;
+                rt::GProj& q = gbproj[nb];
+                q.G = g->cur; q.L = g->L; q.J = g->J; q.R = g->R; q.ldj = g->J;
+                q.Q = g->Qallf + g->kcols; q.ldq = g->cap;
+                q.ellmax = g->bi; q.ell_dev = nullptr;
+                q.out = g->B; q.ldo = g->cap; q.koff = g->kcols;
+                q.wi0 = pwi; q.nct = (int)nct; q.nch = (g->bi + 7) / 8;
+                pwi += nct * q.nch;
+                q.nrm_partial = g->bnrm;
+                q.rb_norm = &rb->bnorm2;
+                ++nb;
+            } else if (g->phase == GState::TRUNC) {
+                rt::GTrunc& t = gtr[nt];
+                t.B = g->B; t.L = g->L; t.ldk = g->cap; t.R = g->R; t.kcols = g->kcols;
+                t.Qall = g->Qall; t.J = g->J; t.cap = g->cap;
+                t.E = g->E; t.tau2 = g->tau2;
+                t.wi0 = gwi; t.nchunk = g->nchunk;
+                gwi += g->nchunk;
+                t.gpart = g->gpart; t.A = g->fac[g->n]; t.Uf = g->Uf; t.kout = g->ints + 1; t.rb = rb;
+                rt::GProj& q = gcproj[nt];
+                q.G = g->B; q.L = g->L; q.J = g->kcols; q.R = g->R; q.ldj = g->cap;
+                q.Q = g->Uf; q.ldq = g->kcols;
+                q.ellmax = g->kcols; q.ell_dev = g->ints + 1;
+                q.out = g->core[g->pp]; q.ldo = 0; q.koff = 0;
+                q.wi0 = cwi; q.nct = (int)nct; q.nch = (g->kcols + 7) / 8;
+                cwi += nct * q.nch;
+                q.nrm_partial = g->cnrm;
+                q.rb_norm = &rb->gnorm2;
+                ++nt;
+            }
+        }
+        hdr->nblock = nb; hdr->nbproj = nb; hdr->ntrunc = nt; hdr->ncproj = nt;
+        hdr->sketch_items = swi; hdr->bproj_items = pwi; hdr->gram_items = gwi; hdr->cproj_items = cwi;
+        // one graph: the descriptor copy and the iteration's launches (captured
+        // once, replayed every iteration with the pinned buffer's new contents)
+        bool launched = false;
+        if (graph_ok && !gexec) {
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const bool body = hipMemcpyAsync(desc_dev, desc_host, dbytes, hipMemcpyHostToDevice, st) == hipSuccess &&
+                                  rt::launch_group_iteration(desc_dev, maxreq, st) == hipSuccess;
+                ok = hipStreamEndCapture(st, &graph) == hipSuccess && body && graph;
+            }
+            ok = ok && hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!ok) {
+                graph_ok = false;
+                gexec = nullptr;
+                (void)hipGetLastError();
+            }
+        }
+        if (graph_ok && gexec) launched = hipGraphLaunch(gexec, st) == hipSuccess;
+        if (!launched)
+            launched = hipMemcpyAsync(desc_dev, desc_host, dbytes, hipMemcpyHostToDevice, st) == hipSuccess &&
+                       rt::launch_group_iteration(desc_dev, maxreq, st) == hipSuccess;
+        const bool synced = launched && hipStreamSynchronize(st) == hipSuccess;
+        // advance every request from its readback slot
+        for (GState* g : active) {
+            if (!synced) { fail(g, RT_EHIP, "grouped launch failed"); continue; }
+            const rt::GRead& rb = rb_host[g->slot];
+            if (g->phase == GState::BLOCK) {
+                if (!g->have_norm) {
+                    g->nx2 = rb.xnorm2;
+                    if (!std::isfinite(g->nx2)) { fail(g, RT_ENONFINITE, "input holds NaN or Inf"); continue; }
+                    g->have_norm = true;
+                    const double en = eps_n_base / std::sqrt((double)g->d) * std::sqrt(g->nx2);
+                    g->tau2 = en * en;
+                    g->E = g->nx2;
+                    g->cur_norm2 = g->nx2;
+                    if (!(g->E > g->tau2)) { end_blocks(g); continue; }   // the block is discarded
+                }
+                ++g->blk;
+                const int kn = rb.knew;
+                if (kn <= 0) { end_blocks(g); continue; }                  // range exhausted
+                g->E -= rb.bnorm2;
+                g->kcols += kn;
+                if (!(g->E > g->tau2)) end_blocks(g);
+                else if (g->kcols >= g->cap) { g->capped = true; end_blocks(g); }
+            } else if (g->phase == GState::TRUNC) {
+                const int k = rb.kfinal;
+                g->ranks[g->n] = k;
+                g->cdims[g->n] = k;
+                g->cur_norm2 = rb.gnorm2;
+                g->cur = g->core[g->pp];
+                g->pp ^= 1;
+                ++g->mi;
+                next_mode(g);
+            }
+        }
+        for (size_t i = 0; i < active.size();) {
+            if (active[i]->phase == GState::DONE) { finish(active[i]); active.erase(active.begin() + i); }
+            else ++i;
+        }
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (dX) cache.put(dX);
+    if (ctx) rt_destroy(ctx);
+    cache.clear();
+    pool.clear();
+    if (stage) (void)hipHostFree(stage);
+    if (desc_host) (void)hipHostFree(desc_host);
+    if (desc_dev) (void)hipFree(desc_dev);
+    if (rb_host) (void)hipHostFree(rb_host);
     if (st) (void)hipStreamDestroy(st);
 }
 
@@ -263,6 +816,10 @@ rt_status rt_server_create(rt_server** srv, int device, const rt_server_opts* op
         return rt::set_error(RT_EINVAL, "serving precision must be RT_PREC_F32 or RT_PREC_BF16_SKETCH");
     if (!(opts->eps >= 0.0) || !std::isfinite(opts->eps)) return rt::set_error(RT_EINVAL, "eps must be finite and >= 0");
     if (opts->block < 1 || opts->block > RT_LMAX) return rt::set_error(RT_EINVAL, "block must be in [1, RT_LMAX]");
+    if (opts->mode != RT_SERVE_GROUPED && opts->mode != RT_SERVE_SLOTS)
+        return rt::set_error(RT_EINVAL, "mode must be RT_SERVE_GROUPED or RT_SERVE_SLOTS");
+    if (opts->mode == RT_SERVE_GROUPED && (opts->prec != RT_PREC_F32 || opts->block > 16))
+        return rt::set_error(RT_EINVAL, "grouped serving runs float32 sketches with blocks of at most 16 columns");
     if (hipSetDevice(device) != hipSuccess) return rt::set_error(RT_EHIP, "hipSetDevice failed");
     size_t budget = opts->hbm_budget;
     if (budget == 0) {
@@ -275,7 +832,10 @@ rt_status rt_server_create(rt_server** srv, int device, const rt_server_opts* op
     s->opts = *opts;
     s->budget = budget;
     s->slot_errors.assign(opts->max_inflight, std::string());
-    for (int i = 0; i < opts->max_inflight; ++i) s->threads.emplace_back(&rt_server::slot_main, s, i);
+    if (opts->mode == RT_SERVE_GROUPED)
+        s->threads.emplace_back(&rt_server::exec_main, s);
+    else
+        for (int i = 0; i < opts->max_inflight; ++i) s->threads.emplace_back(&rt_server::slot_main, s, i);
     *srv = s;
     return RT_OK;
 }

@@ -22,11 +22,13 @@ constexpr int SK_NACC = LMAX / 4;
 // EXPL: Omega is not generated but read from Om, an (L, ell, R) row-major tensor
 // with Omega[l R + r][k] = Om[(l ell + k) R + r] (the subspace-iteration product
 // Y = X_(n) Z with Z = Om_(n)^T); seed, mode and col0 are unused.
-template <typename TX, typename TA, bool EXPL = false>
-__global__ __launch_bounds__(256) void sketch_generic_kernel(
+// The work of one workgroup (split `split`, row tile `rowtile` of nsplit
+// splits), shared by the per-request kernel below and the grouped one.
+template <typename TX, typename TA, bool EXPL>
+__device__ __forceinline__ void sketch_generic_tile(
     const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
     uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
-    double* __restrict__ nrm2_partial, const TX* __restrict__ Om = nullptr) {
+    double* __restrict__ nrm2_partial, const TX* __restrict__ Om, int64_t split, int64_t rowtile, int64_t nsplit) {
     __shared__ TA xs[SK_KC][SK_MT + 1];
     __shared__ TA om[SK_KC][LMAX + 4];
     __shared__ double red[256];
@@ -36,8 +38,8 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
     const int kg = tid / SK_MT;            // wave index: columns kg, kg + 4, ...
     const int64_t K = L * R;
     const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
-    const int64_t row0 = (int64_t)blockIdx.y * SK_MT;
-    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_split;
+    const int64_t row0 = rowtile * SK_MT;
+    const int64_t t_begin = split * tiles_per_split;
     const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
     const int64_t q_first = col0 / 4;
     const int64_t q_last = (col0 + ell - 1) / 4;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
     }
     const int64_t i = row0 + row;
     if (i < J) {
-        TA* dst = partial + ((int64_t)blockIdx.x * J + i) * ell;
+        TA* dst = partial + (split * J + i) * ell;
 #pragma unroll
         for (int j = 0; j < SK_NACC; ++j) {
             const int k = kg + 4 * j;
@@ -119,7 +121,39 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
             if (tid < s) red[tid] += red[tid + s];
             __syncthreads();
         }
-        if (tid == 0) nrm2_partial[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        if (tid == 0) nrm2_partial[rowtile * nsplit + split] = red[0];
+    }
+}
+
+template <typename TX, typename TA, bool EXPL = false>
+__global__ __launch_bounds__(256) void sketch_generic_kernel(
+    const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
+    uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
+    double* __restrict__ nrm2_partial, const TX* __restrict__ Om = nullptr) {
+    sketch_generic_tile<TX, TA, EXPL>(X, L, J, R, ell, col0, seed, mode, tiles_per_split, partial, nrm2_partial, Om,
+                                      blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Grouped block sketches: work item w of the group belongs to the request whose
+// [wi0, wi0 + nsplit nrowtile) holds it (wi0 ascending); the workgroups of the
+// fixed grid take items w = blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ __launch_bounds__(256) void sketch_group_kernel(const GHeader* __restrict__ hdr,
+                                                           const GBlock* __restrict__ d) {
+    const int n = hdr->nblock;
+    const int64_t total = hdr->sketch_items;
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {                      // last request with wi0 <= w
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].wi0 <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const GBlock& q = d[lo];
+        const int64_t local = w - q.wi0;
+        sketch_generic_tile<float, float, false>(q.G, q.L, q.J, q.R, q.b, q.col0, q.seed, q.mode, q.tiles_per_split,
+                                                 q.partial, q.nrm_partial, nullptr, local % q.nsplit,
+                                                 local / q.nsplit, q.nsplit);
+        __syncthreads();
     }
 }
 
@@ -316,6 +350,25 @@ hipError_t launch_reduce_rows(const void* in, bool in_is_f64, int64_t nparts, in
 hipError_t launch_reduce_partials(const void* in, bool in_is_f64, int64_t nparts, int64_t n,
                                   double* out, hipStream_t stream, double* tmp) {
     return launch_reduce_rows(in, in_is_f64, nparts, 1, n, n, out, stream, tmp);
+}
+
+void group_sketch_plan(int64_t L, int64_t J, int64_t R, int b, int& nsplit, int& nrowtile, int64_t& tps) {
+    // the generic kernel's plan for a request of its own (depends on the shape only)
+    const int64_t K = L * R;
+    const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
+    nrowtile = (int)((J + SK_MT - 1) / SK_MT);
+    int64_t want = 64 / nrowtile;
+    if (want < 1) want = 1;
+    if (want > ntiles) want = ntiles;
+    tps = (ntiles + want - 1) / want;
+    nsplit = (int)((ntiles + tps - 1) / tps);
+    if (nsplit < 1) nsplit = 1;
+    (void)b;
+}
+
+hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, hipStream_t stream) {
+    hipLaunchKernelGGL(sketch_group_kernel, dim3(1024), dim3(256), 0, stream, hdr, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum_scalar(const double* in, int64_t n, double* out, hipStream_t stream) {

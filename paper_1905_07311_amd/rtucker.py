@@ -56,7 +56,11 @@ class rt_tucker(ctypes.Structure):
 
 class rt_server_opts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("prec", ctypes.c_int),
-                ("eps", ctypes.c_double), ("block", ctypes.c_int32)]
+                ("eps", ctypes.c_double), ("block", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+RT_SERVE_GROUPED, RT_SERVE_SLOTS = 0, 1
+SERVE_MODE = {"grouped": RT_SERVE_GROUPED, "slots": RT_SERVE_SLOTS}
 
 
 class rt_result(ctypes.Structure):
@@ -487,9 +491,12 @@ class ServedResult:
 class Server:
     """Continuous-batching server of adaptive R-STHOSVD requests (float32 host
     tensors in, host results out).  submit() takes a CPU float32 tensor (ideally
-    page-locked) that must stay alive until the request completes."""
+    page-locked) that must stay alive until the request completes.  mode:
+    "grouped" (every admitted request advanced by shared launches in lock-step
+    iterations, float32 sketches) or "slots" (whole requests on per-slot
+    streams); default grouped for float32, slots for the bfloat16 sketch."""
 
-    def __init__(self, device=0, max_inflight=8, eps=1e-3, block=8, prec="f32", hbm_budget=0):
+    def __init__(self, device=0, max_inflight=8, eps=1e-3, block=8, prec="f32", hbm_budget=0, mode=None):
         load()
         o = rt_server_opts()
         o.max_inflight = int(max_inflight)
@@ -497,6 +504,9 @@ class Server:
         o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
         o.eps = float(eps)
         o.block = int(block)
+        if mode is None:
+            mode = "grouped" if o.prec == PREC["f32"] else "slots"
+        o.mode = SERVE_MODE[mode] if isinstance(mode, str) else int(mode)
         self.srv = ctypes.c_void_p()
         _check(_lib.rt_server_create(ctypes.byref(self.srv), int(device), ctypes.byref(o)))
         self._keep = {}
@@ -522,12 +532,16 @@ class Server:
         dims = [int(r.dims[i]) for i in range(r.ndim)]
         core = factors = None
         if r.status in (RT_OK, RT_ECAP):
-            core = np.ctypeslib.as_array(r.core, shape=(int(np.prod(ranks)),)).copy().reshape(ranks)
+            ncore = int(np.prod(ranks))
+            core = (np.ctypeslib.as_array(r.core, shape=(ncore,)).copy().reshape(ranks) if ncore > 0 and r.core
+                    else np.zeros(ranks, dtype=np.float32))
             factors = []
             for i in range(r.ndim):
-                if r.factors[i]:
+                if r.factors[i] and ranks[i] > 0:
                     factors.append(np.ctypeslib.as_array(r.factors[i], shape=(dims[i] * ranks[i],)).copy()
                                    .reshape(dims[i], ranks[i]))
+                elif ranks[i] == 0:
+                    factors.append(np.zeros((dims[i], 0), dtype=np.float32))
                 else:
                     factors.append(None)
         out = ServedResult(int(r.status), ranks, core, factors, r.norm_x, r.core_norm, r.rel_err_est, int(r.flags),
