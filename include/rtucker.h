@@ -319,7 +319,9 @@ rt_status rt_sync(rt_ctx* ctx);
  * choice and factor, core update); the iteration is one captured HIP graph
  * (descriptor copy plus the launches, replayed every iteration) followed by one
  * wait, after which the host advances every request (next block, truncation,
- * next mode, done) and admits new ones.  A request's footprint is the exact
+ * next mode, done).  While an iteration runs, the host copies out the results
+ * of requests finished by the previous one and admits new requests, whose
+ * inputs cross on two copy streams and join the next iteration.  A request's footprint is the exact
  * workspace of its shape (input, basis, projections, cores, factors).  A request
  * whose block step does not fit the grouped kernel (a mode longer than 910 rows
  * for blocks of 8) runs alone through rt_rsthosvd_adaptive.  Float32 sketches.
@@ -371,6 +373,23 @@ rt_status rt_server_wait(rt_server* srv, uint64_t ticket, rt_result* out);
 
 /* Free the host result of a completed request (its pointers become invalid). */
 rt_status rt_server_release(rt_server* srv, uint64_t ticket);
+
+/* Counters of the grouped executor since creation (slots mode: zeros apart
+ * from `completed`).  Per iteration the executor launches, then does the host
+ * work that does not feed this iteration (result copies of the last one,
+ * admission of new requests: overlap_s), then blocks on the device (wait_s);
+ * host_s is its remaining time (descriptors, launch, readback), which the
+ * device spends idle.  The three add up to the executor's wall time while
+ * requests are in flight. */
+typedef struct {
+    int64_t iterations;       /* grouped iterations launched */
+    int64_t request_steps;    /* requests advanced, summed over iterations */
+    int64_t completed;        /* requests completed */
+    double wait_s;
+    double host_s;
+    double overlap_s;
+} rt_server_stats;
+rt_status rt_server_get_stats(rt_server* srv, rt_server_stats* out);
 
 /* Finish the queued requests, stop the threads, free all memory. */
 rt_status rt_server_destroy(rt_server* srv);

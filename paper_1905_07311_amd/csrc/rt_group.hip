@@ -142,64 +142,79 @@ __global__ __launch_bounds__(256) void proj_norm_group_kernel(const GHeader* __r
 }
 
 // fp64 Gram partial of B rows 0 .. n over the columns of chunk `ch`:
-// gpart[ch][u][v] = sum_c B[u][c] B[v][c] (float products exact in fp64);
-// threads own (u, v) pairs u <= v, columns staged GG_TC at a time.
+// gpart[ch][u][v] = sum_c B[u][c] B[v][c] (float products exact in fp64).
+// Thread (tile p, group g) owns the 4 x 4 tile p of the upper triangle and the
+// staged columns g, g + G, ... of every 64-column tile (8 LDS reads per 16
+// fmas); the G partial tiles of a tile are then added in group order.
 __device__ void gram_item(const GTrunc& q, int ch) {
     __shared__ double bs[LMAX][GG_TC + 1];
+    __shared__ double red[256 * 16];
     const int n = q.kcols;
     const int tid = threadIdx.x;
     const int64_t K = q.L * q.R;
     const int64_t per = (K + q.nchunk - 1) / q.nchunk;
     const int64_t c0 = (int64_t)ch * per;
     const int64_t c1 = c0 + per < K ? c0 + per : K;
-    const int npairs = n * (n + 1) / 2;
-    constexpr int PMAX = (LMAX * (LMAX + 1) / 2 + 255) / 256;
-    int pu[PMAX], pv[PMAX];
-    double acc[PMAX];
-#pragma unroll
-    for (int m = 0; m < PMAX; ++m) {
-        const int p = tid + 256 * m;
-        int u = 0, v = 0;
-        if (p < npairs) {
-            // pair p of the upper triangle, row by row
-            int rem = p;
-            while (rem >= n - u) { rem -= n - u; ++u; }
-            v = u + rem;
-        }
-        pu[m] = p < npairs ? u : -1;
-        pv[m] = v;
-        acc[m] = 0.0;
+    const int nt4 = (n + 3) / 4;
+    const int npt = nt4 * (nt4 + 1) / 2;
+    const int G = 256 / npt;                 // >= 1 (npt <= 136)
+    const int pr = tid / G, g = tid - pr * G;
+    const bool own = pr < npt;
+    int ti = 0, tj = 0;
+    {
+        int rem = own ? pr : 0;
+        while (rem >= nt4 - ti) { rem -= nt4 - ti; ++ti; }
+        tj = ti + rem;
     }
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
     for (int64_t t0 = c0; t0 < c1; t0 += GG_TC) {
         const int cols = (int)(c1 - t0 < GG_TC ? c1 - t0 : GG_TC);
         __syncthreads();
-        for (int e = tid; e < n * GG_TC; e += 256) {
+        for (int e = tid; e < LMAX * GG_TC; e += 256) {
             const int u = e / GG_TC, cc = e % GG_TC;
             double x = 0.0;
-            if (cc < cols) {
+            if (cc < cols && u < n) {
                 const int64_t c = t0 + cc, l = c / q.R, r = c - l * q.R;
                 x = (double)q.B[(l * q.ldk + u) * q.R + r];
             }
             bs[u][cc] = x;
         }
         __syncthreads();
+        if (own) {
+            for (int cc = g; cc < cols; cc += G) {
+                double xa[4], xb[4];
 #pragma unroll
-        for (int m = 0; m < PMAX; ++m) {
-            if (pu[m] >= 0) {
-                const double* bu = bs[pu[m]];
-                const double* bv = bs[pv[m]];
-                double s = acc[m];
-                for (int cc = 0; cc < cols; ++cc) s = fma(bu[cc], bv[cc], s);
-                acc[m] = s;
+                for (int x = 0; x < 4; ++x) { xa[x] = bs[4 * ti + x][cc]; xb[x] = bs[4 * tj + x][cc]; }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(xa[x], xb[y], acc[x][y]);
             }
         }
     }
-    double* out = q.gpart + (int64_t)ch * n * n;
+    __syncthreads();
+    if (own) {
 #pragma unroll
-    for (int m = 0; m < PMAX; ++m) {
-        if (pu[m] >= 0) {
-            out[pu[m] * n + pv[m]] = acc[m];
-            out[pv[m] * n + pu[m]] = acc[m];
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) red[(g * npt + pr) * 16 + 4 * x + y] = acc[x][y];
+    }
+    __syncthreads();
+    double* out = q.gpart + (int64_t)ch * n * n;
+    for (int e = tid; e < npt * 16; e += 256) {
+        const int p = e / 16, xy = e % 16, x = xy / 4, y = xy % 4;
+        double sum = 0.0;
+        for (int gg = 0; gg < G; ++gg) sum += red[(gg * npt + p) * 16 + xy];
+        int rem = p, a = 0;
+        while (rem >= nt4 - a) { rem -= nt4 - a; ++a; }
+        const int u = 4 * a + x, v = 4 * (a + rem) + y;
+        if (u < n && v < n) {
+            out[u * n + v] = sum;
+            out[v * n + u] = sum;
         }
     }
 }
@@ -253,7 +268,7 @@ hipError_t launch_group_tensor(const GHeader* hdr, const GBlock* blk, const GPro
     return hipGetLastError();
 }
 
-hipError_t launch_group_iteration(const void* desc_dev, int maxreq, hipStream_t stream) {
+hipError_t launch_group_iteration(const void* desc_dev, int maxreq, int block, hipStream_t stream) {
     const char* p = (const char*)desc_dev;
     const GHeader* hdr = (const GHeader*)p;
     p += align256(sizeof(GHeader));
@@ -266,7 +281,7 @@ hipError_t launch_group_iteration(const void* desc_dev, int maxreq, hipStream_t 
     const GProj* cproj = (const GProj*)p;
     hipError_t e;
     // block steps: sketch, its sums, the orthonormalisation, the projection
-    if ((e = launch_group_sketch(hdr, blk, stream)) != hipSuccess) return e;
+    if ((e = launch_group_sketch(hdr, blk, block, stream)) != hipSuccess) return e;
     if ((e = launch_group_tensor(hdr, blk, bproj, tr, cproj, maxreq, stream, 0)) != hipSuccess) return e;
     if ((e = launch_group_dense(hdr, blk, tr, maxreq, stream, 0)) != hipSuccess) return e;
     if ((e = launch_group_tensor(hdr, blk, bproj, tr, cproj, maxreq, stream, 1)) != hipSuccess) return e;

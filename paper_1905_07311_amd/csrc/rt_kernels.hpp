@@ -298,7 +298,7 @@ struct GHeader {
 // (block projections), maxreq GTrunc, maxreq GProj (core projections).
 size_t group_desc_bytes(int maxreq);
 // The launches of one iteration (fixed grids; empty lists return at once).
-hipError_t launch_group_iteration(const void* desc_dev, int maxreq, hipStream_t stream);
+hipError_t launch_group_iteration(const void* desc_dev, int maxreq, int block, hipStream_t stream);
 // Sketch plan of one block (generic kernel): nsplit, nrowtile, tiles_per_split.
 void group_sketch_plan(int64_t L, int64_t J, int64_t R, int b, int& nsplit, int& nrowtile, int64_t& tps);
 // Largest J the grouped block step serves for block width b.
@@ -306,7 +306,7 @@ int64_t group_block_maxj(int b);
 // Gram column chunks of a truncation over K columns.
 int group_gram_chunks(int64_t K);
 // the launches of the iteration, by file
-hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, hipStream_t stream);
+hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, int block, hipStream_t stream);
 hipError_t launch_group_dense(const GHeader* hdr, const GBlock* blk, const GTrunc* tr, int maxreq, hipStream_t stream,
                               int stage);
 hipError_t launch_group_tensor(const GHeader* hdr, const GBlock* blk, const GProj* bproj, const GTrunc* tr,

@@ -124,6 +124,7 @@ struct rt_server {
     bool stopping = false;
     std::vector<std::thread> threads;
     std::vector<std::string> slot_errors;
+    rt_server_stats stats{};
 
     bool admissible(const Request* r) const { return in_flight == 0 || in_use + r->footprint <= budget; }
     void slot_main(int slot);
@@ -146,6 +147,7 @@ void rt_server::complete(Request* r) {
         for (int i = 0; i < RT_MAXD; ++i)
             r->res.factors[i] = (i < (int)r->factors.size() && !r->factors[i].empty()) ? r->factors[i].data() : nullptr;
         r->done = true;
+        ++stats.completed;
     }
     cv_done.notify_all();
     cv_work.notify_all();
@@ -351,6 +353,9 @@ struct GState {
     double E = 0.0, tau2 = 0.0, nx2 = 0.0, cur_norm2 = 0.0;
     bool have_norm = false, capped = false;
     enum Phase { BLOCK, TRUNC, DONE } phase = BLOCK;
+    hipEvent_t ev = nullptr;  // completion of the input copy, then of the result copy
+    int cs = 0;               // copy stream of both copies (stream order keeps them apart)
+    int64_t ncore = 0;        // result: core entries (staged first, then the factors)
     // scratch views of the mode
     float* partial = nullptr;
     double* nrm_partial = nullptr;
@@ -449,8 +454,15 @@ void rt_server::exec_main() {
     rt_ctx* ctx = nullptr;
     float* dX = nullptr;
     size_t dX_cap = 0;
+    hipStream_t cst[2] = {nullptr, nullptr};   // copy streams (inputs in, results out)
+    int ccur = 0;
+    std::vector<hipEvent_t> evpool;
+    std::vector<float*> sstage(maxreq, nullptr);   // pinned result staging per slot
+    std::vector<size_t> scap(maxreq, 0);
     bool ready = hipSetDevice(device) == hipSuccess &&
                  hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+                 hipStreamCreateWithFlags(&cst[0], hipStreamNonBlocking) == hipSuccess &&
+                 hipStreamCreateWithFlags(&cst[1], hipStreamNonBlocking) == hipSuccess &&
                  hipHostMalloc((void**)&desc_host, dbytes, hipHostMallocDefault) == hipSuccess &&
                  hipMalloc((void**)&desc_dev, dbytes) == hipSuccess &&
                  hipHostMalloc((void**)&rb_host, sizeof(rt::GRead) * maxreq, hipHostMallocMapped) == hipSuccess &&
@@ -459,6 +471,13 @@ void rt_server::exec_main() {
     if (ready) std::memset(desc_host, 0, dbytes);
     ArenaPool pool;
     std::vector<GState*> active;
+    std::vector<GState*> pending, draining;   // input copy issued / result copy issued
+    auto get_event = [&]() -> hipEvent_t {
+        if (!evpool.empty()) { hipEvent_t e = evpool.back(); evpool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    };
     std::vector<int> free_slots;
     for (int i = maxreq - 1; i >= 0; --i) free_slots.push_back(i);
     hipGraphExec_t gexec = nullptr;
@@ -551,88 +570,131 @@ void rt_server::exec_main() {
         r->res.ndim = g->d;
         for (int i = 0; i < g->d; ++i) r->res.dims[i] = g->dims[i];
         r->res.status = RT_OK;
-        if (hipMemcpyAsync(X, r->X.data, (size_t)N * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+        // the input crosses on a copy stream while the current iteration computes;
+        // the request joins the iteration after (or at once when none is running)
+        g->cs = ccur;
+        hipStream_t cs = cst[ccur];
+        ccur ^= 1;
+        g->ev = get_event();
+        if (!g->ev || hipMemcpyAsync(X, r->X.data, (size_t)N * 4, hipMemcpyHostToDevice, cs) != hipSuccess ||
+            hipEventRecord(g->ev, cs) != hipSuccess)
             fail(g, RT_EHIP, "host to device copy failed");
         g->cur = X;
         g->mi = 0;
         if (g->phase != GState::DONE) next_mode(g);
-        active.push_back(g);
+        pending.push_back(g);
         return true;
     };
-    auto finish = [&](GState* g) {
+    // results: core and factors copied into the slot's pinned staging on a copy
+    // stream; the request completes once that copy is done (complete_drain)
+    auto start_drain = [&](GState* g) {
         Request* r = g->r;
         if (r->res.status == RT_OK || r->res.status == RT_ECAP) {
             int64_t ncore = 1;
             for (int i = 0; i < g->d; ++i) ncore *= g->cdims[i];
+            g->ncore = ncore;
             int64_t total = ncore;
             for (int i = 0; i < g->d; ++i) total += g->dims[i] * g->ranks[i];
             bool ok = true;
-            if ((size_t)total > stage_cap) {
-                if (stage) (void)hipHostFree(stage);
-                stage = nullptr;
-                stage_cap = 0;
-                ok = hipHostMalloc((void**)&stage, (size_t)std::max<int64_t>(total, 1) * 4, hipHostMallocDefault) ==
+            float*& stg = sstage[g->slot];
+            if ((size_t)total > scap[g->slot]) {
+                if (stg) (void)hipHostFree(stg);
+                stg = nullptr;
+                scap[g->slot] = 0;
+                ok = hipHostMalloc((void**)&stg, (size_t)std::max<int64_t>(total, 1) * 4, hipHostMallocDefault) ==
                      hipSuccess;
-                if (ok) stage_cap = (size_t)std::max<int64_t>(total, 1);
+                if (ok) scap[g->slot] = (size_t)std::max<int64_t>(total, 1);
             }
+            // the iteration that produced the result has been waited for, and the
+            // request's own input copy went down the same copy stream before
+            hipStream_t cs = cst[g->cs];
+            if (!g->ev) g->ev = get_event();
+            ok = ok && g->ev;
             if (ok && ncore > 0)
-                ok = hipMemcpyAsync(stage, g->cur, (size_t)ncore * 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+                ok = hipMemcpyAsync(stg, g->cur, (size_t)ncore * 4, hipMemcpyDeviceToHost, cs) == hipSuccess;
             int64_t off = ncore;
             for (int i = 0; i < g->d && ok; ++i) {
                 const int64_t nf = g->dims[i] * g->ranks[i];
                 if (nf > 0)
-                    ok = hipMemcpyAsync(stage + off, g->fac[i], (size_t)nf * 4, hipMemcpyDeviceToHost, st) == hipSuccess;
+                    ok = hipMemcpyAsync(stg + off, g->fac[i], (size_t)nf * 4, hipMemcpyDeviceToHost, cs) == hipSuccess;
                 off += nf;
             }
-            ok = ok && hipStreamSynchronize(st) == hipSuccess;
+            ok = ok && hipEventRecord(g->ev, cs) == hipSuccess;
             if (!ok) {
                 r->res.status = RT_EHIP;
                 r->err = "device to host copy failed";
-            } else {
-                r->core.assign(stage, stage + ncore);
-                r->factors.assign(g->d, std::vector<float>());
-                off = ncore;
-                for (int i = 0; i < g->d; ++i) {
-                    const int64_t nf = g->dims[i] * g->ranks[i];
-                    r->factors[i].assign(stage + off, stage + off + nf);
-                    off += nf;
-                    r->res.ranks[i] = g->ranks[i];
-                }
-                r->res.norm_x = std::sqrt(std::max(g->nx2, 0.0));
-                r->res.core_norm = std::sqrt(std::max(g->cur_norm2, 0.0));
-                r->res.rel_err_est = r->res.norm_x > 0
-                                         ? std::sqrt(std::max(0.0, g->nx2 - g->cur_norm2)) / r->res.norm_x : 0.0;
-                r->res.flags = 0;
-                if (g->capped) {
-                    r->res.status = RT_ECAP;
-                    r->err = "a mode reached its rank cap before the tolerance";
-                }
             }
         }
+        draining.push_back(g);
+    };
+    auto complete_drain = [&](GState* g) {
+        Request* r = g->r;
+        if (r->res.status == RT_OK || r->res.status == RT_ECAP) {
+            const float* stg = sstage[g->slot];
+            const int64_t ncore = g->ncore;
+            r->core.assign(stg, stg + ncore);
+            r->factors.assign(g->d, std::vector<float>());
+            int64_t off = ncore;
+            for (int i = 0; i < g->d; ++i) {
+                const int64_t nf = g->dims[i] * g->ranks[i];
+                r->factors[i].assign(stg + off, stg + off + nf);
+                off += nf;
+                r->res.ranks[i] = g->ranks[i];
+            }
+            r->res.norm_x = std::sqrt(std::max(g->nx2, 0.0));
+            r->res.core_norm = std::sqrt(std::max(g->cur_norm2, 0.0));
+            r->res.rel_err_est = r->res.norm_x > 0 ? std::sqrt(std::max(0.0, g->nx2 - g->cur_norm2)) / r->res.norm_x
+                                                   : 0.0;
+            r->res.flags = 0;
+            if (g->capped) {
+                r->res.status = RT_ECAP;
+                r->err = "a mode reached its rank cap before the tolerance";
+            }
+        }
+        if (g->ev) evpool.push_back(g->ev);
         pool.put(g->arena, g->bytes);
         free_slots.push_back(g->slot);
         delete g;
-        complete(r);
+    };
+    // completes every drained request whose copy has finished (all of them when wait)
+    auto poll_drains = [&](bool wait) {
+        for (size_t i = 0; i < draining.size();) {
+            GState* g = draining[i];
+            const bool done = !g->ev || (wait ? hipEventSynchronize(g->ev) == hipSuccess
+                                              : hipEventQuery(g->ev) != hipErrorNotReady);
+            if (done) {
+                Request* r = g->r;
+                draining.erase(draining.begin() + i);
+                complete_drain(g);
+                complete(r);
+            } else {
+                ++i;
+            }
+        }
     };
 
     const double eps_n_base = opts.eps;
-    for (;;) {
-        // admission: arrival order, while a slot is free and the footprint fits
+    using Sec = std::chrono::duration<double>;
+    std::vector<GState*> finished;   // done at the last readback, results not yet copied out
+    // admission: arrival order, while a slot is free and the footprint fits;
+    // may_wait: block for work when nothing at all is in flight
+    auto admit_queue = [&](bool may_wait) {
         for (;;) {
             Request* r = nullptr;
             bool alone = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                if (active.empty())
+                if (may_wait && active.empty() && pending.empty() && draining.empty() && finished.empty())
                     cv_work.wait(lk, [&] { return !queue.empty() || stopping; });
-                if (queue.empty() || (int)active.size() >= maxreq) break;
+                if (queue.empty() || free_slots.empty()) break;
                 Request* h = queue.front();
                 size_t bytes = 0, scratch = 0, big = 0;
                 alone = !group_footprint(h->X, block, bytes, scratch, big);
-                if (!alone && !active.empty() && in_use + bytes > budget) break;
+                const bool busy = !active.empty() || !pending.empty();
+                if (!alone && busy && in_use + bytes > budget) break;
                 queue.pop_front();
-                h->footprint = bytes;
-                in_use += alone ? 0 : bytes;
+                h->footprint = alone ? 0 : bytes;
+                in_use += h->footprint;
                 ++in_flight;
                 h->t_admit = Clock::now();
                 r = h;
@@ -644,13 +706,12 @@ void rt_server::exec_main() {
                 continue;
             }
             if (alone) {
-                r->footprint = 0;
                 run(r, ctx, st, cache, dX, dX_cap, stage, stage_cap);
                 complete(r);
                 continue;
             }
             if (!admit(r)) {
-                if (!active.empty()) {
+                if (!active.empty() || !pending.empty() || !draining.empty()) {
                     // no memory now: back to the head of the queue until requests finish
                     std::lock_guard<std::mutex> lk(mu);
                     in_use -= r->footprint;
@@ -663,17 +724,45 @@ void rt_server::exec_main() {
                 complete(r);
             }
         }
+    };
+    // requests whose input copy has landed join the next iteration (no request
+    // waits on another's copy); with nothing running, wait for the oldest copy
+    auto activate = [&](bool wait) {
+        if (wait && active.empty() && !pending.empty() && pending.front()->ev)
+            (void)hipEventSynchronize(pending.front()->ev);
+        size_t k = 0;
+        for (GState* g : pending) {
+            if (!g->ev || hipEventQuery(g->ev) != hipErrorNotReady) active.push_back(g);
+            else pending[k++] = g;
+        }
+        pending.resize(k);
+    };
+    auto drain_finished = [&]() {
+        for (GState* g : finished) start_drain(g);
+        finished.clear();
+        poll_drains(false);
+    };
+    for (;;) {
+        const Clock::time_point t_top = Clock::now();
+        activate(false);
         if (active.empty()) {
+            // nothing running: copy results out, admit, and start the new requests
+            drain_finished();
+            admit_queue(true);
+            activate(true);
+        }
+        // requests that finished without device work (rank 0 everywhere, failures)
+        for (size_t i = 0; i < active.size();) {
+            if (active[i]->phase == GState::DONE) { finished.push_back(active[i]); active.erase(active.begin() + i); }
+            else ++i;
+        }
+        if (active.empty()) {
+            if (!finished.empty()) continue;
+            if (!draining.empty()) { poll_drains(true); continue; }
             std::lock_guard<std::mutex> lk(mu);
             if (stopping && queue.empty()) break;
             continue;
         }
-        // requests that finished without device work (rank 0 everywhere, failures)
-        for (size_t i = 0; i < active.size();) {
-            if (active[i]->phase == GState::DONE) { finish(active[i]); active.erase(active.begin() + i); }
-            else ++i;
-        }
-        if (active.empty()) continue;
         // descriptors of this iteration
         std::memset(hdr, 0, sizeof(rt::GHeader));
         int nb = 0, nt = 0;
@@ -739,7 +828,7 @@ void rt_server::exec_main() {
             bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
             if (ok) {
                 const bool body = hipMemcpyAsync(desc_dev, desc_host, dbytes, hipMemcpyHostToDevice, st) == hipSuccess &&
-                                  rt::launch_group_iteration(desc_dev, maxreq, st) == hipSuccess;
+                                  rt::launch_group_iteration(desc_dev, maxreq, block, st) == hipSuccess;
                 ok = hipStreamEndCapture(st, &graph) == hipSuccess && body && graph;
             }
             ok = ok && hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -753,8 +842,16 @@ void rt_server::exec_main() {
         if (graph_ok && gexec) launched = hipGraphLaunch(gexec, st) == hipSuccess;
         if (!launched)
             launched = hipMemcpyAsync(desc_dev, desc_host, dbytes, hipMemcpyHostToDevice, st) == hipSuccess &&
-                       rt::launch_group_iteration(desc_dev, maxreq, st) == hipSuccess;
+                       rt::launch_group_iteration(desc_dev, maxreq, block, st) == hipSuccess;
+        const Clock::time_point t_launch = Clock::now();
+        // while the iteration runs: results of the last one out, new requests in
+        // (their inputs cross on the copy streams and join a later iteration)
+        drain_finished();
+        admit_queue(false);
+        const Clock::time_point t_overlap = Clock::now();
         const bool synced = launched && hipStreamSynchronize(st) == hipSuccess;
+        const Clock::time_point t_synced = Clock::now();
+        const int64_t nadv = (int64_t)active.size();
         // advance every request from its readback slot
         for (GState* g : active) {
             if (!synced) { fail(g, RT_EHIP, "grouped launch failed"); continue; }
@@ -789,10 +886,20 @@ void rt_server::exec_main() {
             }
         }
         for (size_t i = 0; i < active.size();) {
-            if (active[i]->phase == GState::DONE) { finish(active[i]); active.erase(active.begin() + i); }
+            if (active[i]->phase == GState::DONE) { finished.push_back(active[i]); active.erase(active.begin() + i); }
             else ++i;
         }
+        {
+            const Clock::time_point t_end = Clock::now();
+            std::lock_guard<std::mutex> lk(mu);
+            ++stats.iterations;
+            stats.request_steps += nadv;
+            stats.wait_s += Sec(t_synced - t_overlap).count();
+            stats.overlap_s += Sec(t_overlap - t_launch).count();
+            stats.host_s += Sec(t_launch - t_top).count() + Sec(t_end - t_synced).count();
+        }
     }
+    poll_drains(true);
     if (st) (void)hipStreamSynchronize(st);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (dX) cache.put(dX);
@@ -803,6 +910,9 @@ void rt_server::exec_main() {
     if (desc_host) (void)hipHostFree(desc_host);
     if (desc_dev) (void)hipFree(desc_dev);
     if (rb_host) (void)hipHostFree(rb_host);
+    for (float* p : sstage) if (p) (void)hipHostFree(p);
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    for (hipStream_t c : cst) if (c) { (void)hipStreamSynchronize(c); (void)hipStreamDestroy(c); }
     if (st) (void)hipStreamDestroy(st);
 }
 
@@ -897,6 +1007,13 @@ rt_status rt_server_release(rt_server* srv, uint64_t ticket) {
     if (!it->second->done) return rt::set_error(RT_EINVAL, "request has not completed");
     delete it->second;
     srv->reqs.erase(it);
+    return RT_OK;
+}
+
+rt_status rt_server_get_stats(rt_server* srv, rt_server_stats* out) {
+    if (!srv || !out) return rt::set_error(RT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->stats;
     return RT_OK;
 }
 

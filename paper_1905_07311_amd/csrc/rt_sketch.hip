@@ -7,7 +7,8 @@
 // unfolding.  Per tile it stages X[rows, cols] through LDS with loads that are
 // contiguous in memory for the tensor's stride class (along c when R > 1, along
 // the rows when R == 1) and generates the 64 x ell slab of Omega once into LDS;
-// each wave then accumulates a quarter of the ell columns for all 64 rows.
+// each wave then accumulates every fourth group of four adjacent columns for all
+// 64 rows.  The next tile's loads are issued before the current one is consumed.
 #include "rt_kernels.hpp"
 #include "rt_philox.hpp"
 
@@ -24,7 +25,7 @@ constexpr int SK_NACC = LMAX / 4;
 // Y = X_(n) Z with Z = Om_(n)^T); seed, mode and col0 are unused.
 // The work of one workgroup (split `split`, row tile `rowtile` of nsplit
 // splits), shared by the per-request kernel below and the grouped one.
-template <typename TX, typename TA, bool EXPL>
+template <typename TX, typename TA, bool EXPL, int NACC = SK_NACC>
 __device__ __forceinline__ void sketch_generic_tile(
     const TX* __restrict__ X, int64_t L, int64_t J, int64_t R, int ell, int64_t col0,
     uint64_t seed, uint32_t mode, int64_t tiles_per_split, TA* __restrict__ partial,
@@ -35,7 +36,7 @@ __device__ __forceinline__ void sketch_generic_tile(
 
     const int tid = threadIdx.x;
     const int row = tid % SK_MT;
-    const int kg = tid / SK_MT;            // wave index: columns kg, kg + 4, ...
+    const int kg = tid / SK_MT;            // wave index: column groups kg, kg + 4, ...
     const int64_t K = L * R;
     const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
     const int64_t row0 = rowtile * SK_MT;
@@ -44,30 +45,54 @@ __device__ __forceinline__ void sketch_generic_tile(
     const int64_t q_first = col0 / 4;
     const int64_t q_last = (col0 + ell - 1) / 4;
     const int nq = (int)(q_last - q_first + 1);
+    static_assert(NACC % 4 == 0, "accumulators come in groups of four columns");
+    constexpr int NG = NACC / 4;           // groups of four adjacent columns per thread
+    constexpr int NLD = SK_MT * SK_KC / 256;
 
-    TA acc[SK_NACC];
+    // Staging map: element m of this thread is X tile entry (rl, cl) with
+    // cl = tid % 64, rl = tid / 64 + 4 m (R > 1: runs along c are contiguous)
+    // or rl = tid % 64, cl = tid / 64 + 4 m (R == 1: runs along the rows are).
+    // Its address is base + m * step, so a tile costs one division per thread.
+    TX xr[NLD];
+    auto load_tile = [&](int64_t t) {
+        const int64_t cbase = t * SK_KC;
+        int64_t base, step, c0;
+        int64_t i0;
+        if (R == 1) {
+            c0 = cbase + kg;
+            i0 = row0 + row;
+            base = c0 * J + i0;
+            step = 4 * J;
+        } else {
+            c0 = cbase + row;
+            i0 = row0 + kg;
+            const int64_t l = c0 / R;
+            base = (l * J + i0) * R + (c0 - l * R);
+            step = 4 * R;
+        }
 #pragma unroll
-    for (int j = 0; j < SK_NACC; ++j) acc[j] = TA(0);
+        for (int m = 0; m < NLD; ++m) {
+            const int64_t c = R == 1 ? c0 + 4 * m : c0;
+            const int64_t i = R == 1 ? i0 : i0 + 4 * m;
+            xr[m] = (c < K && i < J) ? X[base + m * step] : TX(0);
+        }
+    };
+
+    TA acc[NACC];
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) acc[j] = TA(0);
     double nrm = 0.0;
 
+    if (t_begin < t_end) load_tile(t_begin);
     for (int64_t t = t_begin; t < t_end; ++t) {
         const int64_t cbase = t * SK_KC;
         __syncthreads();
-        // stage X tile: 64 x 64 elements, 16 per thread
-        for (int e = tid; e < SK_MT * SK_KC; e += 256) {
-            int rl, cl;
-            if (R == 1) { rl = e % SK_MT; cl = e / SK_MT; }
-            else        { cl = e % SK_KC; rl = e / SK_KC; }
-            const int64_t c = cbase + cl;
-            const int64_t i = row0 + rl;
-            TA v = TA(0);
-            if (c < K && i < J) {
-                const int64_t l = c / R;
-                const int64_t r = c - l * R;
-                v = (TA)X[(l * J + i) * R + r];
-                if (nrm2_partial) nrm += (double)v * (double)v;
-            }
-            xs[cl][rl] = v;
+#pragma unroll
+        for (int m = 0; m < NLD; ++m) {
+            const TA v = (TA)xr[m];
+            if (nrm2_partial) nrm += (double)v * (double)v;
+            if (R == 1) xs[kg + 4 * m][row] = v;
+            else        xs[row][kg + 4 * m] = v;
         }
         // generate (or, EXPL, load) the Omega slab for these 64 unfolding columns
         if (EXPL) {
@@ -94,14 +119,20 @@ __device__ __forceinline__ void sketch_generic_tile(
                 if (k >= 0 && k < ell) om[cl][k] = z[tt];
             }
         }
+        // the next tile's loads are in flight while this one is consumed
+        if (t + 1 < t_end) load_tile(t + 1);
         __syncthreads();
         const int cmax = (int)((K - cbase) < SK_KC ? (K - cbase) : SK_KC);
         for (int cl = 0; cl < cmax; ++cl) {
             const TA x = xs[cl][row];
 #pragma unroll
-            for (int j = 0; j < SK_NACC; ++j) {
-                const int k = kg + 4 * j;
-                if (k < ell) acc[j] += x * om[cl][k];
+            for (int g = 0; g < NG; ++g) {
+                const int k0 = 4 * (kg + 4 * g);
+                if (k0 < ell) {
+                    const TA* o = &om[cl][k0];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[4 * g + u] += x * o[u];
+                }
             }
         }
     }
@@ -109,9 +140,12 @@ __device__ __forceinline__ void sketch_generic_tile(
     if (i < J) {
         TA* dst = partial + (split * J + i) * ell;
 #pragma unroll
-        for (int j = 0; j < SK_NACC; ++j) {
-            const int k = kg + 4 * j;
-            if (k < ell) dst[k] = acc[j];
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 4 * (kg + 4 * g) + u;
+                if (k < ell) dst[k] = acc[4 * g + u];
+            }
         }
     }
     if (nrm2_partial) {
@@ -136,7 +170,10 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
 
 // Grouped block sketches: work item w of the group belongs to the request whose
 // [wi0, wi0 + nsplit nrowtile) holds it (wi0 ascending); the workgroups of the
-// fixed grid take items w = blockIdx.x, blockIdx.x + gridDim.x, ...
+// fixed grid take items w = blockIdx.x, blockIdx.x + gridDim.x, ...  NACC
+// accumulators per thread cover blocks of up to 4 NACC columns (the same sums,
+// in the same order, as the per-request kernel).
+template <int NACC>
 __global__ __launch_bounds__(256) void sketch_group_kernel(const GHeader* __restrict__ hdr,
                                                            const GBlock* __restrict__ d) {
     const int n = hdr->nblock;
@@ -150,7 +187,7 @@ __global__ __launch_bounds__(256) void sketch_group_kernel(const GHeader* __rest
         }
         const GBlock& q = d[lo];
         const int64_t local = w - q.wi0;
-        sketch_generic_tile<float, float, false>(q.G, q.L, q.J, q.R, q.b, q.col0, q.seed, q.mode, q.tiles_per_split,
+        sketch_generic_tile<float, float, false, NACC>(q.G, q.L, q.J, q.R, q.b, q.col0, q.seed, q.mode, q.tiles_per_split,
                                                  q.partial, q.nrm_partial, nullptr, local % q.nsplit,
                                                  local / q.nsplit, q.nsplit);
         __syncthreads();
@@ -357,7 +394,7 @@ void group_sketch_plan(int64_t L, int64_t J, int64_t R, int b, int& nsplit, int&
     const int64_t K = L * R;
     const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
     nrowtile = (int)((J + SK_MT - 1) / SK_MT);
-    int64_t want = 64 / nrowtile;
+    int64_t want = 128 / nrowtile;
     if (want < 1) want = 1;
     if (want > ntiles) want = ntiles;
     tps = (ntiles + want - 1) / want;
@@ -366,8 +403,9 @@ void group_sketch_plan(int64_t L, int64_t J, int64_t R, int b, int& nsplit, int&
     (void)b;
 }
 
-hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, hipStream_t stream) {
-    hipLaunchKernelGGL(sketch_group_kernel, dim3(1024), dim3(256), 0, stream, hdr, d);
+hipError_t launch_group_sketch(const GHeader* hdr, const GBlock* d, int block, hipStream_t stream) {
+    (void)block;   // blocks of at most 16 columns: one group of four columns per wave
+    hipLaunchKernelGGL(sketch_group_kernel<4>, dim3(1024), dim3(256), 0, stream, hdr, d);
     return hipGetLastError();
 }
 

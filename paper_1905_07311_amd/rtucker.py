@@ -28,7 +28,7 @@ EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_des
             "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
-            "rt_server_destroy"]
+            "rt_server_get_stats", "rt_server_destroy"]
 
 
 class RtError(RuntimeError):
@@ -69,6 +69,11 @@ class rt_result(ctypes.Structure):
                 ("factors", ctypes.POINTER(ctypes.c_float) * RT_MAXD), ("norm_x", ctypes.c_double),
                 ("core_norm", ctypes.c_double), ("rel_err_est", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+class rt_server_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("request_steps", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("wait_s", ctypes.c_double), ("host_s", ctypes.c_double), ("overlap_s", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -123,6 +128,7 @@ def load(path=None):
     lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_result)]
     lib.rt_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(rt_result)]
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.rt_server_get_stats.argtypes = [P, ctypes.POINTER(rt_server_stats)]
     lib.rt_server_destroy.argtypes = [P]
     for fn in EXPORTED:
         if fn not in ("rt_version", "rt_last_error"):
@@ -560,6 +566,16 @@ class Server:
         r = rt_result()
         _check(_lib.rt_server_wait(self.srv, ctypes.c_uint64(ticket), ctypes.byref(r)), allow=(RT_ECAP,))
         return self._take(ticket, r)
+
+    def stats(self):
+        """Executor counters since creation: iterations, request_steps, completed,
+        wait_s (host blocked on the device), host_s (serial host time between
+        iterations), overlap_s (host work done while an iteration runs)."""
+        st = rt_server_stats()
+        _check(_lib.rt_server_get_stats(self.srv, ctypes.byref(st)))
+        return {"iterations": int(st.iterations), "request_steps": int(st.request_steps),
+                "completed": int(st.completed), "wait_s": float(st.wait_s), "host_s": float(st.host_s),
+                "overlap_s": float(st.overlap_s)}
 
     def close(self):
         if getattr(self, "srv", None) and _lib is not None:
