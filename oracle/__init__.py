@@ -21,6 +21,7 @@ from .tucker import (rhosvd, rsthosvd, hosvd, sthosvd, default_order, TuckerResu
 from .adaptive import adapt_range_finder, adaptive_rsthosvd, adaptive_rhosvd
 from .precision import split_bf16, sketch_bf16x3
 from .structure import pivoted_rows, select_rows, sp_sthosvd
+from .sparse import unfold_coo, fold_coo, densify, sketch_coo, sp_sthosvd_coo
 
 __all__ = [
     "philox4x32_10", "omega_block", "omega", "PHILOX_M0", "PHILOX_M1", "PHILOX_W0", "PHILOX_W1",
@@ -30,5 +31,6 @@ __all__ = [
     "per_mode_residuals",
     "adapt_range_finder", "adaptive_rsthosvd", "adaptive_rhosvd",
     "pivoted_rows", "select_rows", "sp_sthosvd",
+    "unfold_coo", "fold_coo", "densify", "sketch_coo", "sp_sthosvd_coo",
     "split_bf16", "sketch_bf16x3",
 ]

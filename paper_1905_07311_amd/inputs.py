@@ -122,6 +122,38 @@ def serving_request_host(req_id, dims, ranks, noise=1e-6, dtype=np.float32):
                           noise=noise).astype(dtype)
 
 
+def sparse_vector(rng, n, density):
+    """Sparse vector in the manner of MATLAB's sprand(n, 1, density): round(density n)
+    positions drawn uniformly with replacement (repeats collapse), values uniform
+    on (0, 1).  Returns (positions ascending, values)."""
+    pos = np.unique(rng.integers(0, n, size=int(round(density * n))))
+    return pos, rng.random(pos.shape[0])
+
+
+def sparse_outer_sum(n=200, gamma=10.0, density=0.05, terms=200, lead=10, seed=0):
+    """Synthetic sparse tensor of eq. sparse (§6.1): the sum over i = 1..terms of
+    w_i x_i o y_i o z_i with w_i = gamma / i^2 for i <= lead and 1 / i^2 after,
+    x_i, y_i, z_i sparse vectors of length n (sparse_vector).  At n = 200 and 5 %
+    density it has about 1.84e5 nonzeros (the paper reports 185,211 for its draw).
+    Returns (idx int64 [3, nnz] in row-major order, vals float64, dims)."""
+    rng = np.random.default_rng([DATA_SEED_BASE + 6, int(seed), int(round(1000 * gamma))])
+    X = np.zeros((n, n, n))
+    for i in range(1, terms + 1):
+        w = (gamma if i <= lead else 1.0) / (i * i)
+        (px, vx), (py, vy), (pz, vz) = (sparse_vector(rng, n, density) for _ in range(3))
+        X[np.ix_(px, py, pz)] += w * vx[:, None, None] * vy[None, :, None] * vz[None, None, :]
+    idx = np.array(np.nonzero(X), dtype=np.int64)
+    return idx, X[tuple(idx)], (n, n, n)
+
+
+def random_sparse(rng, dims, density):
+    """Sparse tensor with each entry nonzero with probability `density`, values
+    N(0, 1).  Returns (idx int64 [d, nnz] in row-major order, vals float64)."""
+    mask = rng.random(dims) < density
+    idx = np.array(np.nonzero(mask), dtype=np.int64)
+    return idx, rng.standard_normal(idx.shape[1])
+
+
 # --------------------------------------------------------------------------- device
 
 def _torch():
