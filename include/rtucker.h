@@ -9,13 +9,15 @@
  *   rt_rsthosvd_adaptive - adaptive R-STHOSVD, Alg. 5 (§4)
  *   rt_rhosvd_adaptive   - adaptive R-HOSVD, Alg. 4 (§4)
  *   rt_sp_sthosvd        - structure-preserving STHOSVD, Alg. 6 (§5)
+ *   rt_sp_sthosvd_coo    - the same on a sparse tensor in coordinate storage
  * and exposes the steps of their hot path for testing: the on-the-fly Gaussian
  * sketch Y = X_(n) Omega (Alg. 1 step 1), Q = orth(Y) (Alg. 1 step 2) and the
  * projection B = X x_n Q^T (Alg. 1 step 3).
  *
  * Conventions (all calls):
  *  - Tensors are dense, row-major (last index fastest), float32 or float64,
- *    in device memory of the context's device.  Modes are 0-based.
+ *    in device memory of the context's device (rt_coo: sparse, coordinate
+ *    storage).  Modes are 0-based.
  *  - The mode-n unfolding X_(n) has the mode-n fibres as columns; column c is
  *    the row-major linear index over the remaining modes in increasing order.
  *  - Omega_n[c, k] ~ N(0, 1) comes from Philox4x32-10 with key (seed lo, seed hi)
@@ -26,7 +28,7 @@
  *  - Pointers are device pointers unless marked "host".  The caller keeps
  *    ownership of every input; the library never writes an input tensor.
  *  - Work is enqueued on the context's stream.  The fixed-rank decompositions
- *    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd) and rt_reconstruct are
+ *    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd, rt_sp_sthosvd_coo) and rt_reconstruct are
  *    asynchronous: they return once their work is enqueued, with the ranks and
  *    the core and factor buffers of the result set; the contents of those
  *    buffers are valid once the stream reaches that point, and the scalars
@@ -88,6 +90,8 @@ typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_pr
                                 was completed with zero-weight orthonormal columns */
 #define RT_FLAG_FALLBACK 2u  /* orth used the Householder fallback instead of CholeskyQR2 */
 #define RT_FLAG_NONFINITE 4u /* the input held NaN or Inf (the result is not meaningful) */
+#define RT_FLAG_BADCOORD 8u  /* a sparse input had a coordinate out of range; those
+                                entries were ignored (rt_sync returns RT_EINVAL) */
 
 typedef struct rt_ctx rt_ctx;
 
@@ -293,18 +297,61 @@ rt_status rt_timing_entry(rt_ctx* ctx, int64_t i, int32_t* kind, double* ms, dou
  * MFMA), RT_SKETCH_SPLIT_BF16 (float32 products formed from three bfloat16
  * pieces per operand, six piece products on the 16x16x32 bfloat16 MFMA, float32
  * accuracy), RT_SKETCH_BF16X3 (the bfloat16 sketch: two bfloat16 pieces per
- * operand, three piece products on the same MFMA); 0 for the other kinds. */
+ * operand, three piece products on the same MFMA), RT_SKETCH_COO (the sketch of
+ * a sparse tensor); 0 for the other kinds. */
 #define RT_SKETCH_GENERIC 0
 #define RT_SKETCH_MFMA_F32 1
 #define RT_SKETCH_SPLIT_BF16 3
 #define RT_SKETCH_BF16X3 4
+#define RT_SKETCH_COO 5       /* sparse (coordinate) sketch, atomic fp64 adds */
 rt_status rt_timing_variant(rt_ctx* ctx, int64_t i, int32_t* variant);
 
 /* Block until the context's stream is idle, then fill the scalars of every
  * result of an asynchronous call made since the last rt_sync.  Returns
  * RT_ENONFINITE if the input of any of them held NaN or Inf (that result's
- * flags carry RT_FLAG_NONFINITE), RT_EHIP if the stream failed, else RT_OK. */
+ * flags carry RT_FLAG_NONFINITE), RT_EINVAL if a sparse input had a coordinate
+ * out of range (RT_FLAG_BADCOORD), RT_EHIP if the stream failed, else RT_OK. */
 rt_status rt_sync(rt_ctx* ctx);
+
+/* ---- sparse tensors: structure-preserving STHOSVD (Alg. 6, §5) ---------------- */
+/* A d-way tensor in coordinate (COO) storage: entry e has coordinates
+ * idx[m * nnz + e] (0 <= idx < dims[m]) and value vals[e].  Coordinates should
+ * be distinct; repeated ones act as one entry holding their sum, except that
+ * norm_x is then sqrt(sum of vals^2) rather than ||X||_F. */
+typedef struct {
+    int32_t ndim;             /* 2 .. RT_MAXD */
+    int64_t dims[RT_MAXD];    /* 1 .. 2^31 - 1 */
+    int64_t nnz;              /* >= 0 */
+    rt_dtype dtype;
+    const int32_t* idx;       /* device, ndim x nnz int32, mode-major */
+    const void* vals;         /* device, nnz values of dtype */
+} rt_coo;
+
+/* SP-STHOSVD (Alg. 6) of a sparse tensor.  Every intermediate core stays in
+ * coordinate storage: step n sketches the current core, Y = G_(n) Omega_n
+ * (cost O(nnz ell), §5), selects ell = r_n + p rows P of Q = orth(Y) as
+ * rt_sp_sthosvd does, and keeps the entries of the selected mode-n slices,
+ * renumbered by their position in the selection (G_(n) <- P^T G_(n)), so the
+ * core holds entries of X only and never grows.  The result is laid out as
+ * rt_sp_sthosvd's on the dense tensor: a dense core (ell_1 x ... x ell_d) of
+ * entries of X, factors A_n = Q (P^T Q)^-1 (dims[n] x ell_n) that contain the
+ * ell x ell identity, rel_err_est = -1.  opts->prec: RT_PREC_F64 for RT_F64
+ * values, RT_PREC_F32 for RT_F32 (sketch in fp64 accumulation either way);
+ * power_iters must be 0.  Asynchronous as the other fixed-rank calls; entries
+ * with a coordinate out of range are ignored and rt_sync then returns
+ * RT_EINVAL.  The sketch adds into Y with atomic operations, so results are
+ * reproducible to fp64 rounding rather than bitwise. */
+rt_status rt_sp_sthosvd_coo(rt_ctx* ctx, const rt_coo* X, const int32_t* ranks, const rt_opts* opts,
+                            rt_tucker* out);
+
+/* Y = X_(mode) Omega_mode[:, col0 : col0 + ell] of a sparse tensor (the sketch
+ * step of Alg. 6), Y device float64 dims[mode] x ell; Omega is the generator of
+ * rt_sketch in the precision of the values (float32 normals for RT_F32, float64
+ * for RT_F64).  nrm2 (device, optional) receives the sum of vals^2.  Waits for
+ * the stream; RT_EINVAL if some coordinate is out of range (those entries are
+ * skipped).  1 <= ell <= RT_LMAX. */
+rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
+                        double* Y, double* nrm2);
 
 /* ---- serving: continuous batching of many requests --------------------------- */
 /* A server runs adaptive R-STHOSVD (Alg. 5, §4) on a stream of float32 tensors of

@@ -140,6 +140,31 @@ hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, i
 // out (L, ell, R) = G (L, J, R) at the mode indices sel[0..ell) (dtype dt)
 hipError_t launch_gather_mode(const void* G, Dt dt, Shape3 s, const int* sel, int ell, void* out, hipStream_t stream);
 
+// ---- sparse (COO) steps of SP-STHOSVD (Alg. 6, §5) ------------------------------------
+// Entry e of a COO tensor: coordinates idx[m * ldi + e] (int32), value vals[e].
+// nnz_dev: the entry count on the device (NULL: `bound` itself); bound: an upper
+// bound used to size grids.  Entries with a coordinate outside dims are skipped.
+struct CooDims { int32_t d; int64_t dims[RT_MAXD]; };
+int64_t coo_chunks(int64_t bound);   // compaction chunks (length of cnt / off)
+// status |= bit when some entry has a coordinate out of range
+hipError_t launch_coo_check(const int32_t* idx, int64_t ldi, int64_t nnz, const CooDims& cd, uint32_t* status,
+                            uint32_t bit, hipStream_t stream);
+// Y (J x ell, double, zeroed by the caller) += G_(mode) Omega[:, col0 : col0 + ell]
+hipError_t launch_coo_sketch(const int32_t* idx, int64_t ldi, const void* vals, Dt dt, const int64_t* nnz_dev,
+                             int64_t bound, const CooDims& cd, int mode, int ell, int64_t col0, uint64_t seed,
+                             double* Y, hipStream_t stream);
+// G_(mode) <- P^T G_(mode): the entries whose mode coordinate is sel[j] for some j,
+// in input order, with that coordinate replaced by j, into (idx_out, ldo,
+// vals_out); their count into *nnz_out.  inv: dims[mode] ints; cnt, off:
+// coo_chunks(bound) int64 each (scratch).
+hipError_t launch_coo_restrict(const int32_t* idx, int64_t ldi, const void* vals, Dt dt, const int64_t* nnz_dev,
+                               int64_t bound, const CooDims& cd, int mode, const int* sel, int ell, int32_t* inv,
+                               int64_t* cnt, int64_t* off, int32_t* idx_out, int64_t ldo, void* vals_out,
+                               int64_t* nnz_out, hipStream_t stream);
+// out (dense row-major dims, zeroed by the caller) += the entries
+hipError_t launch_coo_densify(const int32_t* idx, int64_t ldi, const void* vals, Dt dt, const int64_t* nnz_dev,
+                              int64_t bound, const CooDims& cd, void* out, hipStream_t stream);
+
 // ---- adaptive block step (reading of AdaptRangeFinder, §4) ----------------------------
 // Y (J x b, double) is orthogonalised twice against Qall[:, :k] (J x ld, double),
 // then orthonormalised with a rank-revealing drop (singular values <= drop * ||Y_in||_F

@@ -233,6 +233,35 @@ rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
     return RT_OK;
 }
 
+rt_status check_coo(const rt_coo* X) {
+    if (!X) return fail(RT_EINVAL, "X is NULL");
+    if (X->ndim < 2 || X->ndim > RT_MAXD) return fail(RT_EINVAL, "ndim must be in [2, RT_MAXD]");
+    if (X->dtype != RT_F32 && X->dtype != RT_F64) return fail(RT_EINVAL, "dtype must be RT_F32 or RT_F64");
+    if (X->nnz < 0) return fail(RT_EINVAL, "nnz must be >= 0");
+    if (X->nnz > 0 && (!X->idx || !X->vals)) return fail(RT_EINVAL, "idx or vals is NULL");
+    if (X->nnz > ((int64_t)1 << 40)) return fail(RT_EINVAL, "nnz too large");
+    for (int i = 0; i < X->ndim; ++i)
+        if (X->dims[i] < 1 || X->dims[i] > INT32_MAX) return fail(RT_EINVAL, "every dim must be in [1, 2^31 - 1]");
+    return RT_OK;
+}
+
+// The dense header of a COO tensor (dims, dtype) for the shape and rank checks.
+rt_tensor coo_header(const rt_coo* X) {
+    rt_tensor t{};
+    t.ndim = X->ndim;
+    for (int i = 0; i < X->ndim; ++i) t.dims[i] = X->dims[i];
+    t.dtype = X->dtype;
+    t.data = X->vals ? X->vals : (const void*)X;
+    return t;
+}
+
+rt::CooDims coo_dims(const std::vector<int64_t>& dims) {
+    rt::CooDims cd{};
+    cd.d = (int32_t)dims.size();
+    for (size_t i = 0; i < dims.size(); ++i) cd.dims[i] = dims[i];
+    return cd;
+}
+
 }  // namespace
 
 namespace rt {
@@ -506,8 +535,12 @@ rt_status fill_result(rt_tucker* out, const rt::FinishScalars* h, bool oblique) 
     uint32_t fl = 0;
     bool nonfinite = false;
     for (int i = 0; i < RT_MAXD; ++i) {
-        fl |= h->status[i] & 3u;
-        if (h->status[i] & 4u) nonfinite = true;
+        fl |= h->status[i] & (RT_FLAG_PADDED | RT_FLAG_FALLBACK | RT_FLAG_BADCOORD);
+        if (h->status[i] & RT_FLAG_NONFINITE) nonfinite = true;
+    }
+    if (fl & RT_FLAG_BADCOORD) {
+        out->flags = fl | (nonfinite ? RT_FLAG_NONFINITE : 0u);
+        return RT_EINVAL;
     }
     if (nonfinite || !std::isfinite(h->nx2)) {
         out->flags = fl | RT_FLAG_NONFINITE;
@@ -515,6 +548,11 @@ rt_status fill_result(rt_tucker* out, const rt::FinishScalars* h, bool oblique) 
     }
     out->flags = fl;
     return RT_OK;
+}
+
+const char* deferred_message(rt_status s) {
+    return s == RT_EINVAL ? "sparse input has a coordinate out of range (those entries were ignored)"
+                          : "input holds NaN or Inf";
 }
 
 // Waits for the stream and fills every pending result; returns the first
@@ -529,7 +567,7 @@ rt_status drain_pending(rt_ctx* c, const rt_tucker* self = nullptr, rt_status* m
         if (s != RT_OK && first == RT_OK) first = s;
     }
     c->pending.clear();
-    if (first != RT_OK) fail(first, "input holds NaN or Inf");
+    if (first != RT_OK) fail(first, deferred_message(first));
     return first;
 }
 
@@ -569,7 +607,7 @@ rt_status finish(Call& k, rt_tucker* out, const void* core_dev, const std::vecto
     rt_status mine = RT_OK;
     const rt_status all = drain_pending(k.c, out, &mine);
     if (all == RT_EHIP) return all;
-    if (mine != RT_OK) return fail(mine, "input holds NaN or Inf");
+    if (mine != RT_OK) return fail(mine, deferred_message(mine));
     return RT_OK;
 }
 
@@ -800,6 +838,104 @@ rt_status rt_sp_sthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, c
     }
     rt_status rs = finish(k, out, cur, dims, dt, nx2, status, true, true);
     if (rs != RT_OK && rs != RT_ENONFINITE) release_partial(ctx, out);
+    return rs;
+}
+
+rt_status rt_sp_sthosvd_coo(rt_ctx* ctx, const rt_coo* X, const int32_t* ranks, const rt_opts* opts,
+                            rt_tucker* out) {
+    if (!ctx || !opts || !out) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_coo(X));
+    const rt_tensor T = coo_header(X);
+    RT_TRY(check_prec(&T, opts->prec));
+    if (opts->prec == RT_PREC_BF16_SKETCH) return fail(RT_EINVAL, "sparse tensors take RT_PREC_F32 or RT_PREC_F64");
+    if (opts->power_iters != 0) return fail(RT_EINVAL, "power_iters must be 0 for rt_sp_sthosvd_coo");
+    RT_TRY(check_ranks(&T, ranks, opts->oversample));
+    std::vector<int> order;
+    RT_TRY(make_order(&T, opts->order, order));
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    hipStream_t st = ctx->stream;
+    const Dt dt = dt_of(X->dtype);
+    const size_t es = dsize(X->dtype);
+    const int d = X->ndim;
+    const int64_t bound = X->nnz;
+    init_out(out, &T);
+    std::vector<int64_t> dims(X->dims, X->dims + d);
+    double* nx2 = k.ws<double>(1);
+    uint32_t* status = k.ws<uint32_t>(RT_MAXD);
+    int* sel = k.ws<int>(RT_LMAX);
+    int* swaps = k.ws<int>(1);
+    int64_t* cnt_dev = k.ws<int64_t>(2);
+    // two coordinate buffers (capacity: the input's entry count) alternate as
+    // the intermediate cores
+    const int64_t cap = std::max<int64_t>(bound, 1);
+    int32_t* cidx[2] = {k.ws<int32_t>((size_t)d * cap), k.ws<int32_t>((size_t)d * cap)};
+    void* cval[2] = {k.c->ws((size_t)cap * es), k.c->ws((size_t)cap * es)};
+    const int64_t nb = rt::coo_chunks(bound);
+    int64_t* cnt = k.ws<int64_t>(std::max<int64_t>(nb, 1));
+    int64_t* off = k.ws<int64_t>(std::max<int64_t>(nb, 1));
+    if (!nx2 || !status || !sel || !swaps || !cnt_dev || !cidx[0] || !cidx[1] || !cval[0] || !cval[1] || !cnt ||
+        !off)
+        return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, st));
+    const rt::CooDims xdims = coo_dims(dims);
+    if (bound > 0) RT_TRY(do_norm2(k, X->vals, dt, bound, nx2));
+    else RT_HIP(hipMemsetAsync(nx2, 0, sizeof(double), st));
+    const int32_t* cur_idx = X->idx;
+    int64_t cur_ld = bound;
+    const void* cur_val = X->vals;
+    const int64_t* cur_nnz = nullptr;   // the input's count is `bound` itself
+    int pp = 0;
+    for (int n : order) {
+        if (ranks[n] == RT_KEEP) continue;
+        const int ell = ranks[n] + opts->oversample;
+        const int64_t J = dims[n];
+        double* Y = k.ws<double>((size_t)J * ell);
+        double* oscr = k.ws<double>(rt::orth_scratch(J, ell));
+        double* sscr = k.ws<double>((size_t)2 * J * ell);
+        int32_t* inv = k.ws<int32_t>((size_t)J);
+        out->factors[n] = ctx->raw_alloc((size_t)J * ell * es);
+        if (!Y || !oscr || !sscr || !inv || !out->factors[n]) {
+            release_partial(ctx, out);
+            return fail(RT_ENOMEM, "allocation failed");
+        }
+        // Alg. 6: Y = G_(n) Omega, Q = orth(Y), selection P, A = Q (P^T Q)^-1, G <- P^T G
+        RT_HIP(hipMemsetAsync(Y, 0, (size_t)J * ell * sizeof(double), st));
+        {
+            TimeScope ts(k.c, 0, (double)bound * (d * 4.0 + es), 2.0 * ell * bound, J, bound, ell);
+            ts.t.variant = RT_SKETCH_COO;
+            RT_HIP(rt::launch_coo_sketch(cur_idx, cur_ld, cur_val, dt, cur_nnz, bound, coo_dims(dims), n, ell, 0,
+                                         opts->seed, Y, st));
+        }
+        {
+            TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
+            RT_HIP(rt::launch_orth(Y, J, ell, nullptr, orth_accept_ratio(), status + n, oscr, st));
+            RT_HIP(rt::launch_select_rows(Y, J, ell, 2.0, 1000, sscr, out->factors[n], dt, sel, swaps, st));
+        }
+        RT_HIP(rt::launch_coo_restrict(cur_idx, cur_ld, cur_val, dt, cur_nnz, bound, coo_dims(dims), n, sel, ell, inv,
+                                       cnt, off, cidx[pp], cap, cval[pp], cnt_dev + pp, st));
+        cur_idx = cidx[pp];
+        cur_ld = cap;
+        cur_val = cval[pp];
+        cur_nnz = cnt_dev + pp;
+        pp ^= 1;
+        out->ranks[n] = ell;
+        dims[n] = ell;
+    }
+    // entries with a coordinate out of range (skipped by every kernel) are
+    // reported through the status words (after orth has written its own)
+    RT_HIP(rt::launch_coo_check(X->idx, bound, bound, xdims, status, RT_FLAG_BADCOORD, st));
+    int64_t ncore = 1;
+    for (auto v : dims) ncore *= v;
+    void* core = k.c->ws((size_t)ncore * es);
+    if (!core) {
+        release_partial(ctx, out);
+        return fail(RT_ENOMEM, "allocation failed");
+    }
+    RT_HIP(hipMemsetAsync(core, 0, (size_t)ncore * es, st));
+    RT_HIP(rt::launch_coo_densify(cur_idx, cur_ld, cur_val, dt, cur_nnz, bound, coo_dims(dims), core, st));
+    rt_status rs = finish(k, out, core, dims, dt, nx2, status, true, true);
+    if (rs != RT_OK && rs != RT_ENONFINITE && rs != RT_EINVAL) release_partial(ctx, out);
     return rs;
 }
 
@@ -1183,6 +1319,41 @@ rt_status rt_sketch(rt_ctx* ctx, const rt_tensor* X, int32_t mode, int32_t ell, 
     std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
     RT_TRY(do_sketch(k, dt_of(X->dtype), (int)prec, X->data, shape3(dims, mode), ell, col0, seed, mode, Y, nrm2));
     RT_HIP(hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell, int64_t col0, uint64_t seed,
+                        double* Y, double* nrm2) {
+    if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
+    RT_TRY(check_coo(X));
+    if (mode < 0 || mode >= X->ndim) return fail(RT_EINVAL, "mode out of range");
+    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
+    if (col0 < 0) return fail(RT_EINVAL, "col0 must be >= 0");
+    RT_HIP(hipSetDevice(ctx->device));
+    Call k(ctx);
+    hipStream_t st = ctx->stream;
+    const Dt dt = dt_of(X->dtype);
+    std::vector<int64_t> dims(X->dims, X->dims + X->ndim);
+    uint32_t* status = k.ws<uint32_t>(1);
+    if (!status) return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t), st));
+    RT_HIP(rt::launch_coo_check(X->idx, X->nnz, X->nnz, coo_dims(dims), status, 1u, st));
+    RT_HIP(hipMemsetAsync(Y, 0, (size_t)dims[mode] * ell * sizeof(double), st));
+    {
+        TimeScope ts(k.c, 0, (double)X->nnz * (X->ndim * 4.0 + dsize(X->dtype)), 2.0 * ell * X->nnz, dims[mode],
+                     X->nnz, ell);
+        ts.t.variant = RT_SKETCH_COO;
+        RT_HIP(rt::launch_coo_sketch(X->idx, X->nnz, X->vals, dt, nullptr, X->nnz, coo_dims(dims), mode, ell, col0,
+                                     seed, Y, st));
+    }
+    if (nrm2) {
+        if (X->nnz > 0) RT_TRY(do_norm2(k, X->vals, dt, X->nnz, nrm2));
+        else RT_HIP(hipMemsetAsync(nrm2, 0, sizeof(double), st));
+    }
+    uint32_t* h = (uint32_t*)ctx->host;
+    RT_HIP(hipMemcpyAsync(h, status, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    if (h[0]) return fail(RT_EINVAL, "sparse input has a coordinate out of range (those entries were skipped)");
     return RT_OK;
 }
 

@@ -25,7 +25,7 @@ RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
-            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
+            "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_sp_sthosvd_coo", "rt_sketch_coo", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_get_stats", "rt_server_destroy"]
@@ -71,9 +71,25 @@ class rt_result(ctypes.Structure):
                 ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
 
 
+class rt_coo(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD), ("nnz", ctypes.c_int64),
+                ("dtype", ctypes.c_int), ("idx", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
 class rt_server_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("request_steps", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("wait_s", ctypes.c_double), ("host_s", ctypes.c_double), ("overlap_s", ctypes.c_double)]
+
+
+class _Shape:
+    """Dims and dtype of a tensor that is not held densely (a sparse input)."""
+
+    def __init__(self, dims, dtype):
+        self.shape = tuple(int(x) for x in dims)
+        self.dtype = dtype
+
+    def dim(self):
+        return len(self.shape)
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -104,6 +120,10 @@ def load(path=None):
         getattr(lib, fn).argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_opts),
                                      ctypes.POINTER(rt_tucker)]
+    lib.rt_sp_sthosvd_coo.argtypes = [P, ctypes.POINTER(rt_coo), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(rt_opts), ctypes.POINTER(rt_tucker)]
+    lib.rt_sketch_coo.argtypes = [P, ctypes.POINTER(rt_coo), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint64, P, P]
     lib.rt_tucker_release.argtypes = [P, ctypes.POINTER(rt_tucker)]
     lib.rt_reconstruct.argtypes = [P, ctypes.POINTER(rt_tucker), P]
     lib.rt_sketch.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
@@ -144,12 +164,13 @@ def _check(status, allow=()):
 
 
 RT_FLAG_NONFINITE = 4
+RT_FLAG_BADCOORD = 8
 
 
 class Tucker:
     """A decomposition [G; A_1..A_d] on the device.  The core and factors are
     torch tensors written on the context's stream.  After an asynchronous call
-    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd) the scalars are filled by rt_sync:
+    (rt_rhosvd, rt_rsthosvd, rt_sp_sthosvd, rt_sp_sthosvd_coo) the scalars are filled by rt_sync:
     reading norm_x, core_norm, rel_err_est or flags calls it once."""
 
     def __init__(self, core, factors, ranks, out, ctx=None, status=RT_OK):
@@ -166,8 +187,10 @@ class Tucker:
             try:
                 ctx.sync()
             except RtError as e:
-                if e.status != RT_ENONFINITE:
+                if e.status not in (RT_ENONFINITE, RT_EINVAL):
                     raise
+        if self._out.flags & RT_FLAG_BADCOORD:
+            raise RtError(RT_EINVAL, "sparse input has a coordinate out of range")
         if self._out.flags & RT_FLAG_NONFINITE:
             raise RtError(RT_ENONFINITE, "input holds NaN or Inf")
         return self._out
@@ -298,6 +321,49 @@ class Context:
 
     def sp_sthosvd(self, X, ranks, p, seed, order=None, prec=None):
         return self._fixed("rt_sp_sthosvd", X, ranks, p, seed, order, prec)
+
+    def _coo(self, idx, vals, dims):
+        torch = self.torch
+        d = len(dims)
+        if idx.device != self.device or vals.device != self.device:
+            raise ValueError("idx and vals must be on the context's device")
+        if idx.dtype != torch.int32 or idx.dim() != 2 or idx.shape[0] != d or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int32 (ndim, nnz) tensor")
+        if vals.dtype not in (torch.float32, torch.float64) or vals.dim() != 1 or vals.shape[0] != idx.shape[1] \
+                or not vals.is_contiguous():
+            raise ValueError("vals must be a contiguous float32/float64 (nnz,) tensor")
+        t = rt_coo()
+        t.ndim = d
+        for i, s in enumerate(dims):
+            t.dims[i] = int(s)
+        t.nnz = int(idx.shape[1])
+        t.dtype = RT_F64 if vals.dtype == torch.float64 else RT_F32
+        t.idx = idx.data_ptr() if t.nnz else None
+        t.vals = vals.data_ptr() if t.nnz else None
+        return t
+
+    def sp_sthosvd_coo(self, idx, vals, dims, ranks, p, seed, order=None):
+        """SP-STHOSVD (Alg. 6) of the sparse tensor with coordinates idx (int32,
+        (ndim, nnz)) and values vals on this device: rt_sp_sthosvd_coo."""
+        self._sync_stream()
+        t = self._coo(idx, vals, dims)
+        shape = _Shape(dims, vals.dtype)
+        rk = (ctypes.c_int32 * len(dims))(*[RT_KEEP if (r is None or r < 0) else int(r) for r in ranks])
+        o = self._opts(shape, p, seed, order, None)
+        out = rt_tucker()
+        st = _check(_lib.rt_sp_sthosvd_coo(self.ctx, ctypes.byref(t), rk, ctypes.byref(o), ctypes.byref(out)))
+        return self._result(out, shape, st, deferred=True)
+
+    def sketch_coo(self, idx, vals, dims, mode, ell, seed, col0=0, want_norm=False):
+        """Y = X_(mode) Omega[:, col0 : col0 + ell] of a sparse tensor: rt_sketch_coo."""
+        torch = self.torch
+        self._sync_stream()
+        t = self._coo(idx, vals, dims)
+        Y = torch.empty((int(dims[mode]), int(ell)), dtype=torch.float64, device=self.device)
+        nrm = torch.empty(1, dtype=torch.float64, device=self.device) if want_norm else None
+        _check(_lib.rt_sketch_coo(self.ctx, ctypes.byref(t), int(mode), int(ell), int(col0), int(seed), Y.data_ptr(),
+                                  nrm.data_ptr() if nrm is not None else None))
+        return (Y, nrm) if want_norm else Y
 
     def _fixed(self, fn, X, ranks, p, seed, order, prec, power_iters=0):
         self._sync_stream()

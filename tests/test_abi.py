@@ -56,6 +56,12 @@ def test_argument_errors_are_synchronous():
     o.prec, o.block = rtucker.PREC["f32"], 0
     assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
     assert lib.rt_server_submit(None, None, 0, None) == rtucker.RT_EINVAL
+    assert lib.rt_server_get_stats(None, None) == rtucker.RT_EINVAL
+    # sparse inputs
+    c = rtucker.rt_coo()
+    assert lib.rt_sp_sthosvd_coo(None, ctypes.byref(c), None, ctypes.byref(opts), ctypes.byref(out)) == \
+        rtucker.RT_EINVAL
+    assert lib.rt_sketch_coo(None, ctypes.byref(c), 0, 4, 0, 0, None, None) == rtucker.RT_EINVAL
     assert lib.rt_server_destroy(None) == rtucker.RT_OK
 
 
@@ -80,6 +86,10 @@ int main(void) {
          offsetof(rt_server_opts, prec), offsetof(rt_server_opts, eps), offsetof(rt_server_opts, block));
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_result), offsetof(rt_result, ranks), offsetof(rt_result, core),
          offsetof(rt_result, factors), offsetof(rt_result, flags), offsetof(rt_result, latency_s));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_coo), offsetof(rt_coo, nnz), offsetof(rt_coo, dtype),
+         offsetof(rt_coo, idx), offsetof(rt_coo, vals));
+  printf("%zu %zu %zu\\n", sizeof(rt_server_stats), offsetof(rt_server_stats, wait_s),
+         offsetof(rt_server_stats, overlap_s));
   return 0;
 }
 """)
@@ -97,3 +107,7 @@ int main(void) {
                                                  S.eps.offset, S.block.offset]
     assert [int(v) for v in lines[4].split()] == [ctypes.sizeof(R), R.ranks.offset, R.core.offset,
                                                  R.factors.offset, R.flags.offset, R.latency_s.offset]
+    C, ST = rtucker.rt_coo, rtucker.rt_server_stats
+    assert [int(v) for v in lines[5].split()] == [ctypes.sizeof(C), C.nnz.offset, C.dtype.offset, C.idx.offset,
+                                                 C.vals.offset]
+    assert [int(v) for v in lines[6].split()] == [ctypes.sizeof(ST), ST.wait_s.offset, ST.overlap_s.offset]
