@@ -1982,6 +1982,8 @@ hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, i
     if (J <= NT)
         hipLaunchKernelGGL(select_rows_kernel<true>, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad,
                            Aout, da == Dt::F64 ? 1 : 0, sel, swaps);
+    else if (J <= select_grid_rows())
+        return launch_select_rows_grid(Q, J, ell, eta, max_swaps, scratch, Aout, da, sel, swaps, stream);
     else
         hipLaunchKernelGGL(select_rows_kernel<false>, dim3(1), dim3(NT), 0, stream, Q, J, ell, eta, max_swaps, R, Ad,
                            Aout, da == Dt::F64 ? 1 : 0, sel, swaps);

@@ -137,6 +137,11 @@ hipError_t launch_svqb(const double* W, int ell, double drop, double* T, float* 
 // to Aout (J x ell, dtype da); swaps[0] = exchanges made.  scratch: 2 J ell doubles.
 hipError_t launch_select_rows(const double* Q, int64_t J, int ell, double eta, int max_swaps, double* scratch,
                               void* Aout, Dt da, int* sel, int* swaps, hipStream_t stream);
+// The same selection for 512 < J <= select_grid_rows(): one cooperative grid of
+// ceil(J / 256) workgroups with a grid-wide barrier per step (identical result).
+int64_t select_grid_rows();
+hipError_t launch_select_rows_grid(const double* Q, int64_t J, int ell, double eta, int max_swaps, double* scratch,
+                                   void* Aout, Dt da, int* sel, int* swaps, hipStream_t stream);
 // out (L, ell, R) = G (L, J, R) at the mode indices sel[0..ell) (dtype dt)
 hipError_t launch_gather_mode(const void* G, Dt dt, Shape3 s, const int* sel, int ell, void* out, hipStream_t stream);
 

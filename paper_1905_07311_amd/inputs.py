@@ -241,6 +241,30 @@ def odeco_device(seed, dims, decay, device, dtype):
     return out
 
 
+def sparse_counts_device(seed, dims, nnz, device, dtype):
+    """Sparse tensor of count-like data (a stand-in for the word-count and
+    knowledge-base tensors of §6.2.3): about `nnz` distinct coordinates drawn
+    uniformly (linear indices drawn with replacement, repeats collapsed), values
+    geometric on {1, 2, ...} with mean 2.  Returns (idx int32 [d, nnz'] in
+    row-major order, vals, dims) on `device`."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    total = 1
+    for n in dims:
+        total *= int(n)
+    lin = torch.randint(0, total, (int(nnz),), generator=gen, dtype=torch.int64, device=device)
+    lin = torch.unique(lin)
+    idx = torch.empty((len(dims), lin.shape[0]), dtype=torch.int32, device=device)
+    rest = lin
+    for m in range(len(dims) - 1, -1, -1):
+        idx[m] = (rest % int(dims[m])).to(torch.int32)
+        rest = rest // int(dims[m])
+    u = torch.rand(lin.shape[0], generator=gen, dtype=torch.float64, device=device)
+    vals = torch.floor(torch.log(u) / math.log(0.5)) + 1.0        # geometric, P(k) = 2^-k
+    return idx, vals.to(dtype), tuple(int(n) for n in dims)
+
+
 def config_seed(k):
     return DATA_SEED_BASE + k
 

@@ -158,3 +158,17 @@ def test_sp_sthosvd_coo_edge_cases(ctx):
     with pytest.raises(rtucker.RtError) as err:
         gb.norm_x
     assert err.value.status == rtucker.RT_EINVAL
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sp_sthosvd_coo_tall_modes(ctx, dtype):
+    # a stand-in of the condensed word-count tensor of §6.2.3 (807 x 613 x 1922,
+    # 19,841 counts), target rank 30, p = 5, order 3-1-2: every mode is longer
+    # than 512 rows, so the selection runs on the multi-workgroup kernel
+    idx, vals, dims = inputs.sparse_counts_device(11, (807, 613, 1922), 19841, torch.device("cuda", 0), dtype)
+    ih, vh = idx.cpu().numpy().astype(np.int64), vals.double().cpu().numpy()
+    X = oracle.densify(ih, vh, dims)
+    g = ctx.sp_sthosvd_coo(idx, vals, dims, [30, 30, 30], 5, seed=3, order=[2, 0, 1])
+    o = oracle.sp_sthosvd_coo(ih, vh, dims, [30, 30, 30], 5, seed=3, order=[2, 0, 1])
+    _check_against_oracle(g, o, X, 1e-10 if dtype == torch.float64 else 1e-4)
+    print(f"condensed-count stand-in {dtype}: error {np.linalg.norm(o.reconstruct() - X) / np.linalg.norm(X):.4f}")

@@ -352,7 +352,8 @@ def test_reconstruct_device(ctx, dtype):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dims,core,ranks,p", [((40, 33, 27), (10, 9, 8), [6, 5, 4], 3),
-                                               ((64, 48, 20), (12, 12, 10), [10, 8, 6], 4)])
+                                               ((64, 48, 20), (12, 12, 10), [10, 8, 6], 4),
+                                               ((1300, 600, 24), (14, 12, 10), [9, 8, 6], 4)])
 def test_sp_sthosvd_parity(ctx, dtype, dims, core, ranks, p):
     # Alg. 6: same selections as the oracle (index work: exact), factors
     # A = Q (P^T Q)^-1 (independent of the basis Q), core = X at the selections
