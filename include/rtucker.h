@@ -267,6 +267,47 @@ rt_status rt_omega(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t
 rt_status rt_philox_words(rt_ctx* ctx, uint64_t seed, int32_t mode, int64_t c0, int64_t n, uint32_t q,
                           uint32_t* out);
 
+/* ---- tile table (autotuning) ----------------------------------------------------- */
+/* The launch shape of the sketch (which kernel variant, its row blocking, and
+ * how many workgroups the split over the unfolding's columns aims for) comes
+ * from a process-wide table when an entry matches, else from built-in rules.
+ * The table is written by the project's tuner, which times the candidate shapes
+ * of representative problems on the device (paper_1905_07311_amd/tune.py, table
+ * in paper_1905_07311_amd/tuning/); the Python binding installs it at load.  An
+ * entry applies to sketches of tensors of `dtype` at precision `prec` whose
+ * mode-n unfolding has J in [j_lo, j_hi] rows and K in [k_lo, k_hi] columns,
+ * width ell in [ell_lo, ell_hi], and stride class `stride`; the first matching
+ * entry wins.  An entry whose variant does not serve the shape, or would lower
+ * the precision (the bfloat16 sketch for RT_PREC_F32), is skipped. */
+#define RT_TUNE_SKETCH 0
+#define RT_STRIDE_FIRST 0   /* mode 0: the unfolding's columns are contiguous rows of X */
+#define RT_STRIDE_INNER 1   /* 0 < n < d - 1 */
+#define RT_STRIDE_LAST 2    /* the last mode: X_(n) is read along its rows */
+typedef struct {
+    int32_t op;               /* RT_TUNE_SKETCH */
+    rt_dtype dtype;
+    rt_precision prec;
+    int32_t stride;           /* RT_STRIDE_* */
+    int64_t j_lo, j_hi;
+    int64_t k_lo, k_hi;
+    int32_t ell_lo, ell_hi;
+    int32_t kind;             /* RT_SKETCH_* variant */
+    int32_t rb, rw;           /* row blocking: RT_SKETCH_SPLIT_BF16 / BF16X3: rb in {1, 2, 4}
+                                 (16-row blocks per wave); RT_SKETCH_MFMA_F32: (rb, rw) in
+                                 {(1,1), (2,1), (2,2)}; 0 = the built-in rule */
+    int32_t wgs;              /* workgroups the column split aims for (0 = built-in) */
+} rt_tune_entry;
+
+/* Replace the process-wide table with n entries (copied); n = 0 clears it. */
+rt_status rt_tuning_set(const rt_tune_entry* entries, int32_t n);
+
+/* The launch shape the sketch of mode `mode` of a tensor of `dims` (host, ndim
+ * values) would use at width ell (col0 = 0, 16-byte aligned data): *out gets
+ * the variant and its parameters (bounds = the shape itself, wgs = the
+ * workgroups of the launch); *from_table is 1 when a table entry chose it. */
+rt_status rt_tuning_plan(rt_dtype dtype, rt_precision prec, const int64_t* dims, int32_t ndim, int32_t mode,
+                         int32_t ell, rt_tune_entry* out, int32_t* from_table);
+
 /* ---- timing log --------------------------------------------------------------- */
 
 /* Kernel kinds of the timing log. */

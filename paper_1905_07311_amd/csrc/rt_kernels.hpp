@@ -195,7 +195,15 @@ hipError_t launch_sketch_f32_cols(const SketchPlan& p, const float* X, Shape3 s,
 // sketch, two truncated bfloat16 pieces per operand and the three products of
 // weight above 2^-16 (hh, hm, mh), relative accuracy about 2^-15.
 bool sketch_x6_ok(Shape3 s, int ell, int64_t col0, const void* X);
-void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16);
+// rb (16-row blocks per wave: 1, 2 or 4) and wgs (workgroups the column split
+// aims for): 0 = the built-in rule
+void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16, int rb = 0, int wgs = 0);
+// Process-wide tile table (rt_tuning_set / rt_tuning_plan).
+rt_status tuning_set(const rt_tune_entry* entries, int32_t n);
+// plan_sketch's choice for a shape, and whether a table entry made it
+SketchPlan plan_sketch_info(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3,
+                            bool* from_table);
+int stride_class(Shape3 s);
 hipError_t launch_sketch_f32_x6(const SketchPlan& p, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed,
                                 uint32_t mode, float* partial, double* nrm2, hipStream_t stream);
 // explicit Omega from Om ((L, ell, R) float tensor, 16-byte aligned); needs R % 4 == 0

@@ -9,6 +9,9 @@
 // the rows when R == 1) and generates the 64 x ell slab of Omega once into LDS;
 // each wave then accumulates every fourth group of four adjacent columns for all
 // 64 rows.  The next tile's loads are issued before the current one is consumed.
+#include <mutex>
+#include <vector>
+
 #include "rt_kernels.hpp"
 #include "rt_philox.hpp"
 
@@ -270,9 +273,106 @@ int sketch_nq_bucket(int nq) {
 int64_t sketch_target_wg(const SketchPlan&) { return 1024; }
 }  // namespace
 
-SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3) {
-    SketchPlan p{};
+namespace {
+
+// The split of the unfolding's columns: `target` workgroups over nrowtile row tiles.
+void split_columns(SketchPlan& p, int64_t ntl, int64_t target) {
+    int64_t want = target / p.nrowtile;
+    if (want < 1) want = 1;
+    if (want > ntl) want = ntl;
+    p.tiles_per_split = (ntl + want - 1) / want;
+    p.nsplit = (int)((ntl + p.tiles_per_split - 1) / p.tiles_per_split);
+    if (p.nsplit < 1) p.nsplit = 1;
+    p.nwg = p.nsplit * p.nrowtile;
+}
+
+void plan_mfma(SketchPlan& p, Shape3 s, int ell, int rb, int rw, int wgs) {
+    p.kind = 1;
+    if ((rb == 1 && rw == 1) || (rb == 2 && rw == 1) || (rb == 2 && rw == 2)) { p.rb = rb; p.rw = rw; }
+    else sketch_rows_config(s.J, p.rb, p.rw);
+    p.nq = sketch_nq_bucket((ell + 3) / 4);
+    p.ldp = 4 * p.nq;
+    const int64_t mt = 64 * p.rb * p.rw;
+    p.nrowtile = (int)((s.J + mt - 1) / mt);
+    split_columns(p, (s.L * s.R + 31) / 32, wgs > 0 ? wgs : sketch_target_wg(p));
+    p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)p.ldp;
+}
+
+void plan_generic(SketchPlan& p, Shape3 s, int ell, int wgs) {
+    p.kind = 0;
+    p.rb = p.rw = p.nq = 0;
+    p.ldp = ell;
+    p.nrowtile = (int)((s.J + SK_MT - 1) / SK_MT);
+    split_columns(p, (s.L * s.R + SK_KC - 1) / SK_KC, wgs > 0 ? wgs : 2048);
+    p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
+}
+
+std::mutex g_tune_mu;
+std::vector<rt_tune_entry> g_tune;
+
+bool find_entry(Dt dt, int prec, Shape3 s, int ell, rt_tune_entry& out) {
     const int64_t K = s.L * s.R;
+    const int sc = stride_class(s);
+    const rt_dtype dtype = dt == Dt::F64 ? RT_F64 : RT_F32;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const rt_tune_entry& e : g_tune)
+        if (e.op == RT_TUNE_SKETCH && e.dtype == dtype && (int)e.prec == prec && e.stride == sc && s.J >= e.j_lo &&
+            s.J <= e.j_hi && K >= e.k_lo && K <= e.k_hi && ell >= e.ell_lo && ell <= e.ell_hi) {
+            out = e;
+            return true;
+        }
+    return false;
+}
+
+// The plan of a table entry, when its variant serves the shape at (at least) the
+// requested precision.
+bool plan_from_entry(const rt_tune_entry& e, Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X,
+                     SketchPlan& p) {
+    const bool f32 = dt == Dt::F32;
+    switch (e.kind) {
+        case 3:   // float32-accurate sketch from bfloat16 pieces
+            if (!(f32 && prec == 1 && sketch_x6_ok(s, ell, col0, X))) return false;
+            plan_sketch_x6(p, s, ell, false, e.rb, e.wgs);
+            return true;
+        case 4:   // the bfloat16 sketch
+            if (!(f32 && prec == 2 && sketch_x6_ok(s, ell, col0, X))) return false;
+            plan_sketch_x6(p, s, ell, true, e.rb, e.wgs);
+            return true;
+        case 1:
+            if (!(f32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X))) return false;
+            plan_mfma(p, s, ell, e.rb, e.rw, e.wgs);
+            return true;
+        case 0:
+            plan_generic(p, s, ell, e.wgs);
+            return true;
+        default:
+            return false;
+    }
+}
+
+}  // namespace
+
+int stride_class(Shape3 s) { return s.L == 1 ? RT_STRIDE_FIRST : (s.R == 1 ? RT_STRIDE_LAST : RT_STRIDE_INNER); }
+
+rt_status tuning_set(const rt_tune_entry* entries, int32_t n) {
+    std::vector<rt_tune_entry> t;
+    if (n > 0) t.assign(entries, entries + n);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(t);
+    return RT_OK;
+}
+
+SketchPlan plan_sketch_info(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3,
+                            bool* from_table) {
+    SketchPlan p{};
+    if (from_table) *from_table = false;
+    // a table entry (for the ordinary sketch with generated Omega)
+    rt_tune_entry e;
+    if (split3 && find_entry(dt, prec, s, ell, e) && plan_from_entry(e, dt, prec, s, ell, col0, X, p)) {
+        if (from_table) *from_table = true;
+        return p;
+    }
+    // built-in rules
     if (dt == Dt::F32 && (prec == 1 || prec == 2) && split3 && sketch_x6_ok(s, ell, col0, X)) {
         plan_sketch_x6(p, s, ell, prec == 2);
         return p;
@@ -280,36 +380,15 @@ SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const v
     // the bfloat16 sketch exists on the 16x16x32 kernel only; other modes take
     // the float32 sketch (at least as accurate)
     if (dt == Dt::F32 && prec != 0 && sketch_mfma_ok(s, ell, col0, X)) {
-        p.kind = 1;
-        sketch_rows_config(s.J, p.rb, p.rw);
-        p.nq = sketch_nq_bucket((ell + 3) / 4);
-        p.ldp = 4 * p.nq;
-        const int64_t mt = 64 * p.rb * p.rw;
-        const int64_t ntl = (K + 31) / 32;
-        p.nrowtile = (int)((s.J + mt - 1) / mt);
-        int64_t want = sketch_target_wg(p) / p.nrowtile;
-        if (want < 1) want = 1;
-        if (want > ntl) want = ntl;
-        p.tiles_per_split = (ntl + want - 1) / want;
-        p.nsplit = (int)((ntl + p.tiles_per_split - 1) / p.tiles_per_split);
-        p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)p.ldp;
-        p.nwg = p.nsplit * p.nrowtile;
+        plan_mfma(p, s, ell, 0, 0, 0);
         return p;
     }
-    const int64_t ntiles = (K + SK_KC - 1) / SK_KC;
-    p.nrowtile = (int)((s.J + SK_MT - 1) / SK_MT);
-    int64_t want = 2048 / p.nrowtile;
-    if (want < 1) want = 1;
-    if (want > ntiles) want = ntiles;
-    p.tiles_per_split = (ntiles + want - 1) / want;
-    p.nsplit = (int)((ntiles + p.tiles_per_split - 1) / p.tiles_per_split);
-    if (p.nsplit < 1) p.nsplit = 1;
-    p.partial_elems = (size_t)p.nsplit * (size_t)s.J * (size_t)ell;
-    p.nwg = p.nsplit * p.nrowtile;
-    p.kind = 0;
-    p.rb = p.rw = p.nq = 0;
-    p.ldp = ell;
+    plan_generic(p, s, ell, 0);
     return p;
+}
+
+SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3) {
+    return plan_sketch_info(dt, prec, s, ell, col0, X, split3, nullptr);
 }
 
 hipError_t launch_sketch(const SketchPlan& p, Dt dt, int prec, const void* X, Shape3 s, int ell,

@@ -319,9 +319,9 @@ bool sketch_x6_ok(Shape3 s, int ell, int64_t col0, const void* X) {
            bytes <= 0x7fff0000LL;
 }
 
-void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16) {
+void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16, int rb, int wgs) {
     p.kind = bf16 ? 4 : 3;
-    p.rb = s.J <= 128 ? 1 : 2;                        // 16-row blocks per wave
+    p.rb = rb == 1 || rb == 2 || rb == 4 ? rb : (s.J <= 128 ? 1 : 2);   // 16-row blocks per wave
     p.rw = 0;
     p.nq = (ell + 15) / 16;
     p.ldp = ell;
@@ -329,7 +329,7 @@ void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16) {
     const int64_t K = s.L * s.R;
     const int64_t ntl = (K + X6_KC - 1) / X6_KC;
     p.nrowtile = (int)((s.J + mt - 1) / mt);
-    int64_t want = 2048 / X6_WPG / p.nrowtile;        // two waves per SIMD
+    int64_t want = (wgs > 0 ? wgs : 2048 / X6_WPG) / p.nrowtile;   // built-in: two waves per SIMD
     if (want < 1) want = 1;
     if (want > ntl) want = ntl;
     p.tiles_per_split = (ntl + want - 1) / want;

@@ -1357,6 +1357,49 @@ rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell,
     return RT_OK;
 }
 
+rt_status rt_tuning_set(const rt_tune_entry* entries, int32_t n) {
+    if (n < 0 || (n > 0 && !entries)) return fail(RT_EINVAL, "entries is NULL or n < 0");
+    for (int32_t i = 0; i < n; ++i) {
+        const rt_tune_entry& e = entries[i];
+        if (e.op != RT_TUNE_SKETCH || (e.dtype != RT_F32 && e.dtype != RT_F64) || e.prec < RT_PREC_F64 ||
+            e.prec > RT_PREC_BF16_SKETCH || e.stride < RT_STRIDE_FIRST || e.stride > RT_STRIDE_LAST ||
+            e.j_lo > e.j_hi || e.k_lo > e.k_hi || e.ell_lo > e.ell_hi || e.wgs < 0 || e.wgs > (1 << 20) ||
+            (e.kind != RT_SKETCH_GENERIC && e.kind != RT_SKETCH_MFMA_F32 && e.kind != RT_SKETCH_SPLIT_BF16 &&
+             e.kind != RT_SKETCH_BF16X3))
+            return fail(RT_EINVAL, "tile table entry " + std::to_string(i) + " is malformed");
+    }
+    return rt::tuning_set(entries, n);
+}
+
+rt_status rt_tuning_plan(rt_dtype dtype, rt_precision prec, const int64_t* dims, int32_t ndim, int32_t mode,
+                         int32_t ell, rt_tune_entry* out, int32_t* from_table) {
+    if (!dims || !out) return fail(RT_EINVAL, "NULL argument");
+    if (ndim < 2 || ndim > RT_MAXD || mode < 0 || mode >= ndim) return fail(RT_EINVAL, "bad ndim or mode");
+    if (ell < 1 || ell > RT_LMAX) return fail(RT_EINVAL, "ell must be in [1, RT_LMAX]");
+    if (dtype != RT_F32 && dtype != RT_F64) return fail(RT_EINVAL, "dtype must be RT_F32 or RT_F64");
+    std::vector<int64_t> d(dims, dims + ndim);
+    for (auto v : d)
+        if (v < 1) return fail(RT_EINVAL, "every dim must be >= 1");
+    const Shape3 s = shape3(d, mode);
+    bool tab = false;
+    alignas(256) static const double aligned_probe[2] = {0.0, 0.0};   // stands for aligned data
+    const rt::SketchPlan p = rt::plan_sketch_info(dt_of(dtype), (int)prec, s, ell, 0, aligned_probe, true, &tab);
+    std::memset(out, 0, sizeof(*out));
+    out->op = RT_TUNE_SKETCH;
+    out->dtype = dtype;
+    out->prec = prec;
+    out->stride = rt::stride_class(s);
+    out->j_lo = out->j_hi = s.J;
+    out->k_lo = out->k_hi = s.L * s.R;
+    out->ell_lo = out->ell_hi = ell;
+    out->kind = p.kind;
+    out->rb = p.rb;
+    out->rw = p.rw;
+    out->wgs = p.nwg;
+    if (from_table) *from_table = tab ? 1 : 0;
+    return RT_OK;
+}
+
 rt_status rt_orth(rt_ctx* ctx, double* Y, int64_t rows, int32_t ell, uint32_t* flags) {
     if (!ctx || !Y) return fail(RT_EINVAL, "NULL argument");
     if (ell < 1 || ell > RT_LMAX || rows < ell) return fail(RT_EINVAL, "need 1 <= ell <= min(rows, RT_LMAX)");

@@ -28,7 +28,7 @@ EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_des
             "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_sp_sthosvd_coo", "rt_sketch_coo", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
             "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
-            "rt_server_get_stats", "rt_server_destroy"]
+            "rt_server_get_stats", "rt_server_destroy", "rt_tuning_set", "rt_tuning_plan"]
 
 
 class RtError(RuntimeError):
@@ -74,6 +74,17 @@ class rt_result(ctypes.Structure):
 class rt_coo(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD), ("nnz", ctypes.c_int64),
                 ("dtype", ctypes.c_int), ("idx", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class rt_tune_entry(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("dtype", ctypes.c_int), ("prec", ctypes.c_int), ("stride", ctypes.c_int32),
+                ("j_lo", ctypes.c_int64), ("j_hi", ctypes.c_int64), ("k_lo", ctypes.c_int64), ("k_hi", ctypes.c_int64),
+                ("ell_lo", ctypes.c_int32), ("ell_hi", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("rb", ctypes.c_int32), ("rw", ctypes.c_int32), ("wgs", ctypes.c_int32)]
+
+
+TUNE_FIELDS = [f for f, _ in rt_tune_entry._fields_]
+TUNING_FILE = os.path.join(PKG, "tuning", "gfx950.json")
 
 
 class rt_server_stats(ctypes.Structure):
@@ -150,11 +161,50 @@ def load(path=None):
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
     lib.rt_server_get_stats.argtypes = [P, ctypes.POINTER(rt_server_stats)]
     lib.rt_server_destroy.argtypes = [P]
+    lib.rt_tuning_set.argtypes = [ctypes.POINTER(rt_tune_entry), ctypes.c_int32]
+    lib.rt_tuning_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(rt_tune_entry),
+                                   ctypes.POINTER(ctypes.c_int32)]
     for fn in EXPORTED:
         if fn not in ("rt_version", "rt_last_error"):
             getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
+    if os.path.exists(TUNING_FILE):
+        set_tuning(read_tuning(TUNING_FILE))
     return lib
+
+
+def read_tuning(path=TUNING_FILE):
+    """The entries of a tile table written by the tuner (a JSON file)."""
+    import json
+    with open(path) as fh:
+        doc = json.load(fh)
+    return [{k: e[k] for k in TUNE_FIELDS} for e in doc["entries"]]
+
+
+def set_tuning(entries):
+    """Install a tile table (list of dicts with the rt_tune_entry fields; [] clears)."""
+    lib = load()
+    arr = (rt_tune_entry * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        for k in TUNE_FIELDS:
+            setattr(arr[i], k, int(e[k]))
+    _check(lib.rt_tuning_set(arr, len(entries)))
+
+
+def tuning_plan(dtype, prec, dims, mode, ell):
+    """The sketch launch shape for a tensor of `dims` (mode, width ell): a dict of
+    the rt_tune_entry fields plus from_table."""
+    lib = load()
+    d = (ctypes.c_int64 * len(dims))(*[int(x) for x in dims])
+    out = rt_tune_entry()
+    tab = ctypes.c_int32(0)
+    pr = PREC[prec] if isinstance(prec, str) else int(prec)
+    dt = RT_F64 if dtype in ("f64", RT_F64) else RT_F32
+    _check(lib.rt_tuning_plan(dt, pr, d, len(dims), int(mode), int(ell), ctypes.byref(out), ctypes.byref(tab)))
+    r = {k: getattr(out, k) for k in TUNE_FIELDS}
+    r["from_table"] = bool(tab.value)
+    return r
 
 
 def _check(status, allow=()):

@@ -2,6 +2,9 @@
 the Omega stream (bitwise words, transformed normals), the sketch
 Y = X_(n) Omega (every mode, ragged shapes, column offsets), orth(Y) and the
 projection B = X x_n Q^T with its fused Gram."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -279,3 +282,36 @@ def test_projection_short_mode_many_strips(ctx):
     ref = Qf.astype(np.float64).T @ Xs
     got = B[:, torch.from_numpy(cols).cuda()].double().cpu().numpy()
     assert rel(got, ref) < 2e-6
+
+
+def test_tuned_plans_compute_the_same_sketch():
+    """Every launch shape of the committed tile table computes the same sketch as
+    the built-in plan (to the variant's rounding), on the table's own problems
+    (those up to 2^26 entries)."""
+    need_gpu()
+    import math
+    if not os.path.exists(rtucker.TUNING_FILE):
+        pytest.skip("no tile table")
+    entries = rtucker.read_tuning(rtucker.TUNING_FILE)
+    doc = json.load(open(rtucker.TUNING_FILE))
+    ctx = rtucker.Context(0)
+    try:
+        for e in doc["entries"]:
+            m = e["measured"]
+            if math.prod(m["dims"]) > (1 << 26):
+                continue
+            prec = {0: "f64", 1: "f32", 2: "bf16"}[e["prec"]]
+            dt = torch.float64 if prec == "f64" else torch.float32
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(3)
+            X = torch.randn(m["dims"], generator=gen, dtype=dt, device="cuda")
+            rtucker.set_tuning(entries)
+            assert rtucker.tuning_plan(prec, prec, m["dims"], m["mode"], m["ell"])["from_table"]
+            Yt = ctx.sketch(X, m["mode"], m["ell"], seed=9, prec=prec)
+            rtucker.set_tuning([])
+            Yb = ctx.sketch(X, m["mode"], m["ell"], seed=9, prec=prec)
+            tol = 1e-13 if prec == "f64" else (2e-3 if prec == "bf16" else 2e-5)
+            assert float(torch.linalg.norm(Yt - Yb) / torch.linalg.norm(Yb)) < tol, e["problem"]
+    finally:
+        rtucker.set_tuning(entries)
+        ctx.close()
