@@ -150,11 +150,14 @@ def run_step(ctx, name, X):
 
 # HBM traffic of the dominant kernel, from the committed rocprofv3 counter summary
 # (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy of
-# known size); reported only while the kernel's sources are those it was taken on.
+# known size); reported only while the kernel's sources and its launch plan (the
+# planner and the tile table) are those it was taken on.
 TRAFFIC_FILE = {"c2": "profiles/sketch_split_bf16_mode1_512cube_traffic.md"}
 TRAFFIC_SOURCES = ["paper_1905_07311_amd/csrc/rt_sketch_x6.hip",
+                   "paper_1905_07311_amd/csrc/rt_sketch.hip",
                    "paper_1905_07311_amd/csrc/rt_philox.hpp",
-                   "paper_1905_07311_amd/csrc/rt_kernels.hpp"]
+                   "paper_1905_07311_amd/csrc/rt_kernels.hpp",
+                   "paper_1905_07311_amd/tuning/gfx950.json"]
 
 
 def kernel_source_hash():
@@ -625,7 +628,7 @@ def main():
         "reconstruct": {"ms": round(rec_ms, 4),
                         "output_gbs": round(X.numel() * X.element_size() / (rec_ms * 1e-3) / 1e9, 1)},
         "kind_ms_per_step": {k: round(sum(e["ms"] for e in log_all if e["kind"] == k) / min(3, args.steps), 4)
-                             for k in ("sketch", "orth", "project", "gram", "truncate")},
+                             for k in ("sketch", "reduce", "orth", "project", "gram", "truncate")},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                      "kernel": "sketch TTM, mode 1" + (" (largest: the subspace-iteration product with Z read "

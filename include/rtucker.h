@@ -316,12 +316,13 @@ rt_status rt_tuning_plan(rt_dtype dtype, rt_precision prec, const int64_t* dims,
 #define RT_KIND_ORTH 2      /* single-workgroup orth(Y) */
 #define RT_KIND_TRUNCATE 3  /* single-workgroup eigensolver + factor */
 #define RT_KIND_GRAM 4      /* fp64 Gram of B for the truncation (unfused variant) */
+#define RT_KIND_REDUCE 5    /* fixed-order sum of a sketch's split-K partials, bytes = partials read */
 
 /* Set the per-launch timing log and clear it.  `kinds` is a bit mask over the
  * RT_KIND_* values (bit k records launches of kind k; 0 turns the log off,
  * RT_TIMING_ALL records every kind).  A recorded launch is bracketed by HIP
  * events on the context's stream. */
-#define RT_TIMING_ALL 0x1f
+#define RT_TIMING_ALL 0x3f
 rt_status rt_timing(rt_ctx* ctx, int32_t kinds);
 
 /* Number of entries in the timing log. */

@@ -298,7 +298,10 @@ rt_status do_sketch(Call& k, Dt dt, int prec, const void* G, Shape3 s, int ell, 
     }
     double* rtmp = k.ws<double>(rt::reduce_partials_tmp(plan.nsplit, s.J * ell) + 1);
     if (!rtmp) return fail(RT_ENOMEM, "workspace allocation failed");
-    RT_HIP(rt::launch_reduce_rows(partial, f64acc, plan.nsplit, s.J, ell, plan.ldp, Y, k.c->stream, rtmp));
+    {
+        TimeScope ts(k.c, 5, (double)plan.partial_elems * (f64acc ? 8 : 4), 0.0, s.J, plan.nsplit, ell);
+        RT_HIP(rt::launch_reduce_rows(partial, f64acc, plan.nsplit, s.J, ell, plan.ldp, Y, k.c->stream, rtmp));
+    }
     if (nrm2) RT_HIP(rt::launch_sum_scalar(np, plan.nwg, nrm2, k.c->stream));
     return RT_OK;
 }

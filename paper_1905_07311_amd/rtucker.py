@@ -542,10 +542,10 @@ class Context:
         mask = 0
         if enable:
             names = {v: k for k, v in self.KINDS.items()}
-            mask = 0x1f if kinds is None else sum(1 << names[k] for k in kinds)
+            mask = 0x3f if kinds is None else sum(1 << names[k] for k in kinds)
         _check(_lib.rt_timing(self.ctx, mask))
 
-    KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate", 4: "gram"}
+    KINDS = {0: "sketch", 1: "project", 2: "orth", 3: "truncate", 4: "gram", 5: "reduce"}
 
     def timing_log(self):
         """List of dicts, one per timed launch (kind, ms, bytes, flops, rows, cols, ell,

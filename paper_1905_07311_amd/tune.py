@@ -9,7 +9,8 @@ serving-size tensors) it enumerates the variants that serve the shape at the
 requested precision (the float32-accurate split-bfloat16 kernel or the
 bfloat16 sketch, the float32 MFMA kernel, the LDS-staged vector kernel) with
 their row blockings and column-split targets, times each (HIP events on the
-library's stream, median of several launches after warm-up), checks its result
+library's stream: the sketch launch plus the sum of its split-K partials, median
+of several calls after warm-up), checks its result
 against the built-in plan's, and keeps the fastest.  An entry covers the
 problem's bucket: J in the same power-of-two band, K within a factor of 2,
 ell in the same band, the same stride class.
@@ -99,12 +100,17 @@ def entry_for(dims, mode, ell, prec, kind, rb, rw, wgs, exact):
 
 
 def time_sketch(ctx, X, mode, ell, prec, reps):
-    ctx.timing(True, kinds=["sketch"])
+    """Median over `reps` calls (after two warm-up calls) of the sketch launch plus
+    the fixed-order sum of its split-K partials (a finer column split writes more
+    partials for that sum to read)."""
+    ctx.timing(True, kinds=["sketch", "reduce"])
     for _ in range(reps + 2):
         Y = ctx.sketch(X, mode, ell, seed=5, prec=prec)
-    log = [e["ms"] for e in ctx.timing_log()][2:]
+    log = ctx.timing_log()
     ctx.timing(False)
-    return statistics.median(log), Y
+    sk = [e["ms"] for e in log if e["kind"] == "sketch"][2:]
+    rd = [e["ms"] for e in log if e["kind"] == "reduce"][2:]
+    return statistics.median(sk) + (statistics.median(rd) if rd else 0.0), Y
 
 
 def main():
