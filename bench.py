@@ -156,7 +156,6 @@ TRAFFIC_FILE = {"c2": "profiles/sketch_split_bf16_mode1_512cube_traffic.md"}
 TRAFFIC_SOURCES = ["paper_1905_07311_amd/csrc/rt_sketch_x6.hip",
                    "paper_1905_07311_amd/csrc/rt_sketch.hip",
                    "paper_1905_07311_amd/csrc/rt_philox.hpp",
-                   "paper_1905_07311_amd/csrc/rt_kernels.hpp",
                    "paper_1905_07311_amd/tuning/gfx950.json"]
 
 

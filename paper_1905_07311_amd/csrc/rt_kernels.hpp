@@ -240,6 +240,11 @@ constexpr int64_t FINISH_DIRECT_MAX = 1 << 16;
 hipError_t launch_finish(const void* core, void* out, Dt dt, int64_t n, bool copy, const double* partial, int npart,
                          const double* nx2, const uint32_t* status, FinishScalars* hs, hipStream_t stream);
 hipError_t launch_norm2(const void* X, Dt dt, int64_t n, double* partial, int nwg, hipStream_t stream);
+// Mode expansion of reconstruction: out (L, I, R) with out[l, i, q] =
+// sum_k A[i, k] G[l, k, q] for G viewed as (L, s.J = r, R) and A (I x r,
+// row-major); every R, within the grid limits of expand_ok.
+bool expand_ok(Shape3 s, int64_t I);
+hipError_t launch_expand(Dt dt, const void* G, Shape3 s, const void* A, int64_t I, void* out, hipStream_t stream);
 // AT (cols x rows) = A^T for a row-major rows x cols matrix A, in dtype dt
 hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT, Dt dt, hipStream_t stream);
 // dst (dtype) <- src (double), n elements

@@ -1287,9 +1287,10 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
         RT_HIP(hipMemcpyAsync(out, t->core, (size_t)nout * es, hipMemcpyDeviceToDevice, st));
         return RT_OK;
     }
-    // G x_j A_j one mode at a time: out[l, i, r] = sum_k A_j[i, k] G[l, k, r], i.e. the
-    // projection kernels with Q = A_j^T (r_j x I_j), in column blocks of at most
-    // RT_LMAX written at their offset in the wider mode
+    // G x_j A_j one mode at a time: out[l, i, r] = sum_k A_j[i, k] G[l, k, r], by the
+    // expansion kernels (the output streamed once); shapes beyond their grid
+    // limits take the projection kernels with Q = A_j^T (r_j x I_j), in column
+    // blocks of at most RT_LMAX written at their offset
     std::vector<int64_t> cur_dims(t->ranks, t->ranks + d);
     const void* cur = t->core;
     for (int j = 0; j < d; ++j) {
@@ -1297,9 +1298,16 @@ rt_status rt_reconstruct(rt_ctx* ctx, const rt_tucker* t, void* out) {
         const int64_t I = t->dims[j];
         const int r = t->ranks[j];
         const Shape3 s = shape3(cur_dims, j);
-        void* AT = k.c->ws((size_t)r * I * es);
         void* dst = j == last ? out : k.c->ws((size_t)s.L * I * s.R * es);
-        if (!AT || !dst) return fail(RT_ENOMEM, "workspace allocation failed");
+        if (!dst) return fail(RT_ENOMEM, "workspace allocation failed");
+        if (rt::expand_ok(s, I)) {
+            RT_HIP(rt::launch_expand(dt, cur, s, t->factors[j], I, dst, st));
+            cur_dims[j] = I;
+            cur = dst;
+            continue;
+        }
+        void* AT = k.c->ws((size_t)r * I * es);
+        if (!AT) return fail(RT_ENOMEM, "workspace allocation failed");
         RT_HIP(rt::launch_transpose(t->factors[j], I, r, AT, dt, st));
         for (int64_t i0 = 0; i0 < I; i0 += RT_LMAX) {
             const int e = (int)std::min<int64_t>(RT_LMAX, I - i0);

@@ -335,8 +335,11 @@ def test_adaptive_rhosvd_per_mode_and_zero(ctx):
 def test_reconstruct_device(ctx, dtype):
     # rt_reconstruct against the oracle's mode products: dims above 64 (several
     # column blocks per expansion), a mode kept whole, R = 1 in the last mode
+    # (the last-mode expansion kernel), R >= 64 in a first and in a middle mode
+    # (the row expansion kernel), small R (the projection kernels)
     rng = np.random.default_rng(41)
-    for dims, ranks in (((130, 70, 9), [20, 64, 9]), ((33, 150, 64), [7, 5, 3]), ((40, 33, 27), [6, None, 4])):
+    for dims, ranks in (((130, 70, 9), [20, 64, 9]), ((33, 150, 64), [7, 5, 3]), ((40, 33, 27), [6, None, 4]),
+                        ((12, 50, 20, 30), [3, 4, 8, 9]), ((300, 20, 17), [33, 7, 5])):
         X = inputs.lowrank_tensor(rng, dims, [r or d for r, d in zip(ranks, dims)], noise=1e-3)
         Xs = X.astype(np.float32) if dtype == torch.float32 else X
         g = ctx.rsthosvd(torch.from_numpy(Xs).cuda(), ranks, 0, 2)
