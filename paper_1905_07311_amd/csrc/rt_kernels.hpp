@@ -158,6 +158,17 @@ hipError_t launch_coo_check(const int32_t* idx, int64_t ldi, int64_t nnz, const 
 hipError_t launch_coo_sketch(const int32_t* idx, int64_t ldi, const void* vals, Dt dt, const int64_t* nnz_dev,
                              int64_t bound, const CooDims& cd, int mode, int ell, int64_t col0, uint64_t seed,
                              double* Y, hipStream_t stream);
+// The same sketch for an input core of nnz entries (count on the host), the
+// entries first grouped by blocks of 2^shift rows (so each block's rows are
+// accumulated in LDS and added to Y once).  Scratch: hist (nch x nbk int32), off
+// (nch x nbk int64), bstart and pstart (nbk + 1 int64 each), keys and rv (nnz
+// int64 / double).  ok: the plan fits (J and ell small enough for LDS blocks).
+struct BinPlan { int shift; int nbk; int64_t nch; bool ok; };
+BinPlan plan_coo_bins(int64_t J, int ell, int64_t nnz);
+hipError_t launch_coo_sketch_binned(const BinPlan& bp, const int32_t* idx, const void* vals, Dt dt, int64_t nnz,
+                                    const CooDims& cd, int mode, int ell, int64_t col0, uint64_t seed, double* Y,
+                                    int32_t* hist, int64_t* off, int64_t* bstart, int64_t* pstart, int64_t* keys,
+                                    double* rv, hipStream_t stream);
 // G_(mode) <- P^T G_(mode): the entries whose mode coordinate is sel[j] for some j,
 // in input order, with that coordinate replaced by j, into (idx_out, ldo,
 // vals_out); their count into *nnz_out.  inv: dims[mode] ints; cnt, off:

@@ -186,6 +186,166 @@ __global__ __launch_bounds__(256) void coo_densify_kernel(const int32_t* __restr
     }
 }
 
+// ---- binned sketch: the entries grouped by blocks of 2^shift rows first ----------------
+// Device-scope atomic adds resolve beyond the per-XCD L2, so scattering every
+// v * Omega[c, k] into Y directly runs at the atomic rate.  For a large core the
+// entries are first grouped by row block (a counting sort without stable
+// order: per-chunk histograms in LDS, one scan, LDS cursors), then each piece of
+// a block's entries is accumulated into an LDS copy of the block's rows and
+// added to Y once.
+constexpr int BN_CH = 65536;     // entries per counting workgroup
+constexpr int BN_MAXB = 2048;    // row blocks
+constexpr int BN_PS = 8192;      // entries per accumulation piece
+constexpr int BN_LDSY = 4096;    // doubles of an LDS row block (rows x ell)
+
+__device__ __forceinline__ int64_t coo_column(const int32_t* __restrict__ idx, int64_t ldi, int64_t e,
+                                              const CooDims& cd, int mode) {
+    int64_t c = 0;
+    for (int m = 0; m < cd.d; ++m)
+        if (m != mode) c = c * cd.dims[m] + idx[m * ldi + e];
+    return c;
+}
+
+__global__ __launch_bounds__(256) void coo_bin_count_kernel(const int32_t* __restrict__ idx, int64_t nnz, CooDims cd,
+                                                            int mode, int shift, int nbk, int32_t* __restrict__ hist) {
+    __shared__ int h[BN_MAXB];
+    for (int b = threadIdx.x; b < nbk; b += 256) h[b] = 0;
+    __syncthreads();
+    const int64_t e0 = (int64_t)blockIdx.x * BN_CH;
+    const int64_t e1 = e0 + BN_CH < nnz ? e0 + BN_CH : nnz;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256)
+        if (coo_valid(idx, nnz, e, cd)) atomicAdd(&h[idx[mode * nnz + e] >> shift], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += 256) hist[(int64_t)blockIdx.x * nbk + b] = h[b];
+}
+
+// One workgroup: bucket totals, their exclusive scan (bstart[0 .. nbk]), the
+// pieces per bucket and their scan (pstart[0 .. nbk]), and every chunk's
+// starting offset in every bucket (off[chunk][b]).
+__global__ __launch_bounds__(256) void coo_bin_scan_kernel(const int32_t* __restrict__ hist, int64_t nch, int nbk,
+                                                           int64_t* __restrict__ bstart, int64_t* __restrict__ pstart,
+                                                           int64_t* __restrict__ off) {
+    __shared__ int64_t tot[BN_MAXB];
+    __shared__ int64_t sb[256], sp[256];
+    const int t = threadIdx.x;
+    for (int b = t; b < nbk; b += 256) {
+        int64_t s = 0;
+        for (int64_t c = 0; c < nch; ++c) s += hist[c * nbk + b];
+        tot[b] = s;
+    }
+    __syncthreads();
+    // each thread scans eight consecutive buckets; the 256 partial sums are scanned in LDS
+    constexpr int PER = BN_MAXB / 256;
+    int64_t vb = 0, vp = 0;
+    for (int u = 0; u < PER; ++u) {
+        const int b = t * PER + u;
+        if (b < nbk) { vb += tot[b]; vp += (tot[b] + BN_PS - 1) / BN_PS; }
+    }
+    sb[t] = vb;
+    sp[t] = vp;
+    __syncthreads();
+    for (int s2 = 1; s2 < 256; s2 <<= 1) {
+        const int64_t ab = t >= s2 ? sb[t - s2] : 0, ap = t >= s2 ? sp[t - s2] : 0;
+        __syncthreads();
+        sb[t] += ab;
+        sp[t] += ap;
+        __syncthreads();
+    }
+    int64_t rb = sb[t] - vb, rp = sp[t] - vp;
+    for (int u = 0; u < PER; ++u) {
+        const int b = t * PER + u;
+        if (b < nbk) {
+            bstart[b] = rb;
+            pstart[b] = rp;
+            rb += tot[b];
+            rp += (tot[b] + BN_PS - 1) / BN_PS;
+        }
+    }
+    if (t == 255) { bstart[nbk] = sb[255]; pstart[nbk] = sp[255]; }
+    __syncthreads();
+    for (int b = t; b < nbk; b += 256) {
+        int64_t run = 0;
+        for (int u = 0; u < b; ++u) run += tot[u];
+        for (int64_t c = 0; c < nch; ++c) {
+            off[c * nbk + b] = run;
+            run += hist[c * nbk + b];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void coo_bin_scatter_kernel(const int32_t* __restrict__ idx,
+                                                              const T* __restrict__ vals, int64_t nnz, CooDims cd,
+                                                              int mode, int shift, int nbk,
+                                                              const int64_t* __restrict__ off,
+                                                              int64_t* __restrict__ keys, double* __restrict__ rv) {
+    __shared__ unsigned long long cur[BN_MAXB];
+    for (int b = threadIdx.x; b < nbk; b += 256) cur[b] = (unsigned long long)off[(int64_t)blockIdx.x * nbk + b];
+    __syncthreads();
+    const int64_t e0 = (int64_t)blockIdx.x * BN_CH;
+    const int64_t e1 = e0 + BN_CH < nnz ? e0 + BN_CH : nnz;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        if (!coo_valid(idx, nnz, e, cd)) continue;
+        const int32_t row = idx[mode * nnz + e];
+        const int64_t pos = (int64_t)atomicAdd(&cur[row >> shift], 1ull);
+        keys[pos] = (coo_column(idx, nnz, e, cd, mode) << shift) | (row & ((1 << shift) - 1));
+        rv[pos] = (double)vals[e];
+    }
+}
+
+// Pieces p = blockIdx.x, blockIdx.x + gridDim.x, ... of pstart[nbk]; piece j of
+// bucket b covers its entries [bstart[b] + j BN_PS, ...).
+template <typename TO>
+__global__ __launch_bounds__(256) void coo_bin_sketch_kernel(const int64_t* __restrict__ keys,
+                                                             const double* __restrict__ rv,
+                                                             const int64_t* __restrict__ bstart,
+                                                             const int64_t* __restrict__ pstart, int nbk, int shift,
+                                                             int64_t J, int ell, int64_t col0, uint64_t seed,
+                                                             uint32_t mode, double* __restrict__ Y) {
+    __shared__ double yb[BN_LDSY];
+    const int br = 1 << shift;
+    const int64_t P = pstart[nbk];
+    const int64_t q_first = col0 / 4;
+    const int64_t q_last = (col0 + ell - 1) / 4;
+    for (int64_t p = blockIdx.x; p < P; p += gridDim.x) {
+        int lo = 0, hi = nbk - 1;
+        while (lo < hi) {                          // last bucket with pstart <= p
+            const int mid = (lo + hi + 1) >> 1;
+            if (pstart[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = lo;
+        const int64_t r0 = bstart[b] + (p - pstart[b]) * BN_PS;
+        const int64_t r1 = r0 + BN_PS < bstart[b + 1] ? r0 + BN_PS : bstart[b + 1];
+        for (int e = threadIdx.x; e < br * ell; e += 256) yb[e] = 0.0;
+        __syncthreads();
+        for (int64_t e = r0 + threadIdx.x; e < r1; e += 256) {
+            const int64_t key = keys[e];
+            const double v = rv[e];
+            const int r = (int)(key & (br - 1));
+            const int64_t c = key >> shift;
+            double* yr = yb + r * ell;
+            for (int64_t q = q_first; q <= q_last; ++q) {
+                TO z[4];
+                OmegaGen<TO>::gen4(seed, mode, (uint64_t)c, (uint32_t)q, z);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t k = 4 * q + t - col0;
+                    if (k >= 0 && k < ell)
+                        __hip_atomic_fetch_add(yr + k, v * (double)z[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < br * ell; e += 256) {
+            const int64_t row = (int64_t)b * br + e / ell;
+            const double val = yb[e];
+            if (row < J && val != 0.0) unsafeAtomicAdd(Y + row * ell + e % ell, val);
+        }
+        __syncthreads();
+    }
+}
+
 unsigned stride_grid(int64_t bound) {
     const int64_t g = (bound + 255) / 256;
     return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
@@ -212,6 +372,47 @@ hipError_t launch_coo_check(const int32_t* idx, int64_t ldi, int64_t nnz, const 
                             uint32_t bit, hipStream_t stream) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(coo_check_kernel, dim3(stride_grid(nnz)), dim3(256), 0, stream, idx, ldi, nnz, cd, status, bit);
+    return hipGetLastError();
+}
+
+BinPlan plan_coo_bins(int64_t J, int ell, int64_t nnz) {
+    BinPlan p{};
+    int shift = 0;
+    while (((J + (1LL << shift) - 1) >> shift) > BN_MAXB) ++shift;
+    p.shift = shift;
+    p.nbk = (int)((J + (1LL << shift) - 1) >> shift);
+    p.nch = (nnz + BN_CH - 1) / BN_CH;
+    p.ok = nnz > 0 && (1LL << shift) * ell <= BN_LDSY && shift < 20;
+    return p;
+}
+
+hipError_t launch_coo_sketch_binned(const BinPlan& bp, const int32_t* idx, const void* vals, Dt dt, int64_t nnz,
+                                    const CooDims& cd, int mode, int ell, int64_t col0, uint64_t seed, double* Y,
+                                    int32_t* hist, int64_t* off, int64_t* bstart, int64_t* pstart, int64_t* keys,
+                                    double* rv, hipStream_t stream) {
+    if (!bp.ok || ell < 1 || ell > LMAX) return hipErrorInvalidValue;
+    const unsigned nch = (unsigned)bp.nch;
+    hipLaunchKernelGGL(coo_bin_count_kernel, dim3(nch), dim3(256), 0, stream, idx, nnz, cd, mode, bp.shift, bp.nbk,
+                       hist);
+    hipLaunchKernelGGL(coo_bin_scan_kernel, dim3(1), dim3(256), 0, stream, (const int32_t*)hist, bp.nch, bp.nbk,
+                       bstart, pstart, off);
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(coo_bin_scatter_kernel<double>, dim3(nch), dim3(256), 0, stream, idx, (const double*)vals,
+                           nnz, cd, mode, bp.shift, bp.nbk, (const int64_t*)off, keys, rv);
+    else
+        hipLaunchKernelGGL(coo_bin_scatter_kernel<float>, dim3(nch), dim3(256), 0, stream, idx, (const float*)vals,
+                           nnz, cd, mode, bp.shift, bp.nbk, (const int64_t*)off, keys, rv);
+    // pieces: at most nnz / BN_PS + nbk
+    int64_t maxp = nnz / BN_PS + bp.nbk;
+    const unsigned g = (unsigned)(maxp < 2048 ? maxp : 2048);
+    if (dt == Dt::F64)
+        hipLaunchKernelGGL(coo_bin_sketch_kernel<double>, dim3(g), dim3(256), 0, stream, (const int64_t*)keys,
+                           (const double*)rv, (const int64_t*)bstart, (const int64_t*)pstart, bp.nbk, bp.shift,
+                           cd.dims[mode], ell, col0, seed, (uint32_t)mode, Y);
+    else
+        hipLaunchKernelGGL(coo_bin_sketch_kernel<float>, dim3(g), dim3(256), 0, stream, (const int64_t*)keys,
+                           (const double*)rv, (const int64_t*)bstart, (const int64_t*)pstart, bp.nbk, bp.shift,
+                           cd.dims[mode], ell, col0, seed, (uint32_t)mode, Y);
     return hipGetLastError();
 }
 

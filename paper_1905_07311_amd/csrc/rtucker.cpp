@@ -255,6 +255,32 @@ rt_tensor coo_header(const rt_coo* X) {
     return t;
 }
 
+// Sketch of a COO core whose entry count the host knows (the input): large
+// inputs take the row-binned kernels (LDS accumulation, one add per block row
+// into Y), the others the direct scatter.
+rt_status coo_sketch_input(Call& k, const int32_t* idx, const void* vals, Dt dt, int64_t nnz,
+                           const rt::CooDims& cd, int mode, int ell, int64_t col0, uint64_t seed, double* Y) {
+    hipStream_t st = k.c->stream;
+    int64_t K = 1;
+    for (int m = 0; m < cd.d; ++m)
+        if (m != mode) K *= cd.dims[m];
+    const rt::BinPlan bp = rt::plan_coo_bins(cd.dims[mode], ell, nnz);
+    if (nnz >= (int64_t(1) << 18) && bp.ok && K < (int64_t(1) << (62 - bp.shift))) {
+        int32_t* hist = k.ws<int32_t>((size_t)bp.nch * bp.nbk);
+        int64_t* off = k.ws<int64_t>((size_t)bp.nch * bp.nbk);
+        int64_t* bstart = k.ws<int64_t>((size_t)bp.nbk + 1);
+        int64_t* pstart = k.ws<int64_t>((size_t)bp.nbk + 1);
+        int64_t* keys = k.ws<int64_t>((size_t)nnz);
+        double* rv = k.ws<double>((size_t)nnz);
+        if (!hist || !off || !bstart || !pstart || !keys || !rv) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_HIP(rt::launch_coo_sketch_binned(bp, idx, vals, dt, nnz, cd, mode, ell, col0, seed, Y, hist, off, bstart,
+                                            pstart, keys, rv, st));
+        return RT_OK;
+    }
+    RT_HIP(rt::launch_coo_sketch(idx, nnz, vals, dt, nullptr, nnz, cd, mode, ell, col0, seed, Y, st));
+    return RT_OK;
+}
+
 rt::CooDims coo_dims(const std::vector<int64_t>& dims) {
     rt::CooDims cd{};
     cd.d = (int32_t)dims.size();
@@ -907,8 +933,11 @@ rt_status rt_sp_sthosvd_coo(rt_ctx* ctx, const rt_coo* X, const int32_t* ranks, 
         {
             TimeScope ts(k.c, 0, (double)bound * (d * 4.0 + es), 2.0 * ell * bound, J, bound, ell);
             ts.t.variant = RT_SKETCH_COO;
-            RT_HIP(rt::launch_coo_sketch(cur_idx, cur_ld, cur_val, dt, cur_nnz, bound, coo_dims(dims), n, ell, 0,
-                                         opts->seed, Y, st));
+            if (cur_nnz)
+                RT_HIP(rt::launch_coo_sketch(cur_idx, cur_ld, cur_val, dt, cur_nnz, bound, coo_dims(dims), n, ell, 0,
+                                             opts->seed, Y, st));
+            else
+                RT_TRY(coo_sketch_input(k, cur_idx, cur_val, dt, bound, coo_dims(dims), n, ell, 0, opts->seed, Y));
         }
         {
             TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
@@ -1354,8 +1383,7 @@ rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell,
         TimeScope ts(k.c, 0, (double)X->nnz * (X->ndim * 4.0 + dsize(X->dtype)), 2.0 * ell * X->nnz, dims[mode],
                      X->nnz, ell);
         ts.t.variant = RT_SKETCH_COO;
-        RT_HIP(rt::launch_coo_sketch(X->idx, X->nnz, X->vals, dt, nullptr, X->nnz, coo_dims(dims), mode, ell, col0,
-                                     seed, Y, st));
+        RT_TRY(coo_sketch_input(k, X->idx, X->vals, dt, X->nnz, coo_dims(dims), mode, ell, col0, seed, Y));
     }
     if (nrm2) {
         if (X->nnz > 0) RT_TRY(do_norm2(k, X->vals, dt, X->nnz, nrm2));

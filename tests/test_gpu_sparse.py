@@ -172,3 +172,30 @@ def test_sp_sthosvd_coo_tall_modes(ctx, dtype):
     o = oracle.sp_sthosvd_coo(ih, vh, dims, [30, 30, 30], 5, seed=3, order=[2, 0, 1])
     _check_against_oracle(g, o, X, 1e-10 if dtype == torch.float64 else 1e-4)
     print(f"condensed-count stand-in {dtype}: error {np.linalg.norm(o.reconstruct() - X) / np.linalg.norm(X):.4f}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_binned_sketch_large_inputs(ctx, dtype):
+    # inputs of at least 2^18 entries take the row-binned sketch (entries grouped
+    # by blocks of rows, LDS accumulation); J above 2048 makes the blocks wider
+    # than one row
+    rng = np.random.default_rng(17)
+    cases = [inputs.sparse_outer_sum(n=400, gamma=10.0, density=0.05, terms=200)]
+    idx2, v2 = inputs.random_sparse(rng, (3000, 60, 50), 0.04)
+    cases.append((idx2, v2, (3000, 60, 50)))
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    for idx, vals, dims in cases:
+        assert idx.shape[1] >= 1 << 18
+        i, v = _dev(idx, vals, dtype)
+        vo = _vals_as(vals, dtype)
+        for mode, ell, col0 in ((0, 15, 0), (1, 9, 4), (2, 16, 0)):
+            Y = ctx.sketch_coo(i, v, dims, mode, ell, seed=31, col0=col0)
+            Yo = oracle.sketch_coo(idx, vo, dims, mode, ell, 31, col0)
+            assert np.max(np.abs(to_np(Y) - Yo)) <= tol * np.max(np.abs(Yo)), (dims, mode)
+    # the whole decomposition on the larger eq. sparse tensor (binned first sketch)
+    idx, vals, dims = cases[0]
+    X = oracle.densify(idx, _vals_as(vals, dtype), dims)
+    i, v = _dev(idx, vals, dtype)
+    g = ctx.sp_sthosvd_coo(i, v, dims, [10, 10, 10], 5, seed=8, order=[0, 1, 2])
+    o = oracle.sp_sthosvd_coo(idx, _vals_as(vals, dtype), dims, [10, 10, 10], 5, seed=8, order=[0, 1, 2])
+    _check_against_oracle(g, o, X, 1e-10 if dtype == torch.float64 else 1e-4)
