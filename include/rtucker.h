@@ -397,7 +397,7 @@ rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell,
 
 /* ---- serving: continuous batching of many requests --------------------------- */
 /* A server runs adaptive R-STHOSVD (Alg. 5, §4) on a stream of float32 tensors of
- * uneven shapes.  Requests wait in arrival order and are admitted as soon as a
+ * uneven shapes, and decompressions (rt_server_submit_reconstruct) beside them.  Requests wait in arrival order and are admitted as soon as a
  * slot is free and their device memory fits in `hbm_budget`.
  *
  * RT_SERVE_GROUPED (default): one executor drives every admitted request through
@@ -453,6 +453,24 @@ rt_status rt_server_create(rt_server** srv, int device, const rt_server_opts* op
  * stay valid and unchanged until the request completes; page-locked memory lets
  * the copy to the device overlap other work.  *ticket identifies the request. */
 rt_status rt_server_submit(rt_server* srv, const rt_tensor* X, uint64_t seed, uint64_t* ticket);
+
+/* A Tucker decomposition in host memory, float32 (a served result, or any). */
+typedef struct {
+    int32_t ndim;
+    int64_t dims[RT_MAXD];
+    int32_t ranks[RT_MAXD];
+    const float* core;              /* host, row-major ranks[0] x ... x ranks[ndim-1] */
+    const float* factors[RT_MAXD];  /* host, row-major dims[j] x ranks[j]; NULL: the
+                                       mode is kept (ranks[j] == dims[j]) or ranks[j] == 0 */
+} rt_tucker_host;
+
+/* Queue a decompression: X_hat = G x_1 A_1 ... x_d A_d (rt_reconstruct) written to
+ * `out` (host, prod(dims) float32, row-major).  t's arrays and `out` stay owned
+ * by the caller and must stay valid until the request completes.  The request
+ * takes a slot like a compression; its rt_result carries status, dims, ranks
+ * and the times (core and factors NULL).  In the grouped mode it runs on the
+ * executor between iterations. */
+rt_status rt_server_submit_reconstruct(rt_server* srv, const rt_tucker_host* t, float* out, uint64_t* ticket);
 
 /* *done = 1 and *out filled when the request has completed, else *done = 0. */
 rt_status rt_server_poll(rt_server* srv, uint64_t ticket, int32_t* done, rt_result* out);

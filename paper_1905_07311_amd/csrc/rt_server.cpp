@@ -90,6 +90,9 @@ void cache_free(void* p, void* user) { static_cast<BlockCache*>(user)->put(p); }
 
 struct Request {
     uint64_t id = 0;
+    bool decompress = false;         // rt_server_submit_reconstruct
+    rt_tucker_host T{};              // its input
+    float* out = nullptr;            // and output (host)
     rt_tensor X{};
     uint64_t seed = 0;
     size_t footprint = 0;
@@ -130,6 +133,7 @@ struct rt_server {
     void slot_main(int slot);
     void run(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache, float*& dX, size_t& dX_cap,
              float*& stage, size_t& stage_cap);
+    void run_decompress(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache);
     void complete(Request* r);
     void exec_main();
 };
@@ -143,7 +147,7 @@ void rt_server::complete(Request* r) {
         r->t_done = Clock::now();
         r->res.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
         r->res.latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-        r->res.core = r->core.data();
+        r->res.core = r->core.empty() ? nullptr : r->core.data();
         for (int i = 0; i < RT_MAXD; ++i)
             r->res.factors[i] = (i < (int)r->factors.size() && !r->factors[i].empty()) ? r->factors[i].data() : nullptr;
         r->done = true;
@@ -153,8 +157,72 @@ void rt_server::complete(Request* r) {
     cv_work.notify_all();
 }
 
+// A decompression on the context's stream: the core and factors up, rt_reconstruct,
+// X_hat down into the caller's buffer (device buffers from the block cache).
+void rt_server::run_decompress(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache) {
+    const rt_tucker_host& T = r->T;
+    rt_result& res = r->res;
+    res.ndim = T.ndim;
+    int64_t ncore = 1, nout = 1;
+    for (int i = 0; i < T.ndim; ++i) {
+        res.dims[i] = T.dims[i];
+        res.ranks[i] = T.ranks[i];
+        ncore *= T.ranks[i];
+        nout *= T.dims[i];
+    }
+    std::vector<void*> bufs;
+    bool nomem = false;
+    auto get = [&](int64_t n) -> float* {
+        void* p = cache.get((size_t)std::max<int64_t>(n, 1) * sizeof(float));
+        if (p) bufs.push_back(p);
+        else nomem = true;
+        return static_cast<float*>(p);
+    };
+    rt_tucker d{};
+    d.ndim = T.ndim;
+    d.dtype = RT_F32;
+    bool ok = true;
+    float* dc = get(ncore);
+    float* dout = get(nout);
+    ok = dc && dout;
+    if (ok && ncore > 0) ok = hipMemcpyAsync(dc, T.core, (size_t)ncore * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+    d.core = dc;
+    for (int i = 0; i < T.ndim && ok; ++i) {
+        d.dims[i] = T.dims[i];
+        d.ranks[i] = T.ranks[i];
+        if (T.factors[i]) {
+            float* f = get(T.dims[i] * (int64_t)T.ranks[i]);
+            ok = f && hipMemcpyAsync(f, T.factors[i], (size_t)T.dims[i] * T.ranks[i] * 4, hipMemcpyHostToDevice,
+                                     st) == hipSuccess;
+            d.factors[i] = f;
+        }
+    }
+    if (!ok) {
+        res.status = nomem ? RT_ENOMEM : RT_EHIP;
+        r->err = "device buffers or copies for the decompression failed";
+    } else {
+        const rt_status s = rt_reconstruct(ctx, &d, dout);
+        if (s != RT_OK) {
+            res.status = s;
+            r->err = rt_last_error();
+        } else if (hipMemcpyAsync(r->out, dout, (size_t)nout * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess) {
+            res.status = RT_EHIP;
+            r->err = "device to host copy failed";
+        } else {
+            res.status = RT_OK;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    for (void* p : bufs) cache.put(p);
+}
+
 void rt_server::run(Request* r, rt_ctx* ctx, hipStream_t st, BlockCache& cache, float*& dX, size_t& dX_cap,
                     float*& stage, size_t& stage_cap) {
+    if (r->decompress) {
+        run_decompress(r, ctx, st, cache);
+        return;
+    }
     const int64_t n = numel(r->X);
     rt_result& res = r->res;
     res.ndim = r->X.ndim;
@@ -689,7 +757,7 @@ void rt_server::exec_main() {
                 if (queue.empty() || free_slots.empty()) break;
                 Request* h = queue.front();
                 size_t bytes = 0, scratch = 0, big = 0;
-                alone = !group_footprint(h->X, block, bytes, scratch, big);
+                alone = h->decompress || !group_footprint(h->X, block, bytes, scratch, big);
                 const bool busy = !active.empty() || !pending.empty();
                 if (!alone && busy && in_use + bytes > budget) break;
                 queue.pop_front();
@@ -961,6 +1029,42 @@ rt_status rt_server_submit(rt_server* srv, const rt_tensor* X, uint64_t seed, ui
     r->seed = seed;
     // input + sketch/projection buffers of the first mode + workspace slack
     r->footprint = (size_t)numel(*X) * sizeof(float) * 3 + (size_t(8) << 20);
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stopping) {
+            delete r;
+            return rt::set_error(RT_EINVAL, "server is stopping");
+        }
+        r->id = srv->next_id++;
+        srv->reqs[r->id] = r;
+        srv->queue.push_back(r);
+        *ticket = r->id;
+    }
+    srv->cv_work.notify_one();
+    return RT_OK;
+}
+
+rt_status rt_server_submit_reconstruct(rt_server* srv, const rt_tucker_host* t, float* out, uint64_t* ticket) {
+    if (!srv || !t || !out || !ticket) return rt::set_error(RT_EINVAL, "NULL argument");
+    if (t->ndim < 2 || t->ndim > RT_MAXD) return rt::set_error(RT_EINVAL, "ndim must be in [2, RT_MAXD]");
+    int64_t ncore = 1, nout = 1, nfac = 0;
+    for (int i = 0; i < t->ndim; ++i) {
+        if (t->dims[i] < 1) return rt::set_error(RT_EINVAL, "every dim must be >= 1");
+        if (t->ranks[i] < 0 || t->ranks[i] > t->dims[i]) return rt::set_error(RT_EINVAL, "ranks must be in [0, dims]");
+        if (!t->factors[i] && t->ranks[i] != t->dims[i] && t->ranks[i] != 0)
+            return rt::set_error(RT_EINVAL, "a mode without a factor must keep its dimension");
+        ncore *= t->ranks[i];
+        nout *= t->dims[i];
+        if (t->factors[i]) nfac += t->dims[i] * (int64_t)t->ranks[i];
+    }
+    if (ncore > 0 && !t->core) return rt::set_error(RT_EINVAL, "NULL core");
+    Request* r = new Request();
+    r->decompress = true;
+    r->T = *t;
+    r->out = out;
+    // output, its largest intermediate (at most the output), core and factors
+    r->footprint = (size_t)(2 * nout + ncore + nfac) * sizeof(float) + (size_t(8) << 20);
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(srv->mu);

@@ -27,7 +27,7 @@ RT_FLAG_FALLBACK = 2
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
             "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_sp_sthosvd_coo", "rt_sketch_coo", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
-            "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_wait", "rt_server_release",
+            "rt_server_create", "rt_server_submit", "rt_server_submit_reconstruct", "rt_server_poll", "rt_server_wait", "rt_server_release",
             "rt_server_get_stats", "rt_server_destroy", "rt_tuning_set", "rt_tuning_plan"]
 
 
@@ -69,6 +69,11 @@ class rt_result(ctypes.Structure):
                 ("factors", ctypes.POINTER(ctypes.c_float) * RT_MAXD), ("norm_x", ctypes.c_double),
                 ("core_norm", ctypes.c_double), ("rel_err_est", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+class rt_tucker_host(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * RT_MAXD), ("ranks", ctypes.c_int32 * RT_MAXD),
+                ("core", ctypes.c_void_p), ("factors", ctypes.c_void_p * RT_MAXD)]
 
 
 class rt_coo(ctypes.Structure):
@@ -156,6 +161,7 @@ def load(path=None):
                                     ctypes.POINTER(ctypes.c_int32)]
     lib.rt_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(rt_server_opts)]
     lib.rt_server_submit.argtypes = [P, ctypes.POINTER(rt_tensor), ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rt_server_submit_reconstruct.argtypes = [P, ctypes.POINTER(rt_tucker_host), P, ctypes.POINTER(ctypes.c_uint64)]
     lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_result)]
     lib.rt_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(rt_result)]
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
@@ -608,6 +614,7 @@ class ServedResult:
     flags: int
     queue_s: float
     latency_s: float
+    output: "object" = None     # a decompression's float32 CPU tensor
 
 
 class Server:
@@ -648,11 +655,51 @@ class Server:
         self._keep[ticket.value] = X
         return ticket.value
 
+    def submit_reconstruct(self, core, factors, dims=None, out=None):
+        """Queue a decompression X_hat = core x_1 A_1 ... x_d A_d on the server.
+        core and the factors (A_j of shape dims[j] x ranks[j], None for a kept
+        mode) are contiguous float32 CPU tensors; out, if given, a contiguous
+        float32 CPU tensor of shape dims.  The result's `output` is X_hat."""
+        import torch
+        d = core.dim()
+        if len(factors) != d:
+            raise ValueError("one factor (or None) per mode")
+        for a in [core, out] + list(factors):
+            if a is not None and (a.device.type != "cpu" or a.dtype != torch.float32 or not a.is_contiguous()):
+                raise ValueError("core, factors and out must be contiguous float32 CPU tensors")
+        if dims is None:
+            dims = [int(a.shape[0]) if a is not None else int(core.shape[i]) for i, a in enumerate(factors)]
+        if out is None:
+            out = torch.empty(list(dims), dtype=torch.float32).pin_memory() if torch.cuda.is_available() else \
+                torch.empty(list(dims), dtype=torch.float32)
+        elif list(out.shape) != list(dims):
+            raise ValueError("out must have shape dims")
+        t = rt_tucker_host()
+        t.ndim = d
+        for i in range(d):
+            t.dims[i] = int(dims[i])
+            t.ranks[i] = int(core.shape[i])
+            t.factors[i] = factors[i].data_ptr() if factors[i] is not None else None
+        t.core = core.data_ptr()
+        ticket = ctypes.c_uint64(0)
+        _check(_lib.rt_server_submit_reconstruct(self.srv, ctypes.byref(t), ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.byref(ticket)))
+        self._keep[ticket.value] = (core, list(factors), out)
+        return ticket.value
+
     def _take(self, ticket, r):
         import numpy as np
         ranks = [int(r.ranks[i]) for i in range(r.ndim)]
         dims = [int(r.dims[i]) for i in range(r.ndim)]
         core = factors = None
+        kept = self._keep.get(ticket)
+        if isinstance(kept, tuple):
+            # a decompression: the output tensor is the result
+            out = ServedResult(int(r.status), ranks, None, None, r.norm_x, r.core_norm, r.rel_err_est,
+                               int(r.flags), r.queue_s, r.latency_s, kept[2])
+            _check(_lib.rt_server_release(self.srv, ctypes.c_uint64(ticket)))
+            self._keep.pop(ticket, None)
+            return out
         if r.status in (RT_OK, RT_ECAP):
             ncore = int(np.prod(ranks))
             core = (np.ctypeslib.as_array(r.core, shape=(ncore,)).copy().reshape(ranks) if ncore > 0 and r.core

@@ -57,6 +57,8 @@ def test_argument_errors_are_synchronous():
     assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
     assert lib.rt_server_submit(None, None, 0, None) == rtucker.RT_EINVAL
     assert lib.rt_server_get_stats(None, None) == rtucker.RT_EINVAL
+    th = rtucker.rt_tucker_host()
+    assert lib.rt_server_submit_reconstruct(None, ctypes.byref(th), None, None) == rtucker.RT_EINVAL
     # sparse inputs
     c = rtucker.rt_coo()
     assert lib.rt_sp_sthosvd_coo(None, ctypes.byref(c), None, ctypes.byref(opts), ctypes.byref(out)) == \
@@ -90,6 +92,8 @@ int main(void) {
          offsetof(rt_coo, idx), offsetof(rt_coo, vals));
   printf("%zu %zu %zu\\n", sizeof(rt_server_stats), offsetof(rt_server_stats, wait_s),
          offsetof(rt_server_stats, overlap_s));
+  printf("%zu %zu %zu %zu\\n", sizeof(rt_tucker_host), offsetof(rt_tucker_host, ranks),
+         offsetof(rt_tucker_host, core), offsetof(rt_tucker_host, factors));
   return 0;
 }
 """)
@@ -111,3 +115,6 @@ int main(void) {
     assert [int(v) for v in lines[5].split()] == [ctypes.sizeof(C), C.nnz.offset, C.dtype.offset, C.idx.offset,
                                                  C.vals.offset]
     assert [int(v) for v in lines[6].split()] == [ctypes.sizeof(ST), ST.wait_s.offset, ST.overlap_s.offset]
+    H = rtucker.rt_tucker_host
+    assert [int(v) for v in lines[7].split()] == [ctypes.sizeof(H), H.ranks.offset, H.core.offset,
+                                                 H.factors.offset]

@@ -13,6 +13,8 @@ requests (Alg. 5, §4) of uneven shapes and ranks.
   level of tau^2); bfloat16 sketch - the same ranks, X_hat within 1e-4 ||X||,
   direct error <= eps.
 """
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 import torch
@@ -182,3 +184,53 @@ def test_grouped_edge_shapes_against_oracle():
             assert r.ranks == o.ranks
             d = tucker_dist(r.core, r.factors, o.core, o.factors) / np.sqrt(nx2)
             assert d <= 1e-5, d
+
+
+@pytest.mark.parametrize("mode", ["grouped", "slots"])
+def test_served_decompression(reqs, mode):
+    # decompressions (rt_server_submit_reconstruct) served between compressions:
+    # X_hat of every served result against the oracle's mode products (float32
+    # expansion, sums of length r: 2e-6 relative) and bit-equal to the direct
+    # rt_reconstruct of the same factors; a kept mode, rank 0 and a bad argument
+    srv = rtucker.Server(max_inflight=4, eps=1e-3, block=8, mode=mode)
+    ctx = rtucker.Context(0)
+    try:
+        first = [srv.wait(srv.submit(X, s)) for X, s in reqs[:6]]
+        tickets = []
+        for (X, s), r in zip(reqs[6:], first):
+            core = torch.from_numpy(r.core)
+            facs = [torch.from_numpy(A) for A in r.factors]
+            tickets.append(("d", srv.submit_reconstruct(core, facs), r))
+            tickets.append(("c", srv.submit(X, s), X))
+        for kind, t, src in tickets:
+            res = srv.wait(t)
+            assert res.status == rtucker.RT_OK
+            if kind == "c":
+                assert _rel_err(res, src) <= 1e-3
+                continue
+            out = res.output.numpy()
+            ref = oracle.reconstruct(src.core.astype(np.float64), [A.astype(np.float64) for A in src.factors])
+            assert out.shape == ref.shape
+            assert np.linalg.norm(out - ref) <= 2e-6 * np.linalg.norm(ref)
+            direct = ctx.reconstruct(SimpleNamespace(core=torch.from_numpy(src.core).cuda(),
+                                                     factors=[torch.from_numpy(A).cuda() for A in src.factors]))
+            assert np.array_equal(out, direct.cpu().numpy())
+        # a mode kept whole (no factor) and a rank-0 core
+        rng = np.random.default_rng(5)
+        core = torch.from_numpy(rng.standard_normal((4, 9, 3)).astype(np.float32))
+        facs = [torch.from_numpy(rng.standard_normal((30, 4)).astype(np.float32)), None,
+                torch.from_numpy(rng.standard_normal((17, 3)).astype(np.float32))]
+        res = srv.wait(srv.submit_reconstruct(core, facs))
+        ref = oracle.reconstruct(core.numpy().astype(np.float64),
+                                 [None if A is None else A.numpy().astype(np.float64) for A in facs])
+        assert res.output.shape == (30, 9, 17)
+        assert np.linalg.norm(res.output.numpy() - ref) <= 2e-6 * np.linalg.norm(ref)
+        z = srv.wait(srv.submit_reconstruct(torch.zeros((0, 5, 2)), [torch.zeros((11, 0)), None,
+                                                                    torch.ones((6, 2))]))
+        assert z.status == rtucker.RT_OK and z.output.shape == (11, 5, 6)
+        assert float(z.output.abs().max()) == 0.0
+        with pytest.raises(rtucker.RtError):
+            srv.submit_reconstruct(torch.ones((4, 3)), [torch.ones((3, 4)), torch.ones((5, 3))])
+    finally:
+        ctx.close()
+        srv.close()
