@@ -84,6 +84,7 @@ typedef enum { RT_PREC_F64 = 0, RT_PREC_F32 = 1, RT_PREC_BF16_SKETCH = 2 } rt_pr
 #define RT_MAXD 8
 #define RT_KEEP (-1) /* rank value: leave this mode uncompressed (factor = identity) */
 #define RT_LMAX 64   /* largest sketch width r + p (and adaptive rank) per mode */
+#define RT_LMAX_FIXED 128  /* largest r + p of the fixed-rank rt_rhosvd / rt_rsthosvd */
 
 /* flags of rt_tucker */
 #define RT_FLAG_PADDED 1u    /* some sketch was numerically rank deficient; its basis
@@ -166,9 +167,11 @@ rt_status rt_set_stream(rt_ctx* ctx, void* stream);
 rt_status rt_destroy(rt_ctx* ctx);
 
 /* R-HOSVD (Alg. 2, §3.1).  ranks (host, ndim entries): r_j >= 1 or RT_KEEP, with
- * r_j + p <= min(I_j, prod_{i != j} I_i) and r_j + p <= RT_LMAX.  On success
- * `out` holds a core and factors allocated with the context's allocator; release
- * them with rt_tucker_release. */
+ * r_j + p <= min(I_j, prod_{i != j} I_i) and r_j + p <= RT_LMAX_FIXED.  Modes
+ * with r_j + p > RT_LMAX take a slower path (sketch in column blocks, Householder
+ * orth, one-sided Jacobi truncation, all in fp64 by single workgroups) and need
+ * opts->power_iters == 0.  On success `out` holds a core and factors allocated
+ * with the context's allocator; release them with rt_tucker_release. */
 rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const rt_opts* opts, rt_tucker* out);
 
 /* R-STHOSVD (Alg. 3, §3.1): modes in the order opts->order; the core shrinks

@@ -258,6 +258,19 @@ bool expand_ok(Shape3 s, int64_t I);
 hipError_t launch_expand(Dt dt, const void* G, Shape3 s, const void* A, int64_t I, void* out, hipStream_t stream);
 // AT (cols x rows) = A^T for a row-major rows x cols matrix A, in dtype dt
 hipError_t launch_transpose(const void* A, int64_t rows, int64_t cols, void* AT, Dt dt, hipStream_t stream);
+
+// Fixed-rank steps for RT_LMAX < ell <= RT_LMAX_FIXED (rt_wide.hip).
+hipError_t launch_wide_copy_cols(const double* src, int64_t J, int w, double* dst, int ldd, int off,
+                                 hipStream_t stream);
+size_t wide_orth_scratch(int64_t J, int n);
+hipError_t launch_wide_orth(double* Y, int64_t J, int n, float* Qf, double accept_ratio, uint32_t* status,
+                            double* scratch, hipStream_t stream);
+int plan_wide_gram(int64_t K);
+hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t R, double* part, int nwg,
+                            hipStream_t stream);
+hipError_t launch_wide_eig(const double* W, int n, double tol, double* U, double* lam, hipStream_t stream);
+hipError_t launch_wide_factor(const double* Q, int64_t J, int n, const double* U, int r, double* A64, double* sgn,
+                              void* Aout, Dt da, double* Us, float* Usf, hipStream_t stream);
 // dst (dtype) <- src (double), n elements
 hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream);
 // explicit Omega (testing): out[i][j] = Omega[c0 + i, col0 + j], fp32 or fp64 transform

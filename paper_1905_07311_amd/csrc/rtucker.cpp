@@ -217,7 +217,7 @@ rt_status make_order(const rt_tensor* X, const int32_t* order, std::vector<int>&
     return RT_OK;
 }
 
-rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
+rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p, int cap = RT_LMAX) {
     if (!ranks) return fail(RT_EINVAL, "ranks is NULL");
     if (p < 0) return fail(RT_EINVAL, "oversampling p must be >= 0");
     int64_t total = 1;
@@ -228,8 +228,19 @@ rt_status check_ranks(const rt_tensor* X, const int32_t* ranks, int p) {
         const int64_t ell = (int64_t)ranks[j] + p;
         if (ell > std::min<int64_t>(X->dims[j], total / X->dims[j]))
             return fail(RT_EINVAL, "r_j + p exceeds min(I_j, prod_{i!=j} I_i) for mode " + std::to_string(j));
-        if (ell > RT_LMAX) return fail(RT_EINVAL, "r_j + p exceeds RT_LMAX for mode " + std::to_string(j));
+        if (ell > cap)
+            return fail(RT_EINVAL, std::string("r_j + p exceeds ") + (cap == RT_LMAX ? "RT_LMAX" : "RT_LMAX_FIXED") +
+                                       " for mode " + std::to_string(j));
     }
+    return RT_OK;
+}
+
+// the wide path (r_j + p > RT_LMAX) has no subspace iteration
+rt_status check_wide_power(const rt_tensor* X, const int32_t* ranks, const rt_opts* opts) {
+    if (opts->power_iters == 0) return RT_OK;
+    for (int j = 0; j < X->ndim; ++j)
+        if (ranks[j] != RT_KEEP && ranks[j] + opts->oversample > RT_LMAX)
+            return fail(RT_EINVAL, "power_iters > 0 needs r_j + p <= RT_LMAX");
     return RT_OK;
 }
 
@@ -535,6 +546,78 @@ rt_status fixed_mode(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode
                        core_out ? &core : nullptr, nullptr);                                      // steps 4-6
 }
 
+// B = G x_n Q^T for ncols columns of Q (J x ldq) of any count, in column blocks
+// of at most RT_LMAX written at their offset in B (L, ldk, R).
+rt_status project_cols(Call& k, Dt dx, Dt dq, const void* G, Shape3 s, int64_t ldj, const void* Q, int64_t ldq,
+                       int ncols, void* B, int64_t ldk) {
+    const size_t esq = dq == Dt::F64 ? 8 : 4;
+    for (int c0 = 0; c0 < ncols; c0 += RT_LMAX) {
+        const int w = std::min(RT_LMAX, ncols - c0);
+        RT_TRY(do_project(k, dx, dq, G, s, ldj, (const char*)Q + (size_t)c0 * esq, ldq, w, B, ldk, c0, nullptr,
+                          nullptr));
+    }
+    return RT_OK;
+}
+
+// One fixed-rank RandSVD step (Alg. 1) for RT_LMAX < ell <= RT_LMAX_FIXED: the
+// sketch in column blocks of at most RT_LMAX (the same Omega columns as one wide
+// sketch) gathered into Y (J x ell, fp64), Q by CholeskyQR2 with a Householder
+// fallback, B = G x_n Q^T in
+// column blocks, the fp64 Gram of B, its eigenvectors by one-sided Jacobi, A_n
+// = Q U_r with the sign rule, and the core U_r^T B.
+rt_status fixed_mode_wide(Call& k, Dt dt, int prec, const void* G, Shape3 s, int mode, int ell, int r,
+                          uint64_t seed, void* A_out, void* core_out, double* nrm2_dev, uint32_t* status_dev) {
+    hipStream_t st = k.c->stream;
+    const int64_t J = s.J;
+    const size_t es = dt == Dt::F64 ? 8 : 4;
+    double* Y = k.ws<double>((size_t)J * ell);
+    double* Yb = k.ws<double>((size_t)J * RT_LMAX);
+    double* V = k.ws<double>(rt::wide_orth_scratch(J, ell));
+    float* Qf = dt == Dt::F32 ? k.ws<float>((size_t)J * ell) : nullptr;
+    if (!Y || !Yb || !V || (dt == Dt::F32 && !Qf)) return fail(RT_ENOMEM, "workspace allocation failed");
+    for (int c0 = 0; c0 < ell; c0 += RT_LMAX) {                                             // step 1
+        const int w = std::min(RT_LMAX, ell - c0);
+        RT_TRY(do_sketch(k, dt, prec, G, s, w, c0, seed, mode, Yb, c0 == 0 ? nrm2_dev : nullptr));
+        RT_HIP(rt::launch_wide_copy_cols(Yb, J, w, Y, ell, c0, st));
+    }
+    {
+        TimeScope ts(k.c, 2, 0.0, 0.0, J, ell, ell);
+        RT_HIP(rt::launch_wide_orth(Y, J, ell, Qf, orth_accept_ratio(), status_dev, V, st));  // step 2
+    }
+    void* B = k.c->ws((size_t)s.L * ell * s.R * es);
+    if (!B) return fail(RT_ENOMEM, "workspace allocation failed");
+    const void* Qp = dt == Dt::F64 ? (const void*)Y : (const void*)Qf;
+    RT_TRY(project_cols(k, dt, dt, G, s, s.J, Qp, ell, ell, B, ell));                        // step 3
+    const int nwg = rt::plan_wide_gram(s.L * s.R);
+    double* gp = k.ws<double>((size_t)nwg * ell * ell);
+    double* Wm = k.ws<double>((size_t)ell * ell);
+    double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)ell * ell) + 1);
+    double* U = k.ws<double>((size_t)ell * ell);
+    double* lam = k.ws<double>(ell);
+    double* A64 = k.ws<double>((size_t)J * r);
+    double* sgn = k.ws<double>(r);
+    double* Us = k.ws<double>((size_t)ell * r);
+    float* Usf = k.ws<float>((size_t)ell * r);
+    if (!gp || !Wm || !rtmp || !U || !lam || !A64 || !sgn || !Us || !Usf)
+        return fail(RT_ENOMEM, "workspace allocation failed");
+    {
+        TimeScope ts(k.c, 4, (double)s.L * ell * s.R * es, 2.0 * ell * ell * (double)s.L * s.R, ell, s.L * s.R, ell);
+        RT_HIP(rt::launch_wide_gram(B, dt, s.L, ell, s.R, gp, nwg, st));
+        RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)ell * ell, Wm, st, rtmp));
+    }
+    {
+        // rotations stop at columns orthogonal to ell u (fp64 data) or 1e-9 (the
+        // Gram of float data is fixed only to ~2^-24 of its norm)
+        TimeScope ts(k.c, 3, 0.0, 0.0, J, ell, ell);
+        RT_HIP(rt::launch_wide_eig(Wm, ell, dt == Dt::F64 ? ell * 0x1p-52 : 1e-9, U, lam, st));   // steps 4-5
+        RT_HIP(rt::launch_wide_factor(Y, J, ell, U, r, A64, sgn, A_out, dt, Us, Usf, st));
+    }
+    if (core_out)                                                                             // step 6
+        RT_TRY(project_cols(k, dt, dt == Dt::F64 ? Dt::F64 : Dt::F32, B, Shape3{s.L, ell, s.R}, ell,
+                            dt == Dt::F64 ? (const void*)Us : (const void*)Usf, r, r, core_out, r));
+    return RT_OK;
+}
+
 void init_out(rt_tucker* out, const rt_tensor* X) {
     std::memset(out, 0, sizeof(*out));
     out->ndim = X->ndim;
@@ -761,7 +844,8 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
     RT_TRY(check_prec(X, opts->prec));
     if (opts->power_iters < 0 || opts->power_iters > RT_MAX_POWER_ITERS)
         return fail(RT_EINVAL, "power_iters must be in [0, RT_MAX_POWER_ITERS]");
-    RT_TRY(check_ranks(X, ranks, opts->oversample));
+    RT_TRY(check_ranks(X, ranks, opts->oversample, RT_LMAX_FIXED));
+    RT_TRY(check_wide_power(X, ranks, opts));
     std::vector<int> order;
     RT_TRY(make_order(X, opts->order, order));
     RT_HIP(hipSetDevice(ctx->device));
@@ -788,8 +872,11 @@ rt_status rt_rsthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, con
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "allocation failed");
         }
-        rt_status rs = fixed_mode(k, dt, prec, cur, s, n, ell, r, opts->seed, opts->power_iters, out->factors[n],
-                                  core, have_norm ? nullptr : nx2, status + n);
+        rt_status rs = ell > RT_LMAX
+                           ? fixed_mode_wide(k, dt, prec, cur, s, n, ell, r, opts->seed, out->factors[n], core,
+                                             have_norm ? nullptr : nx2, status + n)
+                           : fixed_mode(k, dt, prec, cur, s, n, ell, r, opts->seed, opts->power_iters,
+                                        out->factors[n], core, have_norm ? nullptr : nx2, status + n);
         if (rs != RT_OK) { release_partial(ctx, out); return rs; }
         have_norm = true;
         out->ranks[n] = r;
@@ -977,7 +1064,8 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
     RT_TRY(check_prec(X, opts->prec));
     if (opts->power_iters < 0 || opts->power_iters > RT_MAX_POWER_ITERS)
         return fail(RT_EINVAL, "power_iters must be in [0, RT_MAX_POWER_ITERS]");
-    RT_TRY(check_ranks(X, ranks, opts->oversample));
+    RT_TRY(check_ranks(X, ranks, opts->oversample, RT_LMAX_FIXED));
+    RT_TRY(check_wide_power(X, ranks, opts));
     RT_HIP(hipSetDevice(ctx->device));
     Call k(ctx);
     const Dt dt = dt_of(X->dtype);
@@ -1019,8 +1107,11 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
         if (!sj || !done) { release_partial(ctx, out); return fail(RT_EHIP, "stream creation failed"); }
         RT_HIP(hipStreamWaitEvent(sj, fork, 0));
         ctx->stream = sj;
-        rt_status rs = fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, opts->power_iters,
-                                  out->factors[j], core, first < 0 ? nx2 : nullptr, status + j);
+        rt_status rs = ell > RT_LMAX
+                           ? fixed_mode_wide(k, dt, prec, X->data, s, j, ell, r, opts->seed, out->factors[j], core,
+                                             first < 0 ? nx2 : nullptr, status + j)
+                           : fixed_mode(k, dt, prec, X->data, s, j, ell, r, opts->seed, opts->power_iters,
+                                        out->factors[j], core, first < 0 ? nx2 : nullptr, status + j);
         ctx->stream = main_st;
         RT_HIP(hipEventRecord(done, sj));
         RT_HIP(hipStreamWaitEvent(main_st, done, 0));
@@ -1045,7 +1136,7 @@ rt_status rt_rhosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, const
             const int r = ranks[j];
             void* nc = k.c->ws((size_t)s.L * r * s.R * es);
             if (!nc) { release_partial(ctx, out); return fail(RT_ENOMEM, "allocation failed"); }
-            rt_status rs = do_project(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r, 0, nullptr, nullptr);
+            rt_status rs = project_cols(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r);
             if (rs != RT_OK) { release_partial(ctx, out); return rs; }
             dims[j] = r;
             cur = nc;

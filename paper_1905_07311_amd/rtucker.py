@@ -21,6 +21,7 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2}
 RT_MAXD = 8
 RT_KEEP = -1
 RT_LMAX = 64
+RT_LMAX_FIXED = 128
 RT_FLAG_PADDED = 1
 RT_FLAG_FALLBACK = 2
 

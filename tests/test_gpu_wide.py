@@ -1,0 +1,92 @@
+"""GPU parity of the fixed-rank path for sketch widths above RT_LMAX
+(64 < r + p <= RT_LMAX_FIXED = 128: sketch in column blocks, Householder orth,
+Gram and one-sided Jacobi truncation by single workgroups) against the FP64
+oracle, through the C ABI.  Same bars as the narrow path: ||X_hat_gpu -
+X_hat_oracle|| / ||X|| below 1e-10 (FP64) or 1e-5 (FP32), orthonormal factors,
+||X|| and ||G||.  Cases: a low-rank-plus-noise tensor whose modes are all wide
+or mixed wide and narrow, the widest sketch (r + p = 128), and the 0-based
+Hilbert tensor, whose wide sketches are numerically rank deficient (padded)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1905_07311_amd import inputs, rtucker
+from gpu_common import need_gpu, rel, to_np, xhat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    return rtucker.Context(0)
+
+
+def _check(g, o, X, tol):
+    nx = np.linalg.norm(X)
+    assert g.ranks == o.ranks
+    assert np.linalg.norm(xhat(g) - o.reconstruct()) / nx < tol
+    for A in g.factors:
+        if A is not None:
+            A = to_np(A)
+            assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=max(tol, 1e-12) * 10)
+    assert abs(g.norm_x - np.sqrt(oracle.fro2(X))) <= 1e-12 * nx
+    assert abs(g.core_norm - np.sqrt(oracle.fro2(o.core))) <= tol * nx
+
+
+@pytest.mark.parametrize("alg", ["rsthosvd", "rhosvd"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wide_lowrank(ctx, alg, dtype):
+    # ranks (70, 60, 50), p = 10: sketch widths 80 and 70 (wide) and 60 (narrow)
+    rng = np.random.default_rng(61)
+    ranks = [70, 60, 50]
+    X = inputs.lowrank_tensor(rng, (150, 130, 90), ranks, noise=1e-4)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    g = getattr(ctx, alg)(torch.from_numpy(Xs).cuda(), ranks, 10, seed=3)
+    o = getattr(oracle, alg)(Xs.astype(np.float64), ranks, 10, seed=3)
+    _check(g, o, Xs.astype(np.float64), 1e-10 if dtype == torch.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_widest_sketch(ctx, dtype):
+    # r + p = RT_LMAX_FIXED in the first mode (two sketch blocks of 64), a
+    # ragged block width (r + p = 97) in the second, R = 1 in the last
+    rng = np.random.default_rng(62)
+    ranks = [118, 87, 20]
+    X = inputs.lowrank_tensor(rng, (200, 160, 40), ranks, noise=1e-4)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    g = ctx.rsthosvd(torch.from_numpy(Xs).cuda(), ranks, 10, seed=4, order=[0, 1, 2])
+    o = oracle.rsthosvd(Xs.astype(np.float64), ranks, 10, seed=4, order=[0, 1, 2])
+    _check(g, o, Xs.astype(np.float64), 1e-10 if dtype == torch.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wide_rank_deficient_hilbert(ctx, dtype):
+    # numerical rank ~26 (FP64) / ~13 (FP32) against sketches of 80 columns: the
+    # bases are padded with zero-weight directions and stay orthonormal
+    X = inputs.hilbert0((110, 100, 90))
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    g = ctx.rsthosvd(torch.from_numpy(Xs).cuda(), [70, 70, 70], 10, seed=5)
+    o = oracle.rsthosvd(Xf, [70, 70, 70], 10, seed=5)
+    nx = np.linalg.norm(Xf)
+    assert g.ranks == o.ranks == [70, 70, 70]
+    assert np.linalg.norm(xhat(g) - o.reconstruct()) / nx < (1e-10 if dtype == torch.float64 else 1e-5)
+    for A in g.factors:
+        A = to_np(A)
+        assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-10 if dtype == torch.float64 else 1e-5)
+    if dtype == torch.float64:
+        # (float32 rounding of the data leaves the sketches full rank at the
+        # flag's 1e-12 threshold)
+        assert g.flags & rtucker.RT_FLAG_PADDED
+
+
+def test_wide_argument_errors(ctx):
+    X = torch.zeros((140, 140, 20), dtype=torch.float32, device="cuda")
+    with pytest.raises(rtucker.RtError):                       # r + p above RT_LMAX_FIXED
+        ctx.rsthosvd(X, [120, 10, 10], 9, seed=0)
+    with pytest.raises(rtucker.RtError):                       # no subspace iteration on the wide path
+        ctx.rsthosvd(X, [70, 10, 10], 5, seed=0, power_iters=1)
+    g = ctx.rsthosvd(X, [119, 10, 10], 9, seed=0)              # r + p = 128 on a zero tensor
+    assert g.core_norm == 0.0 and g.ranks == [119, 10, 10]
