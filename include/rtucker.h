@@ -195,8 +195,10 @@ rt_status rt_sp_sthosvd(rt_ctx* ctx, const rt_tensor* X, const int32_t* ranks, c
  * sum of squares must equal eps^2 to 1e-12 relative; 0 leaves the mode
  * uncompressed), then truncated to the smallest rank whose error estimate
  * still meets eps_n ||X||_F.  max_rank (host, may be NULL) caps each mode
- * (default min(I_n, RT_LMAX)); RT_ECAP is returned (with a valid result) when
- * a cap stops a mode before its tolerance.  opts->oversample is ignored. */
+ * (default min(I_n, RT_LMAX_FIXED)); RT_ECAP is returned (with a valid result)
+ * when a cap stops a mode before its tolerance.  A basis that grows beyond
+ * RT_LMAX columns takes the wide kernels (block Gram-Schmidt in two parts, fp64
+ * Gram, one-sided Jacobi).  1 <= block <= RT_LMAX.  opts->oversample is ignored. */
 rt_status rt_rsthosvd_adaptive(rt_ctx* ctx, const rt_tensor* X, double eps, const double* eps_per_mode,
                                int32_t block, const int32_t* max_rank, const rt_opts* opts, rt_tucker* out);
 

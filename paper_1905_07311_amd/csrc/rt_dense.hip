@@ -501,13 +501,15 @@ __global__ __launch_bounds__(NT) void orth_kernel(double* __restrict__ Y, int64_
 __global__ __launch_bounds__(NT) void block_orth_kernel(double* __restrict__ Y, int64_t J, int b,
                                                         double* __restrict__ Qall, int ldq, int k, double drop,
                                                         double* __restrict__ V, int* __restrict__ knew,
-                                                        float* __restrict__ Qf) {
+                                                        float* __restrict__ Qf, const double* __restrict__ y0_ext) {
     __shared__ DenseShared S;
     const int tid = threadIdx.x;
-    // y0 = ||Y||_F before the projections
+    // y0 = ||Y||_F before the projections (or the caller's, when Y was already
+    // projected against earlier basis columns)
     double s = 0.0;
     for (int64_t e = tid; e < J * b; e += NT) s += Y[e] * Y[e];
-    const double y0 = sqrt(blk_sum(s, S.red));
+    const double ys = sqrt(blk_sum(s, S.red));
+    const double y0 = y0_ext ? y0_ext[0] : ys;
     // two passes of block Gram-Schmidt: C = Q^T Y (k x b), Y -= Q C
     for (int pass = 0; pass < 2 && k > 0; ++pass) {
         for (int e = tid; e < k * b; e += NT) {
@@ -784,7 +786,7 @@ template <int G, int RW>
 __device__ __forceinline__ void block_orth_small_body(const double* __restrict__ Yin, int64_t J, int b,
                                                       double* __restrict__ Qall, int ldq, int k, double drop,
                                                       int* __restrict__ knew, float* __restrict__ Qf,
-                                                      int* __restrict__ knew2) {
+                                                      int* __restrict__ knew2, const double* __restrict__ y0_ext) {
     __shared__ BlockOrthShared S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ldy = b | 1;
@@ -796,7 +798,8 @@ __device__ __forceinline__ void block_orth_small_body(const double* __restrict__
         s += v * v;
     }
     if (tid < 3) S.flag[tid] = 0;
-    const double y0 = sqrt(blk_sum(s, S.red));     // barrier inside: Y staged
+    const double ys = sqrt(blk_sum(s, S.red));     // barrier inside: Y staged
+    const double y0 = y0_ext ? y0_ext[0] : ys;
     RT_DENSE_TRACE(1);
     for (int pass = 0; pass < 2 && k > 0; ++pass) {
         // C = Qall[:, :k]^T Y (eight running sums per thread, fixed order)
@@ -971,8 +974,9 @@ template <int G, int RW>
 __global__ __launch_bounds__(NT) void block_orth_small_kernel(const double* __restrict__ Yin, int64_t J, int b,
                                                               double* __restrict__ Qall, int ldq, int k,
                                                               double drop, int* __restrict__ knew,
-                                                              float* __restrict__ Qf) {
-    block_orth_small_body<G, RW>(Yin, J, b, Qall, ldq, k, drop, knew, Qf, nullptr);
+                                                              float* __restrict__ Qf,
+                                                              const double* __restrict__ y0_ext) {
+    block_orth_small_body<G, RW>(Yin, J, b, Qall, ldq, k, drop, knew, Qf, nullptr, y0_ext);
 }
 
 // Grouped block steps: workgroup i serves request i of the group when its mode
@@ -984,7 +988,8 @@ __global__ __launch_bounds__(NT) void block_orth_group_kernel(const GHeader* __r
     if (i >= hdr->nblock) return;
     const GBlock& q = d[i];
     if (q.J <= jlo || q.J > 64 * RW) return;
-    block_orth_small_body<0, RW>(q.Y, q.J, q.b, q.Qall, q.cap, q.kcols, q.drop, q.knew, q.Qallf, &q.rb->knew);
+    block_orth_small_body<0, RW>(q.Y, q.J, q.b, q.Qall, q.cap, q.kcols, q.drop, q.knew, q.Qallf, &q.rb->knew,
+                                 nullptr);
 }
 
 struct EigShared {
@@ -1948,11 +1953,11 @@ size_t truncate_scratch(int64_t J, int ell) {
 }
 
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k, double drop, int* knew,
-                             float* Qf, double* scratch, hipStream_t stream) {
+                             float* Qf, double* scratch, hipStream_t stream, const double* y0_ext) {
     if (b <= BO_MAXB && J * (int64_t)(b | 1) <= BO_MAXE && k <= LMAX && J <= 1024) {
 #define RT_BO(GV, RWV)                                                                                          \
     hipLaunchKernelGGL((block_orth_small_kernel<GV, RWV>), dim3(1), dim3(NT), 0, stream, (const double*)Y, J, b, \
-                       Qall, ldq, k, drop, knew, Qf)
+                       Qall, ldq, k, drop, knew, Qf, y0_ext)
         const int G = b <= 8 ? 16 : 8;
         if (G == 16 && J <= 16) RT_BO(16, 1);
         else if (G == 16 && J <= 32) RT_BO(16, 2);
@@ -1970,7 +1975,7 @@ hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(block_orth_kernel, dim3(1), dim3(NT), 0, stream, Y, J, b, Qall, ldq, k, drop,
-                       scratch, knew, Qf);
+                       scratch, knew, Qf, y0_ext);
     return hipGetLastError();
 }
 

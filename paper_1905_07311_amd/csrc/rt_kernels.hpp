@@ -187,9 +187,11 @@ hipError_t launch_coo_densify(const int32_t* idx, int64_t ldi, const void* vals,
 // are dropped).  The kept columns are appended to Qall at column k and columns
 // k + kept .. k + b - 1 are zeroed; knew[0] = kept; Qf (optional, J x ld floats)
 // gets the float copy of these b columns.
-// `scratch`: 2 J b doubles.
+// `scratch`: 2 J b doubles.  y0_ext (device, optional): the norm the drop rule
+// compares with, when Y was already projected against earlier basis columns.
 hipError_t launch_block_orth(double* Y, int64_t J, int b, double* Qall, int ldq, int k,
-                             double drop, int* knew, float* Qf, double* scratch, hipStream_t stream);
+                             double drop, int* knew, float* Qf, double* scratch, hipStream_t stream,
+                             const double* y0_ext = nullptr);
 // one-time per-device set-up of the single-workgroup dense kernels (LDS > 64 KiB)
 hipError_t dense_init();
 
@@ -266,11 +268,13 @@ size_t wide_orth_scratch(int64_t J, int n);
 hipError_t launch_wide_orth(double* Y, int64_t J, int n, float* Qf, double accept_ratio, uint32_t* status,
                             double* scratch, hipStream_t stream);
 int plan_wide_gram(int64_t K);
-hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t R, double* part, int nwg,
+hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t ldb, int64_t R, double* part, int nwg,
                             hipStream_t stream);
 hipError_t launch_wide_eig(const double* W, int n, double tol, double* U, double* lam, hipStream_t stream);
-hipError_t launch_wide_factor(const double* Q, int64_t J, int n, const double* U, int r, double* A64, double* sgn,
-                              void* Aout, Dt da, double* Us, float* Usf, hipStream_t stream);
+hipError_t launch_wide_factor(const double* Q, int64_t ldq, int64_t J, int n, const double* U, int r, double* A64,
+                              double* sgn, void* Aout, Dt da, double* Us, float* Usf, hipStream_t stream);
+hipError_t launch_wide_cgs(double* Y, int64_t J, int b, const double* Q, int ldq, int ka, double* y0,
+                           hipStream_t stream);
 // dst (dtype) <- src (double), n elements
 hipError_t launch_cast_from_f64(const double* src, void* dst, Dt dt, int64_t n, hipStream_t stream);
 // explicit Omega (testing): out[i][j] = Omega[c0 + i, col0 + j], fp32 or fp64 transform

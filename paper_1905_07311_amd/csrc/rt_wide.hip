@@ -170,6 +170,41 @@ __global__ __launch_bounds__(WT) void wide_orth_kernel(double* __restrict__ Y, i
     }
 }
 
+// Block Gram-Schmidt of an adaptive block against earlier basis columns:
+// y0 = ||Y||_F, then twice C = Q^T Y (ka x b), Y -= Q C, for Y (J x b) and
+// Q (J x ka, row stride ldq), ka, b <= RT_LMAX; one workgroup.
+__global__ __launch_bounds__(WT) void wide_cgs_kernel(double* __restrict__ Y, int64_t J, int b,
+                                                      const double* __restrict__ Q, int ldq, int ka,
+                                                      double* __restrict__ y0) {
+    __shared__ double C[RT_LMAX][RT_LMAX + 1];
+    __shared__ double red[WT / 64];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t e = tid; e < J * b; e += WT) s = fma(Y[e], Y[e], s);
+    s = wg_sum(s, red);
+    if (tid == 0) y0[0] = sqrt(s);
+    for (int pass = 0; pass < 2; ++pass) {
+        // one wave per entry of C, its lanes across the rows
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int e = wave; e < ka * b; e += WT / 64) {
+            const int a = e / b, c = e - (e / b) * b;
+            double t = 0.0;
+            for (int64_t i = lane; i < J; i += 64) t = fma(Q[i * ldq + a], Y[i * b + c], t);
+            t = wave_sum_w(t);
+            if (lane == 0) C[a][c] = t;
+        }
+        __syncthreads();
+        for (int64_t e = tid; e < J * b; e += WT) {
+            const int64_t i = e / b;
+            const int c = (int)(e - i * b);
+            double v = Y[e];
+            for (int a = 0; a < ka; ++a) v = fma(-Q[i * ldq + a], C[a][c], v);
+            Y[e] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // CholeskyQR step on the fp64 Gram W = Y^T Y (n x n): Cholesky W = L L^T in
 // LDS (right-looking, one column per step), accepted when every pivot ratio
 // pivot_k / W_kk is at least min_ratio (kappa(Y) ~ 1 / sqrt(min_ratio)); then
@@ -261,15 +296,16 @@ __global__ __launch_bounds__(256) void wide_trmm_kernel(const double* __restrict
     if (Qf) Qf[e] = (float)q;
 }
 
-// Partial Grams of the (L, n, R) tensor B (unfolding columns c = l R + r):
+// Partial Grams of the first n mode rows of the (L, ldb, R) tensor B
+// (unfolding columns c = l R + r):
 // workgroup w sums the columns [w cpw, (w + 1) cpw) in tiles of WG_TC staged
 // in LDS as fp64; thread t owns the 8 x 8 block (rows 8 (t / 16), columns
 // 8 (t % 16)) of the n x n result and writes it to part[w].
 constexpr int WG_TC = 32;
 
 template <typename T>
-__global__ __launch_bounds__(256) void wide_gram_kernel(const T* __restrict__ B, int64_t L, int n, int64_t R,
-                                                        int64_t cpw, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void wide_gram_kernel(const T* __restrict__ B, int64_t L, int n, int64_t ldb,
+                                                        int64_t R, int64_t cpw, double* __restrict__ part) {
     __shared__ double bs[WMAX][WG_TC + 1];
     __shared__ int64_t coff[WG_TC];
     const int tid = threadIdx.x;
@@ -287,7 +323,7 @@ __global__ __launch_bounds__(256) void wide_gram_kernel(const T* __restrict__ B,
         if (tid < WG_TC) {
             const int64_t c = c0 + tid;
             const int64_t l = c / R, r = c - (c / R) * R;
-            coff[tid] = tid < nc ? l * n * R + r : -1;
+            coff[tid] = tid < nc ? l * ldb * R + r : -1;
         }
         __syncthreads();
         for (int e = tid; e < WMAX * WG_TC; e += 256) {
@@ -501,14 +537,14 @@ __global__ __launch_bounds__(WT) void wide_eig_kernel(const double* __restrict__
     if (tid < n) lam[tid] = fmax(S.nrm[S.perm[tid]] - delta, 0.0);
 }
 
-// A64[i][k] = sum_a Q[i][a] U[a][k] (i < J, k < r)
-__global__ __launch_bounds__(256) void wide_qu_kernel(const double* __restrict__ Q, int64_t J, int n,
+// A64[i][k] = sum_a Q[i][a] U[a][k] (i < J, k < r; Q with row stride ldq)
+__global__ __launch_bounds__(256) void wide_qu_kernel(const double* __restrict__ Q, int64_t ldq, int64_t J, int n,
                                                       const double* __restrict__ U, int r, double* __restrict__ A64) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= J * r) return;
     const int64_t i = e / r;
     const int k = (int)(e - i * r);
-    const double* q = Q + i * n;
+    const double* q = Q + i * ldq;
     double s0 = 0.0, s1 = 0.0;
     int a = 0;
     for (; a + 1 < n; a += 2) {
@@ -577,7 +613,7 @@ hipError_t launch_wide_copy_cols(const double* src, int64_t J, int w, double* ds
     return hipGetLastError();
 }
 
-hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t R, double* part, int nwg,
+hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t ldb, int64_t R, double* part, int nwg,
                             hipStream_t stream);
 
 int plan_wide_gram(int64_t K) {
@@ -610,14 +646,14 @@ hipError_t launch_wide_orth(double* Y, int64_t J, int n, float* Qf, double accep
     const unsigned gt = (unsigned)((J * n + 255) / 256);
     hipError_t e;
     // pass 1 on the sketch into T1
-    if ((e = launch_wide_gram(Y, Dt::F64, J, n, 1, part, nwg, stream)) != hipSuccess) return e;
+    if ((e = launch_wide_gram(Y, Dt::F64, J, n, n, 1, part, nwg, stream)) != hipSuccess) return e;
     if ((e = launch_reduce_partials(part, true, nwg, (int64_t)n * n, Wm, stream, rtmp)) != hipSuccess) return e;
     hipLaunchKernelGGL(wide_chol_kernel, dim3(1), dim3(WCT), 0, stream, (const double*)Wm, n, accept_ratio, Li, gate,
                        0);
     hipLaunchKernelGGL(wide_trmm_kernel, dim3(gt), dim3(256), 0, stream, (const double*)Y, J, n, (const double*)Li,
                        T1, (float*)nullptr, (const int*)gate);
     // pass 2 on T1 into Y (Y stays the sketch unless both passes are accepted)
-    if ((e = launch_wide_gram(T1, Dt::F64, J, n, 1, part, nwg, stream)) != hipSuccess) return e;
+    if ((e = launch_wide_gram(T1, Dt::F64, J, n, n, 1, part, nwg, stream)) != hipSuccess) return e;
     if ((e = launch_reduce_partials(part, true, nwg, (int64_t)n * n, Wm, stream, rtmp)) != hipSuccess) return e;
     hipLaunchKernelGGL(wide_chol_kernel, dim3(1), dim3(WCT), 0, stream, (const double*)Wm, n, 0.5, Li, gate, 1);
     hipLaunchKernelGGL(wide_trmm_kernel, dim3(gt), dim3(256), 0, stream, (const double*)T1, J, n, (const double*)Li,
@@ -627,18 +663,25 @@ hipError_t launch_wide_orth(double* Y, int64_t J, int n, float* Qf, double accep
     return hipGetLastError();
 }
 
-hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t R, double* part, int nwg,
+hipError_t launch_wide_gram(const void* B, Dt dt, int64_t L, int n, int64_t ldb, int64_t R, double* part, int nwg,
                             hipStream_t stream) {
-    if (n < 1 || n > WMAX || nwg < 1) return hipErrorInvalidValue;
+    if (n < 1 || n > WMAX || ldb < n || nwg < 1) return hipErrorInvalidValue;
     const int64_t K = L * R;
     int64_t cpw = (K + nwg - 1) / nwg;
     cpw = (cpw + WG_TC - 1) / WG_TC * WG_TC;
     if (dt == Dt::F64)
-        hipLaunchKernelGGL(wide_gram_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)B, L, n, R, cpw,
-                           part);
+        hipLaunchKernelGGL(wide_gram_kernel<double>, dim3(nwg), dim3(256), 0, stream, (const double*)B, L, n, ldb, R,
+                           cpw, part);
     else
-        hipLaunchKernelGGL(wide_gram_kernel<float>, dim3(nwg), dim3(256), 0, stream, (const float*)B, L, n, R, cpw,
-                           part);
+        hipLaunchKernelGGL(wide_gram_kernel<float>, dim3(nwg), dim3(256), 0, stream, (const float*)B, L, n, ldb, R,
+                           cpw, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_cgs(double* Y, int64_t J, int b, const double* Q, int ldq, int ka, double* y0,
+                           hipStream_t stream) {
+    if (b < 1 || b > RT_LMAX || ka < 0 || ka > RT_LMAX || ldq < ka) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wide_cgs_kernel, dim3(1), dim3(WT), 0, stream, Y, J, b, Q, ldq, ka, y0);
     return hipGetLastError();
 }
 
@@ -648,11 +691,12 @@ hipError_t launch_wide_eig(const double* W, int n, double tol, double* U, double
     return hipGetLastError();
 }
 
-hipError_t launch_wide_factor(const double* Q, int64_t J, int n, const double* U, int r, double* A64, double* sgn,
-                              void* Aout, Dt da, double* Us, float* Usf, hipStream_t stream) {
-    if (n < 1 || n > WMAX || r < 1 || r > n) return hipErrorInvalidValue;
+hipError_t launch_wide_factor(const double* Q, int64_t ldq, int64_t J, int n, const double* U, int r, double* A64,
+                              double* sgn, void* Aout, Dt da, double* Us, float* Usf, hipStream_t stream) {
+    if (n < 1 || n > WMAX || r < 1 || r > n || ldq < n) return hipErrorInvalidValue;
     const int64_t nA = J * r;
-    hipLaunchKernelGGL(wide_qu_kernel, dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, stream, Q, J, n, U, r, A64);
+    hipLaunchKernelGGL(wide_qu_kernel, dim3((unsigned)((nA + 255) / 256)), dim3(256), 0, stream, Q, ldq, J, n, U, r,
+                       A64);
     hipLaunchKernelGGL(wide_sign_kernel, dim3(r), dim3(256), 0, stream, (const double*)A64, J, r, sgn);
     const int64_t ne = nA > (int64_t)n * r ? nA : (int64_t)n * r;
     hipLaunchKernelGGL(wide_apply_sign_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream,

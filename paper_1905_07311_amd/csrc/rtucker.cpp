@@ -602,7 +602,7 @@ rt_status fixed_mode_wide(Call& k, Dt dt, int prec, const void* G, Shape3 s, int
         return fail(RT_ENOMEM, "workspace allocation failed");
     {
         TimeScope ts(k.c, 4, (double)s.L * ell * s.R * es, 2.0 * ell * ell * (double)s.L * s.R, ell, s.L * s.R, ell);
-        RT_HIP(rt::launch_wide_gram(B, dt, s.L, ell, s.R, gp, nwg, st));
+        RT_HIP(rt::launch_wide_gram(B, dt, s.L, ell, ell, s.R, gp, nwg, st));
         RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)ell * ell, Wm, st, rtmp));
     }
     {
@@ -610,11 +610,66 @@ rt_status fixed_mode_wide(Call& k, Dt dt, int prec, const void* G, Shape3 s, int
         // Gram of float data is fixed only to ~2^-24 of its norm)
         TimeScope ts(k.c, 3, 0.0, 0.0, J, ell, ell);
         RT_HIP(rt::launch_wide_eig(Wm, ell, dt == Dt::F64 ? ell * 0x1p-52 : 1e-9, U, lam, st));   // steps 4-5
-        RT_HIP(rt::launch_wide_factor(Y, J, ell, U, r, A64, sgn, A_out, dt, Us, Usf, st));
+        RT_HIP(rt::launch_wide_factor(Y, ell, J, ell, U, r, A64, sgn, A_out, dt, Us, Usf, st));
     }
     if (core_out)                                                                             // step 6
         RT_TRY(project_cols(k, dt, dt == Dt::F64 ? Dt::F64 : Dt::F32, B, Shape3{s.L, ell, s.R}, ell,
                             dt == Dt::F64 ? (const void*)Us : (const void*)Usf, r, r, core_out, r));
+    return RT_OK;
+}
+
+// Adaptive post-truncation of a QB with RT_LMAX < kb <= RT_LMAX_FIXED basis
+// columns: B is (L, kb, R) stored with mode length ldb, Q (J x kb, row stride
+// ldq).  The eigenvalues of B's fp64 Gram come back to the host, where the rank
+// is the smallest k with max(E, 0) + sum_{t >= k} lambda_t <= tau2; then A (J x
+// k, written with leading dimension k), the core U_k^T B into *core_out and its
+// squared norm into core_nrm2 (device) when those are given.
+rt_status truncate_wide(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, const double* Q, int64_t J,
+                        int64_t ldq, double E, double tau2, void* A_out, void** core_out, double* core_nrm2,
+                        int* k_host) {
+    hipStream_t st = k.c->stream;
+    const int kb = (int)sb.J;
+    const size_t es = dt == Dt::F64 ? 8 : 4;
+    const int nwg = rt::plan_wide_gram(sb.L * sb.R);
+    double* gp = k.ws<double>((size_t)nwg * kb * kb);
+    double* Wm = k.ws<double>((size_t)kb * kb);
+    double* rtmp = k.ws<double>(rt::reduce_partials_tmp(nwg, (int64_t)kb * kb) + 1);
+    double* U = k.ws<double>((size_t)kb * kb);
+    double* lam = k.ws<double>(kb);
+    double* A64 = k.ws<double>((size_t)J * kb);
+    double* sgn = k.ws<double>(kb);
+    double* Us = k.ws<double>((size_t)kb * kb);
+    float* Usf = k.ws<float>((size_t)kb * kb);
+    if (!gp || !Wm || !rtmp || !U || !lam || !A64 || !sgn || !Us || !Usf)
+        return fail(RT_ENOMEM, "workspace allocation failed");
+    RT_HIP(rt::launch_wide_gram(B, dt, sb.L, kb, ldb, sb.R, gp, nwg, st));
+    RT_HIP(rt::launch_reduce_partials(gp, true, nwg, (int64_t)kb * kb, Wm, st, rtmp));
+    {
+        TimeScope ts(k.c, 3, 0.0, 0.0, J, kb, kb);
+        RT_HIP(rt::launch_wide_eig(Wm, kb, dt == Dt::F64 ? kb * 0x1p-52 : 1e-9, U, lam, st));
+    }
+    std::vector<double> lh(kb);
+    RT_HIP(hipMemcpyAsync(lh.data(), lam, sizeof(double) * kb, hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    double tail = 0.0;
+    int kk = kb;
+    const double e0 = std::max(E, 0.0);
+    for (int t = kb - 1; t >= 0; --t) {                  // tail = sum_{t' >= t} lambda_t'
+        if (e0 + tail + lh[t] > tau2) break;
+        tail += lh[t];
+        kk = t;
+    }
+    if (e0 > tau2) kk = kb;                              // a capped mode keeps every column
+    *k_host = kk;
+    if (kk == 0) return RT_OK;
+    RT_HIP(rt::launch_wide_factor(Q, ldq, J, kb, U, kk, A64, sgn, A_out, dt, Us, Usf, st));
+    if (core_out) {
+        if (!*core_out) *core_out = k.c->ws((size_t)sb.L * kk * sb.R * es);
+        if (!*core_out) return fail(RT_ENOMEM, "workspace allocation failed");
+        RT_TRY(project_cols(k, dt, dt == Dt::F64 ? Dt::F64 : Dt::F32, B, sb, ldb,
+                            dt == Dt::F64 ? (const void*)Us : (const void*)Usf, kk, kk, *core_out, kk));
+        if (core_nrm2) RT_TRY(do_norm2(k, *core_out, dt, sb.L * kk * sb.R, core_nrm2));
+    }
     return RT_OK;
 }
 
@@ -1215,7 +1270,7 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         double tau2 = (epsn[n] * normx) * (epsn[n] * normx);
         Shape3 s = shape3(dims, n);
         const int64_t J = s.J, K = s.L * s.R;
-        int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX);
+        int cap = (int)std::min<int64_t>(std::min<int64_t>(J, K), RT_LMAX_FIXED);
         if (max_rank) cap = std::min(cap, (int)max_rank[n]);
         double* Qall = k.ws<double>((size_t)J * cap);
         // float copy of the basis: float32 data is projected on MFMA with a float Q
@@ -1226,7 +1281,8 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         double* scratch = k.ws<double>((size_t)2 * J * block);
         double* W = k.ws<double>((size_t)cap * cap);
         double* Edev = k.ws<double>(1);
-        if (!Qall || !Bbuf || !Y || !scratch || !W || !Edev || (dt == Dt::F32 && !Qallf)) {
+        double* y0dev = k.ws<double>(1);
+        if (!Qall || !Bbuf || !Y || !scratch || !W || !Edev || !y0dev || (dt == Dt::F32 && !Qallf)) {
             release_partial(ctx, out);
             return fail(RT_ENOMEM, "workspace allocation failed");
         }
@@ -1248,9 +1304,18 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
                 {
                     TimeScope ts(k.c, 2, 8.0 * J * (bi + 2.0 * kcols), 8.0 * J * bi * kcols, J, kcols, bi);
-                    RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols,
-                                                 prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop, kdev, Qallf,
-                                                 scratch, st));
+                    const double dr = prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop;
+                    if (kcols + bi <= RT_LMAX) {
+                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, dr, kdev, Qallf, scratch, st));
+                    } else {
+                        // a basis beyond RT_LMAX columns: Gram-Schmidt (twice) against its
+                        // first ka columns, then the block step against the last kb with
+                        // the drop rule on the block's norm before any projection
+                        const int kb = RT_LMAX - bi, ka = kcols - kb;
+                        RT_HIP(rt::launch_wide_cgs(Y, J, bi, Qall, cap, ka, y0dev, st));
+                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall + ka, cap, kb, dr, kdev,
+                                                     Qallf ? Qallf + ka : nullptr, scratch, st, y0dev));
+                    }
                 }
                 // B_i over all bi columns (the dropped ones are zero), then kn and
                 // ||B_i||^2 come back together
@@ -1299,7 +1364,11 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
         void* A = k.c->ws((size_t)J * std::max(kcols, 1) * es);
         void* core = nullptr;
         if (!A) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
-        if (kcols > 0) {
+        if (kcols > RT_LMAX) {
+            rt_status rs = truncate_wide(k, dt, Bbuf, Shape3{s.L, kcols, s.R}, cap, Qall, J, cap, E, tau2, A,
+                                         sequential ? &core : nullptr, sequential ? tmp : nullptr, &kfinal);
+            if (rs != RT_OK) { release_partial(ctx, out); return rs; }
+        } else if (kcols > 0) {
             int nwg = rt::plan_gram3(s.L, s.R);
             double* gp = k.ws<double>((size_t)nwg * kcols * kcols);
             if (!gp) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
@@ -1346,7 +1415,7 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
             void* nc = k.c->ws((size_t)s.L * std::max(r, 1) * s.R * es);
             if (!nc) { release_partial(ctx, out); return fail(RT_ENOMEM, "workspace allocation failed"); }
             if (r > 0) {
-                rt_status rs = do_project(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r, 0, nullptr, nullptr);
+                rt_status rs = project_cols(k, dt, dt, cur, s, s.J, out->factors[j], r, r, nc, r);
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
             }
             dims[j] = r;

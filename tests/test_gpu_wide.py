@@ -90,3 +90,37 @@ def test_wide_argument_errors(ctx):
         ctx.rsthosvd(X, [70, 10, 10], 5, seed=0, power_iters=1)
     g = ctx.rsthosvd(X, [119, 10, 10], 9, seed=0)              # r + p = 128 on a zero tensor
     assert g.core_norm == 0.0 and g.ranks == [119, 10, 10]
+
+
+def _adaptive_check(g, o, X, eps, tol, u):
+    from gpu_common import borderline
+    nx2 = float(np.sum(X * X))
+    assert np.linalg.norm(xhat(g) - X) / np.sqrt(nx2) <= eps
+    diff = np.linalg.norm(xhat(g) - o.reconstruct()) / np.sqrt(nx2)
+    if borderline(o, nx2, u):
+        assert all(abs(a - c) <= 1 for a, c in zip(g.ranks, o.ranks))
+        assert diff <= 2 * eps
+    else:
+        assert g.ranks == o.ranks
+        assert diff < tol
+    for A in g.factors:
+        A = to_np(A)
+        assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=max(tol, 1e-12) * 10)
+
+
+@pytest.mark.parametrize("alg", ["rsthosvd_adaptive", "rhosvd_adaptive"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("b", [8, 16])
+def test_wide_adaptive(ctx, alg, dtype, b):
+    # orthogonally decomposable 120^3 tensor with mode spectra 0.93^k: eps = 1e-3
+    # needs ranks near 100, so every mode's basis grows past RT_LMAX columns
+    rng = np.random.default_rng(63)
+    X = inputs.odeco(rng, (120, 120, 120), 0.93)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    g = getattr(ctx, alg)(torch.from_numpy(Xs).cuda(), 1e-3, b, seed=6)
+    o = getattr(oracle, "adaptive_" + alg.split("_")[0])(Xf, 1e-3, b, seed=6,
+                                                           delta=1e-10 if dtype == torch.float64 else 1e-5)
+    assert min(o.ranks) > 64
+    _adaptive_check(g, o, Xf, 1e-3, 1e-10 if dtype == torch.float64 else 1e-5,
+                    2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
