@@ -351,6 +351,30 @@ __global__ __launch_bounds__(256) void wide_gram_kernel(const T* __restrict__ B,
             if (a0 + i < n && b0 + j < n) pw[(a0 + i) * n + b0 + j] = acc[i][j];
 }
 
+// Rotation (c, s) that makes columns p, q with Gram [[al, ga], [ga, be]]
+// orthogonal under [p q] <- [p q] [c s; -s c]: t = tan of the smaller angle,
+// the root of t^2 + 2 zeta t - 1 = 0 with zeta = (be - al) / (2 ga).  t is
+// formed in single precision from the block scaled by a power of two (an
+// inexact angle only slows the convergence), c = 1 / sqrt(1 + t^2) from the
+// single-precision reciprocal square root refined by two Newton steps and
+// s = t c, so the rotation is orthogonal to double precision; this keeps the
+// fp64 divisions and square roots off the step's critical path.
+__device__ __forceinline__ void wrot(double al, double be, double ga, double& c, double& s) {
+    const double d = be - al;
+    const int e = ilogb(fmax(fmax(fabs(d), fabs(ga)), 1e-300));
+    const float df = (float)ldexp(d, -e), gf = (float)ldexp(ga, -e);
+    const float r = __builtin_amdgcn_sqrtf(df * df + 4.0f * gf * gf);
+    const float den = df >= 0.0f ? df + r : df - r;
+    const float tf = 2.0f * gf * __builtin_amdgcn_rcpf(den == 0.0f ? 1.0f : den);
+    const double t = (double)tf;
+    const double x = fma(t, t, 1.0);
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    c = y;
+    s = t * y;
+}
+
 // Round-robin pairing of m (even) indices: in step `step` (0 .. m - 2) pair t
 // joins a and b; index m - 1 stays, the others rotate; every index once per step.
 __device__ __forceinline__ void wpair(int step, int t, int m, int& p, int& q) {
@@ -404,8 +428,12 @@ __global__ __launch_bounds__(WT) void wide_eig_kernel(const double* __restrict__
     }
     __syncthreads();
     if (f2 > 0.0 && n > 1) {
-        const int t = tid >> 4, sub = tid & 15;
+        // eight threads per pair (512 threads), each over every eighth row: the
+        // step is bound by its LDS traffic, so the pair's rows are read once into
+        // registers and rows past n are not touched
+        const int t = tid >> 3, sub = tid & 7;
         const int half = m / 2;
+        const int nr = (n - sub + 7) / 8;                // rows sub, sub + 8, ... below n
         for (int sweep = 0; sweep < max_sweeps; ++sweep) {
             if (tid == 0) S.changed = 0;
             __syncthreads();
@@ -413,33 +441,39 @@ __global__ __launch_bounds__(WT) void wide_eig_kernel(const double* __restrict__
                 if (t < half) {
                     int p, q;
                     wpair(step, t, m, p, q);
+                    double av[WMAX / 8], bv[WMAX / 8];
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                    for (int u = 0; u < WMAX / 16; ++u) {
-                        const int i = sub + 16 * u;
-                        const double a = S.M[i][p], b = S.M[i][q];
-                        al = fma(a, a, al);
-                        be = fma(b, b, be);
-                        ga = fma(a, b, ga);
+                    for (int u = 0; u < WMAX / 8; ++u) {
+                        if (u < nr) {
+                            const int i = sub + 8 * u;
+                            av[u] = S.M[i][p];
+                            bv[u] = S.M[i][q];
+                            al = fma(av[u], av[u], al);
+                            be = fma(bv[u], bv[u], be);
+                            ga = fma(av[u], bv[u], ga);
+                        }
                     }
 #pragma unroll
-                    for (int off = 8; off > 0; off >>= 1) {
-                        al += __shfl_xor(al, off, 16);
-                        be += __shfl_xor(be, off, 16);
-                        ga += __shfl_xor(ga, off, 16);
+                    for (int off = 4; off > 0; off >>= 1) {
+                        al += __shfl_xor(al, off, 8);
+                        be += __shfl_xor(be, off, 8);
+                        ga += __shfl_xor(ga, off, 8);
                     }
-                    if (q < n && al > 0.0 && be > 0.0 &&
-                        fabs(ga) > tol * sqrt(al * be) + delta * (sqrt(al) + sqrt(be))) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-                        const double c = 1.0 / sqrt(fma(tt, tt, 1.0));
-                        const double s = c * tt;
+                    // (the threshold needs no correctly rounded square roots: the
+                    // hardware reciprocal square root estimate serves)
+                    const double ra = al > 0.0 ? al * __builtin_amdgcn_rsq(al) : 0.0;
+                    const double rb = be > 0.0 ? be * __builtin_amdgcn_rsq(be) : 0.0;
+                    if (q < n && al > 0.0 && be > 0.0 && fabs(ga) > tol * ra * rb + delta * (ra + rb)) {
+                        double c, s;
+                        wrot(al, be, ga, c, s);
 #pragma unroll
-                        for (int u = 0; u < WMAX / 16; ++u) {
-                            const int i = sub + 16 * u;
-                            const double a = S.M[i][p], b = S.M[i][q];
-                            S.M[i][p] = c * a - s * b;
-                            S.M[i][q] = s * a + c * b;
+                        for (int u = 0; u < WMAX / 8; ++u) {
+                            if (u < nr) {
+                                const int i = sub + 8 * u;
+                                S.M[i][p] = c * av[u] - s * bv[u];
+                                S.M[i][q] = s * av[u] + c * bv[u];
+                            }
                         }
                         if (sub == 0) S.changed = 1;
                     }
@@ -505,10 +539,16 @@ __global__ __launch_bounds__(WT) void wide_eig_kernel(const double* __restrict__
                     if (sub == 0 && j < k) S.dots[j] = d;
                 }
                 __syncthreads();
-                if (tid < n) {
-                    double v = S.M[tid][c];
-                    for (int j = 0; j < k; ++j) v = fma(-S.dots[j], S.M[tid][S.perm[j]], v);
-                    S.M[tid][c] = v;
+                // row i -= sum_j dots[j] u_perm[j][i]: eight threads per row, each
+                // over every eighth j, summed by a butterfly
+                {
+                    const int i = tid >> 3, sub = tid & 7;
+                    double v = 0.0;
+                    if (i < n)
+                        for (int j = sub; j < k; j += 8) v = fma(S.dots[j], S.M[i][S.perm[j]], v);
+#pragma unroll
+                    for (int off = 4; off > 0; off >>= 1) v += __shfl_xor(v, off, 8);
+                    if (sub == 0 && i < n) S.M[i][c] -= v;
                 }
                 __syncthreads();
             }
