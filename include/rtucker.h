@@ -418,7 +418,9 @@ rt_status rt_sketch_coo(rt_ctx* ctx, const rt_coo* X, int32_t mode, int32_t ell,
  * inputs cross on two copy streams and join the next iteration.  A request's footprint is the exact
  * workspace of its shape (input, basis, projections, cores, factors).  A request
  * whose block step does not fit the grouped kernel (a mode longer than 910 rows
- * for blocks of 8) runs alone through rt_rsthosvd_adaptive.  Float32 sketches.
+ * for blocks of 8) runs alone through rt_rsthosvd_adaptive, and so is a request
+ * redone whose basis would grow past RT_LMAX columns (the shared kernels' cap;
+ * the single-request path grows to RT_LMAX_FIXED).  Float32 sketches.
  * RT_SERVE_SLOTS: every slot runs whole requests through rt_rsthosvd_adaptive
  * on a stream of its own (float32 or bfloat16 sketches).
  *

@@ -420,6 +420,7 @@ struct GState {
     int kcols = 0, blk = 0, bi = 0;
     double E = 0.0, tau2 = 0.0, nx2 = 0.0, cur_norm2 = 0.0;
     bool have_norm = false, capped = false;
+    bool rerun = false;       // needs more than RT_LMAX basis columns: redone alone
     enum Phase { BLOCK, TRUNC, DONE } phase = BLOCK;
     hipEvent_t ev = nullptr;  // completion of the input copy, then of the result copy
     int cs = 0;               // copy stream of both copies (stream order keeps them apart)
@@ -732,8 +733,13 @@ void rt_server::exec_main() {
                                               : hipEventQuery(g->ev) != hipErrorNotReady);
             if (done) {
                 Request* r = g->r;
+                const bool rerun = g->rerun;
                 draining.erase(draining.begin() + i);
                 complete_drain(g);
+                if (rerun) {
+                    r->err.clear();
+                    run(r, ctx, st, cache, dX, dX_cap, stage, stage_cap);
+                }
                 complete(r);
             } else {
                 ++i;
@@ -941,7 +947,17 @@ void rt_server::exec_main() {
                 g->E -= rb.bnorm2;
                 g->kcols += kn;
                 if (!(g->E > g->tau2)) end_blocks(g);
-                else if (g->kcols >= g->cap) { g->capped = true; end_blocks(g); }
+                else if (g->kcols >= g->cap) {
+                    if (g->cap == RT_LMAX && g->cap < std::min<int64_t>(g->J, g->L * g->R)) {
+                        // the shared kernels stop at RT_LMAX columns, the single-request
+                        // path at RT_LMAX_FIXED: the request is redone alone
+                        g->rerun = true;
+                        fail(g, RT_EINVAL, "redone alone");
+                    } else {
+                        g->capped = true;
+                        end_blocks(g);
+                    }
+                }
             } else if (g->phase == GState::TRUNC) {
                 const int k = rb.kfinal;
                 g->ranks[g->n] = k;

@@ -234,3 +234,33 @@ def test_served_decompression(reqs, mode):
     finally:
         ctx.close()
         srv.close()
+
+
+@pytest.mark.parametrize("mode", ["grouped", "slots"])
+def test_served_rank_above_64(mode):
+    # a request whose tolerance needs ranks near 100 (orthogonally decomposable
+    # 120^3 tensor, spectra 0.93^k) beside small ones: the grouped executor's
+    # shared kernels stop at 64 basis columns, so it redoes that request alone on
+    # the path that grows bases to 128; either way the result equals the
+    # single-call adaptive R-STHOSVD on the same data (same seed) and meets eps
+    need_gpu()
+    rng = np.random.default_rng(63)
+    big = torch.from_numpy(inputs.odeco(rng, (120, 120, 120), 0.93).astype(np.float32)).pin_memory()
+    small = _requests(3, seed=91)
+    srv = rtucker.Server(max_inflight=4, eps=1e-3, block=8, mode=mode)
+    ctx = rtucker.Context(0)
+    try:
+        tickets = [srv.submit(X, s) for X, s in small[:2]] + [srv.submit(big, 17)] + [srv.submit(*small[2])]
+        res = [srv.wait(t) for t in tickets]
+        assert all(r.status == rtucker.RT_OK for r in res)
+        rb = res[2]
+        assert min(rb.ranks) > 64
+        assert _rel_err(rb, big) <= 1e-3
+        d = ctx.rsthosvd_adaptive(big.cuda(), 1e-3, 8, seed=17)
+        assert rb.ranks == d.ranks
+        assert np.array_equal(rb.core, d.core.cpu().numpy())
+        for (X, _), r in zip(small[:2] + small[2:], res[:2] + res[3:]):
+            assert _rel_err(r, X) <= 1e-3
+    finally:
+        ctx.close()
+        srv.close()
