@@ -1254,10 +1254,13 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
     double* nx2 = k.ws<double>(1);
     double* tmp = k.ws<double>(4);
     uint32_t* status = k.ws<uint32_t>(RT_MAXD);
-    int* kdev = k.ws<int>(4);
-    if (!nx2 || !tmp || !status || !kdev) return fail(RT_ENOMEM, "workspace allocation failed");
+    if (!nx2 || !tmp || !status) return fail(RT_ENOMEM, "workspace allocation failed");
     RT_HIP(hipMemsetAsync(status, 0, sizeof(uint32_t) * RT_MAXD, st));
     double* h = ctx->host;
+    // per-block results read by the host: the device writes them into the
+    // pinned block through its mapped address (no copy launches per block)
+    int* kmap = reinterpret_cast<int*>(ctx->host_dev + 1);
+    double* bmap = ctx->host_dev + 2;
     // ||X||^2 is summed by the first sketch (which reads every entry of X) and read
     // back with that block's results; no separate pass over X
     bool have_norm = false;
@@ -1306,24 +1309,22 @@ static rt_status adaptive_impl(rt_ctx* ctx, const rt_tensor* X, double eps, cons
                     TimeScope ts(k.c, 2, 8.0 * J * (bi + 2.0 * kcols), 8.0 * J * bi * kcols, J, kcols, bi);
                     const double dr = prec_cur == RT_PREC_BF16_SKETCH ? drop_bf16 : drop;
                     if (kcols + bi <= RT_LMAX) {
-                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, dr, kdev, Qallf, scratch, st));
+                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall, cap, kcols, dr, kmap, Qallf, scratch, st));
                     } else {
                         // a basis beyond RT_LMAX columns: Gram-Schmidt (twice) against its
                         // first ka columns, then the block step against the last kb with
                         // the drop rule on the block's norm before any projection
                         const int kb = RT_LMAX - bi, ka = kcols - kb;
                         RT_HIP(rt::launch_wide_cgs(Y, J, bi, Qall, cap, ka, y0dev, st));
-                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall + ka, cap, kb, dr, kdev,
+                        RT_HIP(rt::launch_block_orth(Y, J, bi, Qall + ka, cap, kb, dr, kmap,
                                                      Qallf ? Qallf + ka : nullptr, scratch, st, y0dev));
                     }
                 }
-                // B_i over all bi columns (the dropped ones are zero), then kn and
-                // ||B_i||^2 come back together
-                rs = Qallf ? do_project(k, dt, Dt::F32, cur, s, s.J, Qallf + kcols, cap, bi, Bbuf, cap, kcols, nullptr, tmp)
-                           : do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, bi, Bbuf, cap, kcols, nullptr, tmp);
+                // B_i over all bi columns (the dropped ones are zero); kn and ||B_i||^2
+                // are written by the kernels straight into the mapped host block
+                rs = Qallf ? do_project(k, dt, Dt::F32, cur, s, s.J, Qallf + kcols, cap, bi, Bbuf, cap, kcols, nullptr, bmap)
+                           : do_project(k, dt, Dt::F64, cur, s, s.J, Qall + kcols, cap, bi, Bbuf, cap, kcols, nullptr, bmap);
                 if (rs != RT_OK) { release_partial(ctx, out); return rs; }
-                RT_HIP(hipMemcpyAsync(h + 1, kdev, sizeof(int), hipMemcpyDeviceToHost, st));
-                RT_HIP(hipMemcpyAsync(h + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, st));
                 if (!have_norm) RT_HIP(hipMemcpyAsync(h, nx2, sizeof(double), hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
                 if (!have_norm) {
