@@ -95,6 +95,9 @@ WORKLOADS = {
     "c2q1": dict(desc="R-STHOSVD with one step of randomized subspace iteration per mode, dense 512^3 float32 "
                       "X[i,j,k]=1/(i+j+k+1) (0-based), rank (25,25,25), p=10, order 1-2-3, Omega seed 1",
                  dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="rsthosvd", q=1),
+    "c2w": dict(desc="R-STHOSVD at sketch width 100 (the wide dense path), dense 512^3 float32 "
+                     "X[i,j,k]=1/(i+j+k+1) (0-based), rank (90,90,90), p=10, order 1-2-3, Omega seed 1",
+                dims=(512, 512, 512), ranks=(90, 90, 90), p=10, seed=1, prec="f32", algo="rsthosvd"),
     "c2sp": dict(desc="structure-preserving STHOSVD (core of X entries), dense 512^3 float32 X[i,j,k]=1/(i+j+k+1) "
                       "(0-based), rank (25,25,25), p=10 (core 35^3), order 1-2-3, Omega seed 1",
                  dims=(512, 512, 512), ranks=(25, 25, 25), p=10, seed=1, prec="f32", algo="sp_sthosvd"),
@@ -121,7 +124,7 @@ def make_input(name, device):
     import torch
     from paper_1905_07311_amd import inputs
     w = WORKLOADS[name]
-    if name in ("c2", "c2h", "c2q1", "c2sp"):
+    if name in ("c2", "c2h", "c2q1", "c2sp", "c2w"):
         return inputs.hilbert0_device(w["dims"], device, torch.float32)
     if name == "c1":
         return torch.from_numpy(inputs.config1()).to(device)
