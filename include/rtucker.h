@@ -57,7 +57,10 @@ typedef enum {
     RT_ENOMEM = 2,      /* device allocation failed */
     RT_ENONFINITE = 3,  /* the input holds NaN or Inf */
     RT_ECAP = 4,        /* adaptive: rank cap reached before the tolerance */
-    RT_EHIP = 5         /* a HIP runtime call failed */
+    RT_EHIP = 5,        /* a HIP runtime call failed */
+    RT_EBUSY = 6,       /* serving: the wait queue is full (nothing queued), or the
+                           request to cancel has already been admitted */
+    RT_ECANCELLED = 7   /* serving: the request was cancelled before admission */
 } rt_status;
 
 typedef enum { RT_F32 = 0, RT_F64 = 1 } rt_dtype;
@@ -438,6 +441,9 @@ typedef struct {
     double eps;               /* relative tolerance of every request (eps_n = eps / sqrt(d)) */
     int32_t block;            /* adaptive block size, 1 .. RT_LMAX (grouped: 1 .. 16) */
     int32_t mode;             /* RT_SERVE_GROUPED or RT_SERVE_SLOTS */
+    int32_t max_queued;       /* requests waiting for admission; 0 = unbounded.  A
+                                 submission beyond it returns RT_EBUSY and queues
+                                 nothing (back-pressure for the caller) */
 } rt_server_opts;
 
 typedef struct {
@@ -487,6 +493,12 @@ rt_status rt_server_wait(rt_server* srv, uint64_t ticket, rt_result* out);
 
 /* Free the host result of a completed request (its pointers become invalid). */
 rt_status rt_server_release(rt_server* srv, uint64_t ticket);
+
+/* Withdraw a request that is still waiting for admission: it leaves the queue
+ * and completes at once with status RT_ECANCELLED (poll and wait report it;
+ * release it like any other).  A request already admitted, running or done is
+ * not touched: RT_EBUSY.  An unknown ticket: RT_EINVAL. */
+rt_status rt_server_cancel(rt_server* srv, uint64_t ticket);
 
 /* Counters of the grouped executor since creation (slots mode: zeros apart
  * from `completed`).  Per iteration the executor launches, then does the host

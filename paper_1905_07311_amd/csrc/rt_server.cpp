@@ -1012,6 +1012,7 @@ rt_status rt_server_create(rt_server** srv, int device, const rt_server_opts* op
     if (opts->block < 1 || opts->block > RT_LMAX) return rt::set_error(RT_EINVAL, "block must be in [1, RT_LMAX]");
     if (opts->mode != RT_SERVE_GROUPED && opts->mode != RT_SERVE_SLOTS)
         return rt::set_error(RT_EINVAL, "mode must be RT_SERVE_GROUPED or RT_SERVE_SLOTS");
+    if (opts->max_queued < 0) return rt::set_error(RT_EINVAL, "max_queued must be >= 0");
     if (opts->mode == RT_SERVE_GROUPED && (opts->prec != RT_PREC_F32 || opts->block > 16))
         return rt::set_error(RT_EINVAL, "grouped serving runs float32 sketches with blocks of at most 16 columns");
     if (hipSetDevice(device) != hipSuccess) return rt::set_error(RT_EHIP, "hipSetDevice failed");
@@ -1052,6 +1053,10 @@ rt_status rt_server_submit(rt_server* srv, const rt_tensor* X, uint64_t seed, ui
             delete r;
             return rt::set_error(RT_EINVAL, "server is stopping");
         }
+        if (srv->opts.max_queued > 0 && srv->queue.size() >= (size_t)srv->opts.max_queued) {
+            delete r;
+            return rt::set_error(RT_EBUSY, "the wait queue is full");
+        }
         r->id = srv->next_id++;
         srv->reqs[r->id] = r;
         srv->queue.push_back(r);
@@ -1087,6 +1092,10 @@ rt_status rt_server_submit_reconstruct(rt_server* srv, const rt_tucker_host* t, 
         if (srv->stopping) {
             delete r;
             return rt::set_error(RT_EINVAL, "server is stopping");
+        }
+        if (srv->opts.max_queued > 0 && srv->queue.size() >= (size_t)srv->opts.max_queued) {
+            delete r;
+            return rt::set_error(RT_EBUSY, "the wait queue is full");
         }
         r->id = srv->next_id++;
         srv->reqs[r->id] = r;
@@ -1127,6 +1136,34 @@ rt_status rt_server_release(rt_server* srv, uint64_t ticket) {
     if (!it->second->done) return rt::set_error(RT_EINVAL, "request has not completed");
     delete it->second;
     srv->reqs.erase(it);
+    return RT_OK;
+}
+
+rt_status rt_server_cancel(rt_server* srv, uint64_t ticket) {
+    if (!srv) return rt::set_error(RT_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->reqs.find(ticket);
+        if (it == srv->reqs.end()) return rt::set_error(RT_EINVAL, "unknown ticket");
+        Request* r = it->second;
+        auto q = std::find(srv->queue.begin(), srv->queue.end(), r);
+        if (q == srv->queue.end()) return rt::set_error(RT_EBUSY, "request already admitted");
+        srv->queue.erase(q);
+        r->t_admit = r->t_done = Clock::now();
+        rt_result& res = r->res;
+        res.status = RT_ECANCELLED;
+        res.ndim = r->decompress ? r->T.ndim : r->X.ndim;
+        for (int i = 0; i < res.ndim; ++i) {
+            res.dims[i] = r->decompress ? r->T.dims[i] : r->X.dims[i];
+            res.ranks[i] = r->decompress ? r->T.ranks[i] : 0;
+        }
+        res.queue_s = 0.0;
+        res.latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+        r->err = "request cancelled";
+        r->done = true;
+    }
+    srv->cv_done.notify_all();
+    srv->cv_work.notify_all();
     return RT_OK;
 }
 

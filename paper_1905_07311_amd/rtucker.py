@@ -15,7 +15,7 @@ from typing import List, Optional
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "librtucker.so")
 
-RT_OK, RT_EINVAL, RT_ENOMEM, RT_ENONFINITE, RT_ECAP, RT_EHIP = range(6)
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_ENONFINITE, RT_ECAP, RT_EHIP, RT_EBUSY, RT_ECANCELLED = range(8)
 RT_F32, RT_F64 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 RT_MAXD = 8
@@ -28,7 +28,7 @@ RT_FLAG_FALLBACK = 2
 EXPORTED = ["rt_version", "rt_last_error", "rt_create", "rt_set_stream", "rt_destroy", "rt_rhosvd", "rt_rsthosvd",
             "rt_rsthosvd_adaptive", "rt_rhosvd_adaptive", "rt_sp_sthosvd", "rt_sp_sthosvd_coo", "rt_sketch_coo", "rt_reconstruct", "rt_tucker_release", "rt_sketch", "rt_sketch_noalloc", "rt_orth", "rt_project", "rt_omega",
             "rt_philox_words", "rt_sync", "rt_timing", "rt_timing_count", "rt_timing_entry", "rt_timing_variant",
-            "rt_server_create", "rt_server_submit", "rt_server_submit_reconstruct", "rt_server_poll", "rt_server_wait", "rt_server_release",
+            "rt_server_create", "rt_server_submit", "rt_server_submit_reconstruct", "rt_server_poll", "rt_server_wait", "rt_server_release", "rt_server_cancel",
             "rt_server_get_stats", "rt_server_destroy", "rt_tuning_set", "rt_tuning_plan"]
 
 
@@ -57,7 +57,8 @@ class rt_tucker(ctypes.Structure):
 
 class rt_server_opts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("prec", ctypes.c_int),
-                ("eps", ctypes.c_double), ("block", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("eps", ctypes.c_double), ("block", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_queued", ctypes.c_int32)]
 
 
 RT_SERVE_GROUPED, RT_SERVE_SLOTS = 0, 1
@@ -166,6 +167,7 @@ def load(path=None):
     lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(rt_result)]
     lib.rt_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(rt_result)]
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.rt_server_cancel.argtypes = [P, ctypes.c_uint64]
     lib.rt_server_get_stats.argtypes = [P, ctypes.POINTER(rt_server_stats)]
     lib.rt_server_destroy.argtypes = [P]
     lib.rt_tuning_set.argtypes = [ctypes.POINTER(rt_tune_entry), ctypes.c_int32]
@@ -626,7 +628,8 @@ class Server:
     iterations, float32 sketches) or "slots" (whole requests on per-slot
     streams); default grouped for float32, slots for the bfloat16 sketch."""
 
-    def __init__(self, device=0, max_inflight=8, eps=1e-3, block=8, prec="f32", hbm_budget=0, mode=None):
+    def __init__(self, device=0, max_inflight=8, eps=1e-3, block=8, prec="f32", hbm_budget=0, mode=None,
+                 max_queued=0):
         load()
         o = rt_server_opts()
         o.max_inflight = int(max_inflight)
@@ -637,6 +640,7 @@ class Server:
         if mode is None:
             mode = "grouped" if o.prec == PREC["f32"] else "slots"
         o.mode = SERVE_MODE[mode] if isinstance(mode, str) else int(mode)
+        o.max_queued = int(max_queued)
         self.srv = ctypes.c_void_p()
         _check(_lib.rt_server_create(ctypes.byref(self.srv), int(device), ctypes.byref(o)))
         self._keep = {}
@@ -728,8 +732,14 @@ class Server:
 
     def wait(self, ticket):
         r = rt_result()
-        _check(_lib.rt_server_wait(self.srv, ctypes.c_uint64(ticket), ctypes.byref(r)), allow=(RT_ECAP,))
+        _check(_lib.rt_server_wait(self.srv, ctypes.c_uint64(ticket), ctypes.byref(r)), allow=(RT_ECAP, RT_ECANCELLED))
         return self._take(ticket, r)
+
+    def cancel(self, ticket):
+        """Withdraw a request still waiting for admission (True; it then completes
+        with status RT_ECANCELLED); False when it was already admitted."""
+        st = _check(_lib.rt_server_cancel(self.srv, ctypes.c_uint64(ticket)), allow=(RT_EBUSY,))
+        return st == RT_OK
 
     def stats(self):
         """Executor counters since creation: iterations, request_steps, completed,

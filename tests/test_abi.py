@@ -55,6 +55,9 @@ def test_argument_errors_are_synchronous():
     assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
     o.prec, o.block = rtucker.PREC["f32"], 0
     assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
+    o.block, o.max_queued = 8, -1
+    assert lib.rt_server_create(ctypes.byref(srv), 0, ctypes.byref(o)) == rtucker.RT_EINVAL
+    assert lib.rt_server_cancel(None, 1) == rtucker.RT_EINVAL
     assert lib.rt_server_submit(None, None, 0, None) == rtucker.RT_EINVAL
     assert lib.rt_server_get_stats(None, None) == rtucker.RT_EINVAL
     th = rtucker.rt_tucker_host()
@@ -84,8 +87,9 @@ int main(void) {
          offsetof(rt_opts, power_iters));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_tucker), offsetof(rt_tucker, core), offsetof(rt_tucker, factors),
          offsetof(rt_tucker, norm_x), offsetof(rt_tucker, flags));
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_server_opts), offsetof(rt_server_opts, hbm_budget),
-         offsetof(rt_server_opts, prec), offsetof(rt_server_opts, eps), offsetof(rt_server_opts, block));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_server_opts), offsetof(rt_server_opts, hbm_budget),
+         offsetof(rt_server_opts, prec), offsetof(rt_server_opts, eps), offsetof(rt_server_opts, block),
+         offsetof(rt_server_opts, max_queued));
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_result), offsetof(rt_result, ranks), offsetof(rt_result, core),
          offsetof(rt_result, factors), offsetof(rt_result, flags), offsetof(rt_result, latency_s));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_coo), offsetof(rt_coo, nnz), offsetof(rt_coo, dtype),
@@ -94,6 +98,8 @@ int main(void) {
          offsetof(rt_server_stats, overlap_s));
   printf("%zu %zu %zu %zu\\n", sizeof(rt_tucker_host), offsetof(rt_tucker_host, ranks),
          offsetof(rt_tucker_host, core), offsetof(rt_tucker_host, factors));
+  printf("%d %d %d %d %d %d %d %d\\n", RT_OK, RT_EINVAL, RT_ENOMEM, RT_ENONFINITE, RT_ECAP, RT_EHIP, RT_EBUSY,
+         RT_ECANCELLED);
   return 0;
 }
 """)
@@ -108,7 +114,7 @@ int main(void) {
                                                  K.norm_x.offset, K.flags.offset]
     S, R = rtucker.rt_server_opts, rtucker.rt_result
     assert [int(v) for v in lines[3].split()] == [ctypes.sizeof(S), S.hbm_budget.offset, S.prec.offset,
-                                                 S.eps.offset, S.block.offset]
+                                                 S.eps.offset, S.block.offset, S.max_queued.offset]
     assert [int(v) for v in lines[4].split()] == [ctypes.sizeof(R), R.ranks.offset, R.core.offset,
                                                  R.factors.offset, R.flags.offset, R.latency_s.offset]
     C, ST = rtucker.rt_coo, rtucker.rt_server_stats
@@ -118,3 +124,6 @@ int main(void) {
     H = rtucker.rt_tucker_host
     assert [int(v) for v in lines[7].split()] == [ctypes.sizeof(H), H.ranks.offset, H.core.offset,
                                                  H.factors.offset]
+    assert [int(v) for v in lines[8].split()] == [rtucker.RT_OK, rtucker.RT_EINVAL, rtucker.RT_ENOMEM,
+                                                 rtucker.RT_ENONFINITE, rtucker.RT_ECAP, rtucker.RT_EHIP,
+                                                 rtucker.RT_EBUSY, rtucker.RT_ECANCELLED]

@@ -13,6 +13,7 @@ requests (Alg. 5, §4) of uneven shapes and ranks.
   level of tau^2); bfloat16 sketch - the same ranks, X_hat within 1e-4 ||X||,
   direct error <= eps.
 """
+import ctypes
 from types import SimpleNamespace
 
 import numpy as np
@@ -263,4 +264,50 @@ def test_served_rank_above_64(mode):
             assert _rel_err(r, X) <= 1e-3
     finally:
         ctx.close()
+        srv.close()
+
+
+@pytest.mark.parametrize("mode", ["grouped", "slots"])
+def test_queue_bound_and_cancel(reqs, mode):
+    # back-pressure and withdrawal: one request in flight (a 192^3 tensor, which
+    # takes milliseconds) and at most two waiting; a burst of six more
+    # submissions sees RT_EBUSY for those beyond the queue (nothing queued for
+    # them); a waiting request withdrawn by cancel completes with RT_ECANCELLED,
+    # and every accepted one still completes within eps
+    need_gpu()
+    rng = np.random.default_rng(5)
+    big = torch.from_numpy(inputs.odeco(rng, (192, 192, 192), 0.7).astype(np.float32)).pin_memory()
+    srv = rtucker.Server(max_inflight=1, eps=1e-3, block=8, mode=mode, max_queued=2)
+    lib = rtucker._lib
+    try:
+        t0 = srv.submit(big, 1)
+        accepted, busy = [], 0
+        for X, s in reqs[:6]:
+            try:
+                accepted.append((srv.submit(X, s), X))
+            except rtucker.RtError as e:
+                assert e.status == rtucker.RT_EBUSY
+                busy += 1
+        assert busy >= 3 and 1 <= len(accepted) <= 2
+        tc, _ = accepted.pop()
+        assert srv.cancel(tc)
+        rc = srv.wait(tc)
+        assert rc.status == rtucker.RT_ECANCELLED and rc.core is None
+        with pytest.raises(rtucker.RtError):
+            srv.cancel(tc)                  # released by wait()
+        # a completed request is not withdrawn
+        r = rtucker.rt_result()
+        assert lib.rt_server_wait(srv.srv, t0, ctypes.byref(r)) == rtucker.RT_OK
+        assert lib.rt_server_cancel(srv.srv, t0) == rtucker.RT_EBUSY
+        assert lib.rt_server_release(srv.srv, t0) == rtucker.RT_OK
+        srv._keep.pop(t0, None)
+        for t, X in accepted:
+            ra = srv.wait(t)
+            assert ra.status == rtucker.RT_OK
+            assert _rel_err(ra, X) <= 1e-3
+        # the queue has drained: submissions are accepted again
+        X, s = reqs[0]
+        ra = srv.wait(srv.submit(X, s))
+        assert ra.status == rtucker.RT_OK and _rel_err(ra, X) <= 1e-3
+    finally:
         srv.close()
