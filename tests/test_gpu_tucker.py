@@ -245,6 +245,31 @@ def test_adaptive_parity(ctx, dtype, b):
                     2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
 
 
+# the smallest and the largest order the interface takes: d = 2, where both
+# algorithms reduce to the randomized SVD of the matrix (Alg. 1), and d = 8
+# (RT_MAXD), every mode short, with r + p = I_j in two of them
+ORDER_EXTREMES = [((120, 90), (7, 5)), ((5, 4, 6, 3, 5, 4, 3, 6), (2, 3, 2, 2, 3, 2, 2, 3))]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dims,ranks", ORDER_EXTREMES)
+def test_order_extremes(ctx, dtype, dims, ranks):
+    rng = np.random.default_rng(len(dims))
+    X = inputs.lowrank_tensor(rng, dims, ranks, noise=1e-6)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    Xd = torch.from_numpy(Xs).cuda()
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    for alg in ("rsthosvd", "rhosvd"):
+        g = getattr(ctx, alg)(Xd, list(ranks), 1, seed=2)
+        o = getattr(oracle, alg)(Xf, list(ranks), 1, seed=2)
+        _check(g, o, Xf, tol)
+    for b in (1, 2):
+        g = ctx.rsthosvd_adaptive(Xd, 1e-3, b, seed=4)
+        o = oracle.adaptive_rsthosvd(Xf, 1e-3, b, seed=4, delta=1e-10 if dtype == torch.float64 else 1e-5)
+        _adaptive_check(g, o, Xf, 1e-3, tol, 2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_adaptive_five_way_odeco(ctx, dtype):
     # 24^5 orthogonally decomposable tensor, mode spectra 0.7^k: every later mode
