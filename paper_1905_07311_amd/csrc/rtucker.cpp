@@ -654,9 +654,10 @@ rt_status truncate_wide(Call& k, Dt dt, const void* B, Shape3 sb, int64_t ldb, c
     double tail = 0.0;
     int kk = kb;
     const double e0 = std::max(E, 0.0);
-    for (int t = kb - 1; t >= 0; --t) {                  // tail = sum_{t' >= t} lambda_t'
-        if (e0 + tail + lh[t] > tau2) break;
-        tail += lh[t];
+    for (int t = kb - 1; t >= 0; --t) {                  // tail = sum_{t' >= t} max(lambda_t', 0)
+        const double lt = std::max(lh[t], 0.0);          // a Gram's eigenvalue is >= 0 up to rounding
+        if (e0 + tail + lt > tau2) break;
+        tail += lt;
         kk = t;
     }
     if (e0 > tau2) kk = kb;                              // a capped mode keeps every column
