@@ -297,7 +297,7 @@ def cpu_baseline(name, X_host, ctx=None):
                 seconds_per_call=dt, one_core={"value": flops / dt1 / 1e12, "seconds_per_call": dt1, "calls": n1})
 
 
-def serving_measure(with_cpu=False):
+def serving_measure(with_cpu=False, slots=True):
     """The serving half of the metric: the continuous-batching server on 1024
     adaptive requests against the plain per-tensor float32 path, closed loop
     (all requests queued at once) and open loop (Poisson arrivals at 400/s),
@@ -376,7 +376,8 @@ def serving_measure(with_cpu=False):
     srv.close()
     # per-slot pipelines (whole requests on per-slot streams), float32 and the other sketch precision
     t_slots = {}
-    for prec in (w["prec"], w["alt_prec"]):
+    srv2_err = None
+    for prec in ((w["prec"], w["alt_prec"]) if slots else ()):
         srv2 = rtucker.Server(max_inflight=w["slots"], eps=w["eps"], block=w["block"], prec=prec, mode="slots")
         for t in [srv2.submit(X, s) for X, s in warm]:
             srv2.wait(t)
@@ -397,8 +398,9 @@ def serving_measure(with_cpu=False):
         "server": "grouped: %d requests in flight advanced by shared launches (one graph replay and one wait "
                   "per iteration), float32 sketches" % w["group_inflight"],
         "plain_f32_tensors_per_s": round(w["nreq"] / t_plain, 2),
-        "served_slots_f32_tensors_per_s": round(w["nreq"] / t_slots[w["prec"]], 2),
-        "served_slots_%s_sketch_tensors_per_s" % w["alt_prec"]: round(w["nreq"] / t_slots[w["alt_prec"]], 2),
+        "served_slots_f32_tensors_per_s": round(w["nreq"] / t_slots[w["prec"]], 2) if slots else None,
+        "served_slots_%s_sketch_tensors_per_s" % w["alt_prec"]:
+            round(w["nreq"] / t_slots[w["alt_prec"]], 2) if slots else None,
         "speedup_vs_plain": round(t_plain / t_srv, 3),
         "closed_loop_s": round(t_srv, 4),
         "request_status_counts": statuses,
@@ -489,7 +491,7 @@ def sparse_measure(calls=10):
 def run_serving(args):
     """Workload c5: the continuous-batching server against the plain per-tensor path."""
     w = WORKLOADS["c5"]
-    sv = serving_measure(with_cpu=not args.no_cpu)
+    sv = serving_measure(with_cpu=not args.no_cpu, slots=not args.grouped_only)
     out = {
         "metric": METRIC, "value": sv["served_tensors_per_s"], "unit": "tensors/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": round(sv["closed_loop_s"] * 1e3, 2), "higher_is_better": True,
@@ -518,6 +520,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave the serving measurement out of the default workload's line")
+    ap.add_argument("--grouped-only", action="store_true",
+                    help="c5: measure the plain path and the grouped server only (no per-slot servers)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for the HBM counter passes)")
     args = ap.parse_args()
