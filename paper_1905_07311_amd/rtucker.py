@@ -324,6 +324,8 @@ class Context:
             raise ValueError("tensor must be float32 or float64")
         if not X.is_contiguous():
             raise ValueError("tensor must be contiguous (row-major)")
+        if X.dim() > RT_MAXD:
+            raise ValueError(f"tensor order must be at most {RT_MAXD}")
         t = rt_tensor()
         t.ndim = X.dim()
         for i, s in enumerate(X.shape):
@@ -649,6 +651,8 @@ class Server:
         import torch
         if X.device.type != "cpu" or X.dtype != torch.float32 or not X.is_contiguous():
             raise ValueError("X must be a contiguous float32 CPU tensor")
+        if X.dim() > RT_MAXD:
+            raise ValueError(f"tensor order must be at most {RT_MAXD}")
         t = rt_tensor()
         t.ndim = X.dim()
         for i, s in enumerate(X.shape):

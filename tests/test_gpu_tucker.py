@@ -3,6 +3,7 @@ oracle (same seeded inputs, same Omega stream), through the C ABI.  Primary
 metric: ||X_hat_gpu - X_hat_oracle|| / ||X|| (1e-10 in FP64, 1e-5 in FP32);
 also projector distances on well-separated modes, core norms and factor
 orthonormality."""
+import ctypes
 import os
 
 import numpy as np
@@ -403,3 +404,43 @@ def test_sp_sthosvd_parity(ctx, dtype, dims, core, ranks, p):
     nx = np.linalg.norm(X)
     assert np.linalg.norm(to_np(ctx.reconstruct(g)) - o.reconstruct()) / nx < (1e-10 if dtype == torch.float64 else 1e-4)
     assert g.rel_err_est == -1.0
+
+
+def test_argument_errors(ctx):
+    # every argument error is reported synchronously as RT_EINVAL: orders 1 and
+    # 9 (the interface takes 2 .. RT_MAXD), an empty mode, rank 0 in a
+    # fixed-rank call, negative oversampling, r + p above min(I_j, prod of the
+    # others), a negative tolerance, block sizes outside 1 .. RT_LMAX and
+    # per-mode tolerances whose squares do not sum to eps^2
+    lib = rtucker._lib
+    X = torch.rand((12, 10, 8), dtype=torch.float64, device="cuda")
+
+    def einval(fn, *a, **kw):
+        with pytest.raises(rtucker.RtError) as ei:
+            fn(*a, **kw)
+        assert ei.value.status == rtucker.RT_EINVAL
+
+    einval(ctx.rsthosvd, torch.rand(10, dtype=torch.float64, device="cuda"), [2], 1, seed=0)
+    t = rtucker.rt_tensor()
+    t.ndim, t.dtype, t.data = 9, rtucker.RT_F64, X.data_ptr()
+    for i in range(rtucker.RT_MAXD):
+        t.dims[i] = 2
+    o = ctx._opts(X, 1, 0, None, None)
+    out = rtucker.rt_tucker()
+    ranks = (ctypes.c_int32 * 9)(*([1] * 9))
+    assert lib.rt_rsthosvd(ctx.ctx, ctypes.byref(t), ranks, ctypes.byref(o), ctypes.byref(out)) == rtucker.RT_EINVAL
+    with pytest.raises(ValueError):
+        ctx.rsthosvd(torch.zeros((2,) * 9, dtype=torch.float64, device="cuda"), [1] * 9, 0, seed=0)
+    einval(ctx.rsthosvd, torch.zeros((0, 4, 4), dtype=torch.float64, device="cuda"), [1, 1, 1], 0, seed=0)
+    for alg in (ctx.rsthosvd, ctx.rhosvd):
+        einval(alg, X, [0, 2, 2], 1, seed=0)
+        einval(alg, X, [2, 2, 2], -1, seed=0)
+        einval(alg, X, [2, 2, 7], 2, seed=0)             # r + p = 9 > I_3 = 8
+    einval(ctx.rsthosvd_adaptive, X, -1e-3, 4, seed=0)
+    einval(ctx.rsthosvd_adaptive, X, 1e-3, 0, seed=0)
+    einval(ctx.rsthosvd_adaptive, X, 1e-3, rtucker.RT_LMAX + 1, seed=0)
+    einval(ctx.rsthosvd_adaptive, X, 1e-3, 4, seed=0, eps_per_mode=[1e-3, 1e-3, 1e-3])
+    # the context still works afterwards
+    g = ctx.rsthosvd(X, [2, 2, 2], 1, seed=0)
+    ctx.sync()
+    assert g.ranks == [2, 2, 2]
