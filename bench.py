@@ -526,8 +526,8 @@ def main():
                     help="also run a plain 512 MiB device copy (reference for the HBM counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the multi-GPU layout is design-only "
-                                   "(see the sharding note in DESIGN.md); use --gpus 1"}))
+        print(json.dumps({"error": "this library runs on one GPU only; its multi-GPU layout is a design, "
+                                   "not code: use --gpus 1"}))
         sys.exit(2)
     if args.workload == "c5":
         run_serving(args)

@@ -3,7 +3,7 @@
 The paper only names its adaptive range finder, Q = AdaptRangeFinder(X, eps, b)
 (§4): it grows Q by b Gaussian columns at a time until
 ||X - Q Q^T X|| <= eps ||X|| (eq. tolerance), following the blocked scheme of
-Martinsson and Voronin refined by Yu, Gu and Li.  This build's reading,
+Martinsson and Voronin refined by Yu, Gu and Li.  The reading taken here,
 written from those descriptions:
 
   E = ||M||_F^2 (float64); Q = [], B = [], block i = 0

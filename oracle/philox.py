@@ -3,7 +3,7 @@
 The paper draws every Omega with i.i.d. N(0,1) entries (Alg. 1 input, §2.4;
 Alg. 2 and Alg. 3, §3.1) and notes that Omega never has to be stored: its
 entries can be produced on the fly, column-wise or in blocks (§3.1, remark
-after Alg. 2).  It fixes no generator.  This build fixes one so that the HIP
+after Alg. 2).  It fixes no generator.  One is fixed here so that the HIP
 path and this oracle see the same Omega:
 
 * Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and

@@ -1,7 +1,7 @@
 """Tensor primitives of §2.1 (oracle side).
 
 * unfolding X_(n): the mode-n fibres become the columns.  The paper leaves the
-  column order open; this build orders the columns row-major over the
+  column order open; here the columns are ordered row-major over the
   remaining modes in increasing mode order (the storage order of a row-major
   array), which is the order the Omega counter map indexes.
 * mode product X x_n A (A of size K x I_n): Y_(n) = A X_(n)  (§2.1, the
