@@ -127,12 +127,12 @@ def make_input(name, device):
     if name in ("c2", "c2h", "c2q1", "c2sp", "c2w"):
         return inputs.hilbert0_device(w["dims"], device, torch.float32)
     if name == "c1":
-        return torch.from_numpy(inputs.config1()).to(device)
+        return torch.from_numpy(inputs.lowrank_64cube()).to(device)
     if name == "c3":
-        return inputs.lowrank_device(inputs.config_seed(3), w["dims"], w["ranks"], device, torch.float32,
+        return inputs.lowrank_device(inputs.data_seed(3), w["dims"], w["ranks"], device, torch.float32,
                                      noise=1e-6, core_base=0.8)
     if name in ("c4", "c4h"):
-        return inputs.odeco_device(inputs.config_seed(4), w["dims"], 0.7, device, torch.float32)
+        return inputs.odeco_device(inputs.data_seed(4), w["dims"], 0.7, device, torch.float32)
     raise ValueError(name)
 
 
@@ -261,7 +261,7 @@ def cpu_baseline(name, X_host, ctx=None):
         import torch
         from paper_1905_07311_amd import inputs
         dims = (24,) * len(w["dims"])
-        Xs = inputs.odeco_device(inputs.config_seed(4), dims, 0.7, torch.device("cuda", 0), torch.float32)
+        Xs = inputs.odeco_device(inputs.data_seed(4), dims, 0.7, torch.device("cuda", 0), torch.float32)
         ctx.timing(True)
         if w["algo"] == "adaptive_hosvd":
             ctx.rhosvd_adaptive(Xs, w["eps"], w["block"], w["seed"], prec=w["prec"])
@@ -313,7 +313,7 @@ def serving_measure(with_cpu=False, slots=True):
     # host memory before the clock starts), each with its own Omega seed
     pool = []
     for i in range(min(w["pool"], w["nreq"])):
-        Xd = inputs.lowrank_device(inputs.config_seed(5) * 1000 + i, tuple(sides[i]), tuple(ranks[i]), dev,
+        Xd = inputs.lowrank_device(inputs.data_seed(5) * 1000 + i, tuple(sides[i]), tuple(ranks[i]), dev,
                                    torch.float32, noise=1e-6)
         pool.append(Xd.cpu().pin_memory())
     torch.cuda.synchronize()

@@ -79,26 +79,26 @@ def odeco(rng, dims, decay, nterms=None):
     return tucker_product(core, U)
 
 
-def config1():
+def lowrank_64cube():
     """64^3 FP64: Gaussian 8^3 core times Haar 64 x 8 factors plus 1e-8 N(0,1);
     target rank (8, 8, 8), p = 5, Omega seed 0."""
     rng = np.random.default_rng(DATA_SEED_BASE + 1)
     return lowrank_tensor(rng, (64, 64, 64), (8, 8, 8), noise=1e-8)
 
 
-def config2(n=512, dtype=np.float32):
+def hilbert_cube(n=512, dtype=np.float32):
     """n^3 tensor 1/(i+j+k+1), 0-based, computed in float64, stored as dtype."""
     return hilbert0((n, n, n)).astype(dtype)
 
 
-def config3(n=128, r=30, dtype=np.float32):
+def graded_lowrank_4way(n=128, r=30, dtype=np.float32):
     """n^4: Gaussian r^4 core graded by 0.8^(i+j+k+l), Haar factors, + 1e-6 N(0,1)."""
     rng = np.random.default_rng(DATA_SEED_BASE + 3)
     X = lowrank_tensor(rng, (n,) * 4, (r,) * 4, noise=1e-6, core_scale=graded_scale((r,) * 4, 0.8))
     return X.astype(dtype)
 
 
-def config4(n=48, d=5, dtype=np.float32):
+def odeco_cube(n=48, d=5, dtype=np.float32):
     """n^d orthogonally decomposable tensor with mode spectra 0.7^k."""
     rng = np.random.default_rng(DATA_SEED_BASE + 4)
     return odeco(rng, (n,) * d, 0.7).astype(dtype)
@@ -265,7 +265,8 @@ def sparse_counts_device(seed, dims, nnz, device, dtype):
     return idx, vals.to(dtype), tuple(int(n) for n in dims)
 
 
-def config_seed(k):
+def data_seed(k):
+    """Seed of synthetic data family k (one per workload recipe)."""
     return DATA_SEED_BASE + k
 
 

@@ -160,7 +160,7 @@ def test_adaptive_36pow5_against_oracle(ctx):
     LDS-staged sketch, short-mode projection and block-step kernels as 48^5),
     against the FP64 oracle on the same float32 values."""
     w = bench.WORKLOADS["c4"]
-    X = inputs.odeco_device(inputs.config_seed(4), (36,) * 5, 0.7, torch.device("cuda", 0), torch.float32)
+    X = inputs.odeco_device(inputs.data_seed(4), (36,) * 5, 0.7, torch.device("cuda", 0), torch.float32)
     g = bench.run_step(ctx, "c4", X)
     torch.cuda.synchronize()
     _check_adaptive_closed_form(ctx, g, X, w["eps"])

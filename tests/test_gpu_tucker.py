@@ -38,8 +38,8 @@ def _check(res_g, res_o, X, tol, check_proj=True):
     assert abs(res_g.core_norm - np.sqrt(oracle.fro2(res_o.core))) <= tol * nx
 
 
-def test_config1_rsthosvd_f64(ctx):
-    X = inputs.config1()
+def test_lowrank_64cube_rsthosvd_f64(ctx):
+    X = inputs.lowrank_64cube()
     Xd = torch.from_numpy(X).cuda()
     g = ctx.rsthosvd(Xd, [8, 8, 8], 5, seed=0, order=[0, 1, 2])
     o = oracle.rsthosvd(X, [8, 8, 8], 5, seed=0, order=[0, 1, 2])
