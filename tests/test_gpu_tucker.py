@@ -444,3 +444,82 @@ def test_argument_errors(ctx):
     g = ctx.rsthosvd(X, [2, 2, 2], 1, seed=0)
     ctx.sync()
     assert g.ranks == [2, 2, 2]
+
+
+def _random_case(seed):
+    # a seeded random problem: order 2-4, sides 5-90 (ragged against every tile
+    # size), ranks and oversampling inside the interface's limits, a random mode
+    # order, float32 or float64; low-rank signal of the requested ranks + 1e-3 noise
+    rng = np.random.default_rng(900 + seed)
+    d = int(rng.integers(2, 5))
+    dims = [int(v) for v in rng.integers(5, 91 if d < 4 else 31, size=d)]
+    total = int(np.prod(dims))
+    p = int(rng.integers(2, 6))
+    ranks = []
+    for j in range(d):
+        lim = min(dims[j], total // dims[j], 64) - p
+        ranks.append(int(rng.integers(1, max(lim, 1) + 1)) if lim >= 1 else None)
+    if all(r is None for r in ranks):
+        ranks[int(np.argmax(dims))] = 1
+        p = 0
+    order = [int(v) for v in rng.permutation(d)]
+    # R-STHOSVD sketches the current core: keep r_j + p within its column count
+    cur = list(dims)
+    for j in order:
+        if ranks[j] is None:
+            continue
+        kcur = int(np.prod(cur)) // cur[j]
+        ranks[j] = max(1, min(ranks[j], kcur - p)) if kcur - p >= 1 else None
+        if ranks[j] is not None:
+            cur[j] = ranks[j]
+    if all(r is None for r in ranks):
+        ranks[order[0]] = 1
+        p = 0
+    if d == 2 and None not in ranks:
+        ranks = [min(ranks)] * 2            # a matrix has one rank
+    # the signal's ranks are the requested ones, so every truncation falls on
+    # the signal/noise gap (a truncation inside the noise spectrum is decided
+    # by rounding in float32: see the float32 bar's scope)
+    true = [r if r is not None else dims[j] for j, r in enumerate(ranks)]
+    X = inputs.lowrank_tensor(rng, tuple(dims), tuple(true), noise=1e-3)
+    dtype = torch.float64 if seed % 2 == 0 else torch.float32
+    return X, ranks, p, order, dtype
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_shapes_parity(ctx, seed):
+    X, ranks, p, order, dtype = _random_case(seed)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    Xd = torch.from_numpy(Xs).cuda()
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    g = ctx.rsthosvd(Xd, ranks, p, seed=seed, order=order)
+    o = oracle.rsthosvd(Xf, ranks, p, seed=seed, order=order)
+    _check(g, o, Xf, tol)
+    g = ctx.rhosvd(Xd, ranks, p, seed=seed)
+    o = oracle.rhosvd(Xf, ranks, p, seed=seed)
+    _check(g, o, Xf, tol)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sthosvd_width_above_current_columns(ctx, dtype):
+    # r_j + p within min(I_j, prod of the other I_i) of X, but above the column
+    # count of the core R-STHOSVD has reached: 5 x 48 x 8, ranks (5, 34, 2),
+    # p = 0, modes in the order 2, 1, 0, so mode 1 sees 5 x 48 x 2 (10
+    # columns) with a sketch of 34.  The oracle's SVD of B keeps min(r, K) = 10
+    # directions; the library keeps the requested 34 columns, the extra ones
+    # orthonormal with zero weight.  X_hat is the same.
+    rng = np.random.default_rng(31)
+    X = inputs.lowrank_tensor(rng, (5, 48, 8), (3, 6, 2), noise=1e-3)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    g = ctx.rsthosvd(torch.from_numpy(Xs).cuda(), [5, 34, 2], 0, seed=3, order=[2, 1, 0])
+    o = oracle.rsthosvd(Xf, [5, 34, 2], 0, seed=3, order=[2, 1, 0])
+    assert o.ranks == [5, 10, 2] and g.ranks == [5, 34, 2]
+    nx = np.linalg.norm(Xf)
+    assert np.linalg.norm(xhat(g) - o.reconstruct()) / nx < tol
+    A = to_np(g.factors[1])
+    assert np.allclose(A.T @ A, np.eye(34), atol=max(tol, 1e-12) * 10)
+    G = to_np(g.core)
+    assert np.linalg.norm(G[:, 10:, :]) <= tol * nx
