@@ -523,3 +523,35 @@ def test_sthosvd_width_above_current_columns(ctx, dtype):
     assert np.allclose(A.T @ A, np.eye(34), atol=max(tol, 1e-12) * 10)
     G = to_np(g.core)
     assert np.linalg.norm(G[:, 10:, :]) <= tol * nx
+
+
+def _random_adaptive_case(seed):
+    # a seeded random adaptive problem: order 3-4, sides 12-80, a graded signal
+    # of ranks at most half of each side (core scaled by 0.6^(i_1+...+i_d), so
+    # the spectra decay through the tolerance) plus 1e-6 noise, block 1-16,
+    # tolerance 1e-1 .. 1e-3
+    rng = np.random.default_rng(700 + seed)
+    d = int(rng.integers(3, 5))
+    dims = [int(v) for v in rng.integers(12, 81 if d < 4 else 25, size=d)]
+    true = [int(rng.integers(2, min(n // 2, 14) + 1)) for n in dims]
+    X = inputs.lowrank_tensor(rng, tuple(dims), tuple(true), noise=1e-6,
+                              core_scale=inputs.graded_scale(tuple(true), 0.6))
+    b = int(rng.choice([1, 2, 4, 8, 16]))
+    eps = float(10.0 ** -rng.integers(1, 4))
+    dtype = torch.float64 if seed % 2 == 0 else torch.float32
+    return X, b, eps, dtype
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_shapes_adaptive_parity(ctx, seed):
+    X, b, eps, dtype = _random_adaptive_case(seed)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    Xd = torch.from_numpy(Xs).cuda()
+    f64 = dtype == torch.float64
+    g = ctx.rsthosvd_adaptive(Xd, eps, b, seed=seed)
+    o = oracle.adaptive_rsthosvd(Xf, eps, b, seed=seed, delta=1e-10 if f64 else 1e-5)
+    _adaptive_check(g, o, Xf, eps, 1e-10 if f64 else 1e-5, 2.0 ** -53 if f64 else 2.0 ** -24)
+    g = ctx.rhosvd_adaptive(Xd, eps, b, seed=seed)
+    o = oracle.adaptive_rhosvd(Xf, eps, b, seed=seed, delta=1e-10 if f64 else 1e-5)
+    _adaptive_check(g, o, Xf, eps, 1e-10 if f64 else 1e-5, 2.0 ** -53 if f64 else 2.0 ** -24)
