@@ -315,3 +315,35 @@ def test_tuned_plans_compute_the_same_sketch():
     finally:
         rtucker.set_tuning(entries)
         ctx.close()
+
+
+def _random_step_shape(seed):
+    # seeded ragged shapes: order 2-4, sides 1-150 (product at most ~3e5), every
+    # mode, sketch widths and offsets drawn per mode
+    rng = np.random.default_rng(5000 + seed)
+    d = int(rng.integers(2, 5))
+    hi = {2: 400, 3: 70, 4: 24}[d]
+    shape = tuple(int(v) for v in rng.integers(1, hi + 1, size=d))
+    return rng, shape
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_step_shapes(ctx, seed):
+    rng, shape = _random_step_shape(seed)
+    for dtype in (torch.float64, torch.float32):
+        Xh = rng.standard_normal(shape).astype(np.float64 if dtype == torch.float64 else np.float32)
+        X = torch.from_numpy(Xh).cuda()
+        tol = 1e-13 if dtype == torch.float64 else 2e-6
+        for n in range(len(shape)):
+            M = oracle.unfold(Xh.astype(np.float64), n)
+            ell = int(rng.integers(1, min(64, shape[n]) + 1))
+            col0 = int(rng.integers(0, 1000))
+            Y = ctx.sketch(X, n, ell, seed=seed, col0=col0)
+            ref = M @ oracle.omega(seed, n, M.shape[1], range(col0, col0 + ell))
+            assert rel(to_np(Y), ref) < tol, (shape, n, ell, col0)
+            k = int(rng.integers(1, min(64, shape[n]) + 1))
+            Qh, _ = np.linalg.qr(rng.standard_normal((shape[n], k)))
+            Qh = Qh.astype(Xh.dtype)
+            B = ctx.project(X, n, torch.from_numpy(Qh).cuda())
+            refB = oracle.ttm(Xh.astype(np.float64), Qh.astype(np.float64).T, n)
+            assert rel(to_np(B), refB) < tol, (shape, n, k)
