@@ -35,6 +35,7 @@ struct SketchPlan {
     int rw;                // MFMA variant: row blocks per workgroup (1 or 2)
     int nq;                // MFMA variant: compiled column quads (ell <= 4 nq); kind 3: 16-column blocks
     int ldp;               // row length of a partial (ell, or 4 nq for the MFMA kernel)
+    int kc = 32;           // kinds 3 and 4: unfolding columns per tile (32 or 64)
 };
 // split3: allow the float32 kernel built on bfloat16 pieces (kind 3; not for explicit Omega)
 SketchPlan plan_sketch(Dt dt, int prec, Shape3 s, int ell, int64_t col0, const void* X, bool split3 = true);

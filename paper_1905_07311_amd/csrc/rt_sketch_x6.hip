@@ -21,9 +21,12 @@
 // bound by its memory traffic rather than by the matrix cores.
 //
 // Layout.  A wave owns RM blocks of 16 rows; a workgroup (eight waves) shares
-// the Omega tile.  For an MFMA, lane l = 16 g + i supplies row i of X at the
-// eight unfolding columns 8 g .. 8 g + 7 of the 32-column tile (two 16-byte
-// loads straight into registers; R % 8 == 0 keeps them in one l-slab) and,
+// the Omega tile of KC = 32 or 64 unfolding columns (one or two MFMA steps of
+// 32; the 64-column tile gives each row a 256-byte run per step, which reads
+// faster when a workgroup holds 128 rows).  In MFMA step j, lane l = 16 g + i
+// supplies row i of X at the eight unfolding columns (KC / 4) g + 8 j .. + 7
+// (two 16-byte loads straight into registers; R % 8 == 0 keeps them in one
+// l-slab) and,
 // as the B operand, Omega at the same eight columns for sketch column i of a
 // 16-column block; the accumulator of lane l holds Y[4 g + v][i], v = 0..3.
 // Omega is generated once per tile per workgroup (Philox4x32-10 + Box-Muller,
@@ -45,7 +48,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
-constexpr int X6_KC = 32;     // unfolding columns per tile
+constexpr int X6_KC = 32;     // unfolding columns per MFMA step (one 16x16x32 K block)
 constexpr int X6_WPG = 8;     // waves per workgroup
 
 __device__ __forceinline__ f4 mfma_bf16(u4 a, u4 b, f4 c) {
@@ -70,7 +73,7 @@ __device__ __forceinline__ uint32_t pack2(uint32_t a, uint32_t b) { return (a >>
 
 // NP = 3: the float32 products from three pieces per operand, six MFMAs per
 // block; NP = 2: the bfloat16 sketch from two pieces, three MFMAs per block.
-template <int NB, int RM, int NP>
+template <int NB, int RM, int NP, int KC>
 __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __restrict__ X, int64_t L, int64_t J, int64_t R,
                                                         int ell, int64_t col0, uint64_t seed, uint32_t mode,
                                                         int64_t tiles_per_split, float* __restrict__ partial,
@@ -79,13 +82,14 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     constexpr int MT = 16 * RM * X6_WPG;              // rows per workgroup
     // words per bfloat16 plane: row n (16 k pairs) at n * 16 + (n / 2) * 4, the
     // padding keeps the generation's stores and the 16-byte reads apart in the banks
-    constexpr int PL = NB * 16 * (X6_KC / 2) + NB * 8 * 4;
+    constexpr int NG = KC / X6_KC;                    // MFMA steps (8-column groups per lane) per tile
+    constexpr int PL = NB * 16 * (KC / 2) + NB * 8 * 4;
     __shared__ __align__(16) uint32_t om[2][NP * PL];
     __shared__ double red[X6_WPG];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, i16 = lane & 15;
     const int64_t K = L * R;
-    const int64_t ntiles = (K + X6_KC - 1) / X6_KC;
+    const int64_t ntiles = (K + KC - 1) / KC;
     const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_split;
     const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
     const int64_t wrow0 = (int64_t)blockIdx.y * MT + wave * 16 * RM;
@@ -105,33 +109,41 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     // (l, r) of this lane group's first column 8 g of the next tile to load
     int64_t cl = 0, cr = 0;
     {
-        const int64_t c = t_begin * X6_KC + 8 * g;
+        const int64_t c = t_begin * KC + (KC / 4) * g;
         cl = c / R;
         cr = c - cl * R;
     }
-    auto load = [&](int64_t tile, f4 (&v)[RM][2]) {
-        const uint32_t base = (tile < t_end && cl < L) ? (uint32_t)((cl * J * R + cr) * 4) : 0x7ffffff0u;
+    // a lane's NG groups of eight columns, (KC / 4) g + 8 j, each inside one l-slab
+    auto load = [&](int64_t tile, f4 (&v)[RM][2 * NG]) {
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm) {
-            v[rm][0] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, rowbyte[rm] + base, 0, 0));
-            v[rm][1] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, rowbyte[rm] + base + 16, 0, 0));
+        for (int j = 0; j < NG; ++j) {
+            const bool wrap = cr + 8 * j >= R;
+            const int64_t clj = wrap ? cl + 1 : cl, crj = wrap ? cr + 8 * j - R : cr + 8 * j;
+            const uint32_t base = (tile < t_end && clj < L) ? (uint32_t)((clj * J * R + crj) * 4) : 0x7ffffff0u;
+#pragma unroll
+            for (int rm = 0; rm < RM; ++rm) {
+                v[rm][2 * j] =
+                    __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, rowbyte[rm] + base, 0, 0));
+                v[rm][2 * j + 1] =
+                    __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, rowbyte[rm] + base + 16, 0, 0));
+            }
         }
-        cr += X6_KC;
+        cr += KC;
         while (cr >= R) { cr -= R; ++cl; }
     };
     // Omega of a tile: item (k pair kp, quad q) = columns 2 kp, 2 kp + 1 of sketch
     // columns 4 q .. 4 q + 3, each value split into the three planes
     auto gen = [&](int64_t tile, int buf) {
-        for (int it = tid; it < 16 * nq4; it += NTH) {
-            const int kp = it & 15, q = it >> 4;
-            const uint64_t c = (uint64_t)(tile * X6_KC + 2 * kp);
+        for (int it = tid; it < (KC / 2) * nq4; it += NTH) {
+            const int kp = it % (KC / 2), q = it / (KC / 2);
+            const uint64_t c = (uint64_t)(tile * KC + 2 * kp);
             float za[4], zb[4];
             omega4_f32(seed, mode, c, (uint32_t)(qbase + q), za);
             omega4_f32(seed, mode, c + 1, (uint32_t)(qbase + q), zb);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int n = 4 * q + u;
-                const int w = n * 16 + (n >> 1) * 4 + kp;
+                const int w = n * (KC / 2) + (n >> 1) * 4 + kp;
                 if (NP == 2) {
                     uint32_t ha, ma, hb, mb;
                     split2(za[u], ha, ma);
@@ -157,12 +169,14 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
         for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = f4{0.f, 0.f, 0.f, 0.f};
     double nrm = 0.0;
 
-    auto compute = [&](const f4 (&v)[RM][2], int buf) {
+    auto compute = [&](const f4 (&vv)[RM][2 * NG], int buf) {
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
         u4 bh[NB], bm[NB], bl[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int n = nb * 16 + i16;
-            const int w = n * 16 + (n >> 1) * 4 + 4 * g;
+            const int w = n * (KC / 2) + (n >> 1) * 4 + (KC / 8) * g + 4 * j;
             bh[nb] = *reinterpret_cast<const u4*>(&om[buf][w]);
             if (NP >= 2) bm[nb] = *reinterpret_cast<const u4*>(&om[buf][PL + w]);
             if (NP == 3) bl[nb] = *reinterpret_cast<const u4*>(&om[buf][2 * PL + w]);
@@ -170,8 +184,8 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
         u4 ah[RM], am[RM], al[RM];
 #pragma unroll
         for (int rm = 0; rm < RM; ++rm) {
-            const float x[8] = {v[rm][0].x, v[rm][0].y, v[rm][0].z, v[rm][0].w,
-                                v[rm][1].x, v[rm][1].y, v[rm][1].z, v[rm][1].w};
+            const f4 v0 = vv[rm][2 * j], v1 = vv[rm][2 * j + 1];
+            const float x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
             if (NP == 2) {
                 uint32_t h[8], m[8];
 #pragma unroll
@@ -235,6 +249,7 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
         for (int rm = 0; rm < RM; ++rm)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[rm][nb] = mfma_bf16(ah[rm], bh[nb], acc[rm][nb]);
+      }
     };
 
     // X NSET - 1 tiles ahead in registers (NSET register sets in rotation),
@@ -242,7 +257,7 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     // hands the Omega buffers over.  Loads past t_end read nothing (their
     // offsets are out of range), so they are issued unconditionally.
     constexpr int NSET = 2;
-    f4 xs[NSET][RM][2];
+    f4 xs[NSET][RM][2 * NG];
 #pragma unroll
     for (int s = 0; s + 1 < NSET; ++s) load(t_begin + s, xs[s]);
     __syncthreads();                                   // the zeroed planes before any generation
@@ -288,21 +303,21 @@ __global__ __launch_bounds__(64 * X6_WPG) void sketch_x6_kernel(const float* __r
     }
 }
 
-template <int NB, int NP>
+template <int NB, int NP, int KC>
 hipError_t x6_by_rm(int rm, dim3 grid, const float* X, Shape3 s, int ell, int64_t col0, uint64_t seed, uint32_t mode,
                     int64_t tps, float* partial, double* nrm2, hipStream_t st) {
     switch (rm) {
         case 1:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 1, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
-                               mode, tps, partial, nrm2);
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 1, NP, KC>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tps, partial, nrm2);
             return hipGetLastError();
         case 2:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 2, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
-                               mode, tps, partial, nrm2);
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 2, NP, KC>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tps, partial, nrm2);
             return hipGetLastError();
         case 4:
-            hipLaunchKernelGGL((sketch_x6_kernel<NB, 4, NP>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell, col0, seed,
-                               mode, tps, partial, nrm2);
+            hipLaunchKernelGGL((sketch_x6_kernel<NB, 4, NP, KC>), grid, dim3(64 * X6_WPG), 0, st, X, s.L, s.J, s.R, ell,
+                               col0, seed, mode, tps, partial, nrm2);
             return hipGetLastError();
         default:
             return hipErrorInvalidValue;
@@ -325,9 +340,12 @@ void plan_sketch_x6(SketchPlan& p, Shape3 s, int ell, bool bf16, int rb, int wgs
     p.rw = 0;
     p.nq = (ell + 15) / 16;
     p.ldp = ell;
+    // tiles of 64 columns (two MFMA steps, 256-byte runs per row) for the
+    // bfloat16 sketch over 128-row workgroups, where they read faster; 32 otherwise
+    p.kc = bf16 && p.rb == 1 ? 2 * X6_KC : X6_KC;
     const int64_t mt = 16 * p.rb * X6_WPG;
     const int64_t K = s.L * s.R;
-    const int64_t ntl = (K + X6_KC - 1) / X6_KC;
+    const int64_t ntl = (K + p.kc - 1) / p.kc;
     p.nrowtile = (int)((s.J + mt - 1) / mt);
     int64_t want = (wgs > 0 ? wgs : 2048 / X6_WPG) / p.nrowtile;   // built-in: two waves per SIMD
     if (want < 1) want = 1;
@@ -343,9 +361,10 @@ hipError_t launch_sketch_f32_x6(const SketchPlan& p, const float* X, Shape3 s, i
     if ((p.kind != 3 && p.kind != 4) || !sketch_x6_ok(s, ell, col0, X)) return hipErrorInvalidValue;
     const dim3 grid(p.nsplit, p.nrowtile);
     const int64_t tps = p.tiles_per_split;
-#define RT_X6(NBV)                                                                                               \
-    return p.kind == 3 ? x6_by_rm<NBV, 3>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream) \
-                       : x6_by_rm<NBV, 2>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream)
+#define RT_X6(NBV)                                                                                                  \
+    return p.kind == 3   ? x6_by_rm<NBV, 3, X6_KC>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream) \
+           : p.kc == X6_KC ? x6_by_rm<NBV, 2, X6_KC>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream) \
+                         : x6_by_rm<NBV, 2, 2 * X6_KC>(p.rb, grid, X, s, ell, col0, seed, mode, tps, partial, nrm2, stream)
     switch (p.nq) {
         case 1: RT_X6(1);
         case 2: RT_X6(2);
