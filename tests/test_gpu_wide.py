@@ -124,3 +124,38 @@ def test_wide_adaptive(ctx, alg, dtype, b):
     assert min(o.ranks) > 64
     _adaptive_check(g, o, Xf, 1e-3, 1e-10 if dtype == torch.float64 else 1e-5,
                     2.0 ** -53 if dtype == torch.float64 else 2.0 ** -24)
+
+
+def _random_wide_case(seed):
+    # seeded: order 3, sides 90-220, a low-rank signal of ranks 40-110 in two
+    # modes (the others narrow) plus 1e-3 noise, p from 2 to 10 with r + p <= 128
+    # in the wide modes, a random mode order
+    rng = np.random.default_rng(1300 + seed)
+    dims = [int(v) for v in rng.integers(90, 221, size=3)]
+    p = int(rng.integers(2, 11))
+    wide = rng.choice(3, size=2, replace=False)
+    ranks = []
+    for j in range(3):
+        if j in wide:
+            ranks.append(int(rng.integers(max(65 - p, 40), min(128 - p, dims[j] - p, 110) + 1)))
+        else:
+            ranks.append(int(rng.integers(4, 20)))
+    order = [int(v) for v in rng.permutation(3)]
+    X = inputs.lowrank_tensor(rng, tuple(dims), tuple(ranks), noise=1e-3)
+    dtype = torch.float64 if seed % 2 == 0 else torch.float32
+    return X, ranks, p, order, dtype
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_wide_shapes(ctx, seed):
+    X, ranks, p, order, dtype = _random_wide_case(seed)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    Xd = torch.from_numpy(Xs).cuda()
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    g = ctx.rsthosvd(Xd, ranks, p, seed=seed, order=order)
+    o = oracle.rsthosvd(Xf, ranks, p, seed=seed, order=order)
+    _check(g, o, Xf, tol)
+    g = ctx.rhosvd(Xd, ranks, p, seed=seed)
+    o = oracle.rhosvd(Xf, ranks, p, seed=seed)
+    _check(g, o, Xf, tol)
