@@ -199,3 +199,27 @@ def test_binned_sketch_large_inputs(ctx, dtype):
     g = ctx.sp_sthosvd_coo(i, v, dims, [10, 10, 10], 5, seed=8, order=[0, 1, 2])
     o = oracle.sp_sthosvd_coo(idx, _vals_as(vals, dtype), dims, [10, 10, 10], 5, seed=8, order=[0, 1, 2])
     _check_against_oracle(g, o, X, 1e-10 if dtype == torch.float64 else 1e-4)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_sparse_sketches(ctx, seed):
+    # seeded random coordinate tensors: order 2-4, sides 2-150, densities 0.1 %
+    # to 30 %, entries in a random order, every mode at a random sketch width and
+    # column offset, both precisions, against the oracle's COO sketch
+    rng = np.random.default_rng(4100 + seed)
+    d = int(rng.integers(2, 5))
+    dims = tuple(int(v) for v in rng.integers(2, {2: 151, 3: 61, 4: 21}[d], size=d))
+    idx, vals = inputs.random_sparse(rng, dims, float(10.0 ** rng.uniform(-3, np.log10(0.3))))
+    perm = rng.permutation(idx.shape[1])
+    idx, vals = idx[:, perm], vals[perm]
+    for dtype in (torch.float64, torch.float32):
+        i, v = _dev(idx, vals, dtype)
+        vo = _vals_as(vals, dtype)
+        tol = 1e-12 if dtype == torch.float64 else 2e-6
+        for mode in range(d):
+            ell = int(rng.integers(1, 65))
+            col0 = int(rng.integers(0, 1000))
+            Y = ctx.sketch_coo(i, v, dims, mode, ell, seed=seed, col0=col0)
+            Yo = oracle.sketch_coo(idx, vo, dims, mode, ell, seed, col0)
+            scale = max(float(np.max(np.abs(Yo))), 1e-300) if Yo.size else 1.0
+            assert np.max(np.abs(to_np(Y) - Yo), initial=0.0) <= tol * scale, (dims, mode, ell, col0, idx.shape[1])
