@@ -555,3 +555,32 @@ def test_random_shapes_adaptive_parity(ctx, seed):
     g = ctx.rhosvd_adaptive(Xd, eps, b, seed=seed)
     o = oracle.adaptive_rhosvd(Xf, eps, b, seed=seed, delta=1e-10 if f64 else 1e-5)
     _adaptive_check(g, o, Xf, eps, 1e-10 if f64 else 1e-5, 2.0 ** -53 if f64 else 2.0 ** -24)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_reconstruct(ctx, seed):
+    # seeded random Tucker tensors: order 2-5, sides 1-120 (at most ~2e6
+    # entries out), core sides 1..min(side, 40) or a kept mode (no factor),
+    # Gaussian core and factors, both precisions, against the oracle's mode
+    # products
+    from types import SimpleNamespace
+    rng = np.random.default_rng(2500 + seed)
+    d = int(rng.integers(2, 6))
+    hi = {2: 121, 3: 121, 4: 38, 5: 18}[d]
+    dims = [int(v) for v in rng.integers(1, hi, size=d)]
+    ranks, kept = [], []
+    for j in range(d):
+        keep = rng.random() < 0.2 and dims[j] <= 40
+        kept.append(keep)
+        ranks.append(dims[j] if keep else int(rng.integers(1, min(dims[j], 40) + 1)))
+    core = rng.standard_normal(ranks)
+    facs = [None if kept[j] else rng.standard_normal((dims[j], ranks[j])) for j in range(d)]
+    for dtype, npd, tol in ((torch.float64, np.float64, 1e-13), (torch.float32, np.float32, 2e-6)):
+        c = core.astype(npd)
+        f = [None if A is None else A.astype(npd) for A in facs]
+        t = SimpleNamespace(core=torch.from_numpy(c).cuda(),
+                            factors=[None if A is None else torch.from_numpy(A).cuda() for A in f])
+        Xh = to_np(ctx.reconstruct(t))
+        ref = oracle.reconstruct(c.astype(np.float64), [None if A is None else A.astype(np.float64) for A in f])
+        assert Xh.shape == tuple(dims)
+        assert rel(Xh, ref) < tol, (dims, ranks, kept)
