@@ -584,3 +584,30 @@ def test_random_reconstruct(ctx, seed):
         ref = oracle.reconstruct(c.astype(np.float64), [None if A is None else A.astype(np.float64) for A in f])
         assert Xh.shape == tuple(dims)
         assert rel(Xh, ref) < tol, (dims, ranks, kept)
+
+
+def _random_power_case(seed):
+    # seeded: order 3 or 4, sides 20-80, a graded signal (core 0.7^(i+j+...))
+    # truncated inside it, p from 2 to 5, one or two subspace-iteration steps
+    rng = np.random.default_rng(3300 + seed)
+    d = int(rng.integers(3, 5))
+    dims = [int(v) for v in rng.integers(20, 81 if d == 3 else 31, size=d)]
+    core = [int(rng.integers(8, min(n // 2, 14) + 1)) for n in dims]
+    p = int(rng.integers(2, 6))
+    ranks = [int(rng.integers(2, c - 1)) for c in core]
+    q = 1 + (seed // 4) % 2
+    X = inputs.lowrank_tensor(rng, tuple(dims), tuple(core), noise=1e-4,
+                              core_scale=inputs.graded_scale(tuple(core), 0.7))
+    alg = "rsthosvd" if seed % 2 == 0 else "rhosvd"
+    dtype = torch.float64 if (seed // 2) % 2 == 0 else torch.float32
+    return X, ranks, p, q, alg, dtype
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_subspace_iteration(ctx, seed):
+    X, ranks, p, q, alg, dtype = _random_power_case(seed)
+    Xs = X.astype(np.float32) if dtype == torch.float32 else X
+    Xf = Xs.astype(np.float64)
+    g = getattr(ctx, alg)(torch.from_numpy(Xs).cuda(), ranks, p, seed, power_iters=q)
+    o = getattr(oracle, alg)(Xf, ranks, p, seed, q=q)
+    _check(g, o, Xf, 1e-10 if dtype == torch.float64 else 1e-5)
